@@ -1,0 +1,122 @@
+"""Integrated Green's function (IGF) of the free-space Poisson equation (oracle).
+
+Reading (the paper gives only "Poisson solve" in the bunch rest frame, sections "ImpactX" and
+"Model Assumptions"; the integrated Green's function is the published method of J. Qiang et al.,
+Phys. Rev. ST Accel. Beams 9, 044204 (2006)):
+
+    Gbar(i, j, k) = (1 / (hx hy hz)) * integral over the cell centred at (i hx, j hy, k hz)
+                    of dV / |r|
+
+with (hx, hy, hz) the REST-FRAME cell (hz = gamma * lab hz).  The cell integral is the
+alternating sum over the 8 cell corners of the antiderivative
+
+    F(x,y,z) = x y ln(z+r) + y z ln(x+r) + z x ln(y+r)
+               - x^2/2 atan(y z/(x r)) - y^2/2 atan(z x/(y r)) - z^2/2 atan(x y/(z r)),
+
+r = sqrt(x^2+y^2+z^2), with every term whose prefactor is zero taken as zero
+(d^3 F / dx dy dz = 1/r).  The corner formula is used only on the non-negative octant; a cell
+that straddles a coordinate plane (index 0 on that axis) is folded onto [0, h/2] with weight 2,
+using the evenness of 1/r.
+
+Conditioning: the 8-corner sum cancels by a factor up to ~1e8 for far cells of elongated
+rest-frame cells, which in plain float64 leaves ~1e-7 relative error in Gbar and ~1e-11 in
+the field.  The oracle therefore evaluates F and the corner sum in double-double arithmetic
+(oracle.dd) and rounds the cell average to float64 once, so the returned array is the cell
+average of 1/r to float64 rounding.
+
+Pinned by tests/test_oracle_igf.py: unit-cube closed form 3 ln(2+sqrt3) - pi/2; scipy adaptive
+cubature for anisotropic cells; 50-digit mpmath corner sums for far, elongated cells;
+Gbar(d) |d| -> 1 with an O((h/d)^4) error for cubic cells.
+"""
+import numpy as np
+
+from . import dd
+
+
+def _corner_coords(n, h):
+    """Corner coordinates e_0 = 0, e_m = (m - 1/2) h, m = 1..n+1, as exact double-doubles."""
+    m = np.arange(n + 2, dtype=np.float64)
+    c = m - 0.5
+    c[0] = 0.0
+    return dd.two_prod(c, np.full_like(c, h))
+
+
+def antiderivative(x, y, z):
+    """F(x, y, z) on double-double inputs x, y, z >= 0 (broadcast arrays)."""
+    x2 = dd.mul(x, x)
+    y2 = dd.mul(y, y)
+    z2 = dd.mul(z, z)
+    r = dd.sqrt(dd.add(dd.add(x2, y2), z2))
+    xz = x[0] == 0
+    yz = y[0] == 0
+    zz = z[0] == 0
+
+    def safe(a, mask):
+        return np.where(mask, 1.0, a[0]), np.where(mask, 0.0, a[1])
+
+    def zero_where(t, mask):
+        return np.where(mask, 0.0, t[0]), np.where(mask, 0.0, t[1])
+
+    xy = dd.mul(x, y)
+    yzp = dd.mul(y, z)
+    zx = dd.mul(z, x)
+    # logarithmic terms: the argument (coord + r) is > 0 whenever the prefactor is non-zero
+    t1 = zero_where(dd.mul(xy, dd.log(safe(dd.add(z, r), xz | yz))), xz | yz)
+    t2 = zero_where(dd.mul(yzp, dd.log(safe(dd.add(x, r), yz | zz))), yz | zz)
+    t3 = zero_where(dd.mul(zx, dd.log(safe(dd.add(y, r), zz | xz))), zz | xz)
+    # arctangent terms
+    t4 = zero_where(dd.mul_d(dd.mul(x2, dd.atan(dd.div(yzp, safe(dd.mul(x, r), xz)))), 0.5), xz)
+    t5 = zero_where(dd.mul_d(dd.mul(y2, dd.atan(dd.div(zx, safe(dd.mul(y, r), yz)))), 0.5), yz)
+    t6 = zero_where(dd.mul_d(dd.mul(z2, dd.atan(dd.div(xy, safe(dd.mul(z, r), zz)))), 0.5), zz)
+    s = dd.add(dd.add(t1, t2), t3)
+    s = dd.sub(s, dd.add(dd.add(t4, t5), t6))
+    return s
+
+
+def cell_average(nx, ny, nz, hx, hy, hz):
+    """Gbar(i, j, k) for i = 0..nx, j = 0..ny, k = 0..nz; array shape (nz+1, ny+1, nx+1).
+
+    hx, hy, hz are the rest-frame cell edges in metres; the result is in 1/m.
+    """
+    ex = _corner_coords(nx, hx)
+    ey = _corner_coords(ny, hy)
+    ez = _corner_coords(nz, hz)
+    # corner grid, axis order (z, y, x)
+    Z = (ez[0][:, None, None], ez[1][:, None, None])
+    Y = (ey[0][None, :, None], ey[1][None, :, None])
+    X = (ex[0][None, None, :], ex[1][None, None, :])
+    shape = (nz + 2, ny + 2, nx + 2)
+    Z = (np.broadcast_to(Z[0], shape), np.broadcast_to(Z[1], shape))
+    Y = (np.broadcast_to(Y[0], shape), np.broadcast_to(Y[1], shape))
+    X = (np.broadcast_to(X[0], shape), np.broadcast_to(X[1], shape))
+    Fc = antiderivative(X, Y, Z)
+    # triple difference over the 8 corners of each cell
+    D = dd.sub((Fc[0][:, :, 1:], Fc[1][:, :, 1:]), (Fc[0][:, :, :-1], Fc[1][:, :, :-1]))
+    D = dd.sub((D[0][:, 1:, :], D[1][:, 1:, :]), (D[0][:, :-1, :], D[1][:, :-1, :]))
+    D = dd.sub((D[0][1:, :, :], D[1][1:, :, :]), (D[0][:-1, :, :], D[1][:-1, :, :]))
+    # fold the cells that straddle a coordinate plane (index 0): weight 2 per folded axis
+    w = np.ones((nz + 1, ny + 1, nx + 1))
+    w[0, :, :] *= 2.0
+    w[:, 0, :] *= 2.0
+    w[:, :, 0] *= 2.0
+    D = (D[0] * w, D[1] * w)
+    vol = dd.mul(dd.two_prod(np.float64(hx), np.float64(hy)), dd.dd(np.float64(hz)))
+    vol = (np.full(D[0].shape, vol[0]), np.full(D[0].shape, vol[1]))
+    return dd.to_float(dd.div(D, vol))
+
+
+def hockney_array(gbar):
+    """Place Gbar even-symmetrically in the (2nz, 2ny, 2nx) cyclic array.
+
+    Index t of an axis of length M = 2n holds offset t for t = 0..n and offset M - t for
+    t = n+1..M-1, so the cyclic convolution with a source on nodes 0..n-1 equals the free-space
+    sum for output nodes -1 (index M-1) through n.
+    """
+    nz, ny, nx = (s - 1 for s in gbar.shape)
+
+    def offs(n):
+        M = 2 * n
+        t = np.arange(M)
+        return np.where(t <= n, t, M - t)
+
+    return gbar[np.ix_(offs(nz), offs(ny), offs(nx))]

@@ -1,0 +1,247 @@
+"""Space-charge PIC step in plain NumPy float64 (oracle; test infrastructure).
+
+What the paper fixes (section "Model Assumptions"): s-based tracking by symplectic maps that
+are linear about the reference orbit; one reference velocity for the whole bunch; space charge
+electrostatic in the bunch rest frame, found by solving the Poisson equation there and applied
+with a map-based split-operator.  It names the steps -- charge deposition, Poisson solve, beam
+statistics (section "ImpactX") -- and the B-spline particle-shape order (Listing 1,
+`set_particle_shape`).  The formulas below are readings where the paper is silent:
+
+* Phase space (x, px, y, py, z, delta): x, y, z in m (z = lab longitudinal offset from the
+  reference particle, head positive), px = p_x/p0, py = p_y/p0, delta = (p - p0)/p0.
+* Reference particle from kinetic energy and rest mass: gamma = 1 + T/m.
+* Macroparticle charge q_m = sign(q) Q/N.
+* Grid: nx x ny x nz nodes (node-centred).  Each step the box is the particle min/max of
+  x, y, z; h_a = (max_a - min_a)/(n_a - 3) and origin_a = min_a - h_a, so every CIC and TSC
+  stencil stays on nodes 0..n_a-1.  Rest frame: z' = gamma z, so the rest-frame cell is
+  (hx, hy, gamma hz); node charges are frame-invariant.
+* Shapes (B-spline order 1 and 2), u = (x - origin)/h:
+  CIC  i = floor(u), f = u - i, weights (1-f, f) on nodes (i, i+1);
+  TSC  i = floor(u + 1/2), d = u - i, weights (1/2 (1/2-d)^2, 3/4 - d^2, 1/2 (1/2+d)^2)
+       on nodes (i-1, i, i+1); 3-D weights are tensor products.
+* Poisson: phi_n = 1/(4 pi eps0) sum_m Q_m Gbar(n - m) with the integrated Green's function
+  (oracle.igf), by Hockney's method: zero-pad to (2nz, 2ny, 2nx), cyclic convolution by FFT.
+  phi is kept on nodes -1..n_a (the cyclic result is exact there).
+* Field: E' = -grad phi by centred differences with spacings (hx, hy, gamma hz) on all nodes.
+* Gather: the deposit's shape (momentum conserving).
+* Kick over a length L (lab transverse force q E'/gamma, longitudinal q E'_z, divided by
+  p0 beta c): dpx = C E'x L, dpy = C E'y L, ddelta = gamma C E'z L, C = (q/m)/(gamma^2 beta^2)
+  with q/m in e/eV (the paper's qm_qeeV) and E' in V/m.
+* Linear drift over l: x += l px, y += l py, z += l delta/gamma^2.
+* Thin quadrupole of integrated strength K (1/m): px -= K x, py += K y.
+* Step (split operator): thin quad K_j, drift L/2, space-charge kick over L with the field
+  of the positions at that point, drift L/2.  The lattice (K_j, L_j) is cycled.
+* Moments: centred second moments (1/N); geometric emittance
+  eps_x = sqrt(<dx^2><dpx^2> - <dx dpx>^2) (unnormalised, as the paper quotes emittance).
+
+Pins: tests/test_oracle_pic.py (charge conservation, shape values, Hockney vs direct
+summation, analytic Gaussian-bunch field, direct Coulomb sums, momentum conservation, mirror
+symmetry, closed-form maps and phase advance, kick constant from SI units) and
+tests/test_oracle_golden.py (the paper's printed emittance).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from .constants import EPS0
+from . import igf
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Constants of one beam: reference particle, species, grid, shape."""
+    gamma: float
+    gb2: float          # gamma^2 beta^2
+    C: float            # kick constant (q/m)/(gamma^2 beta^2), 1/V
+    q_macro: float      # charge per macroparticle, C
+    nodes: tuple        # (nx, ny, nz)
+    shape: int          # 1 = CIC, 2 = TSC
+
+
+def reference(kin_energy_MeV, mass_MeV):
+    """gamma and gamma^2 beta^2 = (gamma-1)(gamma+1) of the reference particle."""
+    t = kin_energy_MeV / mass_MeV
+    gamma = 1.0 + t
+    return gamma, t * (2.0 + t)
+
+
+def make_problem(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, nodes, shape):
+    gamma, gb2 = reference(kin_energy_MeV, mass_MeV)
+    C = qm_qeeV / gb2
+    q_macro = np.copysign(charge_C, qm_qeeV) / n
+    return Problem(gamma, gb2, C, q_macro, tuple(int(v) for v in nodes), int(shape))
+
+
+def init_from_normals(sigma6, xi):
+    """X = L xi with L the lower Cholesky factor of the 6x6 second-moment matrix."""
+    L = np.linalg.cholesky(np.asarray(sigma6, dtype=np.float64))
+    return L @ xi
+
+
+# ----------------------------------------------------------------------------- geometry
+
+@dataclass(frozen=True)
+class Geometry:
+    origin: np.ndarray   # (3,) lab origin of node 0, axes (x, y, z)
+    h: np.ndarray        # (3,) lab spacings
+    h_rest: np.ndarray   # (3,) rest-frame spacings (hx, hy, gamma hz)
+
+
+def geometry(X, prob: Problem):
+    pos = X[[0, 2, 4]]
+    lo = pos.min(axis=1)
+    hi = pos.max(axis=1)
+    if not (np.all(np.isfinite(lo)) and np.all(np.isfinite(hi))):
+        raise FloatingPointError("non-finite particle coordinate")
+    ext = hi - lo
+    if np.any(ext <= 0):
+        raise ValueError("zero extent of the particle box")
+    n = np.asarray(prob.nodes, dtype=np.float64)
+    h = ext / (n - 3.0)
+    origin = lo - h
+    h_rest = np.array([h[0], h[1], prob.gamma * h[2]])
+    return Geometry(origin, h, h_rest)
+
+
+# ----------------------------------------------------------------------------- shapes
+
+def shape_weights(u, shape):
+    """Node indices and weights along one axis; returns (idx, w) of shape (S, n)."""
+    if shape == 1:
+        i = np.floor(u)
+        f = u - i
+        i = i.astype(np.int64)
+        return np.stack([i, i + 1]), np.stack([1.0 - f, f])
+    if shape == 2:
+        i = np.floor(u + 0.5)
+        d = u - i
+        i = i.astype(np.int64)
+        w = np.stack([0.5 * (0.5 - d) ** 2, 0.75 - d * d, 0.5 * (0.5 + d) ** 2])
+        return np.stack([i - 1, i, i + 1]), w
+    raise ValueError("shape must be 1 (CIC) or 2 (TSC)")
+
+
+def _stencil(X, geom, prob):
+    """Flattened node index and 3-D weight for every (particle, stencil point)."""
+    nx, ny, nz = prob.nodes
+    ix, wx = shape_weights((X[0] - geom.origin[0]) / geom.h[0], prob.shape)
+    iy, wy = shape_weights((X[2] - geom.origin[1]) / geom.h[1], prob.shape)
+    iz, wz = shape_weights((X[4] - geom.origin[2]) / geom.h[2], prob.shape)
+    for a, na in ((ix, nx), (iy, ny), (iz, nz)):
+        if a.min() < 0 or a.max() >= na:
+            raise IndexError("stencil outside the grid")
+    flat = (iz[:, None, None, :] * ny + iy[None, :, None, :]) * nx + ix[None, None, :, :]
+    w = wz[:, None, None, :] * wy[None, :, None, :] * wx[None, None, :, :]
+    return flat, w
+
+
+def deposit(X, geom, prob: Problem):
+    """Charge per node Q (coulomb), shape (nz, ny, nx)."""
+    nx, ny, nz = prob.nodes
+    flat, w = _stencil(X, geom, prob)
+    Q = np.bincount(flat.ravel(), weights=(prob.q_macro * w).ravel(), minlength=nx * ny * nz)
+    return Q.reshape(nz, ny, nx)
+
+
+# ----------------------------------------------------------------------------- Poisson
+
+def green(geom, prob: Problem):
+    nx, ny, nz = prob.nodes
+    hx, hy, hz = geom.h_rest
+    return igf.cell_average(nx, ny, nz, hx, hy, hz)
+
+
+def solve(Q, gbar):
+    """phi on nodes -1..n_a (shape (nz+2, ny+2, nx+2)) by zero-padded FFT convolution."""
+    nz, ny, nx = Q.shape
+    shape = (2 * nz, 2 * ny, 2 * nx)
+    Gfull = igf.hockney_array(gbar)
+    Qpad = np.zeros(shape)
+    Qpad[:nz, :ny, :nx] = Q
+    axes = (0, 1, 2)
+    conv = np.fft.irfftn(np.fft.rfftn(Qpad, axes=axes) * np.fft.rfftn(Gfull, axes=axes),
+                         s=shape, axes=axes)
+    keep = [np.concatenate([[m - 1], np.arange(n + 1)]) for m, n in zip(shape, (nz, ny, nx))]
+    return conv[np.ix_(*keep)] / (4.0 * np.pi * EPS0)
+
+
+def field(phi, geom):
+    """Rest-frame E' = -grad phi on nodes 0..n_a-1, shape (3, nz, ny, nx), rows (x, y, z)."""
+    hx, hy, hz = geom.h_rest
+    Ex = -(phi[1:-1, 1:-1, 2:] - phi[1:-1, 1:-1, :-2]) / (2.0 * hx)
+    Ey = -(phi[1:-1, 2:, 1:-1] - phi[1:-1, :-2, 1:-1]) / (2.0 * hy)
+    Ez = -(phi[2:, 1:-1, 1:-1] - phi[:-2, 1:-1, 1:-1]) / (2.0 * hz)
+    return np.stack([Ex, Ey, Ez])
+
+
+def gather(E, X, geom, prob: Problem):
+    """Field at the particles, shape (3, n)."""
+    flat, w = _stencil(X, geom, prob)
+    out = np.empty((3, X.shape[1]))
+    for c in range(3):
+        out[c] = (E[c].ravel()[flat] * w).sum(axis=(0, 1, 2))
+    return out
+
+
+def sc_field(X, prob: Problem):
+    """Geometry, deposit, IGF, Poisson solve, field and gather for the positions in X."""
+    geom = geometry(X, prob)
+    Q = deposit(X, geom, prob)
+    phi = solve(Q, green(geom, prob))
+    E = field(phi, geom)
+    return gather(E, X, geom, prob)
+
+
+# ----------------------------------------------------------------------------- maps
+
+def drift(X, ell, prob: Problem):
+    Y = X.copy()
+    Y[0] = X[0] + ell * X[1]
+    Y[2] = X[2] + ell * X[3]
+    Y[4] = X[4] + ell * X[5] / (prob.gamma * prob.gamma)
+    return Y
+
+
+def thin_quad(X, K):
+    Y = X.copy()
+    Y[1] = X[1] - K * X[0]
+    Y[3] = X[3] + K * X[2]
+    return Y
+
+
+def kick(X, Ep, L, prob: Problem):
+    Y = X.copy()
+    Y[1] = X[1] + prob.C * Ep[0] * L
+    Y[3] = X[3] + prob.C * Ep[1] * L
+    Y[5] = X[5] + prob.gamma * prob.C * Ep[2] * L
+    return Y
+
+
+def step(X, K, L, prob: Problem, space_charge=True):
+    X = thin_quad(X, K)
+    X = drift(X, 0.5 * L, prob)
+    if space_charge:
+        X = kick(X, sc_field(X, prob), L, prob)
+    return drift(X, 0.5 * L, prob)
+
+
+def track(X, ks, dss, n_steps, prob: Problem, space_charge=True):
+    """Apply n_steps steps; step j uses (ks[j mod n_el], dss[j mod n_el])."""
+    n_el = len(ks)
+    for j in range(n_steps):
+        X = step(X, ks[j % n_el], dss[j % n_el], prob, space_charge)
+    return X
+
+
+# ----------------------------------------------------------------------------- statistics
+
+def moments(X):
+    """Mean (6,), centred covariance (6, 6) and (sigma_x, sigma_y, eps_x, eps_y)."""
+    mean = X.mean(axis=1)
+    D = X - mean[:, None]
+    cov = (D @ D.T) / X.shape[1]
+    sx = np.sqrt(cov[0, 0])
+    sy = np.sqrt(cov[2, 2])
+    ex = np.sqrt(cov[0, 0] * cov[1, 1] - cov[0, 1] ** 2)
+    ey = np.sqrt(cov[2, 2] * cov[3, 3] - cov[2, 3] ** 2)
+    return mean, cov, np.array([sx, sy, ex, ey])
