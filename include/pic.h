@@ -1,0 +1,168 @@
+/*
+ * pic.h -- C ABI of libpic.so, a space-charge particle-in-cell step for s-based beam dynamics
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv:2208.02382, section "Model Assumptions"): particles are pushed in s by
+ * symplectic maps that are linear about the reference orbit; space charge is electrostatic in
+ * the bunch rest frame, obtained from a Poisson solve there and applied with a split-operator
+ * (kick between two half drifts).  The paper names the building blocks -- charge deposition,
+ * Poisson solve, beam statistics (section "ImpactX") -- and the user-level calls of its
+ * Listing 1: add_particles(qm, charge_C, distribution, npart), set_particle_shape(order),
+ * ref_particle().set_energy_MeV(E, mass), set_space_charge(bool), lattice.extend([...]),
+ * evolve().  The calls below follow that statement of the problem.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Phase space: caller-owned device array X of 6*n doubles, structure of arrays, rows
+ *   X[0*n+i] = x [m], X[1*n+i] = px = p_x/p0, X[2*n+i] = y [m], X[3*n+i] = py,
+ *   X[4*n+i] = z [m] (lab offset from the reference particle, head positive),
+ *   X[5*n+i] = delta = (p - p0)/p0.
+ * Grids: node-centred, nx*ny*nz nodes, index ((k*ny)+j)*nx+i (x fastest).  Element type is
+ *   double, or float when pic_beam_desc.grid_fp32 = 1 ("pic_real" below).
+ * Geometry: each pic_deposit / pic_track_n_steps step takes the box of the particle positions
+ *   (min/max of x, y, z); h_a = (max_a - min_a)/(n_a - 3), node 0 at min_a - h_a, so every CIC
+ *   and TSC stencil stays on nodes 0..n_a-1.  The rest-frame cell is (hx, hy, gamma*hz).
+ * Memory: the library never allocates device memory.  The caller owns X, every grid and the
+ *   workspace (size from pic_workspace_bytes), all device pointers, 256-byte aligned.  The
+ *   handle (host memory) is owned by the library until pic_beam_destroy.
+ * Streams: every call takes a hipStream_t as `void* stream` (NULL = the null stream) and only
+ *   enqueues work on it, unless stated "synchronises".
+ * Errors: calls return pic_status.  Argument errors are reported synchronously and leave the
+ *   device untouched.  Device-side errors (a non-finite coordinate, a zero-extent box) set a
+ *   flag in the workspace; from then on every kernel of the beam skips its work, and the next
+ *   synchronising call (pic_check, pic_moments, pic_get_geometry) returns PIC_EDOMAIN.
+ *   pic_last_error() gives a message for the last failure on the calling thread.
+ * Thread safety: one handle must not be used from two host threads at once; calls on one
+ *   handle on two streams race.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,        /* bad argument (NULL pointer, size, unsupported combination) */
+  PIC_ENOMEM = -2,        /* workspace too small */
+  PIC_EHIP = -3,          /* a HIP runtime call failed */
+  PIC_EDOMAIN = -4,       /* device flagged a non-finite coordinate or a zero-extent box */
+  PIC_EUNSUPPORTED = -5,  /* grid size whose padded FFT length is not 2^a 3^b, or > 512 */
+  PIC_ENODEV = -6         /* no HIP device */
+} pic_status;
+
+/* Beam description; mirrors add_particles + set_energy_MeV + set_particle_shape +
+ * set_space_charge of the paper's Listing 1. */
+typedef struct {
+  int64_t n;               /* number of macroparticles (npart), >= 1 */
+  double qm_qeeV;          /* species charge/mass in e/eV (electron: -1e-6/0.510998950) */
+  double charge_C;         /* bunch charge magnitude in coulomb; macro charge = sign(qm)*charge_C/n */
+  double kin_energy_MeV;   /* reference particle kinetic energy; gamma = 1 + T/m */
+  double mass_MeV;         /* rest mass */
+  int shape;               /* B-spline order: 1 = CIC, 2 = TSC */
+  int nx, ny, nz;          /* grid nodes per axis, each >= 4; padded FFT length 2*n_a must be
+                              2^a 3^b and <= 512 */
+  int grid_fp32;           /* 0: float64 charge grid, FFT and field; 1: float32 (particles and
+                              the push stay float64) */
+  int space_charge;        /* 0/1 (set_space_charge); 0 makes pic_track_n_steps purely linear */
+} pic_beam_desc;
+
+/* One lattice step of pic_track_n_steps: a thin quadrupole of integrated strength k [1/m]
+ * (px -= k x, py += k y) followed by a space-charge drift of length ds [m] (drift ds/2,
+ * space-charge kick over ds, drift ds/2). */
+typedef struct {
+  double k;
+  double ds;
+} pic_element;
+
+typedef struct pic_beam_s* pic_beam;
+
+/* Push kinds of pic_push. */
+enum { PIC_PUSH_DRIFT = 0, PIC_PUSH_THINQUAD = 1, PIC_PUSH_KICK = 2 };
+
+/* Workspace bytes needed for a beam described by d (0 on an invalid description). */
+size_t pic_workspace_bytes(const pic_beam_desc* d);
+
+/* Bind a description, the caller's phase-space array d_X (6*n doubles) and workspace to a new
+ * handle; enqueues a one-time set-up of the workspace (FFT twiddles, box slots) on `stream`.
+ * PIC_ENOMEM if work_bytes < pic_workspace_bytes(d). */
+pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, size_t work_bytes,
+                           void* stream, pic_beam* out);
+
+/* Release the handle (host memory only; device memory stays the caller's). */
+pic_status pic_beam_destroy(pic_beam b);
+
+/* init_beam: fill X with x = L xi, L the lower Cholesky factor of sigma6x6 (row-major 6x6,
+ * symmetric positive definite; PIC_EINVAL otherwise).  xi is drawn on the device with
+ * Philox4x32-10 (Salmon et al., SC'11; key = seed, counter = (particle index, draw block)) and
+ * Box-Muller; the trailing round(halo_frac*n) particles are instead uniform in [-4, 4]^6
+ * (a uniform halo out to 4 sigma).  halo_frac in [0, 1]. */
+pic_status pic_init_beam(pic_beam b, const double sigma6x6[36], uint64_t seed, double halo_frac,
+                         void* stream);
+
+/* Same as pic_init_beam with caller-supplied draws: d_xi is a device array of 6*n doubles in
+ * the layout of X.  Used to start the device and a reference implementation from the same
+ * draws. */
+pic_status pic_init_beam_from_normals(pic_beam b, const double sigma6x6[36], const double* d_xi,
+                                      void* stream);
+
+/* Charge deposition (paper: "charge deposition"; shape order of Listing 1): computes the
+ * geometry from the current positions, then writes the charge per node in coulomb,
+ * Q_n = sum_i q_macro W(x_i - X_n) with W the CIC or TSC tensor-product B-spline, into
+ * d_rho (nx*ny*nz pic_real, overwritten). */
+pic_status pic_deposit(pic_beam b, void* d_rho, void* stream);
+
+/* Poisson solve in the bunch rest frame (paper: "Poisson solve"; section "Model Assumptions"):
+ * phi_n = 1/(4 pi eps0) sum_m Q_m Gbar(n - m), Gbar the integrated Green's function (cell
+ * average of 1/r over a rest-frame cell; Qiang et al., PRST-AB 9, 044204, 2006), by zero
+ * padding to (2nz, 2ny, 2nx) and FFT convolution; then E' = -grad phi by centred differences
+ * with spacings (hx, hy, gamma hz).  Uses the geometry of the last pic_deposit.
+ * d_rho: nx*ny*nz pic_real (coulomb per node).  d_phi: optional (NULL allowed),
+ * (nx+2)*(ny+2)*(nz+2) pic_real holding phi on nodes -1..n_a (volt).  d_E: 3*nx*ny*nz
+ * pic_real, component-major E'[c][k][j][i] (V/m, rest frame). */
+pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d_E, void* stream);
+
+/* Field gather with the deposit's shape (momentum-conserving): d_Ep[c*n+i] = sum_n
+ * W(x_i - X_n) E'[c][n]; d_E as written by pic_poisson_solve, d_Ep 3*n pic_real.
+ * Uses the geometry of the last pic_deposit. */
+pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream);
+
+/* One linear map on every particle (section "Model Assumptions": maps linear about the
+ * reference orbit):
+ *   PIC_PUSH_DRIFT     value = l  : x += l px, y += l py, z += l delta/gamma^2
+ *   PIC_PUSH_THINQUAD  value = k  : px -= k x, py += k y
+ *   PIC_PUSH_KICK      value = L  : px += C E'x L, py += C E'y L, delta += gamma C E'z L with
+ *                                   C = qm_qeeV/(gamma^2 beta^2) and d_Ep from pic_gather
+ * d_Ep is read only by PIC_PUSH_KICK (NULL allowed otherwise). */
+pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* stream);
+
+/* evolve(): n_steps split-operator steps; step j uses lattice[j mod n_el]: thin quad k, drift
+ * ds/2, space-charge kick over ds with the field of the positions at that point (geometry,
+ * deposit, IGF, Poisson, field, gather), drift ds/2.  Updates X in place (particle order is
+ * preserved).  With desc.space_charge = 0 only the linear maps are applied. */
+pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                             void* stream);
+
+/* Beam statistics (paper: "beam statistics"): mean[6] and centred second moments cov[36]
+ * (row-major, 1/n normalisation) of X.  Synchronises `stream`; PIC_EDOMAIN if the device
+ * error flag is set. */
+pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream);
+
+/* Geometry of the last deposit: out[0..2] origin (x, y, z) [m], out[3..5] lab spacings,
+ * out[6..8] rest-frame spacings (hx, hy, gamma hz).  Synchronises `stream`. */
+pic_status pic_get_geometry(pic_beam b, double out[9], void* stream);
+
+/* Synchronise `stream` and report the device error flag (PIC_OK or PIC_EDOMAIN). */
+pic_status pic_check(pic_beam b, void* stream);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

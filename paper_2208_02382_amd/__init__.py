@@ -1,0 +1,217 @@
+"""Python binding of libpic.so, the MI355X space-charge PIC library (C ABI in include/pic.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.  PyTorch supplies
+device memory (tensors) and the stream (torch's current stream).  Importing this package
+raises if the built library is missing; there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpic.so is not built; run `python -m paper_2208_02382_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_EDOMAIN, PIC_EUNSUPPORTED, PIC_ENODEV = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EHIP",
+                -4: "PIC_EDOMAIN", -5: "PIC_EUNSUPPORTED", -6: "PIC_ENODEV"}
+PUSH_DRIFT, PUSH_THINQUAD, PUSH_KICK = 0, 1, 2
+
+
+class BeamDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("qm_qeeV", ctypes.c_double),
+                ("charge_C", ctypes.c_double), ("kin_energy_MeV", ctypes.c_double),
+                ("mass_MeV", ctypes.c_double), ("shape", ctypes.c_int),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int)]
+
+
+class Element(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_double), ("ds", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SIGS = {
+    "pic_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BeamDesc)]),
+    "pic_beam_create": (_I, [ctypes.POINTER(BeamDesc), _P, _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(_P)]),
+    "pic_beam_destroy": (_I, [_P]),
+    "pic_init_beam": (_I, [_P, ctypes.POINTER(_D), ctypes.c_uint64, _D, _P]),
+    "pic_init_beam_from_normals": (_I, [_P, ctypes.POINTER(_D), _P, _P]),
+    "pic_deposit": (_I, [_P, _P, _P]),
+    "pic_poisson_solve": (_I, [_P, _P, _P, _P, _P]),
+    "pic_gather": (_I, [_P, _P, _P, _P]),
+    "pic_push": (_I, [_P, _I, _D, _P, _P]),
+    "pic_track_n_steps": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P]),
+    "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    "pic_get_geometry": (_I, [_P, ctypes.POINTER(_D), _P]),
+    "pic_check": (_I, [_P, _P]),
+    "pic_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.pic_last_error().decode()
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+
+
+def _check(status, where):
+    if status != PIC_OK:
+        raise PicError(status, where)
+
+
+def last_error():
+    return _lib.pic_last_error().decode()
+
+
+def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,
+              space_charge=True):
+    nx, ny, nz = nodes
+    return BeamDesc(int(n), float(qm_qeeV), float(charge_C), float(kin_energy_MeV),
+                    float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
+                    int(bool(space_charge)))
+
+
+def workspace_bytes(desc):
+    return int(_lib.pic_workspace_bytes(ctypes.byref(desc)))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _sigma(sigma):
+    s = torch.as_tensor(sigma, dtype=torch.float64).reshape(36).tolist()
+    return (ctypes.c_double * 36)(*s)
+
+
+class Beam:
+    """A beam bound to device memory owned by torch tensors.
+
+    X is a (6, n) float64 tensor (rows x, px, y, py, z, delta); the workspace is a uint8
+    tensor of pic_workspace_bytes.  Grids are float64, or float32 when grid_fp32.
+    """
+
+    def __init__(self, n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
+                 grid_fp32=False, space_charge=True, device="cuda:0", X=None):
+        self.desc = make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
+                              grid_fp32, space_charge)
+        self.device = torch.device(device)
+        self.n = int(n)
+        self.nodes = tuple(int(v) for v in nodes)
+        self.grid_dtype = torch.float32 if grid_fp32 else torch.float64
+        nbytes = workspace_bytes(self.desc)
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL if last_error() else PIC_EUNSUPPORTED, "workspace_bytes")
+        if X is None:
+            X = torch.empty((6, self.n), dtype=torch.float64, device=self.device)
+        assert X.dtype == torch.float64 and X.is_contiguous() and tuple(X.shape) == (6, self.n)
+        self.X = X
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.pic_beam_create(ctypes.byref(self.desc), _ptr(self.X), _ptr(self.work),
+                                        nbytes, _stream(), ctypes.byref(h)), "pic_beam_create")
+        self._h = h
+
+    @classmethod
+    def from_config(cls, cfg, grid_fp32=False, space_charge=True, device="cuda:0", n=None):
+        """Build from a workloads.Beam-like object (n, qm_qeeV, charge_C, kin_energy_MeV,
+        mass_MeV, shape, nodes)."""
+        return cls(cfg.n if n is None else n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV,
+                   cfg.mass_MeV, cfg.shape, cfg.nodes, grid_fp32, space_charge, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pic_beam_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- grid allocation helpers
+    def new_rho(self):
+        nx, ny, nz = self.nodes
+        return torch.empty((nz, ny, nx), dtype=self.grid_dtype, device=self.device)
+
+    def new_phi(self):
+        nx, ny, nz = self.nodes
+        return torch.empty((nz + 2, ny + 2, nx + 2), dtype=self.grid_dtype, device=self.device)
+
+    def new_E(self):
+        nx, ny, nz = self.nodes
+        return torch.empty((3, nz, ny, nx), dtype=self.grid_dtype, device=self.device)
+
+    def new_Ep(self):
+        return torch.empty((3, self.n), dtype=self.grid_dtype, device=self.device)
+
+    # --------------------------------------------------------------- calls of the C ABI
+    def init(self, sigma, seed, halo_frac=0.0):
+        _check(_lib.pic_init_beam(self._h, _sigma(sigma), int(seed), float(halo_frac),
+                                  _stream()), "pic_init_beam")
+
+    def init_from_normals(self, sigma, xi):
+        assert xi.dtype == torch.float64 and xi.is_contiguous() and tuple(xi.shape) == (6, self.n)
+        _check(_lib.pic_init_beam_from_normals(self._h, _sigma(sigma), _ptr(xi), _stream()),
+               "pic_init_beam_from_normals")
+
+    def deposit(self, rho=None):
+        rho = self.new_rho() if rho is None else rho
+        _check(_lib.pic_deposit(self._h, _ptr(rho), _stream()), "pic_deposit")
+        return rho
+
+    def poisson_solve(self, rho, phi=None, E=None):
+        E = self.new_E() if E is None else E
+        _check(_lib.pic_poisson_solve(self._h, _ptr(rho), _ptr(phi), _ptr(E), _stream()),
+               "pic_poisson_solve")
+        return phi, E
+
+    def gather(self, E, Ep=None):
+        Ep = self.new_Ep() if Ep is None else Ep
+        _check(_lib.pic_gather(self._h, _ptr(E), _ptr(Ep), _stream()), "pic_gather")
+        return Ep
+
+    def push(self, kind, value, Ep=None):
+        _check(_lib.pic_push(self._h, int(kind), float(value), _ptr(Ep), _stream()), "pic_push")
+
+    def track(self, lattice, n_steps):
+        """lattice: sequence of (k, ds) pairs, cycled over the steps."""
+        arr = (Element * len(lattice))(*[Element(float(k), float(ds)) for k, ds in lattice])
+        _check(_lib.pic_track_n_steps(self._h, arr, len(lattice), int(n_steps), _stream()),
+               "pic_track_n_steps")
+
+    def moments(self):
+        mean = (ctypes.c_double * 6)()
+        cov = (ctypes.c_double * 36)()
+        _check(_lib.pic_moments(self._h, mean, cov, _stream()), "pic_moments")
+        return list(mean), [list(cov[r * 6:(r + 1) * 6]) for r in range(6)]
+
+    def geometry(self):
+        out = (ctypes.c_double * 9)()
+        _check(_lib.pic_get_geometry(self._h, out, _stream()), "pic_get_geometry")
+        return list(out[0:3]), list(out[3:6]), list(out[6:9])
+
+    def check(self):
+        return _lib.pic_check(self._h, _stream())

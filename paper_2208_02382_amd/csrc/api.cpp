@@ -1,0 +1,402 @@
+// C ABI of libpic.so: argument validation, workspace layout and the order of kernel launches.
+// Every numerical step runs in the HIP kernels of particles.hip, igf.hip and fft.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/pic.h"
+#include "internal.hpp"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pic_status fail(pic_status st, const char* msg) {
+  g_last_error = msg;
+  return st;
+}
+
+pic_status fail_hip(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return PIC_EHIP;
+}
+
+#define HIP_OK(call, where)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return fail_hip(e_, where); \
+  } while (0)
+
+// radices of M = 2^a 3^b in order of use: 4s, then a 2, then 3s; 0 on failure
+int factor(int M, int rad[12]) {
+  int n = 0, m = M;
+  while (m % 4 == 0 && n < 12) { rad[n++] = 4; m /= 4; }
+  while (m % 2 == 0 && n < 12) { rad[n++] = 2; m /= 2; }
+  while (m % 3 == 0 && n < 12) { rad[n++] = 3; m /= 3; }
+  if (m != 1) return 0;
+  for (int q = n; q < 12; ++q) rad[q] = 1;
+  return n;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gh, rho, phi, E, total;
+};
+
+pic_status check_desc(const pic_beam_desc* d) {
+  if (!d) return fail(PIC_EINVAL, "NULL description");
+  if (d->n < 1) return fail(PIC_EINVAL, "n must be >= 1");
+  if (d->shape != 1 && d->shape != 2) return fail(PIC_EINVAL, "shape must be 1 (CIC) or 2 (TSC)");
+  if (d->nx < 4 || d->ny < 4 || d->nz < 4) return fail(PIC_EINVAL, "grid needs >= 4 nodes per axis");
+  if (!(d->mass_MeV > 0) || !(d->kin_energy_MeV > 0) || !std::isfinite(d->kin_energy_MeV))
+    return fail(PIC_EINVAL, "mass and kinetic energy must be positive");
+  if (!std::isfinite(d->qm_qeeV) || d->qm_qeeV == 0.0) return fail(PIC_EINVAL, "qm_qeeV must be finite and non-zero");
+  if (!std::isfinite(d->charge_C) || d->charge_C < 0) return fail(PIC_EINVAL, "charge_C must be >= 0");
+  if (d->grid_fp32 != 0 && d->grid_fp32 != 1) return fail(PIC_EINVAL, "grid_fp32 must be 0 or 1");
+  if (d->space_charge != 0 && d->space_charge != 1) return fail(PIC_EINVAL, "space_charge must be 0 or 1");
+  int nn[3] = {d->nx, d->ny, d->nz};
+  for (int a = 0; a < 3; ++a) {
+    int rad[12];
+    int M = 2 * nn[a];
+    if (M > 512 || factor(M, rad) == 0)
+      return fail(PIC_EUNSUPPORTED, "padded FFT length 2*n must be 2^a 3^b and <= 512");
+  }
+  return PIC_OK;
+}
+
+Layout layout(const pic_beam_desc* d) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t es = d->grid_fp32 ? 4 : 8;
+  const size_t nx = d->nx, ny = d->ny, nz = d->nz;
+  const size_t M3 = 8 * nx * ny * nz;
+  L.geom = take(sizeof(Geom));
+  L.box = take(sizeof(Box));
+  L.mom_partial = take(sizeof(double) * kReduceBlocks * kMomentSlots);
+  L.mom_out = take(sizeof(double) * kMomentSlots);
+  int nn[3] = {d->nx, d->ny, d->nz};
+  for (int a = 0; a < 3; ++a) L.tw[a] = take(sizeof(double2) * 2 * nn[a]);
+  for (int a = 0; a < 3; ++a) L.twf[a] = take(sizeof(float2) * 2 * nn[a]);
+  L.corners = take(sizeof(double2) * (nx + 2) * (ny + 2) * (nz + 2));
+  L.W = take(2 * es * M3);
+  L.Gh = take(es * M3);
+  L.rho = take(es * nx * ny * nz);
+  L.phi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
+  L.E = take(3 * es * nx * ny * nz);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct pic_beam_s {
+  pic_beam_desc d;
+  double* X;
+  char* work;
+  Layout L;
+  Consts c;
+  FftPlan plan;
+  Geom* geom;
+  Box* box;
+  double* mom_partial;
+  double* mom_out;
+  double2* corners;
+  void* W;
+  void* Gh;
+  void* rho;
+  void* phi;
+  void* E;
+};
+
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool cholesky6(const double* A, Chol& out) {
+  double L[36] = {0};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      if (!std::isfinite(A[i * 6 + j]) || std::fabs(A[i * 6 + j] - A[j * 6 + i]) >
+                                               1e-12 * (std::fabs(A[i * 6 + j]) + std::fabs(A[j * 6 + i])))
+        return false;
+  for (int j = 0; j < 6; ++j) {
+    double s = A[j * 6 + j];
+    for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k];
+    if (!(s > 0)) return false;
+    L[j * 6 + j] = std::sqrt(s);
+    for (int i = j + 1; i < 6; ++i) {
+      double t = A[i * 6 + j];
+      for (int k = 0; k < j; ++k) t -= L[i * 6 + k] * L[j * 6 + k];
+      L[i * 6 + j] = t / L[j * 6 + j];
+    }
+  }
+  std::memcpy(out.L, L, sizeof(L));
+  return true;
+}
+
+template <typename T>
+pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s) {
+  HIP_OK(launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->W,
+                                  (T*)b->Gh, s),
+         "green spectrum");
+  HIP_OK(launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W, (const T*)b->Gh,
+                         phi, E, s),
+         "poisson solve");
+  return PIC_OK;
+}
+
+template <typename T>
+pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, hipStream_t s) {
+  const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
+  HIP_OK(launch_box_reset(b->box, s), "box reset");
+  HIP_OK(launch_quad_drift(b->X, lat[0].k, 0.5 * lat[0].ds, b->c, b->box, s), "quad+drift");
+  for (int j = 0; j < n_steps; ++j) {
+    const pic_element& e = lat[j % n_el];
+    HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "geometry");
+    HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "zero rho");
+    HIP_OK(launch_deposit<T>(b->X, b->geom, (T*)b->rho, b->c, s), "deposit");
+    pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s);
+    if (st != PIC_OK) return st;
+    const int has_next = j + 1 < n_steps;
+    const pic_element& nx = lat[(j + 1) % n_el];
+    if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
+    HIP_OK(launch_gkd<T>(b->X, b->geom, (const T*)b->E, e.ds, has_next, nx.k, 0.5 * nx.ds, b->c,
+                         b->box, s),
+           "gather-kick-drift");
+  }
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pic_last_error(void) { return g_last_error.c_str(); }
+
+size_t pic_workspace_bytes(const pic_beam_desc* d) {
+  if (check_desc(d) != PIC_OK) return 0;
+  return layout(d).total;
+}
+
+pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, size_t work_bytes,
+                           void* stream, pic_beam* out) {
+  if (!out) return fail(PIC_EINVAL, "NULL output handle");
+  *out = nullptr;
+  pic_status st = check_desc(d);
+  if (st != PIC_OK) return st;
+  if (!d_X || !d_work) return fail(PIC_EINVAL, "NULL device pointer");
+  if (((uintptr_t)d_X & 7) || ((uintptr_t)d_work & 255))
+    return fail(PIC_EINVAL, "X must be 8-byte and the workspace 256-byte aligned");
+  Layout L = layout(d);
+  if (work_bytes < L.total) return fail(PIC_ENOMEM, "workspace smaller than pic_workspace_bytes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PIC_ENODEV, "no HIP device");
+
+  pic_beam b = new (std::nothrow) pic_beam_s;
+  if (!b) return fail(PIC_EINVAL, "host allocation of the handle failed");
+  b->d = *d;
+  b->X = d_X;
+  b->work = (char*)d_work;
+  b->L = L;
+  const double t = d->kin_energy_MeV / d->mass_MeV;
+  const double gamma = 1.0 + t;
+  const double gb2 = t * (2.0 + t);
+  b->c.n = d->n;
+  b->c.nx = d->nx;
+  b->c.ny = d->ny;
+  b->c.nz = d->nz;
+  b->c.shape = d->shape;
+  b->c.gamma = gamma;
+  b->c.inv_gamma2 = 1.0 / (gamma * gamma);
+  b->c.C = d->qm_qeeV / gb2;
+  b->c.q_macro = std::copysign(d->charge_C, d->qm_qeeV) / (double)d->n;
+  char* w = b->work;
+  b->geom = (Geom*)(w + L.geom);
+  b->box = (Box*)(w + L.box);
+  b->mom_partial = (double*)(w + L.mom_partial);
+  b->mom_out = (double*)(w + L.mom_out);
+  b->corners = (double2*)(w + L.corners);
+  b->W = w + L.W;
+  b->Gh = w + L.Gh;
+  b->rho = w + L.rho;
+  b->phi = w + L.phi;
+  b->E = w + L.E;
+  int nn[3] = {d->nx, d->ny, d->nz};
+  for (int a = 0; a < 3; ++a) {
+    b->plan.M[a] = 2 * nn[a];
+    b->plan.nrad[a] = factor(2 * nn[a], b->plan.rad[a]);
+    b->plan.tw[a] = (const double2*)(w + L.tw[a]);
+    b->plan.twf[a] = (const float2*)(w + L.twf[a]);
+  }
+  hipStream_t s = S(stream);
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    e = launch_twiddles((double2*)b->plan.tw[a], (float2*)b->plan.twf[a], b->plan.M[a], s);
+  if (e == hipSuccess) e = launch_box_reset(b->box, s);
+  if (e == hipSuccess) e = launch_clear_status(b->geom, s);
+  if (e != hipSuccess) {
+    delete b;
+    return fail_hip(e, "beam set-up");
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_beam_destroy(pic_beam b) {
+  delete b;
+  return PIC_OK;
+}
+
+pic_status pic_init_beam(pic_beam b, const double sigma[36], uint64_t seed, double halo_frac,
+                         void* stream) {
+  if (!b || !sigma) return fail(PIC_EINVAL, "NULL argument");
+  if (!(halo_frac >= 0.0 && halo_frac <= 1.0)) return fail(PIC_EINVAL, "halo_frac must be in [0, 1]");
+  Chol L;
+  if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
+  int64_t n_halo = (int64_t)std::floor(halo_frac * (double)b->d.n + 0.5);
+  hipStream_t s = S(stream);
+  HIP_OK(launch_init_philox(b->X, b->d.n, n_halo, seed, L, s), "init_beam");
+  HIP_OK(launch_clear_status(b->geom, s), "init_beam");
+  return PIC_OK;
+}
+
+pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const double* d_xi,
+                                      void* stream) {
+  if (!b || !sigma || !d_xi) return fail(PIC_EINVAL, "NULL argument");
+  Chol L;
+  if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
+  hipStream_t s = S(stream);
+  HIP_OK(launch_init_normals(b->X, d_xi, b->d.n, L, s), "init_beam_from_normals");
+  HIP_OK(launch_clear_status(b->geom, s), "init_beam_from_normals");
+  return PIC_OK;
+}
+
+pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
+  if (!b || !d_rho) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
+  HIP_OK(launch_box_reset(b->box, s), "deposit");
+  HIP_OK(launch_box(b->X, b->d.n, b->box, s), "deposit");
+  HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "deposit");
+  if (b->d.grid_fp32) {
+    HIP_OK(launch_zero<float>((float*)d_rho, ng, s), "deposit");
+    HIP_OK(launch_deposit<float>(b->X, b->geom, (float*)d_rho, b->c, s), "deposit");
+  } else {
+    HIP_OK(launch_zero<double>((double*)d_rho, ng, s), "deposit");
+    HIP_OK(launch_deposit<double>(b->X, b->geom, (double*)d_rho, b->c, s), "deposit");
+  }
+  return PIC_OK;
+}
+
+pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d_E, void* stream) {
+  if (!b || !d_rho || !d_E) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  void* phi = d_phi ? d_phi : b->phi;
+  if (b->d.grid_fp32)
+    return green_and_solve<float>(b, (const float*)d_rho, (float*)phi, (float*)d_E, s);
+  return green_and_solve<double>(b, (const double*)d_rho, (double*)phi, (double*)d_E, s);
+}
+
+pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream) {
+  if (!b || !d_E || !d_Ep) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  if (b->d.grid_fp32)
+    HIP_OK(launch_gather<float>(b->X, b->geom, (const float*)d_E, (float*)d_Ep, b->c, s), "gather");
+  else
+    HIP_OK(launch_gather<double>(b->X, b->geom, (const double*)d_E, (double*)d_Ep, b->c, s),
+           "gather");
+  return PIC_OK;
+}
+
+pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* stream) {
+  if (!b) return fail(PIC_EINVAL, "NULL handle");
+  if (kind != PIC_PUSH_DRIFT && kind != PIC_PUSH_THINQUAD && kind != PIC_PUSH_KICK)
+    return fail(PIC_EINVAL, "unknown push kind");
+  if (kind == PIC_PUSH_KICK && !d_Ep) return fail(PIC_EINVAL, "kick needs the particle field");
+  if (!std::isfinite(value)) return fail(PIC_EINVAL, "non-finite push parameter");
+  hipStream_t s = S(stream);
+  if (b->d.grid_fp32)
+    HIP_OK(launch_push<float>(b->X, kind, value, (const float*)d_Ep, b->c, s), "push");
+  else
+    HIP_OK(launch_push<double>(b->X, kind, value, (const double*)d_Ep, b->c, s), "push");
+  return PIC_OK;
+}
+
+pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                             void* stream) {
+  if (!b || !lattice) return fail(PIC_EINVAL, "NULL argument");
+  if (n_el < 1 || n_steps < 0) return fail(PIC_EINVAL, "n_el must be >= 1 and n_steps >= 0");
+  for (int q = 0; q < n_el; ++q)
+    if (!std::isfinite(lattice[q].k) || !std::isfinite(lattice[q].ds))
+      return fail(PIC_EINVAL, "non-finite lattice element");
+  if (n_steps == 0) return PIC_OK;
+  hipStream_t s = S(stream);
+  if (!b->d.space_charge) {
+    for (int j = 0; j < n_steps; ++j) {
+      const pic_element& e = lattice[j % n_el];
+      HIP_OK(launch_quad_drift(b->X, e.k, 0.5 * e.ds, b->c, nullptr, s), "track");
+      HIP_OK(launch_push<double>(b->X, PIC_PUSH_DRIFT, 0.5 * e.ds, nullptr, b->c, s), "track");
+    }
+    return PIC_OK;
+  }
+  if (b->d.grid_fp32) return track_sc<float>(b, lattice, n_el, n_steps, s);
+  return track_sc<double>(b, lattice, n_el, n_steps, s);
+}
+
+pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream) {
+  if (!b || !mean || !cov) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "moments");
+  double host[kMomentSlots];
+  Geom g;
+  HIP_OK(hipMemcpyAsync(host, b->mom_out, sizeof(host), hipMemcpyDeviceToHost, s), "moments");
+  HIP_OK(hipMemcpyAsync(&g, b->geom, sizeof(Geom), hipMemcpyDeviceToHost, s), "moments");
+  HIP_OK(hipStreamSynchronize(s), "moments");
+  for (int r = 0; r < 6; ++r) mean[r] = host[r];
+  int q = 6;
+  for (int a = 0; a < 6; ++a)
+    for (int c = a; c < 6; ++c) {
+      cov[a * 6 + c] = cov[c * 6 + a] = host[q++];
+    }
+  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
+  return PIC_OK;
+}
+
+pic_status pic_get_geometry(pic_beam b, double out[9], void* stream) {
+  if (!b || !out) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  Geom g;
+  HIP_OK(hipMemcpyAsync(&g, b->geom, sizeof(Geom), hipMemcpyDeviceToHost, s), "geometry");
+  HIP_OK(hipStreamSynchronize(s), "geometry");
+  for (int a = 0; a < 3; ++a) {
+    out[a] = g.origin[a];
+    out[3 + a] = g.h[a];
+    out[6 + a] = g.h_rest[a];
+  }
+  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
+  return PIC_OK;
+}
+
+pic_status pic_check(pic_beam b, void* stream) {
+  if (!b) return fail(PIC_EINVAL, "NULL handle");
+  hipStream_t s = S(stream);
+  Geom g;
+  HIP_OK(hipMemcpyAsync(&g, b->geom, sizeof(Geom), hipMemcpyDeviceToHost, s), "check");
+  HIP_OK(hipStreamSynchronize(s), "check");
+  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
+  return PIC_OK;
+}
+
+}  // extern "C"

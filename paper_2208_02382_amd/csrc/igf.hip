@@ -1,0 +1,108 @@
+// Integrated Green's function (Qiang et al., Phys. Rev. ST Accel. Beams 9, 044204, 2006):
+// Gbar(i, j, k) = (1 / (hx hy hz)) * integral of dV/|r| over the rest-frame cell centred at
+// (i hx, j hy, k hz), evaluated as the alternating 8-corner sum of the antiderivative
+//   F(x,y,z) = xy ln(z+r) + yz ln(x+r) + zx ln(y+r)
+//              - x^2/2 atan(yz/(xr)) - y^2/2 atan(zx/(yr)) - z^2/2 atan(xy/(zr)),
+// terms with a zero prefactor being zero.  Cells on a coordinate plane (index 0) are folded onto
+// [0, h/2] with weight 2 by the evenness of 1/r.
+//
+// The corner sum cancels by up to ~1e8 for far cells of elongated rest-frame cells (hz/hx of
+// 80..8000 here), so F and the sum are carried in double-double arithmetic (ddmath.hpp) and
+// the cell average is rounded to double once.
+#include "igf_antideriv.hpp"
+#include "internal.hpp"
+
+namespace pic {
+
+namespace {
+
+// F at every corner (m_x, m_y, m_z), m_a = 0..n_a+1; corners[(mz (ny+2) + my)(nx+2) + mx]
+__global__ __launch_bounds__(256) void k_igf_corners(const Geom* __restrict__ g, int nx, int ny,
+                                                     int nz, double2* __restrict__ corners) {
+  if (g->status) return;
+  const int cx = nx + 2, cy = ny + 2, cz = nz + 2;
+  const int64_t total = (int64_t)cx * cy * cz;
+  const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    int mx = (int)(t % cx);
+    int my = (int)((t / cx) % cy);
+    int mz = (int)(t / ((int64_t)cx * cy));
+    ddv f = antiderivative(corner_coord(mx, hx), corner_coord(my, hy), corner_coord(mz, hz));
+    corners[t] = make_double2(f.hi, f.lo);
+  }
+}
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+__device__ __forceinline__ int fold(int t, int n, int M) { return t <= n ? t : M - t; }
+
+// Hockney placement fused with the 8-corner difference: every position t of the cyclic
+// (2nz, 2ny, 2nx) array receives Gbar(fold(t)), fold(t) = t for t <= n, M - t otherwise,
+// as a complex value with zero imaginary part.
+template <typename T>
+__global__ __launch_bounds__(256) void k_igf_place(const Geom* __restrict__ g, int nx, int ny,
+                                                   int nz, const double2* __restrict__ corners,
+                                                   Cx<T>* __restrict__ W) {
+  if (g->status) return;
+  const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
+  const int cx = nx + 2, cy = ny + 2;
+  const int64_t total = (int64_t)Mx * My * Mz;
+  const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
+  ddv vol = dd_mul_d(two_prod(hx, hy), hz);
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    int tx = (int)(t % Mx);
+    int ty = (int)((t / Mx) % My);
+    int tz = (int)(t / ((int64_t)Mx * My));
+    int i = fold(tx, nx, Mx), j = fold(ty, ny, My), k = fold(tz, nz, Mz);
+    // successive differences along x, then y, then z (corners i, i+1 etc.)
+    ddv dxy[2][2];
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b) {
+        int64_t base = ((int64_t)(k + c) * cy + (j + b)) * cx + i;
+        double2 f0 = corners[base], f1 = corners[base + 1];
+        dxy[c][b] = dd_sub(ddv{f1.x, f1.y}, ddv{f0.x, f0.y});
+      }
+    ddv dz0 = dd_sub(dxy[0][1], dxy[0][0]);
+    ddv dz1 = dd_sub(dxy[1][1], dxy[1][0]);
+    ddv d = dd_sub(dz1, dz0);
+    double w = (i == 0 ? 2.0 : 1.0) * (j == 0 ? 2.0 : 1.0) * (k == 0 ? 2.0 : 1.0);
+    d = {d.hi * w, d.lo * w};
+    ddv gbar = dd_div(d, vol);
+    W[t] = Cx<T>{(T)(gbar.hi + gbar.lo), (T)0};
+  }
+}
+
+int grid_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 16384) b = 16384;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_igf_corners(const Geom* g, int nx, int ny, int nz, double2* corners,
+                              hipStream_t s) {
+  int64_t total = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+  hipLaunchKernelGGL(k_igf_corners, dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz,
+                     corners);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_igf_place(const Geom* g, int nx, int ny, int nz, const double2* corners,
+                            void* W, hipStream_t s) {
+  int64_t total = 8ll * nx * ny * nz;
+  hipLaunchKernelGGL((k_igf_place<T>), dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz,
+                     corners, (Cx<T>*)W);
+  return hipGetLastError();
+}
+
+template hipError_t launch_igf_place<double>(const Geom*, int, int, int, const double2*, void*,
+                                             hipStream_t);
+template hipError_t launch_igf_place<float>(const Geom*, int, int, int, const double2*, void*,
+                                            hipStream_t);
+
+}  // namespace pic

@@ -1,0 +1,579 @@
+// Particle kernels: beam initialisation, box reduction and geometry, charge deposition,
+// field gather, linear maps (drift, thin quadrupole, space-charge kick) and beam moments.
+//
+// Phase space is structure-of-arrays float64 X[6][n] = (x, px, y, py, z, delta); every kernel
+// walks particles with a grid-stride loop so consecutive lanes touch consecutive doubles of
+// each row (coalesced 64-lane reads of 512 B per row).
+#include "internal.hpp"
+
+namespace pic {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ unsigned long long ord_enc(double v) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double ord_dec(unsigned long long u) {
+  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// B-spline stencil along one axis: base node and S+1 weights.  CIC (S = 1): i = floor(u),
+// f = u - i, weights (1 - f, f) on (i, i+1).  TSC (S = 2): i = floor(u + 1/2), d = u - i,
+// weights (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2) on (i-1, i, i+1).  The base is
+// clamped into the grid so that no input can address memory outside it (a valid geometry
+// never needs the clamp).
+template <int S>
+__device__ __forceinline__ int stencil(double u, int n, double* w) {
+  if constexpr (S == 1) {
+    double i = floor(u);
+    double f = u - i;
+    w[0] = 1.0 - f;
+    w[1] = f;
+    int b = (int)i;
+    b = b < 0 ? 0 : (b > n - 2 ? n - 2 : b);
+    return b;
+  } else {
+    double i = floor(u + 0.5);
+    double d = u - i;
+    double a = 0.5 - d, c = 0.5 + d;
+    w[0] = 0.5 * (a * a);
+    w[1] = 0.75 - d * d;
+    w[2] = 0.5 * (c * c);
+    int b = (int)i - 1;
+    b = b < 0 ? 0 : (b > n - 3 ? n - 3 : b);
+    return b;
+  }
+}
+
+// ---------------------------------------------------------------------------- box and geometry
+
+__global__ void k_box_reset(Box* box) {
+  int t = threadIdx.x;
+  if (t < 3) {
+    box->mn[t] = ~0ull;
+    box->mx[t] = 0ull;
+  }
+  if (t == 0) box->nonfinite = 0u;
+}
+
+// Block-wide min/max of x, y, z, then one atomic per block and axis.
+__device__ __forceinline__ void box_accumulate(double lo[3], double hi[3], bool bad, Box* box) {
+  __shared__ double slo[3][kBlock / 64], shi[3][kBlock / 64];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
+    }
+  }
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) {
+      slo[a][wv] = lo[a];
+      shi[a][wv] = hi[a];
+    }
+  if (bad) sbad = 1;
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int a = threadIdx.x;
+    double l = slo[a][0], h = shi[a][0];
+    for (int q = 1; q < kBlock / 64; ++q) {
+      l = fmin(l, slo[a][q]);
+      h = fmax(h, shi[a][q]);
+    }
+    if (l <= h) {
+      atomicMin(&box->mn[a], ord_enc(l));
+      atomicMax(&box->mx[a], ord_enc(h));
+    }
+  }
+  if (threadIdx.x == 0 && sbad) atomicOr(&box->nonfinite, 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_box(const double* __restrict__ X, int64_t n, Box* box) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double p[3] = {X[i], X[2 * n + i], X[4 * n + i]};
+    for (int a = 0; a < 3; ++a) {
+      bad |= !isfinite(p[a]);
+      lo[a] = fmin(lo[a], p[a]);
+      hi[a] = fmax(hi[a], p[a]);
+    }
+  }
+  box_accumulate(lo, hi, bad, box);
+}
+
+// Geometry from the box: h = (max - min)/(n - 3), node 0 at min - h; the rest-frame cell is
+// (hx, hy, gamma hz).  A non-finite coordinate or a zero extent sets status = -4 (PIC_EDOMAIN),
+// which is sticky until the beam is initialised again.
+__global__ void k_geometry(const Box* box, Geom* g, Consts c) {
+  if (threadIdx.x != 0) return;
+  int nn[3] = {c.nx, c.ny, c.nz};
+  bool bad = box->nonfinite != 0u;
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord_dec(box->mn[a]);
+    hi[a] = ord_dec(box->mx[a]);
+    if (!(hi[a] > lo[a])) bad = true;
+  }
+  if (bad) {
+    g->status = -4;
+    return;
+  }
+  for (int a = 0; a < 3; ++a) {
+    double h = (hi[a] - lo[a]) / (double)(nn[a] - 3);
+    g->h[a] = h;
+    g->inv_h[a] = 1.0 / h;
+    g->origin[a] = lo[a] - h;
+  }
+  g->h_rest[0] = g->h[0];
+  g->h_rest[1] = g->h[1];
+  g->h_rest[2] = c.gamma * g->h[2];
+}
+
+// ---------------------------------------------------------------------------- initialisation
+
+__global__ void k_clear_status(Geom* g) {
+  if (threadIdx.x == 0) g->status = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_normals(double* __restrict__ X,
+                                                         const double* __restrict__ xi, int64_t n,
+                                                         Chol L) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = xi[r * n + i];
+    for (int r = 0; r < 6; ++r) {
+      double s = 0.0;
+      for (int q = 0; q <= r; ++q) s += L.L[r * 6 + q] * v[q];
+      X[r * n + i] = s;
+    }
+  }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the 4x32 S-box with
+// multipliers 0xD2511F53, 0xCD9E8D57 and key increments 0x9E3779B9, 0xBB67AE85.
+__device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    unsigned lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    unsigned lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// 53-bit uniform in (0, 1] from two words: ((a >> 5) 2^26 + (b >> 6) + 1) 2^-53.
+__device__ __forceinline__ double u53(unsigned a, unsigned b) {
+  unsigned long long k = ((unsigned long long)(a >> 5) << 26) + (unsigned long long)(b >> 6) + 1ull;
+  return (double)k * 0x1.0p-53;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_philox(double* __restrict__ X, int64_t n,
+                                                        int64_t n_core, unsigned k0, unsigned k1,
+                                                        Chol L) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    bool core = i < n_core;
+    for (unsigned blk = 0; blk < 3; ++blk) {
+      unsigned c[4] = {(unsigned)((unsigned long long)i & 0xffffffffull),
+                       (unsigned)((unsigned long long)i >> 32), blk, 0u};
+      philox4x32_10(c, k0, k1);
+      double ua = u53(c[0], c[1]);
+      double ub = u53(c[2], c[3]);
+      if (core) {
+        double rad = sqrt(-2.0 * log(ua));
+        double s, co;
+        sincospi(2.0 * ub, &s, &co);
+        v[2 * blk] = rad * co;
+        v[2 * blk + 1] = rad * s;
+      } else {
+        v[2 * blk] = -4.0 + 8.0 * ua;
+        v[2 * blk + 1] = -4.0 + 8.0 * ub;
+      }
+    }
+    for (int r = 0; r < 6; ++r) {
+      double s = 0.0;
+      for (int q = 0; q <= r; ++q) s += L.L[r * 6 + q] * v[q];
+      X[r * n + i] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- deposit, gather
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_grid(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Charge deposition with device-scope float atomics into the node array
+// rho[(k ny + j) nx + i]: Q_n += q_macro wz wy wx for the (S+1)^3 stencil nodes.
+template <int S, typename T>
+__global__ __launch_bounds__(kBlock) void k_deposit(const double* __restrict__ X,
+                                                    const Geom* __restrict__ g, T* rho,
+                                                    Consts c) {
+  if (g->status) return;
+  const double ox = g->origin[0], oy = g->origin[1], oz = g->origin[2];
+  const double ix = g->inv_h[0], iy = g->inv_h[1], iz = g->inv_h[2];
+  const int64_t n = c.n;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double wx[S + 1], wy[S + 1], wz[S + 1];
+    int bx = stencil<S>((X[i] - ox) * ix, c.nx, wx);
+    int by = stencil<S>((X[2 * n + i] - oy) * iy, c.ny, wy);
+    int bz = stencil<S>((X[4 * n + i] - oz) * iz, c.nz, wz);
+    for (int a = 0; a <= S; ++a)
+      for (int b = 0; b <= S; ++b) {
+        double wzy = wz[a] * wy[b];
+        T* row = rho + ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + bx;
+        for (int q = 0; q <= S; ++q) atomic_add_grid(row + q, (T)(c.q_macro * (wzy * wx[q])));
+      }
+  }
+}
+
+// Field at the particles from E'[3][nz][ny][nx] with the deposit's weights.
+template <int S, typename T>
+__device__ __forceinline__ void gather_one(double x, double y, double z, const double* o,
+                                           const double* ih, const T* __restrict__ E, Consts c,
+                                           T out[3]) {
+  double wx[S + 1], wy[S + 1], wz[S + 1];
+  int bx = stencil<S>((x - o[0]) * ih[0], c.nx, wx);
+  int by = stencil<S>((y - o[1]) * ih[1], c.ny, wy);
+  int bz = stencil<S>((z - o[2]) * ih[2], c.nz, wz);
+  const int64_t plane = (int64_t)c.nx * c.ny * c.nz;
+  T ex = 0, ey = 0, ez = 0;
+  for (int a = 0; a <= S; ++a)
+    for (int b = 0; b <= S; ++b) {
+      double wzy = wz[a] * wy[b];
+      int64_t row = ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + bx;
+      for (int q = 0; q <= S; ++q) {
+        T w = (T)(wzy * wx[q]);
+        ex += w * E[row + q];
+        ey += w * E[plane + row + q];
+        ez += w * E[2 * plane + row + q];
+      }
+    }
+  out[0] = ex;
+  out[1] = ey;
+  out[2] = ez;
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(const double* __restrict__ X,
+                                                   const Geom* __restrict__ g,
+                                                   const T* __restrict__ E, T* __restrict__ Ep,
+                                                   Consts c) {
+  if (g->status) return;
+  double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int64_t n = c.n;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    T e[3];
+    gather_one<S, T>(X[i], X[2 * n + i], X[4 * n + i], o, ih, E, c, e);
+    Ep[i] = e[0];
+    Ep[n + i] = e[1];
+    Ep[2 * n + i] = e[2];
+  }
+}
+
+// ---------------------------------------------------------------------------- linear maps
+
+// drift: x += l px, y += l py, z += l delta / gamma^2
+__device__ __forceinline__ void drift(double v[6], double ell, double inv_g2) {
+  v[0] = v[0] + ell * v[1];
+  v[2] = v[2] + ell * v[3];
+  v[4] = v[4] + ell * v[5] * inv_g2;
+}
+
+// thin quadrupole of integrated strength k: px -= k x, py += k y
+__device__ __forceinline__ void thin_quad(double v[6], double k) {
+  v[1] = v[1] - k * v[0];
+  v[3] = v[3] + k * v[2];
+}
+
+// space-charge kick over L: px += C E'x L, py += C E'y L, delta += gamma C E'z L
+__device__ __forceinline__ void sc_kick(double v[6], double ex, double ey, double ez, double L,
+                                        Consts c) {
+  v[1] = v[1] + c.C * ex * L;
+  v[3] = v[3] + c.C * ey * L;
+  v[5] = v[5] + c.gamma * c.C * ez * L;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push(double* __restrict__ X, int kind, double value,
+                                                 const T* __restrict__ Ep, Consts c) {
+  const int64_t n = c.n;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    if (kind == 0) drift(v, value, c.inv_gamma2);
+    else if (kind == 1) thin_quad(v, value);
+    else sc_kick(v, (double)Ep[i], (double)Ep[n + i], (double)Ep[2 * n + i], value, c);
+    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
+  }
+}
+
+// First half of a step: thin quad k then drift l; accumulates the box of the new positions.
+__global__ __launch_bounds__(kBlock) void k_quad_drift(double* __restrict__ X, double k, double ell,
+                                                       Consts c, Box* box) {
+  const int64_t n = c.n;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    thin_quad(v, k);
+    drift(v, ell, c.inv_gamma2);
+    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
+    double p[3] = {v[0], v[2], v[4]};
+    for (int a = 0; a < 3; ++a) {
+      bad |= !isfinite(p[a]);
+      lo[a] = fmin(lo[a], p[a]);
+      hi[a] = fmax(hi[a], p[a]);
+    }
+  }
+  if (box) box_accumulate(lo, hi, bad, box);
+}
+
+// Fused second half of step j and first half of step j+1: gather E' at the current positions,
+// kick over L, drift L/2; if has_next, thin quad k_next and drift half_next, and accumulate
+// the box of the new positions (the next step's grid).
+template <int S, typename T>
+__global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Geom* __restrict__ g,
+                                                const T* __restrict__ E, double L, int has_next,
+                                                double k_next, double half_next, Consts c,
+                                                Box* box) {
+  if (g->status) return;
+  double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int64_t n = c.n;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    T e[3];
+    gather_one<S, T>(v[0], v[2], v[4], o, ih, E, c, e);
+    sc_kick(v, (double)e[0], (double)e[1], (double)e[2], L, c);
+    drift(v, 0.5 * L, c.inv_gamma2);
+    if (has_next) {
+      thin_quad(v, k_next);
+      drift(v, half_next, c.inv_gamma2);
+      double p[3] = {v[0], v[2], v[4]};
+      for (int a = 0; a < 3; ++a) {
+        bad |= !isfinite(p[a]);
+        lo[a] = fmin(lo[a], p[a]);
+        hi[a] = fmax(hi[a], p[a]);
+      }
+    }
+    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
+  }
+  if (has_next) box_accumulate(lo, hi, bad, box);
+}
+
+// ---------------------------------------------------------------------------- moments
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < kBlock / 64; ++q) s += sh[q];
+  return s;
+}
+
+// pass 1: per-block sums of the six coordinates
+__global__ __launch_bounds__(kBlock) void k_mom_sum(const double* __restrict__ X, int64_t n,
+                                                    double* partial) {
+  __shared__ double sh[kBlock / 64];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    for (int r = 0; r < 6; ++r) s[r] += X[r * n + i];
+  for (int r = 0; r < 6; ++r) {
+    double t = block_sum(s[r], sh);
+    if (threadIdx.x == 0) partial[blockIdx.x * kMomentSlots + r] = t;
+  }
+}
+
+// combine the per-block partials of slots [s0, s1) in block order; slots 0..5 become means
+__global__ void k_mom_combine(const double* partial, int nblocks, int s0, int s1, int64_t n,
+                              double* out) {
+  int s = s0 + threadIdx.x;
+  if (s >= s1) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblocks; ++b) acc += partial[b * kMomentSlots + s];
+  out[s] = acc / (double)n;
+}
+
+// pass 2: per-block sums of the 21 centred products (upper triangle, row-major)
+__global__ __launch_bounds__(kBlock) void k_mom_cov(const double* __restrict__ X, int64_t n,
+                                                    const double* __restrict__ mean,
+                                                    double* partial) {
+  __shared__ double sh[kBlock / 64];
+  double m[6];
+  for (int r = 0; r < 6; ++r) m[r] = mean[r];
+  double s[21];
+  for (int q = 0; q < 21; ++q) s[q] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double d[6];
+    for (int r = 0; r < 6; ++r) d[r] = X[r * n + i] - m[r];
+    int q = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b) s[q++] += d[a] * d[b];
+  }
+  for (int q = 0; q < 21; ++q) {
+    double t = block_sum(s[q], sh);
+    if (threadIdx.x == 0) partial[blockIdx.x * kMomentSlots + 6 + q] = t;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero(T* p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = T(0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- launch wrappers
+
+hipError_t launch_box_reset(Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_box_reset, dim3(1), dim3(64), 0, s, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_box(const double* X, int64_t n, Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_box, dim3(grid_for(n)), dim3(kBlock), 0, s, X, n, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry(const Box* box, Geom* g, Consts c, hipStream_t s) {
+  hipLaunchKernelGGL(k_geometry, dim3(1), dim3(64), 0, s, box, g, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_normals(double* X, const double* xi, int64_t n, Chol L, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_normals, dim3(grid_for(n)), dim3(kBlock), 0, s, X, xi, n, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_philox(double* X, int64_t n, int64_t n_halo, uint64_t seed, Chol L,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_init_philox, dim3(grid_for(n)), dim3(kBlock), 0, s, X, n, n - n_halo,
+                     (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32), L);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_status(Geom* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit(const double* X, const Geom* g, T* rho, Consts c, hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_deposit<1, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, rho, c);
+  else
+    hipLaunchKernelGGL((k_deposit<2, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, rho, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(const double* X, const Geom* g, const T* E, T* Ep, Consts c,
+                         hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_gather<1, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, Ep, c);
+  else
+    hipLaunchKernelGGL((k_gather<2, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, Ep, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_push(double* X, int kind, double value, const T* Ep, Consts c, hipStream_t s) {
+  hipLaunchKernelGGL((k_push<T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, kind, value, Ep, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_drift(double* X, double k, double ell, Consts c, Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_quad_drift, dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, k, ell, c, box);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, int has_next, double k_next,
+                      double half_next, Consts c, Box* box, hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_gkd<1, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, L,
+                       has_next, k_next, half_next, c, box);
+  else
+    hipLaunchKernelGGL((k_gkd<2, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, L,
+                       has_next, k_next, half_next, c, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const double* X, int64_t n, double* partial, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_mom_sum, dim3(kReduceBlocks), dim3(kBlock), 0, s, X, n, partial);
+  hipLaunchKernelGGL(k_mom_combine, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 0, 6, n, out);
+  hipLaunchKernelGGL(k_mom_cov, dim3(kReduceBlocks), dim3(kBlock), 0, s, X, n, out, partial);
+  hipLaunchKernelGGL(k_mom_combine, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 6, 27, n,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero(T* p, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<T>), dim3(grid_for(count)), dim3(kBlock), 0, s, p, count);
+  return hipGetLastError();
+}
+
+template hipError_t launch_deposit<double>(const double*, const Geom*, double*, Consts, hipStream_t);
+template hipError_t launch_deposit<float>(const double*, const Geom*, float*, Consts, hipStream_t);
+template hipError_t launch_gather<double>(const double*, const Geom*, const double*, double*,
+                                          Consts, hipStream_t);
+template hipError_t launch_gather<float>(const double*, const Geom*, const float*, float*, Consts,
+                                         hipStream_t);
+template hipError_t launch_push<double>(double*, int, double, const double*, Consts, hipStream_t);
+template hipError_t launch_push<float>(double*, int, double, const float*, Consts, hipStream_t);
+template hipError_t launch_gkd<double>(double*, const Geom*, const double*, double, int, double,
+                                       double, Consts, Box*, hipStream_t);
+template hipError_t launch_gkd<float>(double*, const Geom*, const float*, double, int, double,
+                                      double, Consts, Box*, hipStream_t);
+template hipError_t launch_zero<double>(double*, int64_t, hipStream_t);
+template hipError_t launch_zero<float>(float*, int64_t, hipStream_t);
+
+}  // namespace pic

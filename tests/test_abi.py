@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every function include/pic.h declares, and rejects bad
+arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2208_02382_amd as pic
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"^(?:pic_status|size_t|const char\*)\s+(pic_\w+)\(", text,
+                                 re.M)))
+
+
+def test_header_symbols_are_exported():
+    names = _declared()
+    assert len(names) == 14
+    lib = ctypes.CDLL(pic.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _desc(**kw):
+    c = workloads.SMALL
+    d = dict(n=c.n, qm_qeeV=c.qm_qeeV, charge_C=c.charge_C, kin_energy_MeV=c.kin_energy_MeV,
+             mass_MeV=c.mass_MeV, shape=c.shape, nodes=c.nodes)
+    d.update(kw)
+    return pic.make_desc(**d)
+
+
+def test_workspace_bytes_validates_the_description():
+    assert pic.workspace_bytes(_desc()) > 0
+    assert pic.workspace_bytes(_desc(nodes=(48, 32, 96))) > 0      # 96 and 192 = 2^a 3^b
+    assert pic.workspace_bytes(_desc(shape=3)) == 0
+    assert pic.workspace_bytes(_desc(nodes=(3, 32, 32))) == 0
+    assert pic.workspace_bytes(_desc(nodes=(7, 32, 32))) == 0       # 14 = 2 * 7
+    assert "2^a 3^b" in pic.last_error()
+    assert pic.workspace_bytes(_desc(nodes=(320, 32, 32))) == 0     # 640 > 512
+    assert pic.workspace_bytes(_desc(n=0)) == 0
+    assert pic.workspace_bytes(_desc(kin_energy_MeV=-1.0)) == 0
+
+
+def test_create_rejects_bad_arguments_without_touching_a_device():
+    lib = pic._lib
+    d = _desc()
+    nbytes = pic.workspace_bytes(d)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.pic_beam_create(ctypes.byref(d), None, fake, nbytes, None, ctypes.byref(h)) == pic.PIC_EINVAL
+    assert lib.pic_beam_create(ctypes.byref(d), fake, ctypes.c_void_p(0x10008), nbytes, None,
+                               ctypes.byref(h)) == pic.PIC_EINVAL   # misaligned workspace
+    assert lib.pic_beam_create(ctypes.byref(d), fake, fake, nbytes - 1, None,
+                               ctypes.byref(h)) == pic.PIC_ENOMEM
+    bad = _desc(nodes=(10, 32, 32))   # 20 = 2^2 * 5
+    assert lib.pic_beam_create(ctypes.byref(bad), fake, fake, nbytes, None,
+                               ctypes.byref(h)) == pic.PIC_EUNSUPPORTED
+    assert lib.pic_beam_create(None, fake, fake, nbytes, None, ctypes.byref(h)) == pic.PIC_EINVAL
+    assert lib.pic_track_n_steps(None, None, 0, 0, None) == pic.PIC_EINVAL
+    assert lib.pic_deposit(None, None, None) == pic.PIC_EINVAL
+    assert lib.pic_moments(None, None, None, None) == pic.PIC_EINVAL
+    assert lib.pic_beam_destroy(None) == pic.PIC_OK
+
+
+@pytest.mark.skipif(torch.cuda.device_count() > 0, reason="a device is present")
+def test_create_reports_no_device():
+    d = _desc()
+    nbytes = pic.workspace_bytes(d)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x10000)
+    st = pic._lib.pic_beam_create(ctypes.byref(d), fake, fake, nbytes, None, ctypes.byref(h))
+    assert st == pic.PIC_ENODEV
+    assert h.value is None

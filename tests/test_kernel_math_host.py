@@ -1,0 +1,50 @@
+"""CPU unit tests of the kernels' double-double and integrated-Green's-function arithmetic
+(ddmath.hpp, igf_antideriv.hpp built for the host as libpic_hostcheck.so), against 50-digit
+mpmath and against the oracle."""
+import ctypes
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import igf
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_2208_02382_amd", "libpic_hostcheck.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="host check library not built")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ctypes.CDLL(LIB)
+
+
+@pytest.mark.parametrize("fn,name", [(0, "log"), (1, "atan"), (2, "sqrt")])
+def test_dd_functions(lib, fn, name):
+    mp.mp.dps = 50
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 1, 200) * 10.0 ** rng.integers(-8, 8, 200)
+    lo = x * rng.uniform(-1e-17, 1e-17, 200)
+    inp = np.ascontiguousarray(np.stack([x, lo], 1).ravel())
+    out = np.zeros_like(inp)
+    lib.pic_hostcheck_dd(fn, 200, inp.ctypes.data_as(ctypes.c_void_p),
+                         out.ctypes.data_as(ctypes.c_void_p))
+    f = getattr(mp, name)
+    worst = max(abs((mp.mpf(out[2 * i]) + mp.mpf(out[2 * i + 1])
+                     - f(mp.mpf(x[i]) + mp.mpf(lo[i]))) / f(mp.mpf(x[i]) + mp.mpf(lo[i])))
+                for i in range(200))
+    assert worst < 1e-30
+
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (1.0, 1.0, 80.0), (3e-4, 3.1e-4, 2.5e-2),
+                               (1e-4, 1e-4, 0.78)])
+def test_kernel_igf_equals_oracle(lib, h):
+    n = 20
+    g = np.zeros((n + 1) ** 3)
+    lib.pic_hostcheck_igf(n, n, n, ctypes.c_double(h[0]), ctypes.c_double(h[1]),
+                          ctypes.c_double(h[2]), g.ctypes.data_as(ctypes.c_void_p))
+    go = igf.cell_average(n, n, n, *h)
+    # both are the cell average rounded once from a double-double value
+    assert np.abs(g.reshape(go.shape) - go).max() <= 2.3e-16 * np.abs(go).max()
+    assert (np.abs(g.reshape(go.shape) - go) / np.abs(go)).max() < 2.3e-16
