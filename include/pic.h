@@ -58,7 +58,7 @@ typedef enum {
 /* Beam description; mirrors add_particles + set_energy_MeV + set_particle_shape +
  * set_space_charge of the paper's Listing 1. */
 typedef struct {
-  int64_t n;               /* number of macroparticles (npart), >= 1 */
+  int64_t n;               /* number of macroparticles (npart), 1 <= n < 2^31 */
   double qm_qeeV;          /* species charge/mass in e/eV (electron: -1e-6/0.510998950) */
   double charge_C;         /* bunch charge magnitude in coulomb; macro charge = sign(qm)*charge_C/n */
   double kin_energy_MeV;   /* reference particle kinetic energy; gamma = 1 + T/m */
@@ -142,8 +142,10 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
 
 /* evolve(): n_steps split-operator steps; step j uses lattice[j mod n_el]: thin quad k, drift
  * ds/2, space-charge kick over ds with the field of the positions at that point (geometry,
- * deposit, IGF, Poisson, field, gather), drift ds/2.  Updates X in place (particle order is
- * preserved).  With desc.space_charge = 0 only the linear maps are applied. */
+ * deposit, IGF, Poisson, field, gather), drift ds/2.  Updates X in place; the particle order
+ * of X is preserved (internally the particles are binned by grid tile every step in two
+ * workspace copies and returned to X in the caller's order at the end of the call).  With
+ * desc.space_charge = 0 only the linear maps are applied. */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 
@@ -155,6 +157,28 @@ pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream)
 /* Geometry of the last deposit: out[0..2] origin (x, y, z) [m], out[3..5] lab spacings,
  * out[6..8] rest-frame spacings (hx, hy, gamma hz).  Synchronises `stream`. */
 pic_status pic_get_geometry(pic_beam b, double out[9], void* stream);
+
+/* Stage timing of pic_track_n_steps (section "ImpactX" lists profiling among the shared PIC
+ * routines).  pic_profile_start resets the counters and makes the following
+ * pic_track_n_steps calls record a HIP event pair around every launch of each stage, on the
+ * caller's stream; pic_profile_read synchronises those events, writes the summed milliseconds
+ * and the number of launches per stage, and stops recording.  Stages:
+ *   PIC_STAGE_PROLOGUE  thin quad + half drift of the first step, with the box reduction
+ *   PIC_STAGE_GEOMETRY  grid geometry from the box, clearing of the charge grid
+ *   PIC_STAGE_GREEN     integrated Green's function and its forward FFT
+ *   PIC_STAGE_DEPOSIT   the charge-deposition kernel alone
+ *   PIC_STAGE_SOLVE     zero padding, forward FFT, spectral product, inverse FFT, gradient
+ *   PIC_STAGE_GKD       the fused gather, kick, drift (and next thin quad, half drift, box)
+ *                       kernel alone
+ *   PIC_STAGE_BIN       tile keys and histogram, scan and work list, counting-sort scatter
+ *   PIC_STAGE_UNPERMUTE return of the particles to the caller's order and array */
+enum {
+  PIC_STAGE_PROLOGUE = 0, PIC_STAGE_GEOMETRY = 1, PIC_STAGE_GREEN = 2, PIC_STAGE_DEPOSIT = 3,
+  PIC_STAGE_SOLVE = 4, PIC_STAGE_GKD = 5, PIC_STAGE_BIN = 6, PIC_STAGE_UNPERMUTE = 7,
+  PIC_NSTAGES = 8
+};
+pic_status pic_profile_start(pic_beam b);
+pic_status pic_profile_read(pic_beam b, double ms[8], int64_t launches[8]);
 
 /* Synchronise `stream` and report the device error flag (PIC_OK or PIC_EDOMAIN). */
 pic_status pic_check(pic_beam b, void* stream);

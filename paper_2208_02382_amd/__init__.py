@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libpic.so is not built; run `python -m paper_2208_02382_amd.build` "
+    raise ImportError("libpic.so is not built; run `python paper_2208_02382_amd/build.py` "
                       "(or __graft_entry__.build())")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -23,6 +23,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_EDOMAIN, PIC_EUNSUPPORTED, PIC_ENO
 STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EHIP",
                 -4: "PIC_EDOMAIN", -5: "PIC_EUNSUPPORTED", -6: "PIC_ENODEV"}
 PUSH_DRIFT, PUSH_THINQUAD, PUSH_KICK = 0, 1, 2
+STAGES = ("prologue", "geometry", "green", "deposit", "solve", "gkd", "bin", "unpermute")
 
 
 class BeamDesc(ctypes.Structure):
@@ -55,6 +56,8 @@ _SIGS = {
     "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "pic_get_geometry": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_check": (_I, [_P, _P]),
+    "pic_profile_start": (_I, [_P]),
+    "pic_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
     "pic_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -212,6 +215,16 @@ class Beam:
         out = (ctypes.c_double * 9)()
         _check(_lib.pic_get_geometry(self._h, out, _stream()), "pic_get_geometry")
         return list(out[0:3]), list(out[3:6]), list(out[6:9])
+
+    def profile_start(self):
+        _check(_lib.pic_profile_start(self._h), "pic_profile_start")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} since profile_start; synchronises."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(_lib.pic_profile_read(self._h, ms, cnt), "pic_profile_read")
+        return {STAGES[q]: (ms[q], cnt[q]) for q in range(8)}
 
     def check(self):
         return _lib.pic_check(self._h, _stream())

@@ -1,6 +1,7 @@
 """Build libpic.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2208_02382_amd.build   (or call build()).
+Usage: python paper_2208_02382_amd/build.py   (or __graft_entry__.build()).  Run it by path:
+importing the package loads the library this script builds.
 """
 import os
 import shutil
@@ -13,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 # host build of the device double-double / IGF arithmetic, for CPU unit tests only
 HOSTCHECK = os.path.join(HERE, "libpic_hostcheck.so")
-SOURCES = ["particles.hip", "igf.hip", "fft.hip", "api.cpp"]
+SOURCES = ["particles.hip", "sort.hip", "igf.hip", "fft.hip", "api.cpp"]
 
 # -Xclang -target-feature -Xclang -packed-fp32-ops: no packed FP32 instructions are emitted.
 # -munsafe-fp-atomics: float atomic adds map to the hardware global_atomic_add_f32/f64.

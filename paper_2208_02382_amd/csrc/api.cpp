@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/pic.h"
 #include "internal.hpp"
@@ -47,12 +48,14 @@ int factor(int M, int rad[12]) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gh, rho, phi, E, total;
+  size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gd, Gh, rho, phi, E;
+  size_t XA, XB, idA, idB, keys, hist, cursor, chunks, nchunks, total;
 };
 
 pic_status check_desc(const pic_beam_desc* d) {
   if (!d) return fail(PIC_EINVAL, "NULL description");
   if (d->n < 1) return fail(PIC_EINVAL, "n must be >= 1");
+  if (d->n > 0x7fffffffLL) return fail(PIC_EUNSUPPORTED, "n must be < 2^31");
   if (d->shape != 1 && d->shape != 2) return fail(PIC_EINVAL, "shape must be 1 (CIC) or 2 (TSC)");
   if (d->nx < 4 || d->ny < 4 || d->nz < 4) return fail(PIC_EINVAL, "grid needs >= 4 nodes per axis");
   if (!(d->mass_MeV > 0) || !(d->kin_energy_MeV > 0) || !std::isfinite(d->kin_energy_MeV))
@@ -81,7 +84,9 @@ Layout layout(const pic_beam_desc* d) {
   };
   const size_t es = d->grid_fp32 ? 4 : 8;
   const size_t nx = d->nx, ny = d->ny, nz = d->nz;
-  const size_t M3 = 8 * nx * ny * nz;
+  // half spectrum of the padded grid: (2 nz)(2 ny)(nx + 1) complex values
+  const size_t Wn = 4 * nz * ny * (nx + 1);
+  const size_t G3 = (nx + 1) * (ny + 1) * (nz + 1);
   L.geom = take(sizeof(Geom));
   L.box = take(sizeof(Box));
   L.mom_partial = take(sizeof(double) * kReduceBlocks * kMomentSlots);
@@ -90,19 +95,63 @@ Layout layout(const pic_beam_desc* d) {
   for (int a = 0; a < 3; ++a) L.tw[a] = take(sizeof(double2) * 2 * nn[a]);
   for (int a = 0; a < 3; ++a) L.twf[a] = take(sizeof(float2) * 2 * nn[a]);
   L.corners = take(sizeof(double2) * (nx + 2) * (ny + 2) * (nz + 2));
-  L.W = take(2 * es * M3);
-  L.Gh = take(es * M3);
+  L.W = take(2 * es * Wn);
+  L.Gd = take(sizeof(double) * G3);
+  L.Gh = take(es * G3);
   L.rho = take(es * nx * ny * nz);
   L.phi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   L.E = take(3 * es * nx * ny * nz);
+  // tracking-loop buffers: two sorted copies of the phase space, particle ids, tile keys,
+  // tile histogram / sort cursors and the deposit work list
+  const size_t n = (size_t)d->n;
+  const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n);
+  L.XA = take(6 * sizeof(double) * n);
+  L.XB = take(6 * sizeof(double) * n);
+  L.idA = take(sizeof(uint32_t) * n);
+  L.idB = take(sizeof(uint32_t) * n);
+  L.keys = take(sizeof(uint32_t) * n);
+  L.hist = take(sizeof(uint32_t) * kMaxTiles);
+  L.cursor = take(sizeof(uint32_t) * kMaxTiles);
+  L.chunks = take(sizeof(int4) * (size_t)sp.max_chunks);
+  L.nchunks = take(sizeof(uint32_t));
   L.total = off;
   return L;
 }
 
 }  // namespace
 
+// HIP event pairs around the stages of pic_track_n_steps (enabled by pic_profile_start)
+struct StageProfiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // created on demand, reused across reads
+  std::vector<int> stage;         // stage of pair k (events 2k, 2k+1)
+  size_t used = 0;                // pairs recorded since the last start
+  hipError_t begin(int st, hipStream_t s) {
+    if (!on) return hipSuccess;
+    while (pool.size() < 2 * (used + 1)) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      pool.push_back(e);
+    }
+    if (stage.size() < used + 1) stage.resize(used + 1);
+    stage[used] = st;
+    return hipEventRecord(pool[2 * used], s);
+  }
+  hipError_t end(hipStream_t s) {
+    if (!on) return hipSuccess;
+    hipError_t r = hipEventRecord(pool[2 * used + 1], s);
+    ++used;
+    return r;
+  }
+  ~StageProfiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct pic_beam_s {
   pic_beam_desc d;
+  StageProfiler prof;
   double* X;
   char* work;
   Layout L;
@@ -114,10 +163,21 @@ struct pic_beam_s {
   double* mom_out;
   double2* corners;
   void* W;
+  double* Gd;
   void* Gh;
   void* rho;
   void* phi;
   void* E;
+  SortPlan sp;
+  double* XA;
+  double* XB;
+  uint32_t* idA;
+  uint32_t* idB;
+  uint32_t* keys;
+  uint32_t* hist;
+  uint32_t* cursor;
+  int4* chunks;
+  uint32_t* nchunks;
 };
 
 namespace {
@@ -146,36 +206,71 @@ bool cholesky6(const double* A, Chol& out) {
   return true;
 }
 
+#define STAGE(b, st, s, call, where)            \
+  do {                                          \
+    HIP_OK((b)->prof.begin((st), (s)), "profile"); \
+    HIP_OK((call), (where));                    \
+    HIP_OK((b)->prof.end(s), "profile");        \
+  } while (0)
+
 template <typename T>
 pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s) {
-  HIP_OK(launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->W,
-                                  (T*)b->Gh, s),
-         "green spectrum");
-  HIP_OK(launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W, (const T*)b->Gh,
-                         phi, E, s),
-         "poisson solve");
+  STAGE(b, PIC_STAGE_GREEN, s,
+        launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd,
+                                 (T*)b->Gh, s),
+        "green spectrum");
+  STAGE(b, PIC_STAGE_SOLVE, s,
+        launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W,
+                        (const T*)b->Gh, phi, E, s),
+        "poisson solve");
   return PIC_OK;
 }
 
 template <typename T>
 pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, hipStream_t s) {
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
+  double* A = b->XA;
+  double* B = b->XB;
+  uint32_t* idA = b->idA;
+  uint32_t* idB = b->idB;
   HIP_OK(launch_box_reset(b->box, s), "box reset");
-  HIP_OK(launch_quad_drift(b->X, lat[0].k, 0.5 * lat[0].ds, b->c, b->box, s), "quad+drift");
+  STAGE(b, PIC_STAGE_PROLOGUE, s,
+        launch_prologue(b->X, A, idA, lat[0].k, 0.5 * lat[0].ds, b->c, b->box, s), "prologue");
   for (int j = 0; j < n_steps; ++j) {
     const pic_element& e = lat[j % n_el];
+    HIP_OK(b->prof.begin(PIC_STAGE_GEOMETRY, s), "profile");
     HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "geometry");
     HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "zero rho");
-    HIP_OK(launch_deposit<T>(b->X, b->geom, (T*)b->rho, b->c, s), "deposit");
+    HIP_OK(b->prof.end(s), "profile");
+    STAGE(b, PIC_STAGE_BIN, s,
+          launch_bin(A, idA, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
+                     b->nchunks, B, idB, s),
+          "binning");
+    STAGE(b, PIC_STAGE_DEPOSIT, s,
+          launch_deposit_tiles<T>(B, b->geom, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
+          "deposit");
     pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s);
     if (st != PIC_OK) return st;
     const int has_next = j + 1 < n_steps;
     const pic_element& nx = lat[(j + 1) % n_el];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
-    HIP_OK(launch_gkd<T>(b->X, b->geom, (const T*)b->E, e.ds, has_next, nx.k, 0.5 * nx.ds, b->c,
-                         b->box, s),
-           "gather-kick-drift");
+    // the E' window of a tile must fit the 64 KB of LDS a workgroup may use
+    const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
+                             (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
+    if (win_bytes <= 65536)
+      STAGE(b, PIC_STAGE_GKD, s,
+            launch_gkd_tiles<T>(B, b->geom, (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks,
+                                e.ds, has_next, nx.k, 0.5 * nx.ds, b->box, s),
+            "gather-kick-drift");
+    else
+      STAGE(b, PIC_STAGE_GKD, s,
+            launch_gkd<T>(B, b->geom, (const T*)b->E, e.ds, has_next, nx.k, 0.5 * nx.ds, b->c,
+                          b->box, s),
+            "gather-kick-drift");
+    double* tX = A; A = B; B = tX;
+    uint32_t* tI = idA; idA = idB; idB = tI;
   }
+  STAGE(b, PIC_STAGE_UNPERMUTE, s, launch_unpermute(A, idA, b->c.n, b->X, s), "unpermute");
   return PIC_OK;
 }
 
@@ -229,22 +324,36 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->mom_out = (double*)(w + L.mom_out);
   b->corners = (double2*)(w + L.corners);
   b->W = w + L.W;
+  b->Gd = (double*)(w + L.Gd);
   b->Gh = w + L.Gh;
   b->rho = w + L.rho;
   b->phi = w + L.phi;
   b->E = w + L.E;
+  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n);
+  b->XA = (double*)(w + L.XA);
+  b->XB = (double*)(w + L.XB);
+  b->idA = (uint32_t*)(w + L.idA);
+  b->idB = (uint32_t*)(w + L.idB);
+  b->keys = (uint32_t*)(w + L.keys);
+  b->hist = (uint32_t*)(w + L.hist);
+  b->cursor = (uint32_t*)(w + L.cursor);
+  b->chunks = (int4*)(w + L.chunks);
+  b->nchunks = (uint32_t*)(w + L.nchunks);
   int nn[3] = {d->nx, d->ny, d->nz};
   for (int a = 0; a < 3; ++a) {
-    b->plan.M[a] = 2 * nn[a];
-    b->plan.nrad[a] = factor(2 * nn[a], b->plan.rad[a]);
+    b->plan.full[a].M = 2 * nn[a];
+    b->plan.full[a].nrad = factor(2 * nn[a], b->plan.full[a].rad);
     b->plan.tw[a] = (const double2*)(w + L.tw[a]);
     b->plan.twf[a] = (const float2*)(w + L.twf[a]);
   }
+  b->plan.half_x.M = nn[0];
+  b->plan.half_x.nrad = factor(nn[0], b->plan.half_x.rad);
   hipStream_t s = S(stream);
   hipError_t e = hipSuccess;
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
-    e = launch_twiddles((double2*)b->plan.tw[a], (float2*)b->plan.twf[a], b->plan.M[a], s);
+    e = launch_twiddles((double2*)b->plan.tw[a], (float2*)b->plan.twf[a], b->plan.full[a].M, s);
   if (e == hipSuccess) e = launch_box_reset(b->box, s);
+  if (e == hipSuccess) e = launch_zero<uint32_t>(b->hist, kMaxTiles, s);
   if (e == hipSuccess) e = launch_clear_status(b->geom, s);
   if (e != hipSuccess) {
     delete b;
@@ -386,6 +495,32 @@ pic_status pic_get_geometry(pic_beam b, double out[9], void* stream) {
     out[6 + a] = g.h_rest[a];
   }
   if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
+  return PIC_OK;
+}
+
+pic_status pic_profile_start(pic_beam b) {
+  if (!b) return fail(PIC_EINVAL, "NULL handle");
+  b->prof.on = true;
+  b->prof.used = 0;
+  return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_beam b, double ms[8], int64_t launches[8]) {
+  if (!b || !ms || !launches) return fail(PIC_EINVAL, "NULL argument");
+  for (int q = 0; q < PIC_NSTAGES; ++q) {
+    ms[q] = 0.0;
+    launches[q] = 0;
+  }
+  StageProfiler& p = b->prof;
+  for (size_t k = 0; k < p.used; ++k) {
+    HIP_OK(hipEventSynchronize(p.pool[2 * k + 1]), "profile read");
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, p.pool[2 * k], p.pool[2 * k + 1]), "profile read");
+    ms[p.stage[k]] += (double)t;
+    launches[p.stage[k]] += 1;
+  }
+  p.on = false;
+  p.used = 0;
   return PIC_OK;
 }
 

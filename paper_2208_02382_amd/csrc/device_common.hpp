@@ -1,0 +1,83 @@
+// Device helpers shared by the particle kernels (particles.hip, sort.hip).
+#pragma once
+#include "internal.hpp"
+
+namespace pic {
+
+constexpr int kBoxBlock = 256;   // block size of every kernel that calls box_accumulate_block
+
+// order-preserving map of doubles to uint64 (so that integer atomic min/max order doubles)
+__device__ __forceinline__ unsigned long long ord_enc(double v) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double ord_dec(unsigned long long u) {
+  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+// B-spline stencil along one axis: base node and S+1 weights.  CIC (S = 1): i = floor(u),
+// f = u - i, weights (1 - f, f) on (i, i+1).  TSC (S = 2): i = floor(u + 1/2), d = u - i,
+// weights (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2) on (i-1, i, i+1).  The base is
+// clamped into the grid so that no input can address memory outside it (a valid geometry
+// never needs the clamp).
+template <int S>
+__device__ __forceinline__ int stencil(double u, int n, double* w) {
+  if constexpr (S == 1) {
+    double i = floor(u);
+    double f = u - i;
+    w[0] = 1.0 - f;
+    w[1] = f;
+    int b = (int)i;
+    b = b < 0 ? 0 : (b > n - 2 ? n - 2 : b);
+    return b;
+  } else {
+    double i = floor(u + 0.5);
+    double d = u - i;
+    double a = 0.5 - d, c = 0.5 + d;
+    w[0] = 0.5 * (a * a);
+    w[1] = 0.75 - d * d;
+    w[2] = 0.5 * (c * c);
+    int b = (int)i - 1;
+    b = b < 0 ? 0 : (b > n - 3 ? n - 3 : b);
+    return b;
+  }
+}
+
+// Block-wide min/max of x, y, z, then one atomic per block and axis.
+__device__ __forceinline__ void box_accumulate_block(double lo[3], double hi[3], bool bad, Box* box) {
+  __shared__ double slo[3][kBoxBlock / 64], shi[3][kBoxBlock / 64];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
+    }
+  }
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) {
+      slo[a][wv] = lo[a];
+      shi[a][wv] = hi[a];
+    }
+  if (bad) sbad = 1;
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int a = threadIdx.x;
+    double l = slo[a][0], h = shi[a][0];
+    for (int q = 1; q < kBoxBlock / 64; ++q) {
+      l = fmin(l, slo[a][q]);
+      h = fmax(h, shi[a][q]);
+    }
+    if (l <= h) {
+      atomicMin(&box->mn[a], ord_enc(l));
+      atomicMax(&box->mx[a], ord_enc(h));
+    }
+  }
+  if (threadIdx.x == 0 && sbad) atomicOr(&box->nonfinite, 1u);
+}
+
+}  // namespace pic

@@ -32,46 +32,35 @@ __global__ __launch_bounds__(256) void k_igf_corners(const Geom* __restrict__ g,
   }
 }
 
-template <typename T>
-struct Cx {
-  T x, y;
-};
-
-__device__ __forceinline__ int fold(int t, int n, int M) { return t <= n ? t : M - t; }
-
-// Hockney placement fused with the 8-corner difference: every position t of the cyclic
-// (2nz, 2ny, 2nx) array receives Gbar(fold(t)), fold(t) = t for t <= n, M - t otherwise,
-// as a complex value with zero imaginary part.
-template <typename T>
-__global__ __launch_bounds__(256) void k_igf_place(const Geom* __restrict__ g, int nx, int ny,
+// Cell averages Gbar(i, j, k), i = 0..nx, j = 0..ny, k = 0..nz, from the corner values:
+// successive double-double differences along x, then y, then z; cells on a coordinate plane
+// carry weight 2 per folded axis; one division by the rest-frame cell volume; rounded to
+// double once.  Output gd[(k (ny+1) + j)(nx+1) + i].
+__global__ __launch_bounds__(256) void k_igf_cells(const Geom* __restrict__ g, int nx, int ny,
                                                    int nz, const double2* __restrict__ corners,
-                                                   Cx<T>* __restrict__ W) {
+                                                   double* __restrict__ gd) {
   if (g->status) return;
-  const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
   const int cx = nx + 2, cy = ny + 2;
-  const int64_t total = (int64_t)Mx * My * Mz;
+  const int ex = nx + 1, ey = ny + 1;
+  const int64_t total = (int64_t)ex * ey * (nz + 1);
   const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
-  ddv vol = dd_mul_d(two_prod(hx, hy), hz);
+  const ddv vol = dd_mul_d(two_prod(hx, hy), hz);
   for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
-    int tx = (int)(t % Mx);
-    int ty = (int)((t / Mx) % My);
-    int tz = (int)(t / ((int64_t)Mx * My));
-    int i = fold(tx, nx, Mx), j = fold(ty, ny, My), k = fold(tz, nz, Mz);
-    // successive differences along x, then y, then z (corners i, i+1 etc.)
+    const int i = (int)(t % ex);
+    const int j = (int)((t / ex) % ey);
+    const int k = (int)(t / ((int64_t)ex * ey));
     ddv dxy[2][2];
     for (int c = 0; c < 2; ++c)
       for (int b = 0; b < 2; ++b) {
-        int64_t base = ((int64_t)(k + c) * cy + (j + b)) * cx + i;
-        double2 f0 = corners[base], f1 = corners[base + 1];
+        const int64_t base = ((int64_t)(k + c) * cy + (j + b)) * cx + i;
+        const double2 f0 = corners[base], f1 = corners[base + 1];
         dxy[c][b] = dd_sub(ddv{f1.x, f1.y}, ddv{f0.x, f0.y});
       }
-    ddv dz0 = dd_sub(dxy[0][1], dxy[0][0]);
-    ddv dz1 = dd_sub(dxy[1][1], dxy[1][0]);
-    ddv d = dd_sub(dz1, dz0);
-    double w = (i == 0 ? 2.0 : 1.0) * (j == 0 ? 2.0 : 1.0) * (k == 0 ? 2.0 : 1.0);
+    ddv d = dd_sub(dd_sub(dxy[1][1], dxy[1][0]), dd_sub(dxy[0][1], dxy[0][0]));
+    const double w = (i == 0 ? 2.0 : 1.0) * (j == 0 ? 2.0 : 1.0) * (k == 0 ? 2.0 : 1.0);
     d = {d.hi * w, d.lo * w};
-    ddv gbar = dd_div(d, vol);
-    W[t] = Cx<T>{(T)(gbar.hi + gbar.lo), (T)0};
+    const ddv gbar = dd_div(d, vol);
+    gd[t] = gbar.hi + gbar.lo;
   }
 }
 
@@ -91,18 +80,12 @@ hipError_t launch_igf_corners(const Geom* g, int nx, int ny, int nz, double2* co
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_igf_place(const Geom* g, int nx, int ny, int nz, const double2* corners,
-                            void* W, hipStream_t s) {
-  int64_t total = 8ll * nx * ny * nz;
-  hipLaunchKernelGGL((k_igf_place<T>), dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz,
-                     corners, (Cx<T>*)W);
+hipError_t launch_igf_cells(const Geom* g, int nx, int ny, int nz, const double2* corners,
+                            double* gd, hipStream_t s) {
+  int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  hipLaunchKernelGGL(k_igf_cells, dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz, corners,
+                     gd);
   return hipGetLastError();
 }
-
-template hipError_t launch_igf_place<double>(const Geom*, int, int, int, const double2*, void*,
-                                             hipStream_t);
-template hipError_t launch_igf_place<float>(const Geom*, int, int, int, const double2*, void*,
-                                            hipStream_t);
 
 }  // namespace pic

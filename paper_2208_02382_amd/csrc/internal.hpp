@@ -36,18 +36,36 @@ struct Consts {
   double q_macro;      // charge per macroparticle [C]
 };
 
-// Twiddle tables and FFT plan for the three padded axes.
+// One transform length and its radices (4s, then a 2, then 3s, in order of use).
+struct FftAxis {
+  int M;
+  int nrad;
+  int rad[12];
+};
+
+// FFT plan for the three padded axes.
 struct FftPlan {
-  int M[3];            // padded lengths (x, y, z)
-  int nrad[3];
-  int rad[3][12];      // radices per axis (4, 2, 3 in that order of use)
-  const double2* tw[3];  // exp(-2 pi i t/M), t = 0..M-1 (float64 master tables)
+  FftAxis full[3];       // padded lengths M_a = 2 n_a
+  FftAxis half_x;        // n_x: the complex transform inside the real x transforms
+  const double2* tw[3];  // exp(-2 pi i t/M_a), t = 0..M_a-1 (float64 master tables)
   const float2* twf[3];  // the same rounded to float32
 };
 
 // 6x6 lower-triangular Cholesky factor (row-major, upper part zero).
 struct Chol {
   double L[36];
+};
+
+constexpr int kMaxTiles = 4096;       // tiles of the per-step particle binning
+
+// Binning plan: tiles of T[a] cells along each axis (NT[a] tiles), work chunks of at most
+// `chunk` particles for the tiled deposit.
+struct SortPlan {
+  int T[3];
+  int NT[3];
+  int ntiles;
+  int chunk;
+  int64_t max_chunks;
 };
 
 constexpr int kReduceBlocks = 1024;   // partial sums for the moments reduction
@@ -77,18 +95,35 @@ hipError_t launch_moments(const double* X, int64_t n, double* partial, double* o
 template <typename T>
 hipError_t launch_zero(T* p, int64_t count, hipStream_t s);
 
+// ---- sort.hip
+SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n);
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, double ell,
+                           Consts c, Box* box, hipStream_t s);
+hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
+                      const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
+                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, hipStream_t s);
+template <typename T>
+hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
+                                const int4* chunks, const uint32_t* nchunks, T* rho,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
+                            const int4* chunks, const uint32_t* nchunks, double L, int has_next,
+                            double k_next, double half_next, Box* box, hipStream_t s);
+hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
+                            hipStream_t s);
+
 // ---- igf.hip
 hipError_t launch_igf_corners(const Geom* g, int nx, int ny, int nz, double2* corners,
                               hipStream_t s);
-template <typename T>
-hipError_t launch_igf_place(const Geom* g, int nx, int ny, int nz, const double2* corners,
-                            void* W /* complex<T> M^3 */, hipStream_t s);
+hipError_t launch_igf_cells(const Geom* g, int nx, int ny, int nz, const double2* corners,
+                            double* gd /* (nz+1)(ny+1)(nx+1) */, hipStream_t s);
 
 // ---- fft.hip
 hipError_t launch_twiddles(double2* tw, float2* twf, int M, hipStream_t s);
 template <typename T>
 hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
-                                 double2* corners, void* W, T* Gh, hipStream_t s);
+                                 double2* corners, double* gd, T* gh, hipStream_t s);
 template <typename T>
 hipError_t launch_solve(const Geom* g, const FftPlan& p, int nx, int ny, int nz, const T* rho,
                         void* W, const T* Gh, T* phi, T* E, hipStream_t s);

@@ -4,6 +4,7 @@
 // Phase space is structure-of-arrays float64 X[6][n] = (x, px, y, py, z, delta); every kernel
 // walks particles with a grid-stride loop so consecutive lanes touch consecutive doubles of
 // each row (coalesced 64-lane reads of 512 B per row).
+#include "device_common.hpp"
 #include "internal.hpp"
 
 namespace pic {
@@ -12,49 +13,11 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ unsigned long long ord_enc(double v) {
-  unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
-}
-
-__device__ __forceinline__ double ord_dec(unsigned long long u) {
-  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
-  return __longlong_as_double((long long)u);
-}
-
 int grid_for(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
   return (int)b;
-}
-
-// B-spline stencil along one axis: base node and S+1 weights.  CIC (S = 1): i = floor(u),
-// f = u - i, weights (1 - f, f) on (i, i+1).  TSC (S = 2): i = floor(u + 1/2), d = u - i,
-// weights (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2) on (i-1, i, i+1).  The base is
-// clamped into the grid so that no input can address memory outside it (a valid geometry
-// never needs the clamp).
-template <int S>
-__device__ __forceinline__ int stencil(double u, int n, double* w) {
-  if constexpr (S == 1) {
-    double i = floor(u);
-    double f = u - i;
-    w[0] = 1.0 - f;
-    w[1] = f;
-    int b = (int)i;
-    b = b < 0 ? 0 : (b > n - 2 ? n - 2 : b);
-    return b;
-  } else {
-    double i = floor(u + 0.5);
-    double d = u - i;
-    double a = 0.5 - d, c = 0.5 + d;
-    w[0] = 0.5 * (a * a);
-    w[1] = 0.75 - d * d;
-    w[2] = 0.5 * (c * c);
-    int b = (int)i - 1;
-    b = b < 0 ? 0 : (b > n - 3 ? n - 3 : b);
-    return b;
-  }
 }
 
 // ---------------------------------------------------------------------------- box and geometry
@@ -66,41 +29,6 @@ __global__ void k_box_reset(Box* box) {
     box->mx[t] = 0ull;
   }
   if (t == 0) box->nonfinite = 0u;
-}
-
-// Block-wide min/max of x, y, z, then one atomic per block and axis.
-__device__ __forceinline__ void box_accumulate(double lo[3], double hi[3], bool bad, Box* box) {
-  __shared__ double slo[3][kBlock / 64], shi[3][kBlock / 64];
-  __shared__ int sbad;
-  if (threadIdx.x == 0) sbad = 0;
-  __syncthreads();
-  for (int a = 0; a < 3; ++a) {
-    for (int off = 32; off > 0; off >>= 1) {
-      lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
-      hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
-    }
-  }
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0)
-    for (int a = 0; a < 3; ++a) {
-      slo[a][wv] = lo[a];
-      shi[a][wv] = hi[a];
-    }
-  if (bad) sbad = 1;
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    int a = threadIdx.x;
-    double l = slo[a][0], h = shi[a][0];
-    for (int q = 1; q < kBlock / 64; ++q) {
-      l = fmin(l, slo[a][q]);
-      h = fmax(h, shi[a][q]);
-    }
-    if (l <= h) {
-      atomicMin(&box->mn[a], ord_enc(l));
-      atomicMax(&box->mx[a], ord_enc(h));
-    }
-  }
-  if (threadIdx.x == 0 && sbad) atomicOr(&box->nonfinite, 1u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_box(const double* __restrict__ X, int64_t n, Box* box) {
@@ -115,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_box(const double* __restrict__ X, in
       hi[a] = fmax(hi[a], p[a]);
     }
   }
-  box_accumulate(lo, hi, bad, box);
+  box_accumulate_block(lo, hi, bad, box);
 }
 
 // Geometry from the box: h = (max - min)/(n - 3), node 0 at min - h; the rest-frame cell is
@@ -359,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_quad_drift(double* __restrict__ X, d
       hi[a] = fmax(hi[a], p[a]);
     }
   }
-  if (box) box_accumulate(lo, hi, bad, box);
+  if (box) box_accumulate_block(lo, hi, bad, box);
 }
 
 // Fused second half of step j and first half of step j+1: gather E' at the current positions,
@@ -396,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Ge
     }
     for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
   }
-  if (has_next) box_accumulate(lo, hi, bad, box);
+  if (has_next) box_accumulate_block(lo, hi, bad, box);
 }
 
 // ---------------------------------------------------------------------------- moments
@@ -575,5 +503,6 @@ template hipError_t launch_gkd<float>(double*, const Geom*, const float*, double
                                       double, Consts, Box*, hipStream_t);
 template hipError_t launch_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t launch_zero<float>(float*, int64_t, hipStream_t);
+template hipError_t launch_zero<uint32_t>(uint32_t*, int64_t, hipStream_t);
 
 }  // namespace pic

@@ -1,0 +1,465 @@
+// Particle binning by grid tile and the LDS-privatised charge deposition of the tracking loop.
+//
+// Every step the particles are counting-sorted by the tile of their stencil's first node
+// (tiles of T_x x T_y x T_z cells, at most 4096 tiles).  Particles move several cells per step,
+// so the order is rebuilt each step; the previous step's order keeps every pass coherent:
+//   k_key_hist     tile key of each particle (4 B) and a block-privatised histogram in LDS,
+//                  flushed with one global atomic per non-empty bin;
+//   k_build_chunks exclusive scan of the tile counts (sort offsets) and the work list of
+//                  (tile, begin, end) chunks of at most `chunk` particles for the deposit;
+//   k_scatter      moves phase space and particle ids to their sorted slots: each block
+//                  counts its keys in LDS, reserves one contiguous range per key with a single
+//                  global atomic, then ranks its particles with LDS atomics, so particles of one
+//                  key leave a block as one contiguous run;
+//   k_deposit_tiles each workgroup takes a chunk, accumulates the (T + S)^3 window of its tile
+//                  with LDS float atomics, and adds the non-zero window entries to the charge
+//                  grid with one global atomic each.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace pic {
+
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kItems = 4096;               // particles per block in key_hist / scatter
+constexpr int kPer = kItems / kBlk;         // 16 per thread
+
+// stencil base node along one axis: the very function the deposit and gather kernels use
+template <int S>
+__device__ __forceinline__ int base_node(double u, int n) {
+  double w[S + 1];
+  return stencil<S>(u, n, w);
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t tile_key(double x, double y, double z, const double* o,
+                                             const double* ih, const Consts& c,
+                                             const SortPlan& sp) {
+  int bx = base_node<S>((x - o[0]) * ih[0], c.nx);
+  int by = base_node<S>((y - o[1]) * ih[1], c.ny);
+  int bz = base_node<S>((z - o[2]) * ih[2], c.nz);
+  return (uint32_t)(((bz / sp.T[2]) * sp.NT[1] + (by / sp.T[1])) * sp.NT[0] + (bx / sp.T[0]));
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlk) void k_key_hist(const double* __restrict__ X,
+                                                   const Geom* __restrict__ g, Consts c,
+                                                   SortPlan sp, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[kMaxTiles];
+  if (g->status) return;
+  const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  for (int t = threadIdx.x; t < sp.ntiles; t += kBlk) lh[t] = 0u;
+  __syncthreads();
+  const int64_t n = c.n;
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    if (i < n) {
+      uint32_t key = tile_key<S>(X[i], X[2 * n + i], X[4 * n + i], o, ih, c, sp);
+      keys[i] = key;
+      atomicAdd(&lh[key], 1u);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < sp.ntiles; t += kBlk)
+    if (lh[t]) atomicAdd(&hist[t], lh[t]);
+}
+
+// Block-wide exclusive scan of per-thread values (1024 threads).
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t add = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  uint32_t incl = sh[t];
+  *total = sh[1023];
+  __syncthreads();
+  return incl - v;
+}
+
+// one block of 1024 threads; each thread owns 4 consecutive tiles
+__global__ __launch_bounds__(1024) void k_build_chunks(const Geom* __restrict__ g, SortPlan sp,
+                                                       uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ cursor,
+                                                       int4* __restrict__ chunks,
+                                                       uint32_t* __restrict__ nchunks) {
+  __shared__ uint32_t sh[1024];
+  if (g->status) {
+    if (threadIdx.x == 0) *nchunks = 0u;
+    return;
+  }
+  const int t0 = threadIdx.x * 4;
+  uint32_t cnt[4], nck[4], sc = 0, sk = 0;
+  for (int q = 0; q < 4; ++q) {
+    int t = t0 + q;
+    cnt[q] = t < sp.ntiles ? hist[t] : 0u;
+    nck[q] = (cnt[q] + sp.chunk - 1) / sp.chunk;
+    sc += cnt[q];
+    sk += nck[q];
+  }
+  uint32_t tot_c, tot_k;
+  uint32_t off = block_exclusive_scan(sc, sh, &tot_c);
+  uint32_t coff = block_exclusive_scan(sk, sh, &tot_k);
+  for (int q = 0; q < 4; ++q) {
+    int t = t0 + q;
+    if (t < sp.ntiles) {
+      cursor[t] = off;
+      hist[t] = 0u;  // ready for the next step
+      for (uint32_t k = 0; k < nck[q]; ++k) {
+        uint32_t b = off + k * sp.chunk;
+        uint32_t e = b + sp.chunk < off + cnt[q] ? b + sp.chunk : off + cnt[q];
+        chunks[coff + k] = make_int4(t, (int)b, (int)e, 0);
+      }
+    }
+    off += cnt[q];
+    coff += nck[q];
+  }
+  if (threadIdx.x == 0) *nchunks = tot_k;
+}
+
+__global__ __launch_bounds__(kBlk) void k_scatter(const double* __restrict__ A,
+                                                  const uint32_t* __restrict__ idA,
+                                                  const uint32_t* __restrict__ keys,
+                                                  const Geom* __restrict__ g, int64_t n,
+                                                  int ntiles, uint32_t* __restrict__ cursor,
+                                                  double* __restrict__ B,
+                                                  uint32_t* __restrict__ idB) {
+  __shared__ uint32_t lh[kMaxTiles];
+  if (g->status) return;
+  for (int t = threadIdx.x; t < ntiles; t += kBlk) lh[t] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  uint32_t key[kPer];
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    key[k] = i < n ? keys[i] : 0u;
+    if (i < n) atomicAdd(&lh[key[k]], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += kBlk)
+    if (lh[t]) lh[t] = atomicAdd(&cursor[t], lh[t]);
+  __syncthreads();
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    if (i < n) {
+      uint32_t pos = atomicAdd(&lh[key[k]], 1u);
+      if (pos < (uint64_t)n) {  // always true for a consistent histogram; keeps writes in bounds
+        for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
+        idB[pos] = idA[i];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void add_global(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
+                                                        const Geom* __restrict__ g, Consts c,
+                                                        SortPlan sp,
+                                                        const int4* __restrict__ chunks,
+                                                        const uint32_t* __restrict__ nchunks,
+                                                        T* __restrict__ rho) {
+  extern __shared__ unsigned char smem_raw[];
+  T* win = reinterpret_cast<T*>(smem_raw);
+  if (g->status) return;
+  const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
+  const int nw = Wx * Wy * Wz;
+  const int64_t n = c.n;
+  const uint32_t nck = *nchunks;
+  for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+    const int4 ch = chunks[ci];
+    const int t = ch.x;
+    const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
+    const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
+    for (int w = threadIdx.x; w < nw; w += kBlk) win[w] = T(0);
+    __syncthreads();
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+      double wx[S + 1], wy[S + 1], wz[S + 1];
+      const int bx = stencil<S>((B[i] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((B[2 * n + i] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((B[4 * n + i] - o[2]) * ih[2], c.nz, wz);
+      const int lx = bx - ox, ly = by - oy, lz = bz - oz;
+      const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
+                          lz < sp.T[2];
+      for (int a = 0; a <= S; ++a)
+        for (int b = 0; b <= S; ++b) {
+          double wzy = wz[a] * wy[b];
+          for (int q = 0; q <= S; ++q) {
+            T v = (T)(c.q_macro * (wzy * wx[q]));
+            if (inside)
+              atomicAdd(&win[((lz + a) * Wy + (ly + b)) * Wx + (lx + q)], v);
+            else
+              add_global(&rho[((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + (bx + q)], v);
+          }
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nw; w += kBlk) {
+      T v = win[w];
+      int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
+      int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
+      if (v != T(0) && gx < c.nx && gy < c.ny && gz < c.nz)
+        add_global(&rho[((int64_t)gz * c.ny + gy) * c.nx + gx], v);
+    }
+    __syncthreads();
+  }
+}
+
+// Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
+// workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
+// rows), the particles gather from LDS, get the space-charge kick over L and the drift L/2,
+// then (has_next) the thin quad k_next and drift half_next, and the box of the new positions
+// is accumulated.  A stencil outside the window (not possible for a consistent binning) reads
+// E' from global memory.
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
+                                                    const Geom* __restrict__ g,
+                                                    const T* __restrict__ E, Consts c,
+                                                    SortPlan sp,
+                                                    const int4* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ nchunks,
+                                                    double L, int has_next, double k_next,
+                                                    double half_next, Box* box) {
+  extern __shared__ unsigned char smem_raw[];
+  T* win = reinterpret_cast<T*>(smem_raw);
+  if (g->status) return;
+  const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
+  const int nw = Wx * Wy * Wz;
+  const int64_t n = c.n;
+  const int64_t plane = (int64_t)c.nx * c.ny * c.nz;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  const uint32_t nck = *nchunks;
+  for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+    const int4 ch = chunks[ci];
+    const int t = ch.x;
+    const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
+    const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
+    __syncthreads();  // the previous chunk's readers are done with the window
+    for (int w = threadIdx.x; w < nw; w += kBlk) {
+      int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
+      int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
+      bool in = gx < c.nx && gy < c.ny && gz < c.nz;
+      int64_t gi = ((int64_t)gz * c.ny + gy) * c.nx + gx;
+      win[w] = in ? E[gi] : T(0);
+      win[nw + w] = in ? E[plane + gi] : T(0);
+      win[2 * nw + w] = in ? E[2 * plane + gi] : T(0);
+    }
+    __syncthreads();
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+      double v[6];
+      for (int r = 0; r < 6; ++r) v[r] = B[r * n + i];
+      double wx[S + 1], wy[S + 1], wz[S + 1];
+      const int bx = stencil<S>((v[0] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((v[2] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((v[4] - o[2]) * ih[2], c.nz, wz);
+      const int lx = bx - ox, ly = by - oy, lz = bz - oz;
+      const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
+                          lz < sp.T[2];
+      T ex = 0, ey = 0, ez = 0;
+      for (int a = 0; a <= S; ++a)
+        for (int b = 0; b <= S; ++b) {
+          double wzy = wz[a] * wy[b];
+          for (int q = 0; q <= S; ++q) {
+            T w = (T)(wzy * wx[q]);
+            if (inside) {
+              int li = ((lz + a) * Wy + (ly + b)) * Wx + (lx + q);
+              ex += w * win[li];
+              ey += w * win[nw + li];
+              ez += w * win[2 * nw + li];
+            } else {
+              int64_t gi = ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + (bx + q);
+              ex += w * E[gi];
+              ey += w * E[plane + gi];
+              ez += w * E[2 * plane + gi];
+            }
+          }
+        }
+      v[1] = v[1] + c.C * (double)ex * L;
+      v[3] = v[3] + c.C * (double)ey * L;
+      v[5] = v[5] + c.gamma * c.C * (double)ez * L;
+      const double hl = 0.5 * L;
+      v[0] = v[0] + hl * v[1];
+      v[2] = v[2] + hl * v[3];
+      v[4] = v[4] + hl * v[5] * c.inv_gamma2;
+      if (has_next) {
+        v[1] = v[1] - k_next * v[0];
+        v[3] = v[3] + k_next * v[2];
+        v[0] = v[0] + half_next * v[1];
+        v[2] = v[2] + half_next * v[3];
+        v[4] = v[4] + half_next * v[5] * c.inv_gamma2;
+        const double p[3] = {v[0], v[2], v[4]};
+        for (int a = 0; a < 3; ++a) {
+          bad |= !isfinite(p[a]);
+          lo[a] = fmin(lo[a], p[a]);
+          hi[a] = fmax(hi[a], p[a]);
+        }
+      }
+      for (int r = 0; r < 6; ++r) B[r * n + i] = v[r];
+    }
+  }
+  if (has_next) box_accumulate_block(lo, hi, bad, box);
+}
+
+// First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
+__global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
+                                                   double* __restrict__ A,
+                                                   uint32_t* __restrict__ idA, double k,
+                                                   double ell, Consts c, Box* box) {
+  const int64_t n = c.n;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    v[1] = v[1] - k * v[0];
+    v[3] = v[3] + k * v[2];
+    v[0] = v[0] + ell * v[1];
+    v[2] = v[2] + ell * v[3];
+    v[4] = v[4] + ell * v[5] * c.inv_gamma2;
+    for (int r = 0; r < 6; ++r) A[r * n + i] = v[r];
+    idA[i] = (uint32_t)i;
+    double p[3] = {v[0], v[2], v[4]};
+    for (int a = 0; a < 3; ++a) {
+      bad |= !isfinite(p[a]);
+      lo[a] = fmin(lo[a], p[a]);
+      hi[a] = fmax(hi[a], p[a]);
+    }
+  }
+  box_accumulate_block(lo, hi, bad, box);
+}
+
+// Back to the caller's order: X[r][id[i]] = A[r][i].
+__global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A,
+                                                    const uint32_t* __restrict__ idA, int64_t n,
+                                                    double* __restrict__ X) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    uint32_t j = idA[i];
+    if (j < (uint64_t)n)
+      for (int r = 0; r < 6; ++r) X[r * n + j] = A[r * n + i];
+  }
+}
+
+int grid_items(int64_t n) { return (int)((n + kItems - 1) / kItems); }
+
+int grid_stride(int64_t n) {
+  int64_t b = (n + kBlk - 1) / kBlk;
+  if (b > 8192) b = 8192;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n) {
+  SortPlan sp;
+  int nn[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a) {
+    int t = (nn[a] + 15) / 16;
+    sp.T[a] = t < 4 ? 4 : t;
+    sp.NT[a] = (nn[a] + sp.T[a] - 1) / sp.T[a];
+  }
+  sp.ntiles = sp.NT[0] * sp.NT[1] * sp.NT[2];
+  sp.chunk = 8192;
+  sp.max_chunks = (int64_t)(n / sp.chunk) + sp.ntiles + 1;
+  (void)n;
+  return sp;
+}
+
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, double ell,
+                           Consts c, Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(grid_stride(c.n)), dim3(kBlk), 0, s, X, A, idA, k, ell, c,
+                     box);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
+                      const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
+                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL(k_key_hist<1>, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, g, c, sp, keys,
+                       hist);
+  else
+    hipLaunchKernelGGL(k_key_hist<2>, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, g, c, sp, keys,
+                       hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, g, sp, hist, cursor, chunks,
+                     nchunks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, idA, keys, g, c.n,
+                     sp.ntiles, cursor, B, idB);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
+                                const int4* chunks, const uint32_t* nchunks, T* rho,
+                                hipStream_t s) {
+  const int S = c.shape;
+  size_t lds = sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
+  int64_t grid = sp.max_chunks < 4096 ? sp.max_chunks : 4096;
+  if (S == 1)
+    hipLaunchKernelGGL((k_deposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, c,
+                       sp, chunks, nchunks, rho);
+  else
+    hipLaunchKernelGGL((k_deposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, c,
+                       sp, chunks, nchunks, rho);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
+                            const int4* chunks, const uint32_t* nchunks, double L, int has_next,
+                            double k_next, double half_next, Box* box, hipStream_t s) {
+  const int S = c.shape;
+  size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
+  int64_t grid = sp.max_chunks < 4096 ? sp.max_chunks : 4096;
+  if (S == 1)
+    hipLaunchKernelGGL((k_gkd_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
+                       sp, chunks, nchunks, L, has_next, k_next, half_next, box);
+  else
+    hipLaunchKernelGGL((k_gkd_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
+                       sp, chunks, nchunks, L, has_next, k_next, half_next, box);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gkd_tiles<double>(double*, const Geom*, const double*, Consts,
+                                             const SortPlan&, const int4*, const uint32_t*, double,
+                                             int, double, double, Box*, hipStream_t);
+template hipError_t launch_gkd_tiles<float>(double*, const Geom*, const float*, Consts,
+                                            const SortPlan&, const int4*, const uint32_t*, double,
+                                            int, double, double, Box*, hipStream_t);
+
+hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, A, idA, n, X);
+  return hipGetLastError();
+}
+
+template hipError_t launch_deposit_tiles<double>(const double*, const Geom*, Consts,
+                                                 const SortPlan&, const int4*, const uint32_t*,
+                                                 double*, hipStream_t);
+template hipError_t launch_deposit_tiles<float>(const double*, const Geom*, Consts,
+                                                const SortPlan&, const int4*, const uint32_t*,
+                                                float*, hipStream_t);
+
+}  // namespace pic
