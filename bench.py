@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="particles in the oracle's timed sample (0 disables)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-grid variant")
+    ap.add_argument("--copy-ref-bytes", type=int, default=0,
+                    help="first run one device-to-device copy of this many bytes (a reference "
+                         "of known traffic for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU "
@@ -131,6 +134,13 @@ def main():
     import workloads
 
     cfg = workloads.CONFIGS[args.workload]
+    if args.copy_ref_bytes > 0:
+        src = torch.ones(args.copy_ref_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     beam, dt, stages, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False)
     ps = cfg.n * args.steps / dt
 

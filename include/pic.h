@@ -30,7 +30,8 @@
  * Errors: calls return pic_status.  Argument errors are reported synchronously and leave the
  *   device untouched.  Device-side errors (a non-finite coordinate, a zero-extent box) set a
  *   flag in the workspace; from then on every kernel of the beam skips its work, and the next
- *   synchronising call (pic_check, pic_moments, pic_get_geometry) returns PIC_EDOMAIN.
+ *   synchronising call (pic_check, pic_moments, pic_get_geometry) returns PIC_EDOMAIN (or
+ *   PIC_EINTERNAL for a fault of the library itself).
  *   pic_last_error() gives a message for the last failure on the calling thread.
  * Thread safety: one handle must not be used from two host threads at once; calls on one
  *   handle on two streams race.
@@ -52,7 +53,8 @@ typedef enum {
   PIC_EHIP = -3,          /* a HIP runtime call failed */
   PIC_EDOMAIN = -4,       /* device flagged a non-finite coordinate or a zero-extent box */
   PIC_EUNSUPPORTED = -5,  /* grid size whose padded FFT length is not 2^a 3^b, or > 512 */
-  PIC_ENODEV = -6         /* no HIP device */
+  PIC_ENODEV = -6,        /* no HIP device */
+  PIC_EINTERNAL = -7      /* the device detected an inconsistency of the library's own binning */
 } pic_status;
 
 /* Beam description; mirrors add_particles + set_energy_MeV + set_particle_shape +
@@ -145,7 +147,8 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * deposit, IGF, Poisson, field, gather), drift ds/2.  Updates X in place; the particle order
  * of X is preserved (internally the particles are binned by grid tile every step in two
  * workspace copies and returned to X in the caller's order at the end of the call).  With
- * desc.space_charge = 0 only the linear maps are applied. */
+ * desc.space_charge = 0 only the linear maps are applied.  If the device flags an error
+ * during the call (see pic_check), X is left as it was before the call. */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 

@@ -20,8 +20,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_EDOMAIN, PIC_EUNSUPPORTED, PIC_ENODEV = (
     0, -1, -2, -3, -4, -5, -6)
+PIC_EINTERNAL = -7
 STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EHIP",
-                -4: "PIC_EDOMAIN", -5: "PIC_EUNSUPPORTED", -6: "PIC_ENODEV"}
+                -4: "PIC_EDOMAIN", -5: "PIC_EUNSUPPORTED", -6: "PIC_ENODEV", -7: "PIC_EINTERNAL"}
 PUSH_DRIFT, PUSH_THINQUAD, PUSH_KICK = 0, 1, 2
 STAGES = ("prologue", "geometry", "green", "deposit", "solve", "gkd", "bin", "unpermute")
 

@@ -184,6 +184,12 @@ namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+pic_status device_status(int st) {
+  if (st == 0) return PIC_OK;
+  if (st == PIC_EINTERNAL) return fail(PIC_EINTERNAL, "device detected an inconsistent particle binning");
+  return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
+}
+
 bool cholesky6(const double* A, Chol& out) {
   double L[36] = {0};
   for (int i = 0; i < 6; ++i)
@@ -270,7 +276,10 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     double* tX = A; A = B; B = tX;
     uint32_t* tI = idA; idA = idB; idB = tI;
   }
-  STAGE(b, PIC_STAGE_UNPERMUTE, s, launch_unpermute(A, idA, b->c.n, b->X, s), "unpermute");
+  STAGE(b, PIC_STAGE_UNPERMUTE, s,
+        launch_unpermute(A, idA, b->c.n, b->X, b->keys, b->hist, b->cursor, b->chunks,
+                         b->nchunks, B, idB, b->geom, s),
+        "unpermute");
   return PIC_OK;
 }
 
@@ -479,8 +488,7 @@ pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream)
     for (int c = a; c < 6; ++c) {
       cov[a * 6 + c] = cov[c * 6 + a] = host[q++];
     }
-  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
-  return PIC_OK;
+  return device_status(g.status);
 }
 
 pic_status pic_get_geometry(pic_beam b, double out[9], void* stream) {
@@ -494,8 +502,7 @@ pic_status pic_get_geometry(pic_beam b, double out[9], void* stream) {
     out[3 + a] = g.h[a];
     out[6 + a] = g.h_rest[a];
   }
-  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
-  return PIC_OK;
+  return device_status(g.status);
 }
 
 pic_status pic_profile_start(pic_beam b) {
@@ -530,8 +537,7 @@ pic_status pic_check(pic_beam b, void* stream) {
   Geom g;
   HIP_OK(hipMemcpyAsync(&g, b->geom, sizeof(Geom), hipMemcpyDeviceToHost, s), "check");
   HIP_OK(hipStreamSynchronize(s), "check");
-  if (g.status) return fail(PIC_EDOMAIN, "device flagged a non-finite coordinate or a zero-extent box");
-  return PIC_OK;
+  return device_status(g.status);
 }
 
 }  // extern "C"

@@ -111,6 +111,8 @@ hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, cons
                             const int4* chunks, const uint32_t* nchunks, double L, int has_next,
                             double k_next, double half_next, Box* box, hipStream_t s);
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
+                            uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
+                            uint32_t* nchunks, double* B, uint32_t* idB, const Geom* g,
                             hipStream_t s);
 
 // ---- igf.hip

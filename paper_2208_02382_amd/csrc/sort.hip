@@ -223,8 +223,9 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict
 // workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
 // rows), the particles gather from LDS, get the space-charge kick over L and the drift L/2,
 // then (has_next) the thin quad k_next and drift half_next, and the box of the new positions
-// is accumulated.  A stencil outside the window (not possible for a consistent binning) reads
-// E' from global memory.
+// is accumulated.  The gather reads LDS only (a per-lane choice between LDS and global memory
+// compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
+// window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
 template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
                                                     const Geom* __restrict__ g,
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
   const int64_t n = c.n;
   const int64_t plane = (int64_t)c.nx * c.ny * c.nz;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  bool bad = false;
+  bool bad = false, bin_fault = false;
   const uint32_t nck = *nchunks;
   for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
     const int4 ch = chunks[ci];
@@ -269,26 +270,25 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
       const int bx = stencil<S>((v[0] - o[0]) * ih[0], c.nx, wx);
       const int by = stencil<S>((v[2] - o[1]) * ih[1], c.ny, wy);
       const int bz = stencil<S>((v[4] - o[2]) * ih[2], c.nz, wz);
-      const int lx = bx - ox, ly = by - oy, lz = bz - oz;
-      const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
-                          lz < sp.T[2];
+      // the binning put this particle in the chunk's tile, so its stencil lies in the window;
+      // a violation is a library fault: flagged, and the indices clamped to stay in bounds
+      int lx = bx - ox, ly = by - oy, lz = bz - oz;
+      if (lx < 0 || lx >= sp.T[0] || ly < 0 || ly >= sp.T[1] || lz < 0 || lz >= sp.T[2]) {
+        bin_fault = true;
+        lx = min(max(lx, 0), sp.T[0] - 1);
+        ly = min(max(ly, 0), sp.T[1] - 1);
+        lz = min(max(lz, 0), sp.T[2] - 1);
+      }
       T ex = 0, ey = 0, ez = 0;
       for (int a = 0; a <= S; ++a)
         for (int b = 0; b <= S; ++b) {
-          double wzy = wz[a] * wy[b];
+          const double wzy = wz[a] * wy[b];
+          const T* row = win + ((lz + a) * Wy + (ly + b)) * Wx + lx;
           for (int q = 0; q <= S; ++q) {
-            T w = (T)(wzy * wx[q]);
-            if (inside) {
-              int li = ((lz + a) * Wy + (ly + b)) * Wx + (lx + q);
-              ex += w * win[li];
-              ey += w * win[nw + li];
-              ez += w * win[2 * nw + li];
-            } else {
-              int64_t gi = ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + (bx + q);
-              ex += w * E[gi];
-              ey += w * E[plane + gi];
-              ez += w * E[2 * plane + gi];
-            }
+            const T w = (T)(wzy * wx[q]);
+            ex += w * row[q];
+            ey += w * row[nw + q];
+            ez += w * row[2 * nw + q];
           }
         }
       v[1] = v[1] + c.C * (double)ex * L;
@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
       for (int r = 0; r < 6; ++r) B[r * n + i] = v[r];
     }
   }
+  if (bin_fault) atomicCAS(const_cast<int*>(&g->status), 0, -7);
   if (has_next) box_accumulate_block(lo, hi, bad, box);
 }
 
@@ -346,10 +347,37 @@ __global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
   box_accumulate_block(lo, hi, bad, box);
 }
 
-// Back to the caller's order: X[r][id[i]] = A[r][i].
+// Bucket keys for the return to the caller's order: key = id >> shift (at most 4096 buckets of
+// consecutive original indices), with the block-privatised histogram of k_key_hist.
+__global__ __launch_bounds__(kBlk) void k_id_hist(const uint32_t* __restrict__ ids, int64_t n,
+                                                  int shift, int nbuckets,
+                                                  uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[kMaxTiles];
+  for (int t = threadIdx.x; t < nbuckets; t += kBlk) lh[t] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    if (i < n) {
+      uint32_t key = ids[i] >> shift;
+      key = key < (uint32_t)nbuckets ? key : (uint32_t)nbuckets - 1u;
+      keys[i] = key;
+      atomicAdd(&lh[key], 1u);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nbuckets; t += kBlk)
+    if (lh[t]) atomicAdd(&hist[t], lh[t]);
+}
+
+// Back to the caller's order: X[r][id[i]] = A[r][i].  After the bucket pass, the particles a
+// block handles have ids in a narrow range, so its writes stay within an L2-sized window.
 __global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A,
                                                     const uint32_t* __restrict__ idA, int64_t n,
+                                                    const Geom* __restrict__ g,
                                                     double* __restrict__ X) {
+  if (g->status) return;  // after a device error X keeps the caller's input
   for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlk) {
     uint32_t j = idA[i];
@@ -379,7 +407,8 @@ SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n) {
   sp.ntiles = sp.NT[0] * sp.NT[1] * sp.NT[2];
   sp.chunk = 8192;
   sp.max_chunks = (int64_t)(n / sp.chunk) + sp.ntiles + 1;
-  (void)n;
+  // the work list also serves the id buckets of the final reordering (up to kMaxTiles entries)
+  if (sp.max_chunks < kMaxTiles + 1) sp.max_chunks = kMaxTiles + 1;
   return sp;
 }
 
@@ -450,8 +479,32 @@ template hipError_t launch_gkd_tiles<float>(double*, const Geom*, const float*, 
                                             int, double, double, Box*, hipStream_t);
 
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
+                            uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
+                            uint32_t* nchunks, double* B, uint32_t* idB, const Geom* g,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, A, idA, n, X);
+  int shift = 0;
+  while (((n - 1) >> shift) >= kMaxTiles) ++shift;
+  const int nb = (int)(((n - 1) >> shift) + 1);
+  SortPlan bp;
+  bp.T[0] = bp.T[1] = bp.T[2] = 1;
+  bp.NT[0] = nb;
+  bp.NT[1] = bp.NT[2] = 1;
+  bp.ntiles = nb;
+  bp.chunk = 1 << 30;  // the work list is not used; one entry per bucket
+  bp.max_chunks = nb + 1;
+  hipLaunchKernelGGL(k_id_hist, dim3(grid_items(n)), dim3(kBlk), 0, s, idA, n, shift, nb, keys,
+                     hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, g, bp, hist, cursor, chunks,
+                     nchunks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_items(n)), dim3(kBlk), 0, s, A, idA, keys, g, n, nb,
+                     cursor, B, idB);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, B, idB, n, g, X);
   return hipGetLastError();
 }
 

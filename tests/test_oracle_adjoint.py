@@ -1,0 +1,184 @@
+"""Pins of the oracle's reverse sweep: dot-product tests of each transposed operation, central
+finite differences with space charge, and the closed-form gradient of the zero-current map."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint as adj
+from oracle import igf, pic
+
+W4 = np.array([0.7, -0.4, 1.3, 0.9])   # weights on (sigma_x, sigma_y, eps_x, eps_y)
+
+
+def _prob(nodes=(12, 12, 12), shape=1, n=400):
+    c = workloads.SMALL
+    return pic.make_problem(n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, nodes, shape)
+
+
+def _beam(n, seed=0):
+    r = np.random.default_rng(seed)
+    X = np.zeros((6, n))
+    X[0], X[2], X[4] = r.standard_normal((3, n)) * np.array([1e-3, 1e-3, 2e-3])[:, None]
+    X[1], X[3], X[5] = r.standard_normal((3, n)) * 1e-3
+    return X
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_transposes_by_dot_products(shape):
+    prob = _prob(nodes=(10, 9, 12), shape=shape, n=300)
+    X = _beam(300, seed=1)
+    geom = pic.geometry(X, prob)
+    r = np.random.default_rng(2)
+    nx, ny, nz = prob.nodes
+    # vector deposit is the transpose of the gather
+    A = r.standard_normal((3, 300))
+    F = r.standard_normal((3, nz, ny, nx))
+    lhs = np.sum(adj.vector_deposit(A, X, geom, prob) * F)
+    rhs = np.sum(A * pic.gather(F, X, geom, prob))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # -D^T is the transpose of the field operator E' = -D phi
+    e = r.standard_normal((3, nz, ny, nx))
+    phi = r.standard_normal((nz + 2, ny + 2, nx + 2))
+    lhs = np.sum(adj.divergence_T(e, geom) * phi)
+    rhs = np.sum(e * pic.field(phi, geom))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # the ghost-source convolution is the transpose of the solve (Gbar is even)
+    gbar = pic.green(geom, prob)
+    psi = r.standard_normal((nz + 2, ny + 2, nx + 2))
+    rho = r.standard_normal((nz, ny, nx))
+    lhs = np.sum(adj.solve_ghost_source(psi, gbar) * rho)
+    rhs = np.sum(psi * pic.solve(rho, gbar))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_grad_gather_is_the_position_derivative_of_the_deposit(shape):
+    prob = _prob(nodes=(10, 10, 10), shape=shape, n=50)
+    X = _beam(50, seed=3)
+    geom = pic.geometry(X, prob)
+    F = np.random.default_rng(4).standard_normal((10, 10, 10))
+    g = prob.q_macro * adj.grad_gather(F, X, geom, prob)
+    for i in (0, 17, 42):
+        for c, row in enumerate((0, 2, 4)):
+            h = 1e-7 * geom.h[c]
+            Xp, Xm = X.copy(), X.copy()
+            Xp[row, i] += h
+            Xm[row, i] -= h
+            fd = (np.sum(pic.deposit(Xp, geom, prob) * F)
+                  - np.sum(pic.deposit(Xm, geom, prob) * F)) / (2 * h)
+            assert abs(fd - g[c, i]) < 1e-6 * np.abs(g).max()
+
+
+def _fd(fun, x0, h):
+    return (fun(x0 + h) - fun(x0 - h)) / (2 * h)
+
+
+def _shifted(geoms):
+    """The run's geometries with h scaled by 1.05 and the origin moved by -0.3 h: every
+    stencil stays on the grid and no particle sits on a node.  (The box of the run itself puts
+    the extreme particles exactly on nodes, where CIC weights have a kink and the derivative
+    is one-sided.)"""
+    out = []
+    for g in geoms:
+        h = 1.05 * g.h
+        origin = g.origin - 0.3 * h
+        out.append(pic.Geometry(origin, h, np.array([h[0], h[1], g.h_rest[2] / g.h[2] * h[2]])))
+    return out
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_adjoint_matches_central_differences_with_space_charge(shape):
+    n, steps = 400, 4
+    prob = _prob(nodes=(12, 12, 12), shape=shape, n=n)
+    X0 = _beam(n, seed=5)
+    ks = np.array([1.0, -1.0, 0.8])
+    dss = np.array([0.5, 0.5, 0.5])
+    _, _, _, run_geoms = adj.adjoint(X0, ks, dss, steps, prob, W4)
+    J, dk, lam0, geoms = adj.adjoint(X0, ks, dss, steps, prob, W4, geoms=_shifted(run_geoms))
+
+    def J_of(ks_, X_=X0):
+        XN, _ = adj.forward(X_, ks_, dss, steps, prob, geoms=geoms)
+        return adj.objective(XN, W4)
+
+    assert abs(J_of(ks) - J) < 1e-15 * abs(J)
+    for j in range(3):
+        h = 1e-6 * abs(ks[j])
+        e = np.zeros(3)
+        e[j] = 1.0
+        fd = _fd(lambda t: J_of(ks + t * e), 0.0, h)
+        assert abs(fd - dk[j]) < 1e-6 * np.abs(dk).max()
+    # directional derivative along a random perturbation of X0
+    D = np.random.default_rng(6).standard_normal(X0.shape) * X0.std(axis=1)[:, None]
+    fd = _fd(lambda t: J_of(ks, X0 + t * D), 0.0, 1e-6)
+    assert abs(fd - np.sum(lam0 * D)) < 1e-6 * abs(np.sum(lam0 * D)) + 1e-12 * abs(J)
+
+
+def _matrix(f):
+    M = np.zeros((6, 6))
+    for c in range(6):
+        e = np.zeros((6, 1))
+        e[c] = 1.0
+        M[:, c] = f(e)[:, 0]
+    return M
+
+
+def test_zero_current_gradient_in_closed_form():
+    # without space charge the map is linear, X_N = M X0 with M a product of drift and thin-quad
+    # matrices; dM/dk_e is the sum over the steps that use element e of (after) D dQ (before)
+    n, steps = 500, 7
+    prob = _prob(n=n)
+    X0 = _beam(n, seed=7)
+    ks = np.array([1.1, -0.9, 0.7])
+    dss = np.array([0.5, 0.4, 0.6])
+    J, dk, lam0, _ = adj.adjoint(X0, ks, dss, steps, prob, W4, space_charge=False)
+    Ps = [_matrix(lambda X, j=j: pic.drift(pic.drift(pic.thin_quad(X, ks[j % 3]),
+                                                     0.5 * dss[j % 3], prob),
+                                            0.5 * dss[j % 3], prob)) for j in range(steps)]
+    M = np.eye(6)
+    for P in Ps:
+        M = P @ M
+    XN = M @ X0
+    Lam = adj.objective_grad(XN, W4)
+    assert np.allclose(lam0, M.T @ Lam, rtol=1e-12, atol=1e-12 * np.abs(lam0).max())
+    dQ = np.zeros((6, 6))
+    dQ[1, 0], dQ[3, 2] = -1.0, 1.0
+    for e in range(3):
+        dM = np.zeros((6, 6))
+        for s in range(steps):
+            if s % 3 != e:
+                continue
+            before = np.eye(6)
+            for P in Ps[:s]:
+                before = P @ before
+            after = np.eye(6)
+            for P in Ps[s + 1:]:
+                after = P @ after
+            Dfull = _matrix(lambda X: pic.drift(pic.drift(X, 0.5 * dss[e], prob), 0.5 * dss[e], prob))
+            dM += after @ Dfull @ dQ @ before
+        ref = np.sum(Lam * (dM @ X0))
+        assert abs(dk[e] - ref) < 1e-12 * np.abs(dk).max()
+
+
+def test_sigma0_gradient_through_the_cholesky_factor():
+    n, steps = 300, 3
+    prob = _prob(nodes=(10, 10, 10), shape=2, n=n)
+    xi = np.random.default_rng(8).standard_normal((6, n))
+    S0 = np.diag(np.array([1e-3, 1e-3, 1.2e-3, 0.9e-3, 2e-3, 1e-3]) ** 2)
+    S0[0, 1] = S0[1, 0] = 0.3e-6
+    S0[2, 4] = S0[4, 2] = -0.5e-6
+    ks = np.array([1.0, -1.0])
+    dss = np.array([0.5, 0.5])
+    L = np.linalg.cholesky(S0)
+    J, dk, lam0, geoms = adj.adjoint(L @ xi, ks, dss, steps, prob, W4)
+    G = adj.cholesky_grad(L, xi, lam0)
+
+    def J_of(S):
+        XN, _ = adj.forward(np.linalg.cholesky(S) @ xi, ks, dss, steps, prob, geoms=geoms)
+        return adj.objective(XN, W4)
+
+    for (a, b) in ((0, 0), (0, 1), (2, 4), (3, 3), (1, 5)):
+        h = 1e-6 * np.sqrt(S0[a, a] * S0[b, b])
+        E = np.zeros((6, 6))
+        E[a, b] = E[b, a] = 1.0
+        fd = (J_of(S0 + h * E) - J_of(S0 - h * E)) / (2 * h)
+        assert abs(fd - G[a, b]) < 1e-5 * np.abs(G).max()
