@@ -20,8 +20,9 @@
  * Grids: node-centred, nx*ny*nz nodes, index ((k*ny)+j)*nx+i (x fastest).  Element type is
  *   double, or float when pic_beam_desc.grid_fp32 = 1 ("pic_real" below).
  * Geometry: each pic_deposit / pic_track_n_steps step takes the box of the particle positions
- *   (min/max of x, y, z); h_a = (max_a - min_a)/(n_a - 3), node 0 at min_a - h_a, so every CIC
- *   and TSC stencil stays on nodes 0..n_a-1.  The rest-frame cell is (hx, hy, gamma*hz).
+ *   (min/max of x, y, z); h_a = (max_a - min_a)/(n_a - 3.5), node 0 at min_a - 1.25 h_a, so
+ *   every CIC and TSC stencil stays on nodes 0..n_a-1 and the extreme particles sit a quarter
+ *   cell from any node or cell boundary.  The rest-frame cell is (hx, hy, gamma*hz).
  * Memory: the library never allocates device memory.  The caller owns X, every grid and the
  *   workspace (size from pic_workspace_bytes), all device pointers, 256-byte aligned.  The
  *   handle (host memory) is owned by the library until pic_beam_destroy.

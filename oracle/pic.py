@@ -12,8 +12,11 @@ statistics (section "ImpactX") -- and the B-spline particle-shape order (Listing
 * Reference particle from kinetic energy and rest mass: gamma = 1 + T/m.
 * Macroparticle charge q_m = sign(q) Q/N.
 * Grid: nx x ny x nz nodes (node-centred).  Each step the box is the particle min/max of
-  x, y, z; h_a = (max_a - min_a)/(n_a - 3) and origin_a = min_a - h_a, so every CIC and TSC
-  stencil stays on nodes 0..n_a-1.  Rest frame: z' = gamma z, so the rest-frame cell is
+  x, y, z; h_a = (max_a - min_a)/(n_a - 3.5) and origin_a = min_a - 1.25 h_a.  The extreme
+  particles then sit at u = 1.25 and u = n_a - 2.25, a quarter cell from the nearest node and
+  from the nearest cell boundary, so every CIC and TSC stencil stays on nodes 0..n_a-1 and no
+  particle of the box sits on a kink of either shape (where the tracked map would only have
+  one-sided derivatives).  Rest frame: z' = gamma z, so the rest-frame cell is
   (hx, hy, gamma hz); node charges are frame-invariant.
 * Shapes (B-spline order 1 and 2), u = (x - origin)/h:
   CIC  i = floor(u), f = u - i, weights (1-f, f) on nodes (i, i+1);
@@ -97,8 +100,8 @@ def geometry(X, prob: Problem):
     if np.any(ext <= 0):
         raise ValueError("zero extent of the particle box")
     n = np.asarray(prob.nodes, dtype=np.float64)
-    h = ext / (n - 3.0)
-    origin = lo - h
+    h = ext / (n - 3.5)
+    origin = lo - 1.25 * h
     h_rest = np.array([h[0], h[1], prob.gamma * h[2]])
     return Geometry(origin, h, h_rest)
 

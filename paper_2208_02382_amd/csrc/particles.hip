@@ -46,8 +46,9 @@ __global__ __launch_bounds__(kBlock) void k_box(const double* __restrict__ X, in
   box_accumulate_block(lo, hi, bad, box);
 }
 
-// Geometry from the box: h = (max - min)/(n - 3), node 0 at min - h; the rest-frame cell is
-// (hx, hy, gamma hz).  A non-finite coordinate or a zero extent sets status = -4 (PIC_EDOMAIN),
+// Geometry from the box: h = (max - min)/(n - 3.5), node 0 at min - 1.25 h (the extreme
+// particles sit a quarter cell from a node and from a cell boundary: inside every stencil, on
+// no kink of the CIC or TSC weights); the rest-frame cell is (hx, hy, gamma hz).  A non-finite coordinate or a zero extent sets status = -4 (PIC_EDOMAIN),
 // which is sticky until the beam is initialised again.
 __global__ void k_geometry(const Box* box, Geom* g, Consts c) {
   if (threadIdx.x != 0) return;
@@ -64,10 +65,10 @@ __global__ void k_geometry(const Box* box, Geom* g, Consts c) {
     return;
   }
   for (int a = 0; a < 3; ++a) {
-    double h = (hi[a] - lo[a]) / (double)(nn[a] - 3);
+    double h = (hi[a] - lo[a]) / ((double)nn[a] - 3.5);
     g->h[a] = h;
     g->inv_h[a] = 1.0 / h;
-    g->origin[a] = lo[a] - h;
+    g->origin[a] = lo[a] - 1.25 * h;
   }
   g->h_rest[0] = g->h[0];
   g->h_rest[1] = g->h[1];

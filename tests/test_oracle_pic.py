@@ -61,7 +61,7 @@ def test_geometry_keeps_stencils_inside_and_rejects_degenerate_boxes():
     geom = pic.geometry(X, prob)
     for ax, row in enumerate((0, 2, 4)):
         u = (X[row] - geom.origin[ax]) / geom.h[ax]
-        assert u.min() >= 1.0 - 1e-12 and u.max() <= prob.nodes[ax] - 2 + 1e-12
+        assert abs(u.min() - 1.25) < 1e-12 and abs(u.max() - (prob.nodes[ax] - 2.25)) < 1e-12
     assert geom.h_rest[2] == prob.gamma * geom.h[2]
     X2 = X.copy()
     X2[2] = 0.0
