@@ -83,6 +83,7 @@ typedef struct {
 } pic_element;
 
 typedef struct pic_beam_s* pic_beam;
+typedef struct pic_batch_s* pic_batch;
 
 /* Push kinds of pic_push. */
 enum { PIC_PUSH_DRIFT = 0, PIC_PUSH_THINQUAD = 1, PIC_PUSH_KICK = 2 };
@@ -152,6 +153,48 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * during the call (see pic_check), X is left as it was before the call. */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
+
+/* Batched tracking of many independent beams (each created with pic_beam_create, all with the
+ * same shape and grid precision, space_charge = 1; grids and particle counts may differ).
+ * pic_batch_create copies the beams' device descriptors and their lattices (lattices[b] has
+ * n_el[b] elements, cycled over the steps) into the caller's workspace d_work
+ * (pic_batch_workspace_bytes, 256-byte aligned) and synchronises `stream`.  The beams' handles,
+ * arrays and workspaces must outlive the batch.
+ * pic_track_batch runs n_steps steps of pic_track_n_steps on every beam, with one launch per
+ * stage covering all beams; the whole n_steps loop is captured into one HIP graph on the first
+ * call with that step count (on `stream`, which must not be the null stream) and replayed by
+ * later calls.  Device errors are reported per beam by pic_check. */
+size_t pic_batch_workspace_bytes(int n_beams, const int* n_el);
+pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
+                            const int* n_el, void* d_work, size_t work_bytes, void* stream,
+                            pic_batch* out);
+pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream);
+pic_status pic_batch_destroy(pic_batch bt);
+
+/* Workspace bytes of pic_track_adjoint for n_steps steps with a checkpoint every ckpt_every
+ * steps (0 on invalid arguments). */
+size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt_every);
+
+/* Reverse sweep (discrete adjoint) of n_steps steps of pic_track_n_steps.  The paper gives no
+ * differentiation; its machine-learning coupling is only named (sections "Software Design",
+ * "ImpactX").  Objective J = w[0] sigma_x + w[1] sigma_y + w[2] eps_x + w[3] eps_y of the final
+ * beam (centred rms sizes and geometric emittances).  The grid geometry of each step is frozen
+ * to the forward run's.
+ * On entry X holds X0; on return X holds the final state (the forward pass, run in the
+ * caller's particle order) and
+ *   out_m[4]     (sigma_x, sigma_y, eps_x, eps_y) of the final state (host),
+ *   dJ_dk[n_el]  dJ/dk of the lattice strengths, summed over the steps that use each (host),
+ *   d_lam        dJ/dX0, device array of 6*n doubles in the layout of X,
+ *   dJ_dL[36]    if d_xi (device, 6*n draws with X0 = L xi) is given: dJ/dL = sum_i lam_i xi_i^T,
+ *                row-major 6x6 (host); only the lower triangle is a parameter of L.
+ * The forward states are checkpointed every ckpt_every steps in the caller's workspace
+ * d_adj_work (pic_adjoint_workspace_bytes, 256-byte aligned) and recomputed per segment.
+ * Needs desc.space_charge = 1 and 1 <= n_el <= 1024.  Synchronises `stream`; returns the device
+ * error flag of any step (PIC_EDOMAIN). */
+pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                             int ckpt_every, const double w[4], void* d_adj_work,
+                             size_t adj_work_bytes, double* d_lam, const double* d_xi,
+                             double out_m[4], double* dJ_dk, double dJ_dL[36], void* stream);
 
 /* Beam statistics (paper: "beam statistics"): mean[6] and centred second moments cov[36]
  * (row-major, 1/n normalisation) of X.  Synchronises `stream`; PIC_EDOMAIN if the device

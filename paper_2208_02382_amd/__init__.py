@@ -59,6 +59,15 @@ _SIGS = {
     "pic_check": (_I, [_P, _P]),
     "pic_profile_start": (_I, [_P]),
     "pic_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
+    "pic_adjoint_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BeamDesc), _I, _I]),
+    "pic_track_adjoint": (_I, [_P, ctypes.POINTER(Element), _I, _I, _I, ctypes.POINTER(_D), _P,
+                               ctypes.c_size_t, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                               ctypes.POINTER(_D), _P]),
+    "pic_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I)]),
+    "pic_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(ctypes.POINTER(Element)),
+                              ctypes.POINTER(_I), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "pic_track_batch": (_I, [_P, _I, _P]),
+    "pic_batch_destroy": (_I, [_P]),
     "pic_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -202,7 +211,7 @@ class Beam:
 
     def track(self, lattice, n_steps):
         """lattice: sequence of (k, ds) pairs, cycled over the steps."""
-        arr = (Element * len(lattice))(*[Element(float(k), float(ds)) for k, ds in lattice])
+        arr = _lattice(lattice)
         _check(_lib.pic_track_n_steps(self._h, arr, len(lattice), int(n_steps), _stream()),
                "pic_track_n_steps")
 
@@ -217,6 +226,30 @@ class Beam:
         _check(_lib.pic_get_geometry(self._h, out, _stream()), "pic_get_geometry")
         return list(out[0:3]), list(out[3:6]), list(out[6:9])
 
+    def track_adjoint(self, lattice, n_steps, w, ckpt_every=10, xi=None):
+        """Reverse sweep from the current X (= X0): returns (m, dJ/dk, dJ/dX0, dJ/dL or None)
+        for J = w . (sigma_x, sigma_y, eps_x, eps_y); X holds the final state afterwards."""
+        n_el = len(lattice)
+        arr = (Element * n_el)(*[Element(float(k), float(ds)) for k, ds in lattice])
+        nbytes = int(_lib.pic_adjoint_workspace_bytes(ctypes.byref(self.desc), int(n_steps),
+                                                      int(ckpt_every)))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "pic_adjoint_workspace_bytes")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        lam = torch.empty((6, self.n), dtype=torch.float64, device=self.device)
+        wv = (ctypes.c_double * 4)(*[float(v) for v in w])
+        m = (ctypes.c_double * 4)()
+        dk = (ctypes.c_double * n_el)()
+        dL = (ctypes.c_double * 36)()
+        if xi is not None:
+            assert xi.dtype == torch.float64 and xi.is_contiguous() and tuple(xi.shape) == (6, self.n)
+        _check(_lib.pic_track_adjoint(self._h, arr, n_el, int(n_steps), int(ckpt_every), wv,
+                                      _ptr(work), nbytes, _ptr(lam), _ptr(xi), m, dk,
+                                      dL if xi is not None else None, _stream()),
+               "pic_track_adjoint")
+        dLm = [list(dL[r * 6:(r + 1) * 6]) for r in range(6)] if xi is not None else None
+        return list(m), list(dk), lam, dLm
+
     def profile_start(self):
         _check(_lib.pic_profile_start(self._h), "pic_profile_start")
 
@@ -229,3 +262,60 @@ class Beam:
 
     def check(self):
         return _lib.pic_check(self._h, _stream())
+
+
+def _lattice(lattice):
+    return (Element * len(lattice))(*[Element(float(k), float(ds)) for k, ds in lattice])
+
+
+class Batch:
+    """Independent beams tracked together: one launch per stage for all of them, the whole
+    step loop replayed from one HIP graph (captured on the first track() with a given step
+    count).  The beams share shape and grid precision; particle counts and grids may differ.
+    Runs on a stream of its own, ordered after and before torch's current stream."""
+
+    def __init__(self, beams, lattices):
+        if len(beams) != len(lattices) or not beams:
+            raise ValueError("one lattice per beam, at least one beam")
+        self.beams = list(beams)
+        self.device = self.beams[0].device
+        nb = len(self.beams)
+        self._lats = [_lattice(l) for l in lattices]
+        n_el = (_I * nb)(*[len(l) for l in lattices])
+        ptrs = (ctypes.POINTER(Element) * nb)(
+            *[ctypes.cast(a, ctypes.POINTER(Element)) for a in self._lats])
+        nbytes = int(_lib.pic_batch_workspace_bytes(nb, n_el))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "pic_batch_workspace_bytes")
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(self.device)
+        handles = (_P * nb)(*[b._h for b in self.beams])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            _check(_lib.pic_batch_create(handles, nb, ptrs, n_el, _ptr(self.work), nbytes,
+                                         ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(h)), "pic_batch_create")
+        self._h = h
+
+    def track(self, n_steps):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _check(_lib.pic_track_batch(self._h, int(n_steps), ctypes.c_void_p(self.stream.cuda_stream)),
+               "pic_track_batch")
+        cur.wait_stream(self.stream)
+
+    def check(self):
+        """Per-beam device status (pic_check), in beam order."""
+        return [b.check() for b in self.beams]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

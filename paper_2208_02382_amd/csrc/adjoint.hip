@@ -1,0 +1,361 @@
+// Reverse sweep (discrete adjoint) of the tracking loop.
+//
+// Gradients of J = w . (sigma_x, sigma_y, eps_x, eps_y) of the final beam with respect to the
+// thin-quad strengths, the initial coordinates and (given the draws xi of X0 = L xi) the
+// Cholesky factor L.  The grid geometry of every step is frozen to the forward run's.  Each
+// linear operation is replaced by its transpose:
+//   drift l          lam_px += l lam_x, lam_py += l lam_y, lam_delta += (l/gamma^2) lam_z
+//   thin quad k      lam_x -= k lam_px, lam_y += k lam_py;  dJ/dk += sum(-x lam_px + y lam_py)
+//   kick over L      a_i = (C L lam_px, C L lam_py, gamma C L lam_delta)
+//                    lam_r,i += sum_n grad W(r_i - r_n) (a_i . E'_n)            (k_adj_b, direct)
+//                    e = sum_i W a_i (vector deposit, k_adj_a); psi = -sum_c D_c^T e_c on nodes
+//                    -1..n (k_adj_div); chi = Gbar * psi / (4 pi eps0) on nodes 0..n-1
+//                    (transposed solve, fft.hip); lam_r,i += q_m sum_n grad W(r_i - r_n) chi_n
+// The kick-point positions are rebuilt from the stored step-start state with the same
+// expressions as the forward kernels (thin quad, then half drift).
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace pic {
+
+namespace {
+
+constexpr int kBlk = 256;
+
+// stencil weights and their derivatives d w / d u along one axis
+template <int S>
+__device__ __forceinline__ int stencil_d(double u, int n, double* w, double* dw) {
+  const int b = stencil<S>(u, n, w);
+  if constexpr (S == 1) {
+    dw[0] = -1.0;
+    dw[1] = 1.0;
+  } else {
+    const double d = u - floor(u + 0.5);
+    dw[0] = -(0.5 - d);
+    dw[1] = -2.0 * d;
+    dw[2] = 0.5 + d;
+  }
+  return b;
+}
+
+// kick-point position of a step-start state: thin quad k, then drift l = L/2 (positions only)
+__device__ __forceinline__ void kick_point(const double* __restrict__ X, int64_t n, int64_t i,
+                                          double k, double ell, double inv_g2, double r[3]) {
+  const double x = X[i], px = X[n + i], y = X[2 * n + i], py = X[3 * n + i];
+  const double z = X[4 * n + i], d = X[5 * n + i];
+  const double px1 = px - k * x, py1 = py + k * y;
+  r[0] = x + ell * px1;
+  r[1] = y + ell * py1;
+  r[2] = z + ell * d * inv_g2;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_global(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Pass A: lam <- drift_T(lam, L/2); e += W a at the kick point.
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
+                                                double* __restrict__ lam,
+                                                const Geom* __restrict__ g, Consts c, double k,
+                                                double L, T* __restrict__ e) {
+  if (g->status) return;
+  const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int64_t n = c.n;
+  const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
+  const double ell = 0.5 * L;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    double r[3];
+    kick_point(X, n, i, k, ell, c.inv_gamma2, r);
+    const double lpx = lam[n + i] + ell * lam[i];
+    const double lpy = lam[3 * n + i] + ell * lam[2 * n + i];
+    const double ld = lam[5 * n + i] + ell * lam[4 * n + i] * c.inv_gamma2;
+    lam[n + i] = lpx;
+    lam[3 * n + i] = lpy;
+    lam[5 * n + i] = ld;
+    const double a[3] = {c.C * L * lpx, c.C * L * lpy, c.gamma * c.C * L * ld};
+    double wx[S + 1], wy[S + 1], wz[S + 1];
+    const int bx = stencil<S>((r[0] - o[0]) * ih[0], c.nx, wx);
+    const int by = stencil<S>((r[1] - o[1]) * ih[1], c.ny, wy);
+    const int bz = stencil<S>((r[2] - o[2]) * ih[2], c.nz, wz);
+    for (int za = 0; za <= S; ++za)
+      for (int yb = 0; yb <= S; ++yb) {
+        const double wzy = wz[za] * wy[yb];
+        const int64_t row = ((int64_t)(bz + za) * c.ny + (by + yb)) * c.nx + bx;
+        for (int q = 0; q <= S; ++q) {
+          const double w = wzy * wx[q];
+          add_global(&e[row + q], (T)(w * a[0]));
+          add_global(&e[ng + row + q], (T)(w * a[1]));
+          add_global(&e[2 * ng + row + q], (T)(w * a[2]));
+        }
+      }
+  }
+}
+
+// psi on nodes -1..n ([(nz+2)][(ny+2)][(nx+2)]) = sum_c (e_c(m + 1_c) - e_c(m - 1_c)) / (2 h_c),
+// e_c = 0 outside nodes 0..n-1 (rest-frame spacings).
+template <typename T>
+__global__ __launch_bounds__(kBlk) void k_adj_div(const Geom* __restrict__ g,
+                                                  const T* __restrict__ e, T* __restrict__ psi,
+                                                  int nx, int ny, int nz) {
+  if (g->status) return;
+  const int px = nx + 2, py = ny + 2, pz = nz + 2;
+  const int64_t total = (int64_t)px * py * pz;
+  const int64_t ng = (int64_t)nx * ny * nz;
+  const double cx = 1.0 / (2.0 * g->h_rest[0]);
+  const double cy = 1.0 / (2.0 * g->h_rest[1]);
+  const double cz = 1.0 / (2.0 * g->h_rest[2]);
+  for (int64_t t = blockIdx.x * (int64_t)kBlk + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kBlk) {
+    const int i = (int)(t % px) - 1, j = (int)((t / px) % py) - 1, k = (int)(t / ((int64_t)px * py)) - 1;
+    auto at = [&](int comp, int ii, int jj, int kk) -> double {
+      if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) return 0.0;
+      return (double)e[comp * ng + ((int64_t)kk * ny + jj) * nx + ii];
+    };
+    const double v = (at(0, i + 1, j, k) - at(0, i - 1, j, k)) * cx +
+                     (at(1, i, j + 1, k) - at(1, i, j - 1, k)) * cy +
+                     (at(2, i, j, k + 1) - at(2, i, j, k - 1)) * cz;
+    psi[t] = (T)v;
+  }
+}
+
+// Pass B: lam_r += sum grad W (a . E') + q sum grad W chi at the kick point; lam <- drift_T(L/2);
+// dk partial += sum(-x lam_px + y lam_py) at the step start; lam <- quad_T(k).
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
+                                                double* __restrict__ lam,
+                                                const Geom* __restrict__ g, Consts c, double k,
+                                                double L, const T* __restrict__ E,
+                                                const T* __restrict__ chi,
+                                                double* __restrict__ dk_partial) {
+  __shared__ double sh[kBlk / 64];
+  double acc = 0.0;
+  if (g->status == 0) {
+    const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+    const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+    const int64_t n = c.n;
+    const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
+    const double ell = 0.5 * L;
+    for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlk) {
+      double r[3];
+      kick_point(X, n, i, k, ell, c.inv_gamma2, r);
+      double lm[6];
+      for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
+      const double a[3] = {c.C * L * lm[1], c.C * L * lm[3], c.gamma * c.C * L * lm[5]};
+      double wx[S + 1], wy[S + 1], wz[S + 1], dx[S + 1], dy[S + 1], dz[S + 1];
+      const int bx = stencil_d<S>((r[0] - o[0]) * ih[0], c.nx, wx, dx);
+      const int by = stencil_d<S>((r[1] - o[1]) * ih[1], c.ny, wy, dy);
+      const int bz = stencil_d<S>((r[2] - o[2]) * ih[2], c.nz, wz, dz);
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      for (int za = 0; za <= S; ++za)
+        for (int yb = 0; yb <= S; ++yb) {
+          const int64_t row = ((int64_t)(bz + za) * c.ny + (by + yb)) * c.nx + bx;
+          for (int q = 0; q <= S; ++q) {
+            const int64_t node = row + q;
+            const double s = a[0] * (double)E[node] + a[1] * (double)E[ng + node] +
+                             a[2] * (double)E[2 * ng + node] + c.q_macro * (double)chi[node];
+            gx += (dx[q] * ih[0]) * wy[yb] * wz[za] * s;
+            gy += wx[q] * (dy[yb] * ih[1]) * wz[za] * s;
+            gz += wx[q] * wy[yb] * (dz[za] * ih[2]) * s;
+          }
+        }
+      lm[0] += gx;
+      lm[2] += gy;
+      lm[4] += gz;
+      // transposed first half drift
+      lm[1] += ell * lm[0];
+      lm[3] += ell * lm[2];
+      lm[5] += ell * lm[4] * c.inv_gamma2;
+      // strength gradient with the step-start positions, then the transposed thin quad
+      const double x = X[i], y = X[2 * n + i];
+      acc += -x * lm[1] + y * lm[3];
+      lm[0] -= k * lm[1];
+      lm[2] += k * lm[3];
+      for (int q = 0; q < 6; ++q) lam[q * n + i] = lm[q];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kBlk / 64; ++q) s += sh[q];
+    dk_partial[blockIdx.x] = s;
+  }
+}
+
+// dk[slot] += sum of the per-block partials (in block order)
+__global__ void k_adj_dk_combine(const double* __restrict__ partial, int nblocks,
+                                 double* __restrict__ dk, int slot) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b];
+  dk[slot] += s;
+}
+
+// lam = dJ/dX of J = w . (sigma_x, sigma_y, eps_x, eps_y); mom = [mean 6][cov upper 21]
+struct Weights {
+  double w[4];
+};
+
+__global__ __launch_bounds__(kBlk) void k_obj_grad(const double* __restrict__ X, int64_t n,
+                                                   const double* __restrict__ mom, Weights wt,
+                                                   double* __restrict__ lam,
+                                                   double* __restrict__ out_m) {
+  // covariance entries (upper triangle, row-major over a <= b)
+  auto cov = [&](int a, int b) {
+    if (a > b) {
+      int t = a;
+      a = b;
+      b = t;
+    }
+    int q = 0;
+    for (int r = 0; r < a; ++r) q += 6 - r;
+    return mom[6 + q + (b - a)];
+  };
+  const double Sxx = cov(0, 0), Sxp = cov(0, 1), Spp = cov(1, 1);
+  const double Syy = cov(2, 2), Syq = cov(2, 3), Sqq = cov(3, 3);
+  const double sx = sqrt(Sxx), sy = sqrt(Syy);
+  const double ex = sqrt(Sxx * Spp - Sxp * Sxp), ey = sqrt(Syy * Sqq - Syq * Syq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out_m[0] = sx;
+    out_m[1] = sy;
+    out_m[2] = ex;
+    out_m[3] = ey;
+  }
+  const double inv_n = 1.0 / (double)n;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    const double dxv = X[i] - mom[0], dpx = X[n + i] - mom[1];
+    const double dyv = X[2 * n + i] - mom[2], dpy = X[3 * n + i] - mom[3];
+    lam[i] = wt.w[0] * dxv * inv_n / sx + wt.w[2] * (Spp * dxv - Sxp * dpx) * inv_n / ex;
+    lam[n + i] = wt.w[2] * (Sxx * dpx - Sxp * dxv) * inv_n / ex;
+    lam[2 * n + i] = wt.w[1] * dyv * inv_n / sy + wt.w[3] * (Sqq * dyv - Syq * dpy) * inv_n / ey;
+    lam[3 * n + i] = wt.w[3] * (Syy * dpy - Syq * dyv) * inv_n / ey;
+    lam[4 * n + i] = 0.0;
+    lam[5 * n + i] = 0.0;
+  }
+}
+
+// partial[b][36] = per-block sums of lam_a xi_b (dJ/dL = lam0 xi^T)
+__global__ __launch_bounds__(kBlk) void k_dL(const double* __restrict__ lam,
+                                             const double* __restrict__ xi, int64_t n,
+                                             double* __restrict__ partial) {
+  __shared__ double sh[kBlk / 64];
+  double s[36];
+  for (int q = 0; q < 36; ++q) s[q] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    double l[6], x[6];
+    for (int r = 0; r < 6; ++r) {
+      l[r] = lam[r * n + i];
+      x[r] = xi[r * n + i];
+    }
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) s[a * 6 + b] += l[a] * x[b];
+  }
+  for (int q = 0; q < 36; ++q) {
+    double v = s[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBlk / 64; ++w) t += sh[w];
+      partial[blockIdx.x * 36 + q] = t;
+    }
+  }
+}
+
+__global__ void k_dL_combine(const double* __restrict__ partial, int nblocks,
+                             double* __restrict__ out) {
+  const int q = threadIdx.x;
+  if (q >= 36) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * 36 + q];
+  out[q] = s;
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + kBlk - 1) / kBlk;
+  if (b > kAdjBlocks) b = kAdjBlocks;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, double k,
+                        double L, T* e, hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_adj_a<1, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
+  else
+    hipLaunchKernelGGL((k_adj_a<2, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int nz,
+                          hipStream_t s) {
+  const int64_t total = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+  hipLaunchKernelGGL((k_adj_div<T>), dim3(grid_for(total)), dim3(kBlk), 0, s, g, e, psi, nx, ny,
+                     nz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, double k, double L,
+                        const T* E, const T* chi, double* dk_partial, double* dk, int slot,
+                        hipStream_t s) {
+  const int nb = grid_for(c.n);
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_adj_b<1, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, k, L, E, chi,
+                       dk_partial);
+  else
+    hipLaunchKernelGGL((k_adj_b<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, k, L, E, chi,
+                       dk_partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
+                           double* lam, double* out_m, hipStream_t s) {
+  Weights wt;
+  for (int q = 0; q < 4; ++q) wt.w[q] = w[q];
+  hipLaunchKernelGGL(k_obj_grad, dim3(grid_for(n)), dim3(kBlk), 0, s, X, n, mom, wt, lam, out_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* partial, double* out,
+                     hipStream_t s) {
+  const int nb = grid_for(n);
+  hipLaunchKernelGGL(k_dL, dim3(nb), dim3(kBlk), 0, s, lam, xi, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dL_combine, dim3(1), dim3(64), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adj_a<double>(const double*, double*, const Geom*, Consts, double,
+                                         double, double*, hipStream_t);
+template hipError_t launch_adj_a<float>(const double*, double*, const Geom*, Consts, double,
+                                        double, float*, hipStream_t);
+template hipError_t launch_adj_div<double>(const Geom*, const double*, double*, int, int, int,
+                                           hipStream_t);
+template hipError_t launch_adj_div<float>(const Geom*, const float*, float*, int, int, int,
+                                          hipStream_t);
+template hipError_t launch_adj_b<double>(const double*, double*, const Geom*, Consts, double,
+                                         double, const double*, const double*, double*, double*,
+                                         int, hipStream_t);
+template hipError_t launch_adj_b<float>(const double*, double*, const Geom*, Consts, double, double,
+                                        const float*, const float*, double*, double*, int,
+                                        hipStream_t);
+
+}  // namespace pic

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -283,7 +284,184 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
   return PIC_OK;
 }
 
+// ---- reverse sweep workspace (caller-owned, see pic_adjoint_workspace_bytes)
+struct AdjLayout {
+  size_t geoms, ckpt, segX, segE, segG, e, psi, chi, dk, dk_part, dL_part, small, total;
+  int nseg;
+};
+
+constexpr size_t kGeomSlot = 128;  // bytes per stored per-step geometry
+
+AdjLayout adj_layout(const pic_beam_desc* d, int n_steps, int ck) {
+  AdjLayout A;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t es = d->grid_fp32 ? 4 : 8;
+  const size_t n = (size_t)d->n, nx = d->nx, ny = d->ny, nz = d->nz;
+  const size_t ng = nx * ny * nz, G3 = (nx + 1) * (ny + 1) * (nz + 1);
+  A.nseg = (n_steps + ck - 1) / ck;
+  A.geoms = take(kGeomSlot * (size_t)n_steps);
+  A.ckpt = take(6 * sizeof(double) * n * (size_t)A.nseg);
+  A.segX = take(6 * sizeof(double) * n * (size_t)ck);
+  A.segE = take(3 * es * ng * (size_t)ck);
+  A.segG = take(es * G3 * (size_t)ck);
+  A.e = take(3 * es * ng);
+  A.psi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
+  A.chi = take(es * ng);
+  A.dk = take(sizeof(double) * kMaxLattice);
+  A.dk_part = take(sizeof(double) * kAdjBlocks);
+  A.dL_part = take(sizeof(double) * 36 * kAdjBlocks);
+  A.small = take(sizeof(double) * 64);  // out moments (4) and dJ/dL (36)
+  A.total = off;
+  static_assert(sizeof(Geom) <= kGeomSlot, "geometry slot too small");
+  return A;
+}
+
+template <typename T>
+pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_element& e,
+                               T* gh, T* E, hipStream_t s, Box* box) {
+  // thin quad + half drift (with the box when a geometry is to be computed), deposit, Green
+  // spectrum, solve, kick + half drift; g is the step's geometry slot
+  const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
+  HIP_OK(launch_quad_drift(X, e.k, 0.5 * e.ds, b->c, box, s), "adjoint forward");
+  if (box) HIP_OK(launch_geometry(box, const_cast<Geom*>(g), b->c, s), "adjoint forward");
+  HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "adjoint forward");
+  HIP_OK(launch_deposit<T>(X, g, (T*)b->rho, b->c, s), "adjoint forward");
+  HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh, s),
+         "adjoint forward");
+  HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
+                         (T*)b->phi, E, s),
+         "adjoint forward");
+  HIP_OK(launch_gkd<T>(X, g, E, e.ds, 0, 0.0, 0.0, b->c, box, s), "adjoint forward");
+  return PIC_OK;
+}
+
+template <typename T>
+pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_steps, int ck,
+                         const double w[4], char* aw, const AdjLayout& A, double* lam,
+                         const double* xi, double out_m[4], double* dJ_dk, double dJ_dL[36],
+                         hipStream_t s) {
+  const size_t n = (size_t)b->d.n;
+  const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
+  const size_t G3 = (size_t)(b->d.nx + 1) * (b->d.ny + 1) * (b->d.nz + 1);
+  auto geom = [&](int j) { return (Geom*)(aw + A.geoms + kGeomSlot * (size_t)j); };
+  double* ckpt = (double*)(aw + A.ckpt);
+  double* segX = (double*)(aw + A.segX);
+  T* segE = (T*)(aw + A.segE);
+  T* segG = (T*)(aw + A.segG);
+  T* e = (T*)(aw + A.e);
+  T* psi = (T*)(aw + A.psi);
+  T* chi = (T*)(aw + A.chi);
+  double* dk = (double*)(aw + A.dk);
+  double* small = (double*)(aw + A.small);
+  HIP_OK(launch_zero<uint32_t>((uint32_t*)(aw + A.geoms), (int64_t)(kGeomSlot / 4) * n_steps, s),
+         "adjoint setup");
+  HIP_OK(launch_zero<double>(dk, kMaxLattice, s), "adjoint setup");
+  // forward: checkpoints at segment starts, geometry of every step kept
+  for (int j = 0; j < n_steps; ++j) {
+    if (j % ck == 0)
+      HIP_OK(hipMemcpyAsync(ckpt + 6 * n * (size_t)(j / ck), b->X, 6 * sizeof(double) * n,
+                            hipMemcpyDeviceToDevice, s),
+             "adjoint checkpoint");
+    HIP_OK(launch_box_reset(b->box, s), "adjoint forward");
+    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), lat[j % n_el], (T*)b->Gh, (T*)b->E,
+                                           s, b->box);
+    if (st != PIC_OK) return st;
+  }
+  HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "adjoint objective");
+  HIP_OK(launch_obj_grad(b->X, b->d.n, b->mom_out, w, lam, small, s), "adjoint objective");
+  // reverse, one checkpoint segment at a time
+  double* XW = b->XA;
+  for (int seg = A.nseg - 1; seg >= 0; --seg) {
+    const int c0 = seg * ck, c1 = std::min(c0 + ck, n_steps);
+    HIP_OK(hipMemcpyAsync(XW, ckpt + 6 * n * (size_t)seg, 6 * sizeof(double) * n,
+                          hipMemcpyDeviceToDevice, s),
+           "adjoint recompute");
+    for (int j = c0; j < c1; ++j) {
+      const int q = j - c0;
+      HIP_OK(hipMemcpyAsync(segX + 6 * n * (size_t)q, XW, 6 * sizeof(double) * n,
+                            hipMemcpyDeviceToDevice, s),
+             "adjoint recompute");
+      pic_status st = forward_step_frozen<T>(b, XW, geom(j), lat[j % n_el], segG + G3 * (size_t)q,
+                                             segE + 3 * ng * (size_t)q, s, nullptr);
+      if (st != PIC_OK) return st;
+    }
+    for (int j = c1 - 1; j >= c0; --j) {
+      const int q = j - c0;
+      const pic_element& el = lat[j % n_el];
+      const double* Xs = segX + 6 * n * (size_t)q;
+      HIP_OK(launch_zero<T>(e, 3 * ng, s), "adjoint");
+      HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el.k, el.ds, e, s), "adjoint");
+      HIP_OK(launch_adj_div<T>(geom(j), e, psi, b->d.nx, b->d.ny, b->d.nz, s), "adjoint");
+      HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi, b->W,
+                                          segG + G3 * (size_t)q, chi, s),
+             "adjoint");
+      HIP_OK(launch_adj_b<T>(Xs, lam, geom(j), b->c, el.k, el.ds, segE + 3 * ng * (size_t)q, chi,
+                             (double*)(aw + A.dk_part), dk, j % n_el, s),
+             "adjoint");
+    }
+  }
+  if (xi)
+    HIP_OK(launch_dL(lam, xi, b->d.n, (double*)(aw + A.dL_part), small + 4, s), "adjoint dL");
+  // results and the error flags of every step
+  double host_small[40];
+  HIP_OK(hipMemcpyAsync(host_small, small, sizeof(host_small), hipMemcpyDeviceToHost, s),
+         "adjoint results");
+  HIP_OK(hipMemcpyAsync(dJ_dk, dk, sizeof(double) * n_el, hipMemcpyDeviceToHost, s),
+         "adjoint results");
+  std::vector<unsigned char> gbuf(kGeomSlot * (size_t)n_steps);
+  HIP_OK(hipMemcpyAsync(gbuf.data(), aw + A.geoms, gbuf.size(), hipMemcpyDeviceToHost, s),
+         "adjoint results");
+  HIP_OK(hipStreamSynchronize(s), "adjoint results");
+  for (int q = 0; q < 4; ++q) out_m[q] = host_small[q];
+  if (xi && dJ_dL)
+    for (int q = 0; q < 36; ++q) dJ_dL[q] = host_small[4 + q];
+  for (int j = 0; j < n_steps; ++j) {
+    const Geom* gj = (const Geom*)(gbuf.data() + kGeomSlot * (size_t)j);
+    if (gj->status) return device_status(gj->status);
+  }
+  return PIC_OK;
+}
+
+// ---- batches of beams tracked by one graph launch
+template <typename T>
+pic_status enqueue_batch(const BeamDev* tab, int nb, const BatchDims& bd, int shape, int n_steps,
+                         hipStream_t s) {
+  HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
+  HIP_OK(launch_batch_prologue_particles(tab, nb, bd, s), "batch");
+  for (int j = 0; j < n_steps; ++j) {
+    const int parity = j & 1;
+    HIP_OK(launch_batch_geometry(tab, nb, s), "batch");
+    HIP_OK(launch_batch_zero_rho<T>(tab, nb, bd, s), "batch");
+    HIP_OK(launch_batch_particles_bin(tab, nb, bd, shape, parity, s), "batch");
+    HIP_OK(launch_batch_deposit<T>(tab, nb, bd, shape, parity, s), "batch");
+    HIP_OK(launch_batch_green<T>(tab, nb, bd, s), "batch");
+    HIP_OK(launch_batch_solve<T>(tab, nb, bd, s), "batch");
+    if (j + 1 < n_steps) HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
+    HIP_OK(launch_batch_gkd<T>(tab, nb, bd, shape, parity, j, n_steps, s), "batch");
+  }
+  HIP_OK(launch_batch_unpermute(tab, nb, bd, n_steps & 1, s), "batch");
+  return PIC_OK;
+}
+
 }  // namespace
+
+struct pic_batch_s {
+  int nb = 0;
+  int shape = 1;
+  int fp32 = 0;
+  std::vector<pic_beam> beams;
+  BeamDev* table = nullptr;  // device, in the caller's batch workspace
+  BatchDims bd;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;  // one instantiated graph per step count
+  ~pic_batch_s() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  }
+};
 
 extern "C" {
 
@@ -503,6 +681,171 @@ pic_status pic_get_geometry(pic_beam b, double out[9], void* stream) {
     out[6 + a] = g.h_rest[a];
   }
   return device_status(g.status);
+}
+
+size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt_every) {
+  if (check_desc(d) != PIC_OK || n_steps < 1 || ckpt_every < 1) return 0;
+  return adj_layout(d, n_steps, ckpt_every).total;
+}
+
+pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                             int ckpt_every, const double w[4], void* d_adj_work,
+                             size_t adj_work_bytes, double* d_lam, const double* d_xi,
+                             double out_m[4], double* dJ_dk, double dJ_dL[36], void* stream) {
+  if (!b || !lattice || !w || !d_adj_work || !d_lam || !out_m || !dJ_dk)
+    return fail(PIC_EINVAL, "NULL argument");
+  if (n_el < 1 || n_el > kMaxLattice || n_steps < 1 || ckpt_every < 1)
+    return fail(PIC_EINVAL, "need 1 <= n_el <= 1024, n_steps >= 1, ckpt_every >= 1");
+  if (!b->d.space_charge) return fail(PIC_EINVAL, "the reverse sweep needs space_charge = 1");
+  if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
+  if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
+  for (int q = 0; q < n_el; ++q)
+    if (!std::isfinite(lattice[q].k) || !std::isfinite(lattice[q].ds))
+      return fail(PIC_EINVAL, "non-finite lattice element");
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(w[q])) return fail(PIC_EINVAL, "non-finite objective weight");
+  AdjLayout A = adj_layout(&b->d, n_steps, ckpt_every);
+  if (adj_work_bytes < A.total)
+    return fail(PIC_ENOMEM, "reverse-sweep workspace smaller than pic_adjoint_workspace_bytes");
+  hipStream_t s = S(stream);
+  if (b->d.grid_fp32)
+    return track_adjoint<float>(b, lattice, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
+                                d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);
+  return track_adjoint<double>(b, lattice, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
+                               d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);
+}
+
+size_t pic_batch_workspace_bytes(int n_beams, const int* n_el) {
+  if (n_beams < 1 || !n_el) return 0;
+  size_t lat = 0;
+  for (int b = 0; b < n_beams; ++b) {
+    if (n_el[b] < 1) return 0;
+    lat += 2 * sizeof(double) * (size_t)n_el[b];
+  }
+  return align256(sizeof(BeamDev) * (size_t)n_beams) + align256(lat);
+}
+
+pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
+                            const int* n_el, void* d_work, size_t work_bytes, void* stream,
+                            pic_batch* out) {
+  if (!out) return fail(PIC_EINVAL, "NULL output handle");
+  *out = nullptr;
+  if (!beams || !lattices || !n_el || !d_work || n_beams < 1)
+    return fail(PIC_EINVAL, "NULL argument or no beams");
+  if ((uintptr_t)d_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = pic_batch_workspace_bytes(n_beams, n_el);
+  if (need == 0) return fail(PIC_EINVAL, "every beam needs a lattice of >= 1 element");
+  if (work_bytes < need) return fail(PIC_ENOMEM, "batch workspace smaller than pic_batch_workspace_bytes");
+  const int shape = beams[0] ? beams[0]->d.shape : 0;
+  const int fp32 = beams[0] ? beams[0]->d.grid_fp32 : 0;
+  BatchDims bd{};
+  std::vector<BeamDev> tab(n_beams);
+  std::vector<double> lat;
+  std::vector<size_t> lat_off(n_beams);
+  for (int b = 0; b < n_beams; ++b) {
+    pic_beam h = beams[b];
+    if (!h || !lattices[b]) return fail(PIC_EINVAL, "NULL beam or lattice");
+    if (h->d.shape != shape || h->d.grid_fp32 != fp32 || !h->d.space_charge)
+      return fail(PIC_EINVAL, "beams of a batch share shape and grid precision and need space charge");
+    const size_t es = fp32 ? 4 : 8;
+    const size_t win = es * (size_t)(h->sp.T[0] + shape) * (h->sp.T[1] + shape) * (h->sp.T[2] + shape);
+    if (3 * win > 65536) return fail(PIC_EUNSUPPORTED, "tile window of a batched beam exceeds 64 KB");
+    bd.max_n = std::max<int64_t>(bd.max_n, h->d.n);
+    bd.max_nx = std::max(bd.max_nx, h->d.nx);
+    bd.max_ny = std::max(bd.max_ny, h->d.ny);
+    bd.max_nz = std::max(bd.max_nz, h->d.nz);
+    bd.dep_lds = std::max(bd.dep_lds, win);
+    bd.gkd_lds = std::max(bd.gkd_lds, 3 * win);
+    lat_off[b] = lat.size();
+    for (int q = 0; q < n_el[b]; ++q) {
+      if (!std::isfinite(lattices[b][q].k) || !std::isfinite(lattices[b][q].ds))
+        return fail(PIC_EINVAL, "non-finite lattice element");
+      lat.push_back(lattices[b][q].k);
+    }
+    for (int q = 0; q < n_el[b]; ++q) lat.push_back(lattices[b][q].ds);
+    BeamDev& d = tab[b];
+    d.c = h->c;
+    d.sp = h->sp;
+    d.plan = h->plan;
+    d.X = h->X;
+    d.XA = h->XA;
+    d.XB = h->XB;
+    d.idA = h->idA;
+    d.idB = h->idB;
+    d.keys = h->keys;
+    d.hist = h->hist;
+    d.cursor = h->cursor;
+    d.chunks = h->chunks;
+    d.nchunks = h->nchunks;
+    d.geom = h->geom;
+    d.box = h->box;
+    d.rho = h->rho;
+    d.phi = h->phi;
+    d.E = h->E;
+    d.W = h->W;
+    d.Gd = h->Gd;
+    d.Gh = h->Gh;
+    d.corners = h->corners;
+    d.n_el = n_el[b];
+  }
+  // per-beam work-list blocks of the tiled kernels: the blocks of a beam stride over its chunks
+  bd.max_chunks = 256;
+  char* w = (char*)d_work;
+  BeamDev* dtab = (BeamDev*)w;
+  double* dlat = (double*)(w + align256(sizeof(BeamDev) * (size_t)n_beams));
+  for (int b = 0; b < n_beams; ++b) {
+    tab[b].lat_k = dlat + lat_off[b];
+    tab[b].lat_ds = dlat + lat_off[b] + n_el[b];
+  }
+  hipStream_t s = S(stream);
+  HIP_OK(hipMemcpyAsync(dtab, tab.data(), sizeof(BeamDev) * tab.size(), hipMemcpyHostToDevice, s),
+         "batch create");
+  HIP_OK(hipMemcpyAsync(dlat, lat.data(), sizeof(double) * lat.size(), hipMemcpyHostToDevice, s),
+         "batch create");
+  HIP_OK(hipStreamSynchronize(s), "batch create");
+  pic_batch bt = new (std::nothrow) pic_batch_s;
+  if (!bt) return fail(PIC_EINVAL, "host allocation of the batch handle failed");
+  bt->nb = n_beams;
+  bt->shape = shape;
+  bt->fp32 = fp32;
+  bt->beams.assign(beams, beams + n_beams);
+  bt->table = dtab;
+  bt->bd = bd;
+  *out = bt;
+  return PIC_OK;
+}
+
+pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream) {
+  if (!bt) return fail(PIC_EINVAL, "NULL batch");
+  if (n_steps < 1) return fail(PIC_EINVAL, "n_steps must be >= 1");
+  if (!stream) return fail(PIC_EINVAL, "a batch is captured into a graph: pass a non-null stream");
+  hipStream_t s = S(stream);
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : bt->graphs)
+    if (g.first == n_steps) exec = g.second;
+  if (!exec) {
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "batch capture");
+    pic_status st = bt->fp32 ? enqueue_batch<float>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s)
+                             : enqueue_batch<double>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != PIC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail_hip(e, "batch capture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(e, "batch graph instantiation");
+    bt->graphs.emplace_back(n_steps, exec);
+  }
+  HIP_OK(hipGraphLaunch(exec, s), "batch graph launch");
+  return PIC_OK;
+}
+
+pic_status pic_batch_destroy(pic_batch bt) {
+  delete bt;
+  return PIC_OK;
 }
 
 pic_status pic_profile_start(pic_beam b) {

@@ -134,6 +134,19 @@ __device__ void fft_lds(Cx<T>* buf, int LB, const FftAxis& ax,
 
 // cyclic index of the ghost-inclusive position p = 0..n+1 (node p - 1): M - 1 for p = 0
 __device__ __forceinline__ int ghost_src(int p, int M) { return p == 0 ? M - 1 : p - 1; }
+
+// Two uses of the same passes.  MODE 0 (Poisson solve): the source lives on nodes 0..n-1 and
+// the result is kept on nodes -1..n.  MODE 1 (transposed solve of the reverse sweep): the
+// source lives on nodes -1..n (node -1 at cyclic index M - 1) and the result is kept on nodes
+// 0..n-1.  Both are exact: every source-to-output offset lies in [-n, n].
+template <int MODE>
+__device__ __forceinline__ bool src_nonzero(int p, int n, int M) {
+  return MODE == 0 ? p < n : (p <= n || p == M - 1);
+}
+template <int MODE>
+__device__ __forceinline__ int out_count(int n) { return MODE == 0 ? n + 2 : n; }
+template <int MODE>
+__device__ __forceinline__ int out_src(int q, int M) { return MODE == 0 ? ghost_src(q, M) : q; }
 __device__ __forceinline__ int fold(int k, int M) { return k <= M / 2 ? k : M - k; }
 
 // ------------------------------------------------------------------------------ Green spectrum
@@ -142,15 +155,15 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M / 2 ? k : M - 
 // line values g_0..g_n are extended to length M = 2n by g_t = g_{M-t}, transformed, and the
 // real outputs k = 0..n stored.  Complex line c carries real lines a = 2c (real part) and
 // a = 2c + 1 (imaginary part); line a starts at a*sa + b*sb, elements at stride st.
-__global__ __launch_bounds__(1024) void k_green_even_dft(double* __restrict__ gd, FftAxis ax,
+__device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, FftAxis ax,
                                                          const double2* __restrict__ tw,
                                                          int64_t st, int64_t sa, int64_t sb,
-                                                         int na, int LB) {
+                                                         int na, int LB, int bx, int by, int nbx) {
   extern __shared__ unsigned char smem_raw[];
   Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem_raw);
   const int M = ax.M, n = M / 2;
-  const int c0 = blockIdx.x * LB;  // first complex line of this block
-  double* base = gd + (int64_t)blockIdx.y * sb;
+  const int c0 = bx * LB;  // first complex line of this block
+  double* base = gd + (int64_t)by * sb;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;  // consecutive threads: consecutive lines
     const int t = p <= n ? p : M - p;
@@ -170,109 +183,161 @@ __global__ __launch_bounds__(1024) void k_green_even_dft(double* __restrict__ gd
   }
 }
 
+__global__ __launch_bounds__(1024) void k_green_even_dft(double* __restrict__ gd, FftAxis ax,
+                                                         const double2* __restrict__ tw,
+                                                         int64_t st, int64_t sa, int64_t sb,
+                                                         int na, int LB) {
+  green_even_dft_body(gd, ax, tw, st, sa, sb, na, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void green_finish_body(const Geom* __restrict__ g,
+                                                      const double* __restrict__ gd,
+                                                      T* __restrict__ gh, int64_t total,
+                                                      double scale, int bx, int by, int nbx) {
+  if (g->status) return;
+  for (int64_t t = bx * 256ll + threadIdx.x; t < total; t += (int64_t)nbx * 256)
+    gh[t] = (T)(gd[t] * scale);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_green_finish(const Geom* __restrict__ g,
                                                       const double* __restrict__ gd,
                                                       T* __restrict__ gh, int64_t total,
                                                       double scale) {
-  if (g->status) return;
-  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256)
-    gh[t] = (T)(gd[t] * scale);
+  green_finish_body<T>(g, gd, gh, total, scale, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ------------------------------------------------------------------------------ solve passes
 
-// Forward real transform of the charge rows: row (y, z) of rho (length n_x, zero-padded to
-// M_x = 2 n_x) -> W[z][y][0..n_x].  Packed z_j = rho_{2j} + i rho_{2j+1}, j < n_x, complex FFT
-// of length n_x (ax), then X_k = E_k + W^k O_k, E_k = (Z_k + conj Z_{n-k})/2,
-// O_k = (Z_k - conj Z_{n-k})/(2i), W = exp(-2 pi i / M_x), k = 0..n_x.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_r2c_x(const Geom* __restrict__ g,
-                                                const T* __restrict__ rho, Cx<T>* __restrict__ W,
+// Forward real transform of the source rows into the half spectrum W[z][y][0..n_x], z and y
+// cyclic.  MODE 0: rows (y < n_y, z < n_z) of the charge src[z][y][x] (length n_x).  MODE 1:
+// rows (yy < n_y + 2, zz < n_z + 2) of the ghost-inclusive source src[zz][yy][xx]
+// (length n_x + 2, node xx - 1), stored at cyclic rows (ghost_src(zz), ghost_src(yy)).
+// Packed z_j = x_{2j} + i x_{2j+1}, j < n_x, complex FFT of length n_x (ax), then
+// X_k = E_k + W^k O_k, E_k = (Z_k + conj Z_{n-k})/2, O_k = (Z_k - conj Z_{n-k})/(2i),
+// W = exp(-2 pi i / M_x), k = 0..n_x.
+template <typename T, int MODE>
+__device__ __forceinline__ void r2c_x_body(const Geom* __restrict__ g,
+                                                const T* __restrict__ src, Cx<T>* __restrict__ W,
                                                 FftAxis ax, const typename TwT<T>::type* __restrict__ tw,
-                                                int nx, int ny, int Kx, int My, int LB) {
+                                                int nx, int ny, int nz, int Kx, int My, int LB, int bx, int by, int nbx) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
   if (g->status) return;
   const int H = ax.M;  // = nx
-  const int y0 = blockIdx.x * LB, z = blockIdx.y;
-  const int nl = min(LB, ny - y0);
-  const T* src = rho + ((int64_t)z * ny + y0) * nx;
+  const int M = 2 * H;
+  const int rows = MODE == 0 ? ny : ny + 2;
+  const int len = MODE == 0 ? nx : nx + 2;
+  const int y0 = bx * LB, z = by;
+  const int nl = min(LB, rows - y0);
+  const T* s0 = src + ((int64_t)z * rows + y0) * len;
   for (int idx = threadIdx.x; idx < LB * H; idx += blockDim.x) {
     const int l = idx / H, j = idx - l * H;
     Cx<T> v = {0, 0};
-    if (l < nl && 2 * j < nx) {
-      v.x = src[(int64_t)l * nx + 2 * j];
-      v.y = 2 * j + 1 < nx ? src[(int64_t)l * nx + 2 * j + 1] : T(0);
+    if (l < nl) {
+      const T* row = s0 + (int64_t)l * len;
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int t = 2 * j + h2;  // cyclic position
+        T val = 0;
+        if (MODE == 0) {
+          if (t < nx) val = row[t];
+        } else {
+          if (t <= nx) val = row[t + 1];
+          else if (t == M - 1) val = row[0];
+        }
+        if (h2 == 0) v.x = val;
+        else v.y = val;
+      }
     }
     buf[l * H + j] = v;
   }
   __syncthreads();
   fft_lds<T, -1>(buf, LB, ax, tw, 2);
-  Cx<T>* dst = W + ((int64_t)z * My + y0) * Kx;
+  const int cz = MODE == 0 ? z : ghost_src(z, 2 * nz);
   for (int idx = threadIdx.x; idx < LB * (H + 1); idx += blockDim.x) {
     const int l = idx / (H + 1), k = idx - l * (H + 1);
     if (l >= nl) continue;
+    const int cy = MODE == 0 ? y0 + l : ghost_src(y0 + l, My);
     const Cx<T> zk = buf[l * H + (k % H)];
     const Cx<T> zc = cconj(buf[l * H + ((H - k) % H)]);
     const Cx<T> e = {(T)0.5 * (zk.x + zc.x), (T)0.5 * (zk.y + zc.y)};
     const Cx<T> dif = csub(zk, zc);
     const Cx<T> o = {(T)0.5 * dif.y, (T)-0.5 * dif.x};  // dif / (2i)
     const auto w = tw[k];                              // exp(-2 pi i k / M_x)
-    dst[(int64_t)l * Kx + k] = cadd(e, cmul(Cx<T>{(T)w.x, (T)w.y}, o));
+    W[((int64_t)cz * My + cy) * Kx + k] = cadd(e, cmul(Cx<T>{(T)w.x, (T)w.y}, o));
   }
 }
 
-// Complex line FFT in place along y (element stride Kx) for lines a = kx (stride 1) and
-// b = plane (stride My Kx).  Inputs p < n_in are read (the rest are zero); GHOST stores only the
-// positions q = 0..n+1 taken from cyclic index ghost_src(q), otherwise all M outputs.
-template <typename T, int DIR, bool GHOST>
-__global__ __launch_bounds__(1024) void k_c2c_y(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_r2c_x(const Geom* __restrict__ g,
+                                                const T* __restrict__ src, Cx<T>* __restrict__ W,
+                                                FftAxis ax, const typename TwT<T>::type* __restrict__ tw,
+                                                int nx, int ny, int nz, int Kx, int My, int LB) {
+  r2c_x_body<T, MODE>(g, src, W, ax, tw, nx, ny, nz, Kx, My, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Complex line FFT in place along y (element stride Kx) for lines a = kx (stride 1) on the
+// planes b = blockIdx.y.  STAGE 0 (forward): the planes holding source rows -- z < n_z
+// (MODE 0) or the cyclic rows of nodes -1..n_z (MODE 1) -- with the source's non-zero inputs
+// only, all M outputs stored.  STAGE 1 (inverse): the planes b < out_count(n_z) written by the
+// z pass, all M inputs, the out_count(n_y) kept rows stored at positions q from out_src(q).
+template <typename T, int DIR, int MODE, int STAGE>
+__device__ __forceinline__ void c2c_y_body(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
                                                 FftAxis ax,
                                                 const typename TwT<T>::type* __restrict__ tw,
-                                                int Kx, int n_in, int n_ghost, int LB) {
+                                                int Kx, int ny, int nz, int LB, int bx, int by, int nbx) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
   if (g->status) return;
   const int M = ax.M;
-  const int a0 = blockIdx.x * LB;
+  const int a0 = bx * LB;
   const int nl = min(LB, Kx - a0);
-  Cx<T>* base = W + (int64_t)blockIdx.y * M * Kx + a0;
+  const int plane = (STAGE == 0 && MODE == 1) ? ghost_src(by, 2 * nz) : (int)by;
+  Cx<T>* base = W + (int64_t)plane * M * Kx + a0;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     Cx<T> v = {0, 0};
-    if (l < nl && p < n_in) v = base[(int64_t)p * Kx + l];
+    if (l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M))) v = base[(int64_t)p * Kx + l];
     buf[l * M + p] = v;
   }
   __syncthreads();
   fft_lds<T, DIR>(buf, LB, ax, tw, 1);
-  const int nout = GHOST ? n_ghost : M;
+  const int nout = STAGE == 0 ? M : out_count<MODE>(ny);
   for (int idx = threadIdx.x; idx < LB * nout; idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
-    if (l < nl) base[(int64_t)q * Kx + l] = buf[l * M + (GHOST ? ghost_src(q, M) : q)];
+    if (l < nl) base[(int64_t)q * Kx + l] = buf[l * M + (STAGE == 0 ? q : out_src<MODE>(q, M))];
   }
 }
 
-// Along z (element stride My Kx) for lines a = kx, b = ky: forward FFT of the n_z non-zero
-// inputs, product with Ghat(fold kz, fold ky, kx) (gh[(fz (ny+1) + fy)(nx+1) + kx]), inverse
-// FFT, and the n_z + 2 ghost-inclusive rows written back in place.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_zconv(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
+template <typename T, int DIR, int MODE, int STAGE>
+__global__ __launch_bounds__(1024) void k_c2c_y(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
+                                                FftAxis ax,
+                                                const typename TwT<T>::type* __restrict__ tw,
+                                                int Kx, int ny, int nz, int LB) {
+  c2c_y_body<T, DIR, MODE, STAGE>(g, W, ax, tw, Kx, ny, nz, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Along z (element stride My Kx) for lines a = kx, b = ky: forward FFT of the source's
+// non-zero inputs, product with Ghat(fold kz, fold ky, kx) (gh[(fz (ny+1) + fy)(nx+1) + kx]),
+// inverse FFT, and the out_count(n_z) kept rows written back in place.
+template <typename T, int MODE>
+__device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
                                                 const T* __restrict__ gh, FftAxis ax,
                                                 const typename TwT<T>::type* __restrict__ tw,
-                                                int Kx, int My, int ny, int nz, int LB) {
+                                                int Kx, int My, int ny, int nz, int LB, int bx, int by, int nbx) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
   if (g->status) return;
   const int M = ax.M;
-  const int a0 = blockIdx.x * LB, ky = blockIdx.y;
+  const int a0 = bx * LB, ky = by;
   const int nl = min(LB, Kx - a0);
   const int64_t sz = (int64_t)My * Kx;
   Cx<T>* base = W + (int64_t)ky * Kx + a0;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     Cx<T> v = {0, 0};
-    if (l < nl && p < nz) v = base[(int64_t)p * sz + l];
+    if (l < nl && src_nonzero<MODE>(p, nz, M)) v = base[(int64_t)p * sz + l];
     buf[l * M + p] = v;
   }
   __syncthreads();
@@ -290,28 +355,37 @@ __global__ __launch_bounds__(1024) void k_zconv(const Geom* __restrict__ g, Cx<T
   }
   __syncthreads();
   fft_lds<T, +1>(buf, LB, ax, tw, 1);
-  for (int idx = threadIdx.x; idx < LB * (nz + 2); idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < LB * out_count<MODE>(nz); idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
-    if (l < nl) base[(int64_t)q * sz + l] = buf[l * M + ghost_src(q, M)];
+    if (l < nl) base[(int64_t)q * sz + l] = buf[l * M + out_src<MODE>(q, M)];
   }
 }
 
-// Inverse real transform of the rows (yy, zz) of W (yy < ny + 2, zz < nz + 2), writing phi on
-// x-nodes -1..n_x: Z_k = (X_k + conj X_{n-k}) + i exp(+2 pi i k/M_x)(X_k - conj X_{n-k}),
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_zconv(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
+                                                const T* __restrict__ gh, FftAxis ax,
+                                                const typename TwT<T>::type* __restrict__ tw,
+                                                int Kx, int My, int ny, int nz, int LB) {
+  zconv_body<T, MODE>(g, W, gh, ax, tw, Kx, My, ny, nz, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Inverse real transform of the kept rows (yy < out_count(n_y), zz < out_count(n_z)) of W,
+// writing the result on the kept x-nodes (MODE 0: -1..n_x into phi[(nz+2)][(ny+2)][(nx+2)];
+// MODE 1: 0..n_x-1 into an [nz][ny][nx] array): Z_k = (X_k + conj X_{n-k}) + i exp(+2 pi i k/M_x)(X_k - conj X_{n-k}),
 // k < n = n_x, inverse complex FFT of length n_x, x_{2j} = Re z_j, x_{2j+1} = Im z_j.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_c2r_x(const Geom* __restrict__ g,
+template <typename T, int MODE>
+__device__ __forceinline__ void c2r_x_body(const Geom* __restrict__ g,
                                                 const Cx<T>* __restrict__ W, T* __restrict__ phi,
                                                 FftAxis ax,
                                                 const typename TwT<T>::type* __restrict__ tw,
-                                                int nx, int ny, int Kx, int My, int LB) {
+                                                int nx, int ny, int Kx, int My, int LB, int bx, int by, int nbx) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
   if (g->status) return;
   const int H = ax.M;  // = nx
   const int M = 2 * H;
-  const int py = ny + 2;
-  const int r0 = blockIdx.x * LB, zz = blockIdx.y;
+  const int py = out_count<MODE>(ny);
+  const int r0 = bx * LB, zz = by;
   const int nl = min(LB, py - r0);
   const Cx<T>* src = W + ((int64_t)zz * My + r0) * Kx;
   for (int idx = threadIdx.x; idx < LB * H; idx += blockDim.x) {
@@ -329,22 +403,31 @@ __global__ __launch_bounds__(1024) void k_c2r_x(const Geom* __restrict__ g,
   }
   __syncthreads();
   fft_lds<T, +1>(buf, LB, ax, tw, 2);
-  const int px = nx + 2;
+  const int px = out_count<MODE>(nx);
   T* dst = phi + ((int64_t)zz * py + r0) * px;
   for (int idx = threadIdx.x; idx < LB * px; idx += blockDim.x) {
     const int l = idx / px, q = idx - l * px;
     if (l < nl) {
-      const int t = ghost_src(q, M);
+      const int t = out_src<MODE>(q, M);
       const Cx<T> zj = buf[l * H + (t >> 1)];
       dst[(int64_t)l * px + q] = (t & 1) ? zj.y : zj.x;
     }
   }
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_c2r_x(const Geom* __restrict__ g,
+                                                const Cx<T>* __restrict__ W, T* __restrict__ phi,
+                                                FftAxis ax,
+                                                const typename TwT<T>::type* __restrict__ tw,
+                                                int nx, int ny, int Kx, int My, int LB) {
+  c2r_x_body<T, MODE>(g, W, phi, ax, tw, nx, ny, Kx, My, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // E'[c][k][j][i] = -(phi(n + e_c) - phi(n - e_c)) / (2 h_c), rest-frame spacings
 template <typename T>
-__global__ __launch_bounds__(256) void k_grad(const Geom* __restrict__ g, const T* __restrict__ phi,
-                                              T* __restrict__ E, int nx, int ny, int nz) {
+__device__ __forceinline__ void grad_body(const Geom* __restrict__ g, const T* __restrict__ phi,
+                                              T* __restrict__ E, int nx, int ny, int nz, int bx, int by, int nbx) {
   if (g->status) return;
   const int px = nx + 2, py = ny + 2;
   const int64_t total = (int64_t)nx * ny * nz;
@@ -352,13 +435,115 @@ __global__ __launch_bounds__(256) void k_grad(const Geom* __restrict__ g, const 
   const T cy = (T)(1.0 / (2.0 * g->h_rest[1]));
   const T cz = (T)(1.0 / (2.0 * g->h_rest[2]));
   const int64_t sy = px, sz = (int64_t)px * py;
-  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+  for (int64_t t = bx * 256ll + threadIdx.x; t < total; t += (int64_t)nbx * 256) {
     int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((int64_t)nx * ny));
     int64_t c = (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
     E[t] = -(phi[c + 1] - phi[c - 1]) * cx;
     E[total + t] = -(phi[c + sy] - phi[c - sy]) * cy;
     E[2 * total + t] = -(phi[c + sz] - phi[c - sz]) * cz;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad(const Geom* __restrict__ g, const T* __restrict__ phi,
+                                              T* __restrict__ E, int nx, int ny, int nz) {
+  grad_body<T>(g, phi, E, nx, ny, nz, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+
+// ------------------------------------------------------------------------ batched wrappers
+// beam = blockIdx.z; lines per workgroup as in shape_for, per beam; blocks beyond a beam's
+// extent exit.
+
+template <typename T>
+__device__ __forceinline__ const typename TwT<T>::type* tw_of(const FftPlan& p, int a);
+template <>
+__device__ __forceinline__ const double2* tw_of<double>(const FftPlan& p, int a) { return p.tw[a]; }
+template <>
+__device__ __forceinline__ const float2* tw_of<float>(const FftPlan& p, int a) { return p.twf[a]; }
+
+__device__ __forceinline__ int lines_per_block(int L, int lines) {
+  int lb = kLdsElems / L;
+  if (lb < 1) lb = 1;
+  return lb > lines ? lines : lb;
+}
+
+__global__ __launch_bounds__(1024) void k_green_even_dft_batch(const BeamDev* __restrict__ beams,
+                                                               int axis) {
+  const BeamDev& d = beams[blockIdx.z];
+  if (d.geom->status) return;
+  const int ex = d.c.nx + 1, ey = d.c.ny + 1, ez = d.c.nz + 1;
+  int64_t st, sa, sb;
+  int na, nplanes;
+  if (axis == 0) {
+    st = 1; sa = ex; sb = (int64_t)ex * ey; na = ey; nplanes = ez;
+  } else if (axis == 1) {
+    st = ex; sa = 1; sb = (int64_t)ex * ey; na = ex; nplanes = ez;
+  } else {
+    st = (int64_t)ex * ey; sa = 1; sb = 0; na = ex * ey; nplanes = 1;
+  }
+  const int ncx = (na + 1) / 2;
+  const int LB = lines_per_block(d.plan.full[axis].M, ncx);
+  if ((int)blockIdx.x >= (ncx + LB - 1) / LB || (int)blockIdx.y >= nplanes) return;
+  green_even_dft_body(d.Gd, d.plan.full[axis], d.plan.tw[axis], st, sa, sb, na, LB, blockIdx.x,
+                      blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_green_finish_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  const int64_t total = (int64_t)(d.c.nx + 1) * (d.c.ny + 1) * (d.c.nz + 1);
+  const double scale = 1.0 / (4.0 * 3.14159265358979323846 * 8.8541878128e-12 *
+                              (8.0 * d.c.nx * d.c.ny * d.c.nz));
+  green_finish_body<T>(d.geom, d.Gd, (T*)d.Gh, total, scale, blockIdx.x, 0, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_r2c_x_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.z];
+  const int nx = d.c.nx, ny = d.c.ny, nz = d.c.nz;
+  const int LB = lines_per_block(d.plan.half_x.M, ny);
+  if ((int)blockIdx.x >= (ny + LB - 1) / LB || (int)blockIdx.y >= nz) return;
+  r2c_x_body<T, 0>(d.geom, (const T*)d.rho, (Cx<T>*)d.W, d.plan.half_x, tw_of<T>(d.plan, 0), nx,
+                   ny, nz, nx + 1, 2 * ny, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T, int DIR, int STAGE>
+__global__ __launch_bounds__(1024) void k_c2c_y_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.z];
+  const int Kx = d.c.nx + 1, ny = d.c.ny, nz = d.c.nz;
+  const int LB = lines_per_block(d.plan.full[1].M, Kx);
+  const int planes = STAGE == 0 ? nz : nz + 2;
+  if ((int)blockIdx.x >= (Kx + LB - 1) / LB || (int)blockIdx.y >= planes) return;
+  c2c_y_body<T, DIR, 0, STAGE>(d.geom, (Cx<T>*)d.W, d.plan.full[1], tw_of<T>(d.plan, 1), Kx, ny,
+                               nz, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_zconv_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.z];
+  const int Kx = d.c.nx + 1, My = 2 * d.c.ny;
+  const int LB = lines_per_block(d.plan.full[2].M, Kx);
+  if ((int)blockIdx.x >= (Kx + LB - 1) / LB || (int)blockIdx.y >= My) return;
+  zconv_body<T, 0>(d.geom, (Cx<T>*)d.W, (const T*)d.Gh, d.plan.full[2], tw_of<T>(d.plan, 2), Kx,
+                   My, d.c.ny, d.c.nz, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_c2r_x_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.z];
+  const int nx = d.c.nx, ny = d.c.ny, nz = d.c.nz;
+  const int LB = lines_per_block(d.plan.half_x.M, ny + 2);
+  if ((int)blockIdx.x >= (ny + 2 + LB - 1) / LB || (int)blockIdx.y >= nz + 2) return;
+  c2r_x_body<T, 0>(d.geom, (const Cx<T>*)d.W, (T*)d.phi, d.plan.half_x, tw_of<T>(d.plan, 0), nx,
+                   ny, nx + 1, 2 * ny, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  grad_body<T>(d.geom, (const T*)d.phi, (T*)d.E, d.c.nx, d.c.ny, d.c.nz, blockIdx.x, 0,
+               gridDim.x);
 }
 
 __global__ void k_twiddles(double2* tw, float2* twf, int M) {
@@ -438,47 +623,129 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
   return hipGetLastError();
 }
 
+namespace {
+
+// MODE 0: phi (nodes -1..n) from rho (nodes 0..n-1); MODE 1: chi (nodes 0..n-1) from a source
+// on nodes -1..n.  src/dst layouts as in k_r2c_x and k_c2r_x.
+template <typename T, int MODE>
+hipError_t run_passes(const Geom* g, const FftPlan& p, int nx, int ny, int nz, const T* src,
+                      Cx<T>* W, const T* gh, T* dst, hipStream_t s) {
+  const int My = 2 * ny, Kx = nx + 1;
+  const int rows_y = MODE == 0 ? ny : ny + 2, rows_z = MODE == 0 ? nz : nz + 2;
+  const int out_y = MODE == 0 ? ny + 2 : ny, out_z = MODE == 0 ? nz + 2 : nz;
+  int LB, NT;
+  size_t lds;
+  shape_for(p.half_x.M, rows_y, &LB, &NT);
+  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_r2c_x<T, MODE>), dim3((rows_y + LB - 1) / LB, rows_z), dim3(NT), lds, s,
+                     g, src, W, p.half_x, table<T>(p, 0), nx, ny, nz, Kx, My, LB);
+  PIC_TRY(hipGetLastError());
+  shape_for(p.full[1].M, Kx, &LB, &NT);
+  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_c2c_y<T, -1, MODE, 0>), dim3((Kx + LB - 1) / LB, rows_z), dim3(NT), lds,
+                     s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+  PIC_TRY(hipGetLastError());
+  shape_for(p.full[2].M, Kx, &LB, &NT);
+  lds = (size_t)LB * p.full[2].M * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_zconv<T, MODE>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W,
+                     gh, p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB);
+  PIC_TRY(hipGetLastError());
+  shape_for(p.full[1].M, Kx, &LB, &NT);
+  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_c2c_y<T, +1, MODE, 1>), dim3((Kx + LB - 1) / LB, out_z), dim3(NT), lds,
+                     s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+  PIC_TRY(hipGetLastError());
+  shape_for(p.half_x.M, out_y, &LB, &NT);
+  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_c2r_x<T, MODE>), dim3((out_y + LB - 1) / LB, out_z), dim3(NT), lds, s, g,
+                     W, dst, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 template <typename T>
 hipError_t launch_solve(const Geom* g, const FftPlan& p, int nx, int ny, int nz, const T* rho,
                         void* Wv, const T* gh, T* phi, T* E, hipStream_t s) {
-  Cx<T>* W = (Cx<T>*)Wv;
-  const int My = 2 * ny, Kx = nx + 1;
-  int LB, NT;
-  size_t lds;
-  // r2c along x: rows (y < ny, z < nz)
-  shape_for(p.half_x.M, ny, &LB, &NT);
-  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_r2c_x<T>), dim3((ny + LB - 1) / LB, nz), dim3(NT), lds, s, g, rho, W,
-                     p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
-  PIC_TRY(hipGetLastError());
-  // forward along y, planes z < nz
-  shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_c2c_y<T, -1, false>), dim3((Kx + LB - 1) / LB, nz), dim3(NT), lds, s, g,
-                     W, p.full[1], table<T>(p, 1), Kx, ny, 0, LB);
-  PIC_TRY(hipGetLastError());
-  // z: forward, product with the Green spectrum, inverse; rows on nodes -1..nz
-  shape_for(p.full[2].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[2].M * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_zconv<T>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W, gh,
-                     p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB);
-  PIC_TRY(hipGetLastError());
-  // inverse along y for the nz + 2 rows; rows on nodes -1..ny
-  shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_c2c_y<T, +1, true>), dim3((Kx + LB - 1) / LB, nz + 2), dim3(NT), lds, s,
-                     g, W, p.full[1], table<T>(p, 1), Kx, My, ny + 2, LB);
-  PIC_TRY(hipGetLastError());
-  // c2r along x for the (ny + 2)(nz + 2) rows, phi on nodes -1..nx
-  shape_for(p.half_x.M, ny + 2, &LB, &NT);
-  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_c2r_x<T>), dim3((ny + 2 + LB - 1) / LB, nz + 2), dim3(NT), lds, s, g, W,
-                     phi, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
-  PIC_TRY(hipGetLastError());
+  PIC_TRY((run_passes<T, 0>(g, p, nx, ny, nz, rho, (Cx<T>*)Wv, gh, phi, s)));
   const int64_t ng = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_grad<T>), dim3(grid_for(ng)), dim3(256), 0, s, g, phi, E, nx, ny, nz);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_solve_ghost_source(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                     const T* psi, void* Wv, const T* gh, T* chi, hipStream_t s) {
+  return run_passes<T, 1>(g, p, nx, ny, nz, psi, (Cx<T>*)Wv, gh, chi, s);
+}
+
+template hipError_t launch_solve_ghost_source<double>(const Geom*, const FftPlan&, int, int, int,
+                                                      const double*, void*, const double*,
+                                                      double*, hipStream_t);
+template hipError_t launch_solve_ghost_source<float>(const Geom*, const FftPlan&, int, int, int,
+                                                     const float*, void*, const float*, float*,
+                                                     hipStream_t);
+// ------------------------------------------------------------------------ batched launches
+
+namespace {
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+int lpb(int L, int lines) {
+  int lb = kLdsElems / L;
+  if (lb < 1) lb = 1;
+  return lb > lines ? lines : lb;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_batch_green(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s) {
+  PIC_TRY(launch_batch_igf(beams, nb, bd.max_nx, bd.max_ny, bd.max_nz, s));
+  const int ex = bd.max_nx + 1, ey = bd.max_ny + 1, ez = bd.max_nz + 1;
+  // grid extents over the beams: the largest grid needs the most blocks along every axis
+  const int M[3] = {2 * bd.max_nx, 2 * bd.max_ny, 2 * bd.max_nz};
+  const int na[3] = {ey, ex, ex * ey}, npl[3] = {ez, ez, 1};
+  for (int a = 0; a < 3; ++a) {
+    // smaller beams have shorter lines and so at least as many lines per block: the largest
+    // beam bounds the block count
+    const int ncx = (na[a] + 1) / 2;
+    const int gx = ceil_div(ncx, lpb(M[a], ncx));
+    hipLaunchKernelGGL(k_green_even_dft_batch, dim3(gx, npl[a], nb), dim3(1024),
+                       (size_t)kLdsElems * sizeof(Cx<double>), s, beams, a);
+    PIC_TRY(hipGetLastError());
+  }
+  const int64_t total = (int64_t)ex * ey * ez;
+  hipLaunchKernelGGL((k_green_finish_batch<T>), dim3(grid_for(total), nb), dim3(256), 0, s, beams);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s) {
+  const int nx = bd.max_nx, ny = bd.max_ny, nz = bd.max_nz;
+  const int Kx = nx + 1, My = 2 * ny;
+  const size_t lds = (size_t)kLdsElems * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_r2c_x_batch<T>), dim3(ceil_div(ny, lpb(nx, ny)), nz, nb), dim3(1024), lds,
+                     s, beams);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_c2c_y_batch<T, -1, 0>), dim3(ceil_div(Kx, lpb(My, Kx)), nz, nb),
+                     dim3(1024), lds, s, beams);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_zconv_batch<T>), dim3(ceil_div(Kx, lpb(2 * nz, Kx)), My, nb), dim3(1024),
+                     lds, s, beams);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_c2c_y_batch<T, +1, 1>), dim3(ceil_div(Kx, lpb(My, Kx)), nz + 2, nb),
+                     dim3(1024), lds, s, beams);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_c2r_x_batch<T>), dim3(ceil_div(ny + 2, lpb(nx, ny + 2)), nz + 2, nb),
+                     dim3(1024), lds, s, beams);
+  PIC_TRY(hipGetLastError());
+  const int64_t ng = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL((k_grad_batch<T>), dim3(grid_for(ng), nb), dim3(256), 0, s, beams);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_green<double>(const BeamDev*, int, const BatchDims&, hipStream_t);
+template hipError_t launch_batch_green<float>(const BeamDev*, int, const BatchDims&, hipStream_t);
+template hipError_t launch_batch_solve<double>(const BeamDev*, int, const BatchDims&, hipStream_t);
+template hipError_t launch_batch_solve<float>(const BeamDev*, int, const BatchDims&, hipStream_t);
 
 template hipError_t launch_green_spectrum<double>(const Geom*, const FftPlan&, int, int, int,
                                                   double2*, double*, double*, hipStream_t);

@@ -17,13 +17,13 @@ namespace pic {
 namespace {
 
 // F at every corner (m_x, m_y, m_z), m_a = 0..n_a+1; corners[(mz (ny+2) + my)(nx+2) + mx]
-__global__ __launch_bounds__(256) void k_igf_corners(const Geom* __restrict__ g, int nx, int ny,
-                                                     int nz, double2* __restrict__ corners) {
+__device__ __forceinline__ void igf_corners_body(const Geom* __restrict__ g, int nx, int ny, int nz,
+                                                 double2* __restrict__ corners, int blk, int nblk) {
   if (g->status) return;
   const int cx = nx + 2, cy = ny + 2, cz = nz + 2;
   const int64_t total = (int64_t)cx * cy * cz;
   const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
-  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+  for (int64_t t = blk * 256ll + threadIdx.x; t < total; t += (int64_t)nblk * 256) {
     int mx = (int)(t % cx);
     int my = (int)((t / cx) % cy);
     int mz = (int)(t / ((int64_t)cx * cy));
@@ -32,20 +32,30 @@ __global__ __launch_bounds__(256) void k_igf_corners(const Geom* __restrict__ g,
   }
 }
 
+__global__ __launch_bounds__(256) void k_igf_corners(const Geom* __restrict__ g, int nx, int ny,
+                                                     int nz, double2* __restrict__ corners) {
+  igf_corners_body(g, nx, ny, nz, corners, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_igf_corners_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  igf_corners_body(d.geom, d.c.nx, d.c.ny, d.c.nz, d.corners, blockIdx.x, gridDim.x);
+}
+
 // Cell averages Gbar(i, j, k), i = 0..nx, j = 0..ny, k = 0..nz, from the corner values:
 // successive double-double differences along x, then y, then z; cells on a coordinate plane
 // carry weight 2 per folded axis; one division by the rest-frame cell volume; rounded to
 // double once.  Output gd[(k (ny+1) + j)(nx+1) + i].
-__global__ __launch_bounds__(256) void k_igf_cells(const Geom* __restrict__ g, int nx, int ny,
-                                                   int nz, const double2* __restrict__ corners,
-                                                   double* __restrict__ gd) {
+__device__ __forceinline__ void igf_cells_body(const Geom* __restrict__ g, int nx, int ny, int nz,
+                                               const double2* __restrict__ corners,
+                                               double* __restrict__ gd, int blk, int nblk) {
   if (g->status) return;
   const int cx = nx + 2, cy = ny + 2;
   const int ex = nx + 1, ey = ny + 1;
   const int64_t total = (int64_t)ex * ey * (nz + 1);
   const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
   const ddv vol = dd_mul_d(two_prod(hx, hy), hz);
-  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+  for (int64_t t = blk * 256ll + threadIdx.x; t < total; t += (int64_t)nblk * 256) {
     const int i = (int)(t % ex);
     const int j = (int)((t / ex) % ey);
     const int k = (int)(t / ((int64_t)ex * ey));
@@ -62,6 +72,17 @@ __global__ __launch_bounds__(256) void k_igf_cells(const Geom* __restrict__ g, i
     const ddv gbar = dd_div(d, vol);
     gd[t] = gbar.hi + gbar.lo;
   }
+}
+
+__global__ __launch_bounds__(256) void k_igf_cells(const Geom* __restrict__ g, int nx, int ny,
+                                                   int nz, const double2* __restrict__ corners,
+                                                   double* __restrict__ gd) {
+  igf_cells_body(g, nx, ny, nz, corners, gd, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_igf_cells_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  igf_cells_body(d.geom, d.c.nx, d.c.ny, d.c.nz, d.corners, d.Gd, blockIdx.x, gridDim.x);
 }
 
 int grid_for(int64_t total) {
@@ -85,6 +106,17 @@ hipError_t launch_igf_cells(const Geom* g, int nx, int ny, int nz, const double2
   int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   hipLaunchKernelGGL(k_igf_cells, dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz, corners,
                      gd);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_igf(const BeamDev* beams, int nb, int max_nx, int max_ny, int max_nz,
+                            hipStream_t s) {
+  const int64_t corners = (int64_t)(max_nx + 2) * (max_ny + 2) * (max_nz + 2);
+  hipLaunchKernelGGL(k_igf_corners_batch, dim3(grid_for(corners), nb), dim3(256), 0, s, beams);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t cells = (int64_t)(max_nx + 1) * (max_ny + 1) * (max_nz + 1);
+  hipLaunchKernelGGL(k_igf_cells_batch, dim3(grid_for(cells), nb), dim3(256), 0, s, beams);
   return hipGetLastError();
 }
 

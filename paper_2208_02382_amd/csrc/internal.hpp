@@ -68,7 +68,40 @@ struct SortPlan {
   int64_t max_chunks;
 };
 
-constexpr int kReduceBlocks = 1024;   // partial sums for the moments reduction
+// Per-beam device descriptor of a batch: every batched kernel takes its beam from the grid
+// (blockIdx.y, or blockIdx.z for the two-dimensional FFT passes) and reads this.
+struct BeamDev {
+  Consts c;
+  SortPlan sp;
+  FftPlan plan;
+  double* X;            // the caller's phase space
+  double* XA;           // workspace copies (step j reads XA for even j, XB for odd j)
+  double* XB;
+  uint32_t* idA;
+  uint32_t* idB;
+  uint32_t* keys;
+  uint32_t* hist;
+  uint32_t* cursor;
+  int4* chunks;
+  uint32_t* nchunks;
+  Geom* geom;
+  Box* box;
+  void* rho;
+  void* phi;
+  void* E;
+  void* W;
+  double* Gd;
+  void* Gh;
+  double2* corners;
+  const double* lat_k;  // lattice of this beam (cycled over the steps)
+  const double* lat_ds;
+  int n_el;
+  int pad;
+};
+
+constexpr int kReduceBlocks = 1024;
+constexpr int kAdjBlocks = 1024;      // grid of the reverse-sweep particle kernels
+constexpr int kMaxLattice = 1024;     // lattice elements of the reverse sweep   // partial sums for the moments reduction
 constexpr int kMomentSlots = 27;      // 6 sums + 21 centred products
 
 // ---- launch wrappers (particles.hip)
@@ -115,6 +148,52 @@ hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, dou
                             uint32_t* nchunks, double* B, uint32_t* idB, const Geom* g,
                             hipStream_t s);
 
+// ---- batched tracking (one launch per stage for all beams of a batch)
+struct BatchDims {      // grid extents over the beams of a batch
+  int64_t max_n;        // largest particle count
+  int max_nx, max_ny, max_nz;
+  int max_chunks;       // work-list blocks per beam for the tiled deposit and gather
+  size_t dep_lds, gkd_lds;
+};
+hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                                      int parity, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                                int parity, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_gkd(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                            int parity, int j, int n_steps, hipStream_t s);
+hipError_t launch_batch_unpermute(const BeamDev* beams, int nb, const BatchDims& bd, int parity,
+                                  hipStream_t s);
+hipError_t launch_batch_prologue_particles(const BeamDev* beams, int nb, const BatchDims& bd,
+                                           hipStream_t s);
+hipError_t launch_batch_box_reset(const BeamDev* beams, int nb, hipStream_t s);
+hipError_t launch_batch_geometry(const BeamDev* beams, int nb, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_zero_rho(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s);
+hipError_t launch_batch_igf(const BeamDev* beams, int nb, int max_nx, int max_ny, int max_nz,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_batch_green(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s);
+
+// ---- adjoint.hip
+template <typename T>
+hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, double k,
+                        double L, T* e, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int nz,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, double k, double L,
+                        const T* E, const T* chi, double* dk_partial, double* dk, int slot,
+                        hipStream_t s);
+hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
+                           double* lam, double* out_m, hipStream_t s);
+hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* partial, double* out,
+                     hipStream_t s);
+
 // ---- igf.hip
 hipError_t launch_igf_corners(const Geom* g, int nx, int ny, int nz, double2* corners,
                               hipStream_t s);
@@ -129,5 +208,9 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
 template <typename T>
 hipError_t launch_solve(const Geom* g, const FftPlan& p, int nx, int ny, int nz, const T* rho,
                         void* W, const T* Gh, T* phi, T* E, hipStream_t s);
+// chi on nodes 0..n-1 = 1/(4 pi eps0) Gbar * psi for psi on nodes -1..n ([(nz+2)][(ny+2)][(nx+2)])
+template <typename T>
+hipError_t launch_solve_ghost_source(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                     const T* psi, void* W, const T* Gh, T* chi, hipStream_t s);
 
 }  // namespace pic

@@ -396,9 +396,80 @@ __global__ __launch_bounds__(kBlock) void k_zero(T* p, int64_t count) {
     p[i] = T(0);
 }
 
+// batched: thread b handles beam b
+__global__ void k_box_reset_batch(const BeamDev* __restrict__ beams, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  Box* box = beams[b].box;
+  for (int a = 0; a < 3; ++a) {
+    box->mn[a] = ~0ull;
+    box->mx[a] = 0ull;
+  }
+  box->nonfinite = 0u;
+}
+
+__global__ void k_geometry_batch(const BeamDev* __restrict__ beams, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const BeamDev& d = beams[b];
+  const Consts c = d.c;
+  const Box* box = d.box;
+  Geom* g = d.geom;
+  int nn[3] = {c.nx, c.ny, c.nz};
+  bool bad = box->nonfinite != 0u;
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord_dec(box->mn[a]);
+    hi[a] = ord_dec(box->mx[a]);
+    if (!(hi[a] > lo[a])) bad = true;
+  }
+  if (bad) {
+    g->status = -4;
+    return;
+  }
+  for (int a = 0; a < 3; ++a) {
+    double h = (hi[a] - lo[a]) / ((double)nn[a] - 3.5);
+    g->h[a] = h;
+    g->inv_h[a] = 1.0 / h;
+    g->origin[a] = lo[a] - 1.25 * h;
+  }
+  g->h_rest[0] = g->h[0];
+  g->h_rest[1] = g->h[1];
+  g->h_rest[2] = c.gamma * g->h[2];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_rho_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  T* p = (T*)d.rho;
+  const int64_t count = (int64_t)d.c.nx * d.c.ny * d.c.nz;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = T(0);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- launch wrappers
+
+hipError_t launch_batch_box_reset(const BeamDev* beams, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_box_reset_batch, dim3((nb + 63) / 64), dim3(64), 0, s, beams, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_geometry(const BeamDev* beams, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_geometry_batch, dim3((nb + 63) / 64), dim3(64), 0, s, beams, nb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_zero_rho(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s) {
+  const int64_t ng = (int64_t)bd.max_nx * bd.max_ny * bd.max_nz;
+  hipLaunchKernelGGL((k_zero_rho_batch<T>), dim3(grid_for(ng), nb), dim3(kBlock), 0, s, beams);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_zero_rho<double>(const BeamDev*, int, const BatchDims&, hipStream_t);
+template hipError_t launch_batch_zero_rho<float>(const BeamDev*, int, const BatchDims&, hipStream_t);
 
 hipError_t launch_box_reset(Box* box, hipStream_t s) {
   hipLaunchKernelGGL(k_box_reset, dim3(1), dim3(64), 0, s, box);

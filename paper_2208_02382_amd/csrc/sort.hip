@@ -43,10 +43,10 @@ __device__ __forceinline__ uint32_t tile_key(double x, double y, double z, const
 }
 
 template <int S>
-__global__ __launch_bounds__(kBlk) void k_key_hist(const double* __restrict__ X,
+__device__ __forceinline__ void key_hist_body(const double* __restrict__ X,
                                                    const Geom* __restrict__ g, Consts c,
                                                    SortPlan sp, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ hist) {
+                                                   uint32_t* __restrict__ hist, int blk, int nblk) {
   __shared__ uint32_t lh[kMaxTiles];
   if (g->status) return;
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlk) void k_key_hist(const double* __restrict__ X,
   for (int t = threadIdx.x; t < sp.ntiles; t += kBlk) lh[t] = 0u;
   __syncthreads();
   const int64_t n = c.n;
-  const int64_t base = (int64_t)blockIdx.x * kItems;
+  const int64_t base = (int64_t)blk * kItems;
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
     if (i < n) {
@@ -66,6 +66,14 @@ __global__ __launch_bounds__(kBlk) void k_key_hist(const double* __restrict__ X,
   __syncthreads();
   for (int t = threadIdx.x; t < sp.ntiles; t += kBlk)
     if (lh[t]) atomicAdd(&hist[t], lh[t]);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlk) void k_key_hist(const double* __restrict__ X,
+                                                   const Geom* __restrict__ g, Consts c,
+                                                   SortPlan sp, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ hist) {
+  key_hist_body<S>(X, g, c, sp, keys, hist, blockIdx.x, gridDim.x);
 }
 
 // Block-wide exclusive scan of per-thread values (1024 threads).
@@ -86,11 +94,11 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* tot
 }
 
 // one block of 1024 threads; each thread owns 4 consecutive tiles
-__global__ __launch_bounds__(1024) void k_build_chunks(const Geom* __restrict__ g, SortPlan sp,
-                                                       uint32_t* __restrict__ hist,
-                                                       uint32_t* __restrict__ cursor,
-                                                       int4* __restrict__ chunks,
-                                                       uint32_t* __restrict__ nchunks) {
+__device__ __forceinline__ void build_chunks_body(const Geom* __restrict__ g, SortPlan sp,
+                                                  uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ cursor,
+                                                  int4* __restrict__ chunks,
+                                                  uint32_t* __restrict__ nchunks) {
   __shared__ uint32_t sh[1024];
   if (g->status) {
     if (threadIdx.x == 0) *nchunks = 0u;
@@ -125,18 +133,26 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const Geom* __restrict__ 
   if (threadIdx.x == 0) *nchunks = tot_k;
 }
 
-__global__ __launch_bounds__(kBlk) void k_scatter(const double* __restrict__ A,
+__global__ __launch_bounds__(1024) void k_build_chunks(const Geom* __restrict__ g, SortPlan sp,
+                                                       uint32_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ cursor,
+                                                       int4* __restrict__ chunks,
+                                                       uint32_t* __restrict__ nchunks) {
+  build_chunks_body(g, sp, hist, cursor, chunks, nchunks);
+}
+
+__device__ __forceinline__ void scatter_body(const double* __restrict__ A,
                                                   const uint32_t* __restrict__ idA,
                                                   const uint32_t* __restrict__ keys,
                                                   const Geom* __restrict__ g, int64_t n,
                                                   int ntiles, uint32_t* __restrict__ cursor,
                                                   double* __restrict__ B,
-                                                  uint32_t* __restrict__ idB) {
+                                                  uint32_t* __restrict__ idB, int blk, int nblk) {
   __shared__ uint32_t lh[kMaxTiles];
   if (g->status) return;
   for (int t = threadIdx.x; t < ntiles; t += kBlk) lh[t] = 0u;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kItems;
+  const int64_t base = (int64_t)blk * kItems;
   uint32_t key[kPer];
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
@@ -159,18 +175,28 @@ __global__ __launch_bounds__(kBlk) void k_scatter(const double* __restrict__ A,
   }
 }
 
+__global__ __launch_bounds__(kBlk) void k_scatter(const double* __restrict__ A,
+                                                  const uint32_t* __restrict__ idA,
+                                                  const uint32_t* __restrict__ keys,
+                                                  const Geom* __restrict__ g, int64_t n,
+                                                  int ntiles, uint32_t* __restrict__ cursor,
+                                                  double* __restrict__ B,
+                                                  uint32_t* __restrict__ idB) {
+  scatter_body(A, idA, keys, g, n, ntiles, cursor, B, idB, blockIdx.x, gridDim.x);
+}
+
 template <typename T>
 __device__ __forceinline__ void add_global(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
+__device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
                                                         const Geom* __restrict__ g, Consts c,
                                                         SortPlan sp,
                                                         const int4* __restrict__ chunks,
                                                         const uint32_t* __restrict__ nchunks,
-                                                        T* __restrict__ rho) {
+                                                        T* __restrict__ rho, int blk, int nblk) {
   extern __shared__ unsigned char smem_raw[];
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
@@ -180,7 +206,7 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict
   const int nw = Wx * Wy * Wz;
   const int64_t n = c.n;
   const uint32_t nck = *nchunks;
-  for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+  for (uint32_t ci = blk; ci < nck; ci += nblk) {
     const int4 ch = chunks[ci];
     const int t = ch.x;
     const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
@@ -219,6 +245,16 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict
   }
 }
 
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
+                                                        const Geom* __restrict__ g, Consts c,
+                                                        SortPlan sp,
+                                                        const int4* __restrict__ chunks,
+                                                        const uint32_t* __restrict__ nchunks,
+                                                        T* __restrict__ rho) {
+  deposit_tiles_body<S, T>(B, g, c, sp, chunks, nchunks, rho, blockIdx.x, gridDim.x);
+}
+
 // Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
 // workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
 // rows), the particles gather from LDS, get the space-charge kick over L and the drift L/2,
@@ -227,14 +263,14 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
+__device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
                                                     const Geom* __restrict__ g,
                                                     const T* __restrict__ E, Consts c,
                                                     SortPlan sp,
                                                     const int4* __restrict__ chunks,
                                                     const uint32_t* __restrict__ nchunks,
                                                     double L, int has_next, double k_next,
-                                                    double half_next, Box* box) {
+                                                    double half_next, Box* box, int blk, int nblk) {
   extern __shared__ unsigned char smem_raw[];
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
@@ -247,7 +283,7 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false, bin_fault = false;
   const uint32_t nck = *nchunks;
-  for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+  for (uint32_t ci = blk; ci < nck; ci += nblk) {
     const int4 ch = chunks[ci];
     const int t = ch.x;
     const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
@@ -318,16 +354,28 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
   if (has_next) box_accumulate_block(lo, hi, bad, box);
 }
 
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
+                                                    const Geom* __restrict__ g,
+                                                    const T* __restrict__ E, Consts c,
+                                                    SortPlan sp,
+                                                    const int4* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ nchunks,
+                                                    double L, int has_next, double k_next,
+                                                    double half_next, Box* box) {
+  gkd_tiles_body<S, T>(B, g, E, c, sp, chunks, nchunks, L, has_next, k_next, half_next, box, blockIdx.x, gridDim.x);
+}
+
 // First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
-__global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
+__device__ __forceinline__ void prologue_body(const double* __restrict__ X,
                                                    double* __restrict__ A,
                                                    uint32_t* __restrict__ idA, double k,
-                                                   double ell, Consts c, Box* box) {
+                                                   double ell, Consts c, Box* box, int blk, int nblk) {
   const int64_t n = c.n;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
-  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlk) {
+  for (int64_t i = blk * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)nblk * kBlk) {
     double v[6];
     for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
     v[1] = v[1] - k * v[0];
@@ -347,16 +395,23 @@ __global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
   box_accumulate_block(lo, hi, bad, box);
 }
 
+__global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
+                                                   double* __restrict__ A,
+                                                   uint32_t* __restrict__ idA, double k,
+                                                   double ell, Consts c, Box* box) {
+  prologue_body(X, A, idA, k, ell, c, box, blockIdx.x, gridDim.x);
+}
+
 // Bucket keys for the return to the caller's order: key = id >> shift (at most 4096 buckets of
 // consecutive original indices), with the block-privatised histogram of k_key_hist.
-__global__ __launch_bounds__(kBlk) void k_id_hist(const uint32_t* __restrict__ ids, int64_t n,
+__device__ __forceinline__ void id_hist_body(const uint32_t* __restrict__ ids, int64_t n,
                                                   int shift, int nbuckets,
                                                   uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ hist) {
+                                                  uint32_t* __restrict__ hist, int blk, int nblk) {
   __shared__ uint32_t lh[kMaxTiles];
   for (int t = threadIdx.x; t < nbuckets; t += kBlk) lh[t] = 0u;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kItems;
+  const int64_t base = (int64_t)blk * kItems;
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
     if (i < n) {
@@ -371,19 +426,134 @@ __global__ __launch_bounds__(kBlk) void k_id_hist(const uint32_t* __restrict__ i
     if (lh[t]) atomicAdd(&hist[t], lh[t]);
 }
 
+__global__ __launch_bounds__(kBlk) void k_id_hist(const uint32_t* __restrict__ ids, int64_t n,
+                                                  int shift, int nbuckets,
+                                                  uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ hist) {
+  id_hist_body(ids, n, shift, nbuckets, keys, hist, blockIdx.x, gridDim.x);
+}
+
 // Back to the caller's order: X[r][id[i]] = A[r][i].  After the bucket pass, the particles a
 // block handles have ids in a narrow range, so its writes stay within an L2-sized window.
-__global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A,
+__device__ __forceinline__ void unpermute_body(const double* __restrict__ A,
                                                     const uint32_t* __restrict__ idA, int64_t n,
                                                     const Geom* __restrict__ g,
-                                                    double* __restrict__ X) {
+                                                    double* __restrict__ X, int blk, int nblk) {
   if (g->status) return;  // after a device error X keeps the caller's input
-  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlk) {
+  for (int64_t i = blk * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)nblk * kBlk) {
     uint32_t j = idA[i];
     if (j < (uint64_t)n)
       for (int r = 0; r < 6; ++r) X[r * n + j] = A[r * n + i];
   }
+}
+
+__global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A,
+                                                    const uint32_t* __restrict__ idA, int64_t n,
+                                                    const Geom* __restrict__ g,
+                                                    double* __restrict__ X) {
+  unpermute_body(A, idA, n, g, X, blockIdx.x, gridDim.x);
+}
+
+
+// ------------------------------------------------------------------------ batched wrappers
+// beam = blockIdx.y; the current phase-space copy of step j is XA for even j (parity 0).
+
+__device__ __forceinline__ double* cur_X(const BeamDev& d, int parity) { return parity ? d.XB : d.XA; }
+__device__ __forceinline__ double* nxt_X(const BeamDev& d, int parity) { return parity ? d.XA : d.XB; }
+__device__ __forceinline__ uint32_t* cur_id(const BeamDev& d, int parity) { return parity ? d.idB : d.idA; }
+__device__ __forceinline__ uint32_t* nxt_id(const BeamDev& d, int parity) { return parity ? d.idA : d.idB; }
+
+__global__ __launch_bounds__(kBlk) void k_prologue_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  prologue_body(d.X, d.XA, d.idA, d.lat_k[0], 0.5 * d.lat_ds[0], d.c, d.box, blockIdx.x,
+                gridDim.x);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlk) void k_key_hist_batch(const BeamDev* __restrict__ beams,
+                                                         int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  if ((int64_t)blockIdx.x * kItems >= d.c.n) return;
+  key_hist_body<S>(cur_X(d, parity), d.geom, d.c, d.sp, d.keys, d.hist, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(1024) void k_build_chunks_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.x];
+  build_chunks_body(d.geom, d.sp, d.hist, d.cursor, d.chunks, d.nchunks);
+}
+
+__global__ __launch_bounds__(kBlk) void k_scatter_batch(const BeamDev* __restrict__ beams,
+                                                        int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  if ((int64_t)blockIdx.x * kItems >= d.c.n) return;
+  scatter_body(cur_X(d, parity), cur_id(d, parity), d.keys, d.geom, d.c.n, d.sp.ntiles, d.cursor,
+               nxt_X(d, parity), nxt_id(d, parity), blockIdx.x, gridDim.x);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
+                                                              int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  deposit_tiles_body<S, T>(nxt_X(d, parity), d.geom, d.c, d.sp, d.chunks, d.nchunks, (T*)d.rho,
+                           blockIdx.x, gridDim.x);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
+                                                          int parity, int j, int n_steps) {
+  const BeamDev& d = beams[blockIdx.y];
+  const int e = j % d.n_el, e1 = (j + 1) % d.n_el;
+  gkd_tiles_body<S, T>(nxt_X(d, parity), d.geom, (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
+                       d.lat_ds[e], j + 1 < n_steps, d.lat_k[e1], 0.5 * d.lat_ds[e1], d.box,
+                       blockIdx.x, gridDim.x);
+}
+
+// reordering at the end: bucket keys of the ids, bucket offsets, bucket scatter, final scatter
+__device__ __forceinline__ void bucket_plan(int64_t n, int* shift, int* nb) {
+  int sh = 0;
+  while (((n - 1) >> sh) >= kMaxTiles) ++sh;
+  *shift = sh;
+  *nb = (int)(((n - 1) >> sh) + 1);
+}
+
+__global__ __launch_bounds__(kBlk) void k_id_hist_batch(const BeamDev* __restrict__ beams,
+                                                        int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  if ((int64_t)blockIdx.x * kItems >= d.c.n) return;
+  int sh, nb;
+  bucket_plan(d.c.n, &sh, &nb);
+  id_hist_body(cur_id(d, parity), d.c.n, sh, nb, d.keys, d.hist, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(1024) void k_bucket_chunks_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.x];
+  int sh, nb;
+  bucket_plan(d.c.n, &sh, &nb);
+  SortPlan bp;
+  bp.T[0] = bp.T[1] = bp.T[2] = 1;
+  bp.NT[0] = nb;
+  bp.NT[1] = bp.NT[2] = 1;
+  bp.ntiles = nb;
+  bp.chunk = 1 << 30;
+  bp.max_chunks = nb + 1;
+  build_chunks_body(d.geom, bp, d.hist, d.cursor, d.chunks, d.nchunks);
+}
+
+__global__ __launch_bounds__(kBlk) void k_bucket_scatter_batch(const BeamDev* __restrict__ beams,
+                                                               int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  if ((int64_t)blockIdx.x * kItems >= d.c.n) return;
+  int sh, nb;
+  bucket_plan(d.c.n, &sh, &nb);
+  scatter_body(cur_X(d, parity), cur_id(d, parity), d.keys, d.geom, d.c.n, nb, d.cursor,
+               nxt_X(d, parity), nxt_id(d, parity), blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlk) void k_unpermute_batch(const BeamDev* __restrict__ beams,
+                                                          int parity) {
+  const BeamDev& d = beams[blockIdx.y];
+  unpermute_body(nxt_X(d, parity), nxt_id(d, parity), d.c.n, d.geom, d.X, blockIdx.x, gridDim.x);
 }
 
 int grid_items(int64_t n) { return (int)((n + kItems - 1) / kItems); }
@@ -507,6 +677,82 @@ hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, dou
   hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, B, idB, n, g, X);
   return hipGetLastError();
 }
+
+// ------------------------------------------------------------------------ batched launches
+
+hipError_t launch_batch_prologue_particles(const BeamDev* beams, int nb, const BatchDims& bd,
+                                           hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue_batch, dim3(grid_stride(bd.max_n), nb), dim3(kBlk), 0, s, beams);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                                      int parity, hipStream_t s) {
+  const dim3 grid(grid_items(bd.max_n), nb);
+  if (shape == 1)
+    hipLaunchKernelGGL(k_key_hist_batch<1>, grid, dim3(kBlk), 0, s, beams, parity);
+  else
+    hipLaunchKernelGGL(k_key_hist_batch<2>, grid, dim3(kBlk), 0, s, beams, parity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_build_chunks_batch, dim3(nb), dim3(1024), 0, s, beams);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_batch, grid, dim3(kBlk), 0, s, beams, parity);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                                int parity, hipStream_t s) {
+  const dim3 grid(bd.max_chunks, nb);
+  if (shape == 1)
+    hipLaunchKernelGGL((k_deposit_tiles_batch<1, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
+                       parity);
+  else
+    hipLaunchKernelGGL((k_deposit_tiles_batch<2, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
+                       parity);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_gkd(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
+                            int parity, int j, int n_steps, hipStream_t s) {
+  const dim3 grid(bd.max_chunks, nb);
+  if (shape == 1)
+    hipLaunchKernelGGL((k_gkd_tiles_batch<1, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
+                       j, n_steps);
+  else
+    hipLaunchKernelGGL((k_gkd_tiles_batch<2, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
+                       j, n_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_unpermute(const BeamDev* beams, int nb, const BatchDims& bd, int parity,
+                                  hipStream_t s) {
+  const dim3 grid(grid_items(bd.max_n), nb);
+  hipLaunchKernelGGL(k_id_hist_batch, grid, dim3(kBlk), 0, s, beams, parity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bucket_chunks_batch, dim3(nb), dim3(1024), 0, s, beams);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bucket_scatter_batch, grid, dim3(kBlk), 0, s, beams, parity);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpermute_batch, dim3(grid_stride(bd.max_n), nb), dim3(kBlk), 0, s, beams,
+                     parity);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch_deposit<double>(const BeamDev*, int, const BatchDims&, int, int,
+                                                 hipStream_t);
+template hipError_t launch_batch_deposit<float>(const BeamDev*, int, const BatchDims&, int, int,
+                                                hipStream_t);
+template hipError_t launch_batch_gkd<double>(const BeamDev*, int, const BatchDims&, int, int, int,
+                                             int, hipStream_t);
+template hipError_t launch_batch_gkd<float>(const BeamDev*, int, const BatchDims&, int, int, int,
+                                            int, hipStream_t);
 
 template hipError_t launch_deposit_tiles<double>(const double*, const Geom*, Consts,
                                                  const SortPlan&, const int4*, const uint32_t*,

@@ -1,0 +1,88 @@
+"""GPU reverse sweep (pic_track_adjoint) against the oracle's reverse sweep, and the
+torch.autograd path against the oracle's gradients."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import adjoint as oadj
+from oracle import pic as opic
+
+pytestmark = pytest.mark.gpu
+
+W4 = np.array([0.7, -0.4, 1.3, 0.9])
+LATTICE = ((1.0, 0.5), (-1.0, 0.5), (0.8, 0.45))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_02382_amd as p
+    return p
+
+
+def _setup(lib, n, nodes, shape, grid_fp32=False):
+    cfg = workloads.SMALL
+    xi = workloads.draw_xi(cfg, n=n, seed=11)
+    b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes,
+                 grid_fp32=grid_fp32)
+    xi_d = torch.from_numpy(xi).cuda()
+    b.init_from_normals(cfg.sigma_matrix, xi_d)
+    prob = opic.make_problem(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
+                             nodes, shape)
+    return cfg, b, xi, xi_d, prob
+
+
+@pytest.mark.parametrize("n,nodes,shape,steps,ck", [(3000, (16, 16, 16), 1, 6, 4),
+                                                    (3001, (12, 18, 24), 2, 5, 2)])
+def test_reverse_sweep_matches_oracle(lib, n, nodes, shape, steps, ck):
+    cfg, b, xi, xi_d, prob = _setup(lib, n, nodes, shape)
+    m, dk, lam, dL = b.track_adjoint(LATTICE, steps, W4, ckpt_every=ck, xi=xi_d)
+    ks = np.array([e[0] for e in LATTICE])
+    dss = np.array([e[1] for e in LATTICE])
+    X0 = opic.init_from_normals(cfg.sigma_matrix, xi)
+    J, dk_o, lam_o, _ = oadj.adjoint(X0, ks, dss, steps, prob, W4)
+    _, _, m_o = opic.moments(opic.track(X0, ks, dss, steps, prob))
+    assert np.allclose(m, m_o, rtol=1e-12, atol=0)
+    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    lg = lam.cpu().numpy()
+    for r in range(6):
+        scale = np.abs(lam_o[r]).max()
+        if scale > 0:
+            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
+    dL_o = lam_o @ xi.T
+    assert np.abs(np.array(dL) - dL_o).max() < 1e-10 * np.abs(dL_o).max()
+
+
+def test_fp32_grid_reverse_sweep_close_to_fp64_oracle(lib):
+    cfg, b, xi, xi_d, prob = _setup(lib, 3000, (16, 16, 16), 1, grid_fp32=True)
+    m, dk, lam, _ = b.track_adjoint(LATTICE, 6, W4, ckpt_every=3)
+    ks = np.array([e[0] for e in LATTICE])
+    dss = np.array([e[1] for e in LATTICE])
+    X0 = opic.init_from_normals(cfg.sigma_matrix, xi)
+    _, dk_o, _, _ = oadj.adjoint(X0, ks, dss, 6, prob, W4)
+    assert np.abs(np.array(dk) - dk_o).max() < 1e-4 * np.abs(dk_o).max()
+
+
+def test_autograd_gradients_match_oracle(lib):
+    from paper_2208_02382_amd.autograd import track_moments
+    cfg, b, xi, xi_d, prob = _setup(lib, 2000, (16, 16, 16), 2)
+    S0 = torch.tensor(cfg.sigma_matrix, dtype=torch.float64)
+    S0[0, 1] = S0[1, 0] = 0.2e-6
+    S0.requires_grad_(True)
+    ks = np.array([e[0] for e in LATTICE])
+    dss = np.array([e[1] for e in LATTICE])
+    k = torch.tensor(ks, dtype=torch.float64, requires_grad=True)
+    m = track_moments(S0, k, b, xi_d, dss, 4, ckpt_every=2)
+    J = (torch.tensor(W4) * m).sum()
+    J.backward()
+    S0n = S0.detach().numpy()
+    L = np.linalg.cholesky(S0n)
+    Jo, dk_o, lam_o, _ = oadj.adjoint(L @ xi, ks, dss, 4, prob, W4)
+    G_o = oadj.cholesky_grad(L, xi, lam_o)
+    assert abs(J.item() - Jo) < 1e-12 * abs(Jo)
+    assert np.abs(k.grad.numpy() - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    # torch returns dJ/dA for the full input matrix (symmetric); the oracle's G is the gradient
+    # with respect to the symmetric parameters (off-diagonal pairs move together)
+    g = S0.grad.numpy()
+    G_t = g + g.T - np.diag(np.diag(g))
+    assert np.abs(G_t - G_o).max() < 1e-9 * np.abs(G_o).max()

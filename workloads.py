@@ -66,6 +66,29 @@ ADJOINT = Beam("gauss-1e6-64c-cic-8quads", 1_000_000, (1e-3, 1e-3, 1e-3, 1e-3, 5
 
 CONFIGS = {b.name: b for b in (SMALL, MEDIUM, LARGE, ADJOINT)}
 
+BATCH_NAME = "batch-256-loguniform-1e4-1e6-cic"
+BATCH_GRIDS = (32, 48, 64)
+
+
+def batch_beams(n_beams=256, seed=4, n_range=(1e4, 1e6), grids=BATCH_GRIDS, k_range=(0.5, 2.0),
+                steps=100):
+    """Independent beams of the batched workload: particle counts round(10^U[log10 lo,
+    log10 hi]), cubic grids drawn uniformly from `grids`, and a thin FODO of strength
+    +-k_b with k_b ~ U[k_range] (0.5 m drifts).  The beam family is MEDIUM's (sigma_z 5 mm,
+    CIC); beam b draws its coordinates with seed 1000 + b."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = np.log10(n_range[0]), np.log10(n_range[1])
+    ns = np.rint(10.0 ** rng.uniform(lo, hi, n_beams)).astype(np.int64)
+    gs = rng.integers(0, len(grids), n_beams)
+    ks = rng.uniform(k_range[0], k_range[1], n_beams)
+    out = []
+    for b in range(n_beams):
+        g = int(grids[gs[b]])
+        k = float(ks[b])
+        out.append(MEDIUM.with_(name="%s-b%d" % (BATCH_NAME, b), n=int(ns[b]), nodes=(g, g, g),
+                                steps=steps, lattice=((k, 0.5), (-k, 0.5)), seed=1000 + b))
+    return out
+
 
 def n_halo(n, halo_frac):
     """Number of trailing halo particles."""
