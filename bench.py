@@ -29,8 +29,8 @@ ALGO_BYTES = {
     "deposit": 24,   # read x, y, z
     "gkd": 96,       # read and write the six coordinates
 }
-KERNEL_SOURCES = {"gkd": "paper_2208_02382_amd/csrc/particles.hip",
-                  "deposit": "paper_2208_02382_amd/csrc/particles.hip"}
+KERNEL_SOURCES = {"gkd": "paper_2208_02382_amd/csrc/sort.hip",
+                  "deposit": "paper_2208_02382_amd/csrc/sort.hip"}
 
 
 def _source_hash(rel):
@@ -57,12 +57,29 @@ def _traffic(kernel, workload):
         return None
 
 
-def run_gpu(cfg, steps, warmup, grid_fp32, X=None):
+def _log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def tuned(cfg, grid_fp32, enabled):
+    """Launch tuning of the binned kernels for this workload (cached, else searched now,
+    outside any timed region)."""
+    if not enabled:
+        return None, None
+    from paper_2208_02382_amd import autotune
+    rec = autotune.tune(cfg, grid_fp32=grid_fp32, log=_log)
+    t = {k: rec[k] for k in ("tile", "chunk", "blocks")}
+    return t, {"tuning": t, "tuned_ms_per_step": rec["s_per_step"] * 1e3,
+               "default_ms_per_step": rec["default_s_per_step"] * 1e3,
+               "candidates": len(rec["tried"])}
+
+
+def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None):
     import torch
     import paper_2208_02382_amd as pic
 
     beam = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
-                    cfg.shape, cfg.nodes, grid_fp32=grid_fp32, X=X)
+                    cfg.shape, cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning)
     beam.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
     if warmup:
         beam.track(cfg.lattice, warmup)
@@ -78,6 +95,125 @@ def run_gpu(cfg, steps, warmup, grid_fp32, X=None):
         raise RuntimeError("device error flag set: %s" % pic.STATUS_NAMES.get(st, st))
     mean, cov = beam.moments()
     return beam, t1 - t0, stages, cov
+
+
+def _rms(cov):
+    import math
+    return [math.sqrt(cov[0][0]), math.sqrt(cov[2][2]),
+            math.sqrt(cov[0][0] * cov[1][1] - cov[0][1] ** 2),
+            math.sqrt(cov[2][2] * cov[3][3] - cov[2][3] ** 2)]
+
+
+def fp32_accuracy(cfg, steps):
+    """Relative rms size and emittance differences of the float32-grid path from the float64
+    path (itself equal to the oracle within 1e-12) after `steps` steps from the same beam."""
+    import torch
+    import paper_2208_02382_amd as pic
+
+    out = []
+    for fp32 in (False, True):
+        b = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
+                     cfg.shape, cfg.nodes, grid_fp32=fp32)
+        b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+        t0 = time.perf_counter()
+        b.track(cfg.lattice, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, cov = b.moments()
+        out.append((_rms(cov), dt))
+        b.close()
+    (m64, t64), (m32, t32) = out
+    err = [abs(a - b) / abs(b) for a, b in zip(m32, m64)]
+    return {"workload": cfg.name, "steps": steps,
+            "rel_err_sigx_sigy_epsx_epsy": err, "max_rel_err": max(err),
+            "f64_particle_steps_per_s": cfg.n * steps / t64,
+            "f32_particle_steps_per_s": cfg.n * steps / t32}
+
+
+def run_batched(n_beams, steps, grid_fp32=False, tune=True):
+    """The batched workload in one graph launch per call, against the same beams tracked one
+    after another by pic_track_n_steps (the plain per-beam form)."""
+    import torch
+    import workloads
+    import paper_2208_02382_amd as pic
+
+    cfgs = workloads.batch_beams(n_beams=n_beams, steps=steps)
+    blocks = 0
+    tune_rec = None
+    if tune:
+        from paper_2208_02382_amd import autotune
+        tune_rec = autotune.tune_batch(cfgs, grid_fp32=grid_fp32, log=_log)
+        blocks = tune_rec["blocks_per_beam"]
+    beams = []
+    for c in cfgs:
+        b = pic.Beam(c.n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, c.shape, c.nodes,
+                     grid_fp32=grid_fp32)
+        b.init(c.sigma_matrix, seed=c.seed)
+        beams.append(b)
+    total = sum(c.n for c in cfgs)
+    batch = pic.Batch(beams, [c.lattice for c in cfgs], blocks_per_beam=blocks)
+    t0 = time.perf_counter()
+    batch.track(steps)  # captures and instantiates the graph, then runs it
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch.track(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bad = [i for i, st in enumerate(batch.check()) if st != pic.PIC_OK]
+    if bad:
+        raise RuntimeError("device error flag set on batched beams %s" % bad[:8])
+    t0 = time.perf_counter()
+    for c, b in zip(cfgs, beams):
+        b.track(c.lattice, steps)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    batch.close()
+    for b in beams:
+        b.close()
+    return {"value": total * steps / dt, "unit": "particle-steps/s", "beams": n_beams,
+            "particles_total": total, "steps": steps, "s_per_call": dt,
+            "first_call_s_incl_capture": t_first,
+            "grid_dtype": "f32" if grid_fp32 else "f64", "blocks_per_beam": blocks or 256,
+            "autotune": None if tune_rec is None else
+            {"tried": tune_rec["tried"], "chosen": tune_rec["blocks_per_beam"]},
+            "per_beam_sequential": {"value": total * steps / dt_seq, "s": dt_seq,
+                                    "note": "same beams, one pic_track_n_steps per beam"}}
+
+
+def run_adjoint(cfg, ckpt_every=10):
+    """Forward plus reverse sweep with gradients of w . (sigma_x, sigma_y, eps_x, eps_y) with
+    respect to the quad strengths and the initial sigma matrix, next to the plain forward."""
+    import torch
+    import workloads
+    import paper_2208_02382_amd as pic
+
+    b = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
+                 cfg.nodes)
+    xi = torch.from_numpy(workloads.draw_xi(cfg)).cuda()
+    w = (1.0, 1.0, 1.0, 1.0)
+    b.init_from_normals(cfg.sigma_matrix, xi)
+    b.track_adjoint(cfg.lattice, 2, w, ckpt_every=2, xi=xi)  # warm-up
+    b.init_from_normals(cfg.sigma_matrix, xi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m, dk, lam, dL = b.track_adjoint(cfg.lattice, cfg.steps, w, ckpt_every=ckpt_every, xi=xi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.init_from_normals(cfg.sigma_matrix, xi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.track(cfg.lattice, cfg.steps)
+    torch.cuda.synchronize()
+    dt_fwd = time.perf_counter() - t0
+    if b.check() != pic.PIC_OK:
+        raise RuntimeError("device error flag set in the reverse sweep")
+    b.close()
+    return {"value": cfg.n * cfg.steps / dt, "unit": "particle-steps/s (forward equivalent)",
+            "workload": cfg.name, "steps": cfg.steps, "checkpoint_every": ckpt_every,
+            "s_forward_plus_reverse": dt, "plain_forward": {"value": cfg.n * cfg.steps / dt_fwd,
+                                                           "s": dt_fwd},
+            "objective_terms": m, "dJ_dk": dk}
 
 
 def cpu_baseline(cfg, n_sample):
@@ -122,6 +258,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="particles in the oracle's timed sample (0 disables)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-grid variant")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched variant")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
+    ap.add_argument("--batch-beams", type=int, default=256)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default launch shapes instead of the autotuned ones")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-ref-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (a reference "
                          "of known traffic for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -141,7 +283,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    beam, dt, stages, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False)
+    tuning, tune_info = tuned(cfg, False, not args.no_tune)
+    beam, dt, stages, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, tuning=tuning)
     ps = cfg.n * args.steps / dt
 
     def roof(name, stg):
@@ -163,14 +306,31 @@ def main():
         X = beam.X
         beam.close()
         del beam
-        b32, dt32, st32, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=True, X=X)
+        tuning32, tune32 = tuned(cfg, True, not args.no_tune)
+        b32, dt32, st32, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=True, X=X,
+                                     tuning=tuning32)
         variants["fp32_grid"] = {
             "value": cfg.n * args.steps / dt32, "ms_per_step": dt32 / args.steps * 1e3,
             "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in st32.items()},
+            "autotune": tune32,
             "note": "charge grid, FFT, field and gather in float32; particles and push float64"}
         b32.close()
+        del X
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if not args.no_fp32:
+        variants["fp32_grid_accuracy"] = fp32_accuracy(workloads.MEDIUM, workloads.MEDIUM.steps)
+    if not args.no_batched:
+        variants["batched"] = run_batched(args.batch_beams, args.batch_steps,
+                                          tune=not args.no_tune)
+        torch.cuda.empty_cache()
+        if not args.no_fp32:
+            variants["batched_fp32_grid"] = run_batched(args.batch_beams, args.batch_steps,
+                                                        grid_fp32=True, tune=not args.no_tune)
+            torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        variants["adjoint"] = run_adjoint(workloads.ADJOINT)
+        torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC, "value": ps, "unit": "particle-steps/s", "n_gpus": 1,
@@ -181,6 +341,7 @@ def main():
                    "shape": "TSC" if cfg.shape == 2 else "CIC", "grid_dtype": "f64",
                    "halo_frac": cfg.halo_frac, "lattice": "thin FODO k=+-1/m, 0.5 m"},
         "roofline": kernels[dominant],
+        "autotune": tune_info,
         "kernels": kernels,
         "stage_ms_per_launch": stage_ms,
         "variants": variants,

@@ -72,6 +72,14 @@ typedef struct {
   int grid_fp32;           /* 0: float64 charge grid, FFT and field; 1: float32 (particles and
                               the push stay float64) */
   int space_charge;        /* 0/1 (set_space_charge); 0 makes pic_track_n_steps purely linear */
+  /* Launch tuning of the binned deposit and gather (0 = the library's default for each);
+   * results do not depend on them beyond the float atomics' summation order. */
+  int tile[3];             /* tile edge in nodes per axis for the per-step binning; the tile
+                              count prod(ceil(n_a/tile_a)) must be <= 4096; default
+                              max(4, ceil(n_a/16)) */
+  int chunk;               /* max particles per work item of a tile, 256..2^20; default 8192 */
+  int blocks;              /* workgroups of the binned deposit and gather, 1..65535; default
+                              min(work items, 4096) */
 } pic_beam_desc;
 
 /* One lattice step of pic_track_n_steps: a thin quadrupole of integrated strength k [1/m]
@@ -158,6 +166,8 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
  * same shape and grid precision, space_charge = 1; grids and particle counts may differ).
  * pic_batch_create copies the beams' device descriptors and their lattices (lattices[b] has
  * n_el[b] elements, cycled over the steps) into the caller's workspace d_work
+ * blocks_per_beam (1..65535, 0 = 256) is the workgroup count per beam of the binned deposit
+ * and gather;
  * (pic_batch_workspace_bytes, 256-byte aligned) and synchronises `stream`.  The beams' handles,
  * arrays and workspaces must outlive the batch.
  * pic_track_batch runs n_steps steps of pic_track_n_steps on every beam, with one launch per
@@ -166,8 +176,8 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
  * later calls.  Device errors are reported per beam by pic_check. */
 size_t pic_batch_workspace_bytes(int n_beams, const int* n_el);
 pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
-                            const int* n_el, void* d_work, size_t work_bytes, void* stream,
-                            pic_batch* out);
+                            const int* n_el, int blocks_per_beam, void* d_work,
+                            size_t work_bytes, void* stream, pic_batch* out);
 pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream);
 pic_status pic_batch_destroy(pic_batch bt);
 

@@ -32,7 +32,8 @@ class BeamDesc(ctypes.Structure):
                 ("charge_C", ctypes.c_double), ("kin_energy_MeV", ctypes.c_double),
                 ("mass_MeV", ctypes.c_double), ("shape", ctypes.c_int),
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
-                ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int)]
+                ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int),
+                ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int)]
 
 
 class Element(ctypes.Structure):
@@ -65,7 +66,8 @@ _SIGS = {
                                ctypes.POINTER(_D), _P]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I)]),
     "pic_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(ctypes.POINTER(Element)),
-                              ctypes.POINTER(_I), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+                              ctypes.POINTER(_I), _I, _P, ctypes.c_size_t, _P,
+                              ctypes.POINTER(_P)]),
     "pic_track_batch": (_I, [_P, _I, _P]),
     "pic_batch_destroy": (_I, [_P]),
     "pic_last_error": (ctypes.c_char_p, []),
@@ -93,11 +95,15 @@ def last_error():
 
 
 def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,
-              space_charge=True):
+              space_charge=True, tuning=None):
+    """tuning: None or a dict with any of tile (3 ints), chunk, blocks (0 = default)."""
     nx, ny, nz = nodes
+    t = tuning or {}
+    tile = t.get("tile", (0, 0, 0))
     return BeamDesc(int(n), float(qm_qeeV), float(charge_C), float(kin_energy_MeV),
                     float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
-                    int(bool(space_charge)))
+                    int(bool(space_charge)), (ctypes.c_int * 3)(*[int(v) for v in tile]),
+                    int(t.get("chunk", 0)), int(t.get("blocks", 0)))
 
 
 def workspace_bytes(desc):
@@ -125,9 +131,9 @@ class Beam:
     """
 
     def __init__(self, n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
-                 grid_fp32=False, space_charge=True, device="cuda:0", X=None):
+                 grid_fp32=False, space_charge=True, device="cuda:0", X=None, tuning=None):
         self.desc = make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
-                              grid_fp32, space_charge)
+                              grid_fp32, space_charge, tuning)
         self.device = torch.device(device)
         self.n = int(n)
         self.nodes = tuple(int(v) for v in nodes)
@@ -147,11 +153,13 @@ class Beam:
         self._h = h
 
     @classmethod
-    def from_config(cls, cfg, grid_fp32=False, space_charge=True, device="cuda:0", n=None):
+    def from_config(cls, cfg, grid_fp32=False, space_charge=True, device="cuda:0", n=None,
+                    tuning=None):
         """Build from a workloads.Beam-like object (n, qm_qeeV, charge_C, kin_energy_MeV,
         mass_MeV, shape, nodes)."""
         return cls(cfg.n if n is None else n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV,
-                   cfg.mass_MeV, cfg.shape, cfg.nodes, grid_fp32, space_charge, device)
+                   cfg.mass_MeV, cfg.shape, cfg.nodes, grid_fp32, space_charge, device,
+                   tuning=tuning)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -274,7 +282,7 @@ class Batch:
     count).  The beams share shape and grid precision; particle counts and grids may differ.
     Runs on a stream of its own, ordered after and before torch's current stream."""
 
-    def __init__(self, beams, lattices):
+    def __init__(self, beams, lattices, blocks_per_beam=0):
         if len(beams) != len(lattices) or not beams:
             raise ValueError("one lattice per beam, at least one beam")
         self.beams = list(beams)
@@ -293,7 +301,8 @@ class Batch:
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
-            _check(_lib.pic_batch_create(handles, nb, ptrs, n_el, _ptr(self.work), nbytes,
+            _check(_lib.pic_batch_create(handles, nb, ptrs, n_el, int(blocks_per_beam),
+                                         _ptr(self.work), nbytes,
                                          ctypes.c_void_p(self.stream.cuda_stream),
                                          ctypes.byref(h)), "pic_batch_create")
         self._h = h

@@ -1,0 +1,178 @@
+"""Autotuner of the binned deposit and gather: tile edge, particles per work item and
+workgroup count (pic_beam_desc.tile / chunk / blocks), and the workgroups per beam of a batch.
+
+Each candidate is timed on the device with the library's own tracking loop
+(pic_track_n_steps, or pic_track_batch for a batch) over a few steps of a beam of the
+problem's size, re-initialised to the same seeded state before every candidate.  The search is
+coordinate-wise: tile edge with the default work items, then the work-item size at the best
+tile, then the workgroup count.  Only launch shapes within the library's documented limits are
+tried (tile count <= 4096, the gather's field window within 64 KB of LDS).  Results go into a
+JSON cache keyed by problem class: particle count rounded to a power of two, grid, shape and
+grid precision.  Results do not depend on the tuning beyond the summation order of the float
+atomics.
+"""
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import Batch, Beam, PIC_OK, STATUS_NAMES
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+TILES = (4, 5, 6, 8, 10, 12, 16)
+CHUNKS = (2048, 4096, 8192, 16384, 32768)
+BLOCKS = (0, 1024, 2048, 8192)          # 0: min(work items, 4096)
+BATCH_BLOCKS = (32, 64, 128, 256, 512)
+
+
+def key(n, nodes, shape, grid_fp32):
+    return "n2^%d-%dx%dx%d-%s-%s" % (round(math.log2(max(int(n), 1))), *nodes,
+                                     "tsc" if shape == 2 else "cic",
+                                     "f32" if grid_fp32 else "f64")
+
+
+def load(cache=DEFAULT_CACHE):
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            return json.load(f)
+    return {}
+
+
+def save(table, cache=DEFAULT_CACHE):
+    tmp = cache + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache)
+
+
+def lookup(n, nodes, shape, grid_fp32, cache=DEFAULT_CACHE):
+    """The cached tuning dict (tile, chunk, blocks) of this problem class, or None."""
+    rec = load(cache).get(key(n, nodes, shape, grid_fp32))
+    return None if rec is None else {k: rec[k] for k in ("tile", "chunk", "blocks")}
+
+
+def _tile_ok(tile, nodes, shape, grid_fp32):
+    es = 4 if grid_fp32 else 8
+    ntiles = 1
+    win = 3 * es
+    for t, n in zip(tile, nodes):
+        ntiles *= -(-n // t)
+        win *= t + shape
+    return ntiles <= 4096 and win <= 65536
+
+
+def _time_single(cfg, tuning, grid_fp32, steps, X):
+    b = Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
+             cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning)
+    try:
+        b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+        b.track(cfg.lattice, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.track(cfg.lattice, steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = b.check()
+        if st != PIC_OK:
+            raise RuntimeError("device error during tuning: %s" % STATUS_NAMES.get(st, st))
+        return dt
+    finally:
+        b.close()
+
+
+def tune(cfg, grid_fp32=False, steps=3, cache=DEFAULT_CACHE, force=False, log=None):
+    """Tune one problem class (cfg: n, nodes, shape, sigma_matrix, seed, halo_frac, lattice,
+    species fields); returns the cache record {tile, chunk, blocks, s_per_step,
+    default_s_per_step, tried}."""
+    k = key(cfg.n, cfg.nodes, cfg.shape, grid_fp32)
+    table = load(cache) if cache else {}
+    if not force and k in table:
+        return table[k]
+    X = torch.empty((6, cfg.n), dtype=torch.float64, device="cuda")
+    tried = []
+
+    def run(tuning):
+        dt = _time_single(cfg, tuning, grid_fp32, steps, X)
+        tried.append({"tuning": tuning, "s_per_step": dt})
+        if log:
+            log("tune %s %s: %.3f ms/step" % (k, tuning, dt * 1e3))
+        return dt
+
+    default = run({})
+    best, best_t = {}, default
+    for t in TILES:
+        tile = [min(t, n) for n in cfg.nodes]
+        if not _tile_ok(tile, cfg.nodes, cfg.shape, grid_fp32):
+            continue
+        cand = {"tile": tile}
+        dt = run(cand)
+        if dt < best_t:
+            best, best_t = cand, dt
+    for c in CHUNKS:
+        cand = dict(best, chunk=c)
+        dt = run(cand)
+        if dt < best_t:
+            best, best_t = cand, dt
+    for bl in BLOCKS[1:]:
+        cand = dict(best, blocks=bl)
+        dt = run(cand)
+        if dt < best_t:
+            best, best_t = cand, dt
+    del X
+    rec = {"tile": list(best.get("tile", (0, 0, 0))), "chunk": int(best.get("chunk", 0)),
+           "blocks": int(best.get("blocks", 0)), "s_per_step": best_t,
+           "default_s_per_step": default, "steps_timed": steps, "tried": tried}
+    if cache:
+        table = load(cache)
+        table[k] = rec
+        save(table, cache)
+    return rec
+
+
+def tune_batch(cfgs, grid_fp32=False, steps=10, cache=DEFAULT_CACHE, force=False, log=None):
+    """Workgroups per beam of the batched deposit and gather, timed on the batch itself (every
+    beam re-initialised before each candidate).  Per-beam tile and work-item sizes come from
+    the cache where a beam's class is tuned.  Returns {blocks_per_beam, s_per_step, tried}."""
+    k = "batch-%d-beams-n%d-%s-%s" % (len(cfgs), sum(c.n for c in cfgs),
+                                      "tsc" if cfgs[0].shape == 2 else "cic",
+                                      "f32" if grid_fp32 else "f64")
+    table = load(cache) if cache else {}
+    if not force and k in table:
+        return table[k]
+    beams = [Beam(c.n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, c.shape, c.nodes,
+                  grid_fp32=grid_fp32,
+                  tuning=lookup(c.n, c.nodes, c.shape, grid_fp32, cache) if cache else None)
+             for c in cfgs]
+    tried = []
+    best, best_t = None, float("inf")
+    try:
+        for bl in BATCH_BLOCKS:
+            batch = Batch(beams, [c.lattice for c in cfgs], blocks_per_beam=bl)
+            for c, b in zip(cfgs, beams):
+                b.init(c.sigma_matrix, seed=c.seed)
+            batch.track(steps)  # capture
+            torch.cuda.synchronize()
+            for c, b in zip(cfgs, beams):
+                b.init(c.sigma_matrix, seed=c.seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            batch.track(steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            batch.close()
+            tried.append({"blocks_per_beam": bl, "s_per_step": dt})
+            if log:
+                log("tune %s blocks_per_beam=%d: %.3f ms/step" % (k, bl, dt * 1e3))
+            if dt < best_t:
+                best, best_t = bl, dt
+    finally:
+        for b in beams:
+            b.close()
+    rec = {"blocks_per_beam": best, "s_per_step": best_t, "steps_timed": steps, "tried": tried}
+    if cache:
+        table = load(cache)
+        table[k] = rec
+        save(table, cache)
+    return rec

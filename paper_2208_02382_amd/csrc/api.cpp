@@ -72,6 +72,19 @@ pic_status check_desc(const pic_beam_desc* d) {
     if (M > 512 || factor(M, rad) == 0)
       return fail(PIC_EUNSUPPORTED, "padded FFT length 2*n must be 2^a 3^b and <= 512");
   }
+  int64_t ntiles = 1, window = d->grid_fp32 ? 4 : 8;
+  for (int a = 0; a < 3; ++a) {
+    if (d->tile[a] < 0 || d->tile[a] > nn[a]) return fail(PIC_EINVAL, "tile must be in 0..n_a");
+    const int t = d->tile[a] > 0 ? d->tile[a] : std::max(4, (nn[a] + 15) / 16);
+    ntiles *= (nn[a] + t - 1) / t;
+    window *= t + d->shape;
+  }
+  if (ntiles > kMaxTiles) return fail(PIC_EINVAL, "tile count must be <= 4096");
+  // the deposit's charge window of a tile lives in LDS (64 KB per workgroup)
+  if (window > 65536) return fail(PIC_EINVAL, "tile charge window exceeds 64 KB of LDS");
+  if (d->chunk != 0 && (d->chunk < 256 || d->chunk > (1 << 20)))
+    return fail(PIC_EINVAL, "chunk must be 0 or 256..2^20");
+  if (d->blocks < 0 || d->blocks > 65535) return fail(PIC_EINVAL, "blocks must be 0..65535");
   return PIC_OK;
 }
 
@@ -105,7 +118,7 @@ Layout layout(const pic_beam_desc* d) {
   // tracking-loop buffers: two sorted copies of the phase space, particle ids, tile keys,
   // tile histogram / sort cursors and the deposit work list
   const size_t n = (size_t)d->n;
-  const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n);
+  const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks);
   L.XA = take(6 * sizeof(double) * n);
   L.XB = take(6 * sizeof(double) * n);
   L.idA = take(sizeof(uint32_t) * n);
@@ -516,7 +529,7 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->rho = w + L.rho;
   b->phi = w + L.phi;
   b->E = w + L.E;
-  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n);
+  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks);
   b->XA = (double*)(w + L.XA);
   b->XB = (double*)(w + L.XB);
   b->idA = (uint32_t*)(w + L.idA);
@@ -726,13 +739,15 @@ size_t pic_batch_workspace_bytes(int n_beams, const int* n_el) {
 }
 
 pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
-                            const int* n_el, void* d_work, size_t work_bytes, void* stream,
-                            pic_batch* out) {
+                            const int* n_el, int blocks_per_beam, void* d_work,
+                            size_t work_bytes, void* stream, pic_batch* out) {
   if (!out) return fail(PIC_EINVAL, "NULL output handle");
   *out = nullptr;
   if (!beams || !lattices || !n_el || !d_work || n_beams < 1)
     return fail(PIC_EINVAL, "NULL argument or no beams");
   if ((uintptr_t)d_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
+  if (blocks_per_beam < 0 || blocks_per_beam > 65535)
+    return fail(PIC_EINVAL, "blocks_per_beam must be 0..65535");
   const size_t need = pic_batch_workspace_bytes(n_beams, n_el);
   if (need == 0) return fail(PIC_EINVAL, "every beam needs a lattice of >= 1 element");
   if (work_bytes < need) return fail(PIC_ENOMEM, "batch workspace smaller than pic_batch_workspace_bytes");
@@ -789,7 +804,7 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     d.n_el = n_el[b];
   }
   // per-beam work-list blocks of the tiled kernels: the blocks of a beam stride over its chunks
-  bd.max_chunks = 256;
+  bd.max_chunks = blocks_per_beam > 0 ? blocks_per_beam : 256;
   char* w = (char*)d_work;
   BeamDev* dtab = (BeamDev*)w;
   double* dlat = (double*)(w + align256(sizeof(BeamDev) * (size_t)n_beams));

@@ -66,6 +66,8 @@ struct SortPlan {
   int ntiles;
   int chunk;
   int64_t max_chunks;
+  int blocks;  // workgroups of the binned deposit and gather
+  int pad;
 };
 
 // Per-beam device descriptor of a batch: every batched kernel takes its beam from the grid
@@ -129,7 +131,9 @@ template <typename T>
 hipError_t launch_zero(T* p, int64_t count, hipStream_t s);
 
 // ---- sort.hip
-SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n);
+// tile[a], chunk, blocks: 0 selects the default
+SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
+                        int blocks);
 hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, double ell,
                            Consts c, Box* box, hipStream_t s);
 hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,

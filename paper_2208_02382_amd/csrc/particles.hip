@@ -50,8 +50,10 @@ __global__ __launch_bounds__(kBlock) void k_box(const double* __restrict__ X, in
 // particles sit a quarter cell from a node and from a cell boundary: inside every stencil, on
 // no kink of the CIC or TSC weights); the rest-frame cell is (hx, hy, gamma hz).  A non-finite coordinate or a zero extent sets status = -4 (PIC_EDOMAIN),
 // which is sticky until the beam is initialised again.
-__global__ void k_geometry(const Box* box, Geom* g, Consts c) {
-  if (threadIdx.x != 0) return;
+// The origin's product and difference are rounded separately (no fused multiply-add), as a
+// plain float64 evaluation of the same formula does.
+__device__ void geometry_from_box(const Box* box, Geom* g, const Consts& c) {
+#pragma clang fp contract(off)
   int nn[3] = {c.nx, c.ny, c.nz};
   bool bad = box->nonfinite != 0u;
   double lo[3], hi[3];
@@ -65,7 +67,7 @@ __global__ void k_geometry(const Box* box, Geom* g, Consts c) {
     return;
   }
   for (int a = 0; a < 3; ++a) {
-    double h = (hi[a] - lo[a]) / ((double)nn[a] - 3.5);
+    const double h = (hi[a] - lo[a]) / ((double)nn[a] - 3.5);
     g->h[a] = h;
     g->inv_h[a] = 1.0 / h;
     g->origin[a] = lo[a] - 1.25 * h;
@@ -73,6 +75,11 @@ __global__ void k_geometry(const Box* box, Geom* g, Consts c) {
   g->h_rest[0] = g->h[0];
   g->h_rest[1] = g->h[1];
   g->h_rest[2] = c.gamma * g->h[2];
+}
+
+__global__ void k_geometry(const Box* box, Geom* g, Consts c) {
+  if (threadIdx.x != 0) return;
+  geometry_from_box(box, g, c);
 }
 
 // ---------------------------------------------------------------------------- initialisation
@@ -411,31 +418,7 @@ __global__ void k_box_reset_batch(const BeamDev* __restrict__ beams, int nb) {
 __global__ void k_geometry_batch(const BeamDev* __restrict__ beams, int nb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
-  const BeamDev& d = beams[b];
-  const Consts c = d.c;
-  const Box* box = d.box;
-  Geom* g = d.geom;
-  int nn[3] = {c.nx, c.ny, c.nz};
-  bool bad = box->nonfinite != 0u;
-  double lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = ord_dec(box->mn[a]);
-    hi[a] = ord_dec(box->mx[a]);
-    if (!(hi[a] > lo[a])) bad = true;
-  }
-  if (bad) {
-    g->status = -4;
-    return;
-  }
-  for (int a = 0; a < 3; ++a) {
-    double h = (hi[a] - lo[a]) / ((double)nn[a] - 3.5);
-    g->h[a] = h;
-    g->inv_h[a] = 1.0 / h;
-    g->origin[a] = lo[a] - 1.25 * h;
-  }
-  g->h_rest[0] = g->h[0];
-  g->h_rest[1] = g->h[1];
-  g->h_rest[2] = c.gamma * g->h[2];
+  geometry_from_box(beams[b].box, beams[b].geom, beams[b].c);
 }
 
 template <typename T>

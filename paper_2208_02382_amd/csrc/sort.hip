@@ -566,19 +566,25 @@ int grid_stride(int64_t n) {
 
 }  // namespace
 
-SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n) {
+SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
+                        int blocks) {
   SortPlan sp;
   int nn[3] = {nx, ny, nz};
   for (int a = 0; a < 3; ++a) {
     int t = (nn[a] + 15) / 16;
-    sp.T[a] = t < 4 ? 4 : t;
+    if (t < 4) t = 4;
+    sp.T[a] = tile && tile[a] > 0 ? tile[a] : t;
     sp.NT[a] = (nn[a] + sp.T[a] - 1) / sp.T[a];
   }
   sp.ntiles = sp.NT[0] * sp.NT[1] * sp.NT[2];
-  sp.chunk = 8192;
-  sp.max_chunks = (int64_t)(n / sp.chunk) + sp.ntiles + 1;
+  sp.chunk = chunk > 0 ? chunk : 8192;
+  // every tile adds at most one partial work item
+  const int64_t items = (int64_t)(n / sp.chunk) + sp.ntiles + 1;
+  sp.max_chunks = items;
   // the work list also serves the id buckets of the final reordering (up to kMaxTiles entries)
   if (sp.max_chunks < kMaxTiles + 1) sp.max_chunks = kMaxTiles + 1;
+  sp.blocks = blocks > 0 ? blocks : (int)(items < 4096 ? items : 4096);
+  sp.pad = 0;
   return sp;
 }
 
@@ -615,7 +621,7 @@ hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const 
                                 hipStream_t s) {
   const int S = c.shape;
   size_t lds = sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  int64_t grid = sp.max_chunks < 4096 ? sp.max_chunks : 4096;
+  const int64_t grid = sp.blocks;
   if (S == 1)
     hipLaunchKernelGGL((k_deposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, c,
                        sp, chunks, nchunks, rho);
@@ -631,7 +637,7 @@ hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, cons
                             double k_next, double half_next, Box* box, hipStream_t s) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  int64_t grid = sp.max_chunks < 4096 ? sp.max_chunks : 4096;
+  const int64_t grid = sp.blocks;
   if (S == 1)
     hipLaunchKernelGGL((k_gkd_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
                        sp, chunks, nchunks, L, has_next, k_next, half_next, box);

@@ -47,6 +47,36 @@ def test_workspace_bytes_validates_the_description():
     assert pic.workspace_bytes(_desc(kin_energy_MeV=-1.0)) == 0
 
 
+def test_tuning_fields_are_validated():
+    base = pic.workspace_bytes(_desc())
+    assert pic.workspace_bytes(_desc(tuning={"tile": (8, 8, 8), "chunk": 2048, "blocks": 512})) > 0
+    # smaller chunks need a longer work list
+    assert pic.workspace_bytes(_desc(nodes=(64, 64, 64), n=10**6, tuning={"chunk": 256})) > \
+        pic.workspace_bytes(_desc(nodes=(64, 64, 64), n=10**6))
+    assert pic.workspace_bytes(_desc(tuning={"tile": (1, 1, 1)})) == 0     # 32^3 tiles > 4096
+    assert "4096" in pic.last_error()
+    assert pic.workspace_bytes(_desc(tuning={"tile": (33, 4, 4)})) == 0    # tile > n
+    assert pic.workspace_bytes(_desc(tuning={"tile": (32, 32, 8)})) == 0   # window > 64 KB
+    assert "LDS" in pic.last_error()
+    assert pic.workspace_bytes(_desc(tuning={"tile": (-1, 0, 0)})) == 0
+    assert pic.workspace_bytes(_desc(tuning={"chunk": 100})) == 0
+    assert pic.workspace_bytes(_desc(tuning={"blocks": 70000})) == 0
+    assert pic.workspace_bytes(_desc()) == base
+
+
+def test_batch_arguments_are_validated_without_a_device():
+    lib = pic._lib
+    n_el = (ctypes.c_int * 2)(2, 0)
+    assert lib.pic_batch_workspace_bytes(2, n_el) == 0                  # an empty lattice
+    n_el[1] = 3
+    assert lib.pic_batch_workspace_bytes(2, n_el) > 0
+    assert lib.pic_batch_workspace_bytes(0, n_el) == 0
+    out = ctypes.c_void_p()
+    assert lib.pic_batch_create(None, 2, None, n_el, 0, None, 0, None, ctypes.byref(out)) \
+        == pic.PIC_EINVAL
+    assert lib.pic_track_batch(None, 3, None) == pic.PIC_EINVAL
+
+
 def test_create_rejects_bad_arguments_without_touching_a_device():
     lib = pic._lib
     d = _desc()

@@ -1,0 +1,62 @@
+"""Launch tuning: non-default tile / work-item / workgroup shapes keep oracle parity (1e-12 of
+each coordinate's rms), and the autotuner's cache round-trips."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import pic as opic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_02382_amd as p
+    return p
+
+
+@pytest.mark.parametrize("tuning", [
+    {"tile": (4, 4, 4), "chunk": 256, "blocks": 7},     # many work items per tile, few groups
+    {"tile": (8, 6, 12), "chunk": 1024},                # uneven tiles
+    {"tile": (24, 18, 9), "blocks": 3},                 # a few large tiles
+])
+def test_launch_shapes_keep_parity(lib, tuning):
+    cfg = workloads.SMALL
+    n, nodes, shape = 10_007, (24, 18, 36), 2
+    xi = workloads.draw_xi(cfg, n=n)
+    b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes,
+                 tuning=tuning)
+    b.init_from_normals(cfg.sigma_matrix, torch.from_numpy(xi).cuda())
+    b.track(cfg.lattice, 5)
+    prob = opic.make_problem(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
+                             nodes, shape)
+    ks, dss = workloads.lattice_arrays(cfg)
+    Xo = opic.track(opic.init_from_normals(cfg.sigma_matrix, xi), ks, dss, 5, prob)
+    err = (np.abs(b.X.cpu().numpy() - Xo).max(axis=1) / Xo.std(axis=1)).max()
+    assert err < 1e-12
+    assert b.check() == lib.PIC_OK
+
+
+def test_autotune_cache_round_trip(lib, tmp_path):
+    from paper_2208_02382_amd import autotune
+    cfg = workloads.SMALL.with_(n=20_000)
+    cache = str(tmp_path / "tuning.json")
+    rec = autotune.tune(cfg, steps=1, cache=cache)
+    assert set(("tile", "chunk", "blocks", "s_per_step", "tried")) <= set(rec)
+    assert rec["s_per_step"] <= rec["default_s_per_step"]
+    assert len(rec["tried"]) >= 5
+    t = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False, cache=cache)
+    assert t == {k: rec[k] for k in ("tile", "chunk", "blocks")}
+    assert autotune.tune(cfg, steps=1, cache=cache)["tried"] == rec["tried"]   # served cached
+    # the chosen shape is a valid description
+    b = lib.Beam.from_config(cfg, tuning=t)
+    b.close()
+
+
+def test_batch_autotune(lib, tmp_path):
+    from paper_2208_02382_amd import autotune
+    cfgs = workloads.batch_beams(n_beams=4, n_range=(3e3, 2e4), grids=(16, 24), steps=4)
+    rec = autotune.tune_batch(cfgs, steps=2, cache=str(tmp_path / "t.json"))
+    assert rec["blocks_per_beam"] in autotune.BATCH_BLOCKS
+    assert len(rec["tried"]) == len(autotune.BATCH_BLOCKS)
