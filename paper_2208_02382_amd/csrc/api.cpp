@@ -72,7 +72,7 @@ pic_status check_desc(const pic_beam_desc* d) {
     if (M > 512 || factor(M, rad) == 0)
       return fail(PIC_EUNSUPPORTED, "padded FFT length 2*n must be 2^a 3^b and <= 512");
   }
-  int64_t ntiles = 1, window = d->grid_fp32 ? 4 : 8;
+  int64_t ntiles = 1, window = 8;  // the deposit window holds 64-bit fixed-point charges
   for (int a = 0; a < 3; ++a) {
     if (d->tile[a] < 0 || d->tile[a] > nn[a]) return fail(PIC_EINVAL, "tile must be in 0..n_a");
     const int t = d->tile[a] > 0 ? d->tile[a] : std::max(4, (nn[a] + 15) / 16);
@@ -264,7 +264,7 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     HIP_OK(b->prof.end(s), "profile");
     STAGE(b, PIC_STAGE_BIN, s,
           launch_bin(A, idA, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
-                     b->nchunks, B, idB, s),
+                     b->nchunks, B, idB, j == 0, s),
           "binning");
     STAGE(b, PIC_STAGE_DEPOSIT, s,
           launch_deposit_tiles<T>(B, b->geom, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
@@ -450,7 +450,7 @@ pic_status enqueue_batch(const BeamDev* tab, int nb, const BatchDims& bd, int sh
     const int parity = j & 1;
     HIP_OK(launch_batch_geometry(tab, nb, s), "batch");
     HIP_OK(launch_batch_zero_rho<T>(tab, nb, bd, s), "batch");
-    HIP_OK(launch_batch_particles_bin(tab, nb, bd, shape, parity, s), "batch");
+    HIP_OK(launch_batch_particles_bin(tab, nb, bd, shape, parity, j == 0, s), "batch");
     HIP_OK(launch_batch_deposit<T>(tab, nb, bd, shape, parity, s), "batch");
     HIP_OK(launch_batch_green<T>(tab, nb, bd, s), "batch");
     HIP_OK(launch_batch_solve<T>(tab, nb, bd, s), "batch");
@@ -763,13 +763,14 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     if (h->d.shape != shape || h->d.grid_fp32 != fp32 || !h->d.space_charge)
       return fail(PIC_EINVAL, "beams of a batch share shape and grid precision and need space charge");
     const size_t es = fp32 ? 4 : 8;
-    const size_t win = es * (size_t)(h->sp.T[0] + shape) * (h->sp.T[1] + shape) * (h->sp.T[2] + shape);
+    const size_t nodes = (size_t)(h->sp.T[0] + shape) * (h->sp.T[1] + shape) * (h->sp.T[2] + shape);
+    const size_t win = es * nodes;
     if (3 * win > 65536) return fail(PIC_EUNSUPPORTED, "tile window of a batched beam exceeds 64 KB");
     bd.max_n = std::max<int64_t>(bd.max_n, h->d.n);
     bd.max_nx = std::max(bd.max_nx, h->d.nx);
     bd.max_ny = std::max(bd.max_ny, h->d.ny);
     bd.max_nz = std::max(bd.max_nz, h->d.nz);
-    bd.dep_lds = std::max(bd.dep_lds, win);
+    bd.dep_lds = std::max(bd.dep_lds, sizeof(unsigned long long) * nodes);
     bd.gkd_lds = std::max(bd.gkd_lds, 3 * win);
     lat_off[b] = lat.size();
     for (int q = 0; q < n_el[b]; ++q) {

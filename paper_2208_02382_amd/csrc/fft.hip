@@ -35,17 +35,6 @@ struct Cx {
 };
 
 template <typename T>
-__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T>
-__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename T>
-__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename T>
-__device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return {a.x, -a.y}; }
-
-template <typename T>
 struct TwT;
 template <>
 struct TwT<double> {
@@ -56,16 +45,37 @@ struct TwT<float> {
   using type = float2;
 };
 
+// complex load through the native vector type (a struct copy of a conditional load otherwise
+// goes through scratch memory)
+template <typename T>
+__device__ __forceinline__ Cx<T> ld(const Cx<T>* p) {
+  const typename TwT<T>::type t = *reinterpret_cast<const typename TwT<T>::type*>(p);
+  return Cx<T>{t.x, t.y};
+}
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return {a.x, -a.y}; }
+
 constexpr int kLdsElems = 4096;  // complex values per workgroup (64 KB for complex double)
 
-// Radix-R DFT in registers; DIR = -1 forward, +1 inverse (no scaling).
-template <typename T, int DIR>
-__device__ __forceinline__ void dft(Cx<T>* v, int R) {
-  if (R == 2) {
+// Radix-R DFT in registers; DIR = -1 forward, +1 inverse (no scaling).  R is a template
+// parameter so that the butterfly values stay in registers (a runtime radix makes the compiler
+// place them in scratch memory).
+template <typename T, int DIR, int R>
+__device__ __forceinline__ void dft(Cx<T>* v) {
+  if constexpr (R == 2) {
     Cx<T> a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     Cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
     Cx<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
     Cx<T> jt3 = DIR < 0 ? Cx<T>{t3.y, -t3.x} : Cx<T>{-t3.y, t3.x};  // -i t3 or +i t3
@@ -85,50 +95,76 @@ __device__ __forceinline__ void dft(Cx<T>* v, int R) {
   }
 }
 
-// In-place LDS FFT of LB lines of length ax.M (line l at buf[l M]).  Twiddle exp(-2 pi i t/M)
-// is tw[t * tws] (tws = 2 when the table belongs to a transform twice as long).  Requires
-// blockDim.x >= LB M / 4.  Ends with a barrier.
+// One Stockham stage of radix R over LB lines of length M (line stride M + 1): butterfly bf
+// (line l, j < M/R, k = j mod Ns) reads buf[l, j + r M/R], applies the twiddles
+// exp(-+2 pi i r k / (Ns R)) and the radix-R DFT, and writes buf[l, (j / Ns) Ns R + k + r Ns].
+// Each thread takes up to two butterflies; inputs are read before the barrier and outputs
+// written after it.
+template <typename T, int DIR, int R>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int LB, int M, int Ns,
+                                          const typename TwT<T>::type* __restrict__ tw, int tws) {
+  const int MR = M / R;
+  const int nbf = LB * MR;
+  const int NT = blockDim.x;
+  Cx<T> v[2][R];
+  int ob[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int bf = threadIdx.x + q * NT;
+    ob[q] = -1;
+    if (bf < nbf) {
+      const int l = bf / MR, j = bf - l * MR;
+      const int k = j % Ns;
+      const Cx<T>* src = buf + l * (M + 1) + j;
+      const int tstep = k * (M / (Ns * R)) * tws;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        Cx<T> a = src[r * MR];
+        if (r && tstep) {
+          const auto w = tw[r * tstep];
+          a = cmul(a, Cx<T>{(T)w.x, DIR < 0 ? (T)w.y : (T)-w.y});
+        }
+        v[q][r] = a;
+      }
+      dft<T, DIR, R>(v[q]);
+      ob[q] = l * (M + 1) + (j / Ns) * Ns * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (ob[q] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[ob[q] + r * Ns] = v[q][r];
+    }
+  __syncthreads();
+}
+
+// In-place LDS FFT of LB lines of length ax.M (line l at buf[l (M + 1)]: the padding of one
+// element per line spreads the transposed loads and stores of y and z lines over the LDS
+// banks).  Twiddle exp(-2 pi i t/M) is tw[t * tws] (tws = 2 when the table belongs to a
+// transform twice as long).  Requires blockDim.x >= LB M / 4.  Ends with a barrier.
 template <typename T, int DIR>
 __device__ void fft_lds(Cx<T>* buf, int LB, const FftAxis& ax,
                         const typename TwT<T>::type* __restrict__ tw, int tws) {
+  // the planner's radix order: all factors 4, then 2, then 3 (derived from M here, so that
+  // no array is indexed at run time)
   const int M = ax.M;
-  const int NT = blockDim.x;
-  const int tid = threadIdx.x;
-  int Ns = 1;
-  for (int s = 0; s < ax.nrad; ++s) {
-    const int R = ax.rad[s];
-    const int MR = M / R;
-    const int nbf = LB * MR;
-    Cx<T> v[2][4];
-    int ob[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int bf = tid + q * NT;
-      ob[q] = -1;
-      if (bf < nbf) {
-        const int l = bf / MR, j = bf - l * MR;
-        const int k = j % Ns;
-        const Cx<T>* src = buf + l * M + j;
-        const int tstep = k * (M / (Ns * R)) * tws;
-        for (int r = 0; r < R; ++r) {
-          Cx<T> a = src[r * MR];
-          if (r && tstep) {
-            const auto w = tw[r * tstep];
-            a = cmul(a, Cx<T>{(T)w.x, DIR < 0 ? (T)w.y : (T)-w.y});
-          }
-          v[q][r] = a;
-        }
-        dft<T, DIR>(v[q], R);
-        ob[q] = l * M + (j / Ns) * Ns * R + k;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (ob[q] >= 0)
-        for (int r = 0; r < R; ++r) buf[ob[q] + r * Ns] = v[q][r];
-    __syncthreads();
-    Ns *= R;
+  int m = M, Ns = 1;
+  while (m % 4 == 0) {
+    fft_stage<T, DIR, 4>(buf, LB, M, Ns, tw, tws);
+    Ns *= 4;
+    m /= 4;
+  }
+  while (m % 2 == 0) {
+    fft_stage<T, DIR, 2>(buf, LB, M, Ns, tw, tws);
+    Ns *= 2;
+    m /= 2;
+  }
+  while (m % 3 == 0) {
+    fft_stage<T, DIR, 3>(buf, LB, M, Ns, tw, tws);
+    Ns *= 3;
+    m /= 3;
   }
 }
 
@@ -170,14 +206,14 @@ __device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, Fft
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
     double re = a0 < na ? base[(int64_t)a0 * sa + (int64_t)t * st] : 0.0;
     double im = a1 < na ? base[(int64_t)a1 * sa + (int64_t)t * st] : 0.0;
-    buf[l * M + p] = Cx<double>{re, im};
+    buf[l * (M + 1) + p] = Cx<double>{re, im};
   }
   __syncthreads();
   fft_lds<double, -1>(buf, LB, ax, tw, 1);
   for (int idx = threadIdx.x; idx < LB * (n + 1); idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
-    const Cx<double> v = buf[l * M + p];
+    const Cx<double> v = buf[l * (M + 1) + p];
     if (a0 < na) base[(int64_t)a0 * sa + (int64_t)p * st] = v.x;
     if (a1 < na) base[(int64_t)a1 * sa + (int64_t)p * st] = v.y;
   }
@@ -250,7 +286,7 @@ __device__ __forceinline__ void r2c_x_body(const Geom* __restrict__ g,
         else v.y = val;
       }
     }
-    buf[l * H + j] = v;
+    buf[l * (H + 1) + j] = v;
   }
   __syncthreads();
   fft_lds<T, -1>(buf, LB, ax, tw, 2);
@@ -259,8 +295,8 @@ __device__ __forceinline__ void r2c_x_body(const Geom* __restrict__ g,
     const int l = idx / (H + 1), k = idx - l * (H + 1);
     if (l >= nl) continue;
     const int cy = MODE == 0 ? y0 + l : ghost_src(y0 + l, My);
-    const Cx<T> zk = buf[l * H + (k % H)];
-    const Cx<T> zc = cconj(buf[l * H + ((H - k) % H)]);
+    const Cx<T> zk = buf[l * (H + 1) + (k % H)];
+    const Cx<T> zc = cconj(buf[l * (H + 1) + ((H - k) % H)]);
     const Cx<T> e = {(T)0.5 * (zk.x + zc.x), (T)0.5 * (zk.y + zc.y)};
     const Cx<T> dif = csub(zk, zc);
     const Cx<T> o = {(T)0.5 * dif.y, (T)-0.5 * dif.x};  // dif / (2i)
@@ -298,15 +334,16 @@ __device__ __forceinline__ void c2c_y_body(const Geom* __restrict__ g, Cx<T>* __
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     Cx<T> v = {0, 0};
-    if (l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M))) v = base[(int64_t)p * Kx + l];
-    buf[l * M + p] = v;
+    if (l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M))) v = ld(base + (int64_t)p * Kx + l);
+    buf[l * (M + 1) + p] = v;
   }
   __syncthreads();
   fft_lds<T, DIR>(buf, LB, ax, tw, 1);
   const int nout = STAGE == 0 ? M : out_count<MODE>(ny);
   for (int idx = threadIdx.x; idx < LB * nout; idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
-    if (l < nl) base[(int64_t)q * Kx + l] = buf[l * M + (STAGE == 0 ? q : out_src<MODE>(q, M))];
+    if (l < nl)
+      base[(int64_t)q * Kx + l] = buf[l * (M + 1) + (STAGE == 0 ? q : out_src<MODE>(q, M))];
   }
 }
 
@@ -337,8 +374,8 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     Cx<T> v = {0, 0};
-    if (l < nl && src_nonzero<MODE>(p, nz, M)) v = base[(int64_t)p * sz + l];
-    buf[l * M + p] = v;
+    if (l < nl && src_nonzero<MODE>(p, nz, M)) v = ld(base + (int64_t)p * sz + l);
+    buf[l * (M + 1) + p] = v;
   }
   __syncthreads();
   fft_lds<T, -1>(buf, LB, ax, tw, 1);
@@ -349,15 +386,15 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
     const int p = idx / LB, l = idx - p * LB;
     if (l < nl) {
       const T s = grow[(int64_t)fold(p, M) * gplane + l];
-      Cx<T> v = buf[l * M + p];
-      buf[l * M + p] = Cx<T>{v.x * s, v.y * s};
+      Cx<T> v = buf[l * (M + 1) + p];
+      buf[l * (M + 1) + p] = Cx<T>{v.x * s, v.y * s};
     }
   }
   __syncthreads();
   fft_lds<T, +1>(buf, LB, ax, tw, 1);
   for (int idx = threadIdx.x; idx < LB * out_count<MODE>(nz); idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
-    if (l < nl) base[(int64_t)q * sz + l] = buf[l * M + out_src<MODE>(q, M)];
+    if (l < nl) base[(int64_t)q * sz + l] = buf[l * (M + 1) + out_src<MODE>(q, M)];
   }
 }
 
@@ -392,14 +429,14 @@ __device__ __forceinline__ void c2r_x_body(const Geom* __restrict__ g,
     const int l = idx / H, k = idx - l * H;
     Cx<T> v = {0, 0};
     if (l < nl) {
-      const Cx<T> xk = src[(int64_t)l * Kx + k];
-      const Cx<T> xc = cconj(src[(int64_t)l * Kx + (H - k)]);
+      const Cx<T> xk = ld(src + (int64_t)l * Kx + k);
+      const Cx<T> xc = cconj(ld(src + (int64_t)l * Kx + (H - k)));
       const auto w = tw[k];
       const Cx<T> winv = {(T)w.x, (T)-w.y};  // exp(+2 pi i k / M_x)
       const Cx<T> d = cmul(winv, csub(xk, xc));
       v = cadd(cadd(xk, xc), Cx<T>{-d.y, d.x});  // + i d
     }
-    buf[l * H + k] = v;
+    buf[l * (H + 1) + k] = v;
   }
   __syncthreads();
   fft_lds<T, +1>(buf, LB, ax, tw, 2);
@@ -409,7 +446,7 @@ __device__ __forceinline__ void c2r_x_body(const Geom* __restrict__ g,
     const int l = idx / px, q = idx - l * px;
     if (l < nl) {
       const int t = out_src<MODE>(q, M);
-      const Cx<T> zj = buf[l * H + (t >> 1)];
+      const Cx<T> zj = buf[l * (H + 1) + (t >> 1)];
       dst[(int64_t)l * px + q] = (t & 1) ? zj.y : zj.x;
     }
   }
@@ -463,7 +500,7 @@ template <>
 __device__ __forceinline__ const float2* tw_of<float>(const FftPlan& p, int a) { return p.twf[a]; }
 
 __device__ __forceinline__ int lines_per_block(int L, int lines) {
-  int lb = kLdsElems / L;
+  int lb = kLdsElems / (L + 1);
   if (lb < 1) lb = 1;
   return lb > lines ? lines : lb;
 }
@@ -563,7 +600,7 @@ int grid_for(int64_t total) {
 
 // lines per workgroup and threads for transforms of length L over `lines` lines
 void shape_for(int L, int lines, int* LB, int* NT) {
-  int lb = kLdsElems / L;
+  int lb = kLdsElems / (L + 1);
   if (lb < 1) lb = 1;
   if (lb > lines) lb = lines;
   int nt = (lb * L + 3) / 4;
@@ -610,7 +647,7 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
     int LB, NT;
     shape_for(p.full[a].M, ncx, &LB, &NT);
     dim3 grid((ncx + LB - 1) / LB, (unsigned)cfg[a][4]);
-    size_t lds = (size_t)LB * p.full[a].M * sizeof(Cx<double>);
+    size_t lds = (size_t)LB * (p.full[a].M + 1) * sizeof(Cx<double>);
     hipLaunchKernelGGL(k_green_even_dft, grid, dim3(NT), lds, s, gd, p.full[a], p.tw[a],
                        cfg[a][0], cfg[a][1], cfg[a][2], na, LB);
     PIC_TRY(hipGetLastError());
@@ -636,27 +673,27 @@ hipError_t run_passes(const Geom* g, const FftPlan& p, int nx, int ny, int nz, c
   int LB, NT;
   size_t lds;
   shape_for(p.half_x.M, rows_y, &LB, &NT);
-  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>);
   hipLaunchKernelGGL((k_r2c_x<T, MODE>), dim3((rows_y + LB - 1) / LB, rows_z), dim3(NT), lds, s,
                      g, src, W, p.half_x, table<T>(p, 0), nx, ny, nz, Kx, My, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>);
   hipLaunchKernelGGL((k_c2c_y<T, -1, MODE, 0>), dim3((Kx + LB - 1) / LB, rows_z), dim3(NT), lds,
                      s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[2].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[2].M * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[2].M + 1) * sizeof(Cx<T>);
   hipLaunchKernelGGL((k_zconv<T, MODE>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W,
                      gh, p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * p.full[1].M * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>);
   hipLaunchKernelGGL((k_c2c_y<T, +1, MODE, 1>), dim3((Kx + LB - 1) / LB, out_z), dim3(NT), lds,
                      s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.half_x.M, out_y, &LB, &NT);
-  lds = (size_t)LB * p.half_x.M * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>);
   hipLaunchKernelGGL((k_c2r_x<T, MODE>), dim3((out_y + LB - 1) / LB, out_z), dim3(NT), lds, s, g,
                      W, dst, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
   return hipGetLastError();
@@ -690,7 +727,7 @@ template hipError_t launch_solve_ghost_source<float>(const Geom*, const FftPlan&
 namespace {
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 int lpb(int L, int lines) {
-  int lb = kLdsElems / L;
+  int lb = kLdsElems / (L + 1);
   if (lb < 1) lb = 1;
   return lb > lines ? lines : lb;
 }

@@ -138,7 +138,8 @@ hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, 
                            Consts c, Box* box, hipStream_t s);
 hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
                       const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
-                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, hipStream_t s);
+                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, bool staged,
+                      hipStream_t s);
 template <typename T>
 hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
                                 const int4* chunks, const uint32_t* nchunks, T* rho,
@@ -160,7 +161,7 @@ struct BatchDims {      // grid extents over the beams of a batch
   size_t dep_lds, gkd_lds;
 };
 hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
-                                      int parity, hipStream_t s);
+                                      int parity, bool first, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                                 int parity, hipStream_t s);
