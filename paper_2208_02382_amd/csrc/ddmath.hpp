@@ -2,14 +2,14 @@
 //
 // A value is an unevaluated sum hi + lo of two doubles (about 106 bits).  Error-free
 // transformations: Knuth's TwoSum and the FMA form of the exact product (a*b = p + fma(a,b,-p)).
-// Elementary functions:
-//   exp  -- k = round(t/ln2), r = t - k ln2 (ln2 as a double pair), exp(r) = (exp(r/512))^512
-//           with a 14-term Taylor polynomial for exp(r/512) - 1 and nine squarings of 1 + e.
-//   log  -- one Newton step on exp: y0 = log(a.hi) in double, log a = y0 + (a exp(-y0) - 1)
-//           - (a exp(-y0) - 1)^2/2 (the correction is ~1e-16, so two terms suffice).
-//   atan -- a > 1 uses pi/2 - atan(1/a); three halvings t -> t/(1 + sqrt(1 + t^2)) bring the
-//           argument below tan(pi/32); then the alternating Taylor series (18 terms).
+// Elementary functions (table-driven argument reduction, then short series):
+//   log  -- a = 2^e m, m in [1, 2); c = 1 + k/32 nearest m; log a = e ln2 + log c
+//           + 2 atanh(t), t = (m - c)/(m + c), |t| <= 1/128, atanh by 9 series terms.
+//   atan -- a > 1 uses pi/2 - atan(1/a); c = k/32 nearest the argument x in [0, 1];
+//           atan x = atan c + atan(t), t = (x - c)/(1 + x c), |t| <= 1/64, 10 series terms.
 //   sqrt -- Karp-Markstein: one correction of the double reciprocal square root.
+// The tables log(1 + k/32) and atan(k/32) (dd_tables.hpp) are double pairs from 60-digit
+// mpmath; series truncation errors are below 1e-33 relative.
 // No fast-math and no contraction: TwoSum and FastTwoSum are exact only if every + and - is
 // rounded on its own.  hipcc contracts a*b + c into an fma by default in device code, which
 // silently turns these sequences into plain double arithmetic, so contraction is switched off
@@ -19,6 +19,8 @@
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 #include <cmath>
+
+#include "dd_tables.hpp"
 
 // Callable from host code as well, so that the arithmetic can be unit-tested on a CPU.
 #define PIC_HD __host__ __device__
@@ -96,24 +98,6 @@ constexpr double kLn2Lo = 2.31904681384629956e-17;
 constexpr double kPi2Hi = 1.57079632679489656e+00;
 constexpr double kPi2Lo = 6.12323399573676604e-17;
 
-// 1/(k+1)! for k = 0..13 as double pairs (hi = nearest double, lo = remainder).
-constexpr double kInvFact[14][2] = {
-    {1.0, 0.0},
-    {0.5, 0.0},
-    {0.16666666666666666, 9.25185853854297e-18},
-    {0.041666666666666664, 2.3129646346357427e-18},
-    {0.008333333333333333, 1.1564823173178714e-19},
-    {0.001388888888888889, -5.300543954373577e-20},
-    {0.0001984126984126984, 1.7209558293420705e-22},
-    {2.48015873015873e-05, 2.1511947866775882e-23},
-    {2.7557319223985893e-06, -1.858393274046472e-22},
-    {2.755731922398589e-07, 2.3767714622250297e-23},
-    {2.505210838544172e-08, -1.448814070935912e-24},
-    {2.08767569878681e-09, -1.20734505911326e-25},
-    {1.6059043836821613e-10, 1.2585294588752098e-26},
-    {1.1470745597729725e-11, 2.0655512752830745e-28},
-};
-
 // 1/(2k+1) for k = 0..17 as double pairs.
 constexpr double kInvOdd[18][2] = {
     {1.0, 0.0},
@@ -136,48 +120,40 @@ constexpr double kInvOdd[18][2] = {
     {0.02857142857142857, 8.921435019309293e-19},
 };
 
-// exp of a double argument t, |t| < 700, to double-double accuracy.
-PIC_HD inline ddv dd_exp_d(double t) {
-  double k = std::rint(t * 1.4426950408889634);   // t / ln 2
-  // r = t - k ln2; k*kLn2Hi and k*kLn2Lo are formed exactly with two_prod
-  ddv r = dd_sub(dd_make(t), dd_add(two_prod(k, kLn2Hi), two_prod(k, kLn2Lo)));
-  ddv s = {std::ldexp(r.hi, -9), std::ldexp(r.lo, -9)};      // |s| < 6.8e-4
-  // e = exp(s) - 1 = s (1/1! + s (1/2! + ... + s/14!)); truncation error < 1e-50
-  ddv e = {kInvFact[13][0], kInvFact[13][1]};
-  for (int q = 12; q >= 0; --q) e = dd_add(dd_mul(e, s), ddv{kInvFact[q][0], kInvFact[q][1]});
-  e = dd_mul(e, s);
-  // (1 + e)^512 by nine squarings, kept as e: (1 + e)^2 - 1 = 2e + e^2
-  for (int q = 0; q < 9; ++q) e = dd_add(dd_mul_d(e, 2.0), dd_mul(e, e));
-  ddv res = dd_add(dd_make(1.0), e);
-  int ki = (int)k;
-  return {std::ldexp(res.hi, ki), std::ldexp(res.lo, ki)};
-}
-
 // natural log of a positive double-double.
 PIC_HD inline ddv dd_log(ddv a) {
-  double y0 = std::log(a.hi);
-  ddv ex = dd_exp_d(-y0);
-  ddv u = dd_sub(dd_mul(a, ex), dd_make(1.0));   // ~1e-16
-  // log(1+u) = u - u^2/2 + u^3/3: with |u| < 1e-15 the cubic term is below 1e-45
-  ddv corr = dd_sub(u, dd_mul_d(dd_mul(u, u), 0.5));
-  return dd_add(dd_make(y0), corr);
+  int e;
+  std::frexp(a.hi, &e);  // a.hi = f 2^e, f in [1/2, 1)
+  e -= 1;
+  const ddv m = {std::ldexp(a.hi, -e), std::ldexp(a.lo, -e)};  // exact; m.hi in [1, 2)
+  const int k = (int)std::rint((m.hi - 1.0) * 32.0);           // 0..32
+  const double c = 1.0 + (double)k * 0.03125;
+  const ddv t = dd_div(dd_sub(m, dd_make(c)), dd_add(m, dd_make(c)));
+  const ddv t2 = dd_mul(t, t);
+  // atanh t = t sum_{j=0}^{8} t^(2j)/(2j+1); the first omitted term is below 1e-37 t
+  ddv p = {kInvOdd[8][0], kInvOdd[8][1]};
+  for (int j = 7; j >= 0; --j) p = dd_add(dd_mul(p, t2), ddv{kInvOdd[j][0], kInvOdd[j][1]});
+  const ddv at = dd_mul_d(dd_mul(t, p), 2.0);
+  const ddv el2 = dd_add(two_prod((double)e, kLn2Hi), two_prod((double)e, kLn2Lo));
+  return dd_add(dd_add(el2, ddv{kLogTab[k][0], kLogTab[k][1]}), at);
 }
 
 // arctangent of a non-negative double-double.
 PIC_HD inline ddv dd_atan(ddv a) {
-  bool inv = a.hi > 1.0;
-  ddv t = inv ? dd_div(dd_make(1.0), a) : a;
-  for (int q = 0; q < 3; ++q)
-    t = dd_div(t, dd_add(dd_make(1.0), dd_sqrt(dd_add(dd_make(1.0), dd_mul(t, t)))));
-  ddv t2 = dd_mul(t, t);
-  // sum_{k=0}^{17} (-1)^k t^(2k) / (2k+1), Horner from the top term (k = 17 is odd)
-  ddv p = dd_neg(ddv{kInvOdd[17][0], kInvOdd[17][1]});
-  for (int k = 16; k >= 0; --k) {
-    ddv ck = {kInvOdd[k][0], kInvOdd[k][1]};
-    if (k & 1) ck = dd_neg(ck);
-    p = dd_add(dd_mul(p, t2), ck);
+  const bool inv = a.hi > 1.0;
+  const ddv x = inv ? dd_div(dd_make(1.0), a) : a;  // in [0, 1]
+  const int k = (int)std::rint(x.hi * 32.0);          // 0..32
+  const double c = (double)k * 0.03125;
+  const ddv t = dd_div(dd_sub(x, dd_make(c)), dd_add(dd_make(1.0), dd_mul_d(x, c)));
+  const ddv t2 = dd_mul(t, t);
+  // atan t = t sum_{j=0}^{9} (-1)^j t^(2j)/(2j+1); the first omitted term is below 1e-36 t
+  ddv p = dd_neg(ddv{kInvOdd[9][0], kInvOdd[9][1]});
+  for (int j = 8; j >= 0; --j) {
+    ddv cj = {kInvOdd[j][0], kInvOdd[j][1]};
+    if (j & 1) cj = dd_neg(cj);
+    p = dd_add(dd_mul(p, t2), cj);
   }
-  ddv r = dd_mul_d(dd_mul(t, p), 8.0);
+  ddv r = dd_add(ddv{kAtanTab[k][0], kAtanTab[k][1]}, dd_mul(t, p));
   if (inv) r = dd_sub(ddv{kPi2Hi, kPi2Lo}, r);
   return r;
 }

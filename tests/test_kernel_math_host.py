@@ -48,3 +48,12 @@ def test_kernel_igf_equals_oracle(lib, h):
     # both are the cell average rounded once from a double-double value
     assert np.abs(g.reshape(go.shape) - go).max() <= 2.3e-16 * np.abs(go).max()
     assert (np.abs(g.reshape(go.shape) - go) / np.abs(go)).max() < 2.3e-16
+
+
+def test_dd_tables_match_their_generator():
+    import subprocess
+    import sys
+    d = os.path.join(os.path.dirname(LIB), "csrc")
+    out = subprocess.run([sys.executable, os.path.join(d, "gen_dd_tables.py")], check=True,
+                         capture_output=True, text=True).stdout
+    assert out == open(os.path.join(d, "dd_tables.hpp")).read()
