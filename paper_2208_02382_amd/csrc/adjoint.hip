@@ -95,6 +95,35 @@ __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
   }
 }
 
+// Pass A for the binned vector deposit: lam <- drift_T(lam, L/2), and the particle's kick-point
+// position and a = (C L lam_px, C L lam_py, gamma C L lam_delta) written as the rows
+// (r_x, a_x, r_y, a_y, r_z, a_z) of P, the layout the binning and the tiled deposit read.
+__global__ __launch_bounds__(kBlk) void k_adj_stage(const double* __restrict__ X,
+                                                    double* __restrict__ lam,
+                                                    const Geom* __restrict__ g, Consts c,
+                                                    double k, double L, double* __restrict__ P) {
+  if (g->status) return;
+  const int64_t n = c.n;
+  const double ell = 0.5 * L;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    double r[3];
+    kick_point(X, n, i, k, ell, c.inv_gamma2, r);
+    const double lpx = lam[n + i] + ell * lam[i];
+    const double lpy = lam[3 * n + i] + ell * lam[2 * n + i];
+    const double ld = lam[5 * n + i] + ell * lam[4 * n + i] * c.inv_gamma2;
+    lam[n + i] = lpx;
+    lam[3 * n + i] = lpy;
+    lam[5 * n + i] = ld;
+    P[i] = r[0];
+    P[n + i] = c.C * L * lpx;
+    P[2 * n + i] = r[1];
+    P[3 * n + i] = c.C * L * lpy;
+    P[4 * n + i] = r[2];
+    P[5 * n + i] = c.gamma * c.C * L * ld;
+  }
+}
+
 // psi on nodes -1..n ([(nz+2)][(ny+2)][(nx+2)]) = sum_c (e_c(m + 1_c) - e_c(m - 1_c)) / (2 h_c),
 // e_c = 0 outside nodes 0..n-1 (rest-frame spacings).
 template <typename T>
@@ -296,6 +325,12 @@ hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, d
     hipLaunchKernelGGL((k_adj_a<1, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
   else
     hipLaunchKernelGGL((k_adj_a<2, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c, double k,
+                            double L, double* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, P);
   return hipGetLastError();
 }
 

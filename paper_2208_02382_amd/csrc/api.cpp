@@ -192,7 +192,23 @@ struct pic_beam_s {
   uint32_t* cursor;
   int4* chunks;
   uint32_t* nchunks;
+  // the Green spectrum of a step runs on `aux`, concurrently with the binning and deposit
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~pic_beam_s() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
 };
+
+// auxiliary stream (default priority) and fork / join events
+hipError_t make_aux(hipStream_t* aux, hipEvent_t* fork, hipEvent_t* join) {
+  hipError_t e = hipStreamCreateWithFlags(aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(join, hipEventDisableTiming);
+  return e;
+}
 
 namespace {
 
@@ -234,11 +250,13 @@ bool cholesky6(const double* A, Chol& out) {
   } while (0)
 
 template <typename T>
-pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s) {
-  STAGE(b, PIC_STAGE_GREEN, s,
-        launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd,
-                                 (T*)b->Gh, s),
-        "green spectrum");
+pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s,
+                           bool green = true) {
+  if (green)
+    STAGE(b, PIC_STAGE_GREEN, s,
+          launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners,
+                                   b->Gd, (T*)b->Gh, s),
+          "green spectrum");
   STAGE(b, PIC_STAGE_SOLVE, s,
         launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W,
                         (const T*)b->Gh, phi, E, s),
@@ -262,6 +280,15 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "geometry");
     HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "zero rho");
     HIP_OK(b->prof.end(s), "profile");
+    // the Green spectrum depends on the geometry only: it runs on the auxiliary stream while
+    // the particles are binned and deposited
+    HIP_OK(hipEventRecord(b->ev_fork, s), "fork");
+    HIP_OK(hipStreamWaitEvent(b->aux, b->ev_fork, 0), "fork");
+    STAGE(b, PIC_STAGE_GREEN, b->aux,
+          launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners,
+                                   b->Gd, (T*)b->Gh, b->aux),
+          "green spectrum");
+    HIP_OK(hipEventRecord(b->ev_join, b->aux), "join");
     STAGE(b, PIC_STAGE_BIN, s,
           launch_bin(A, idA, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
                      b->nchunks, B, idB, j == 0, s),
@@ -269,7 +296,8 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     STAGE(b, PIC_STAGE_DEPOSIT, s,
           launch_deposit_tiles<T>(B, b->geom, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
           "deposit");
-    pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s);
+    HIP_OK(hipStreamWaitEvent(s, b->ev_join, 0), "join");
+    pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
     if (st != PIC_OK) return st;
     const int has_next = j + 1 < n_steps;
     const pic_element& nx = lat[(j + 1) % n_el];
@@ -299,7 +327,7 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
 
 // ---- reverse sweep workspace (caller-owned, see pic_adjoint_workspace_bytes)
 struct AdjLayout {
-  size_t geoms, ckpt, segX, segE, segG, e, psi, chi, dk, dk_part, dL_part, small, total;
+  size_t geoms, ckpt, segX, segE, segG, e, psi, chi, stage, dk, dk_part, dL_part, small, total;
   int nseg;
 };
 
@@ -325,6 +353,7 @@ AdjLayout adj_layout(const pic_beam_desc* d, int n_steps, int ck) {
   A.e = take(3 * es * ng);
   A.psi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   A.chi = take(es * ng);
+  A.stage = take(6 * sizeof(double) * n);
   A.dk = take(sizeof(double) * kMaxLattice);
   A.dk_part = take(sizeof(double) * kAdjBlocks);
   A.dL_part = take(sizeof(double) * 36 * kAdjBlocks);
@@ -343,7 +372,12 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_e
   HIP_OK(launch_quad_drift(X, e.k, 0.5 * e.ds, b->c, box, s), "adjoint forward");
   if (box) HIP_OK(launch_geometry(box, const_cast<Geom*>(g), b->c, s), "adjoint forward");
   HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "adjoint forward");
-  HIP_OK(launch_deposit<T>(X, g, (T*)b->rho, b->c, s), "adjoint forward");
+  // binned deposit from a tile-sorted copy (XB) of the kick-point state
+  HIP_OK(launch_bin(X, b->idA, g, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks, b->nchunks,
+                    b->XB, b->idB, true, s),
+         "adjoint forward");
+  HIP_OK(launch_deposit_tiles<T>(b->XB, g, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
+         "adjoint forward");
   HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh, s),
          "adjoint forward");
   HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
@@ -371,6 +405,10 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
   T* chi = (T*)(aw + A.chi);
   double* dk = (double*)(aw + A.dk);
   double* small = (double*)(aw + A.small);
+  double* P = (double*)(aw + A.stage);
+  // the binned vector deposit keeps three float64 windows of a tile in LDS (64 KB)
+  const int S = b->d.shape;
+  const bool vtiles = 24 * (size_t)(b->sp.T[0] + S) * (b->sp.T[1] + S) * (b->sp.T[2] + S) <= 65536;
   HIP_OK(launch_zero<uint32_t>((uint32_t*)(aw + A.geoms), (int64_t)(kGeomSlot / 4) * n_steps, s),
          "adjoint setup");
   HIP_OK(launch_zero<double>(dk, kMaxLattice, s), "adjoint setup");
@@ -408,7 +446,17 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
       const pic_element& el = lat[j % n_el];
       const double* Xs = segX + 6 * n * (size_t)q;
       HIP_OK(launch_zero<T>(e, 3 * ng, s), "adjoint");
-      HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el.k, el.ds, e, s), "adjoint");
+      if (vtiles) {
+        // kick-point positions and deposit values, tile-sorted, then the binned vector deposit
+        HIP_OK(launch_adj_stage(Xs, lam, geom(j), b->c, el.k, el.ds, P, s), "adjoint");
+        HIP_OK(launch_bin(P, b->idA, geom(j), b->c, b->sp, b->keys, b->hist, b->cursor,
+                          b->chunks, b->nchunks, b->XB, b->idB, true, s),
+               "adjoint");
+        HIP_OK(launch_vdeposit_tiles<T>(b->XB, geom(j), b->c, b->sp, b->chunks, b->nchunks, e, s),
+               "adjoint");
+      } else {
+        HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el.k, el.ds, e, s), "adjoint");
+      }
       HIP_OK(launch_adj_div<T>(geom(j), e, psi, b->d.nx, b->d.ny, b->d.nz, s), "adjoint");
       HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi, b->W,
                                           segG + G3 * (size_t)q, chi, s),
@@ -443,16 +491,21 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
 // ---- batches of beams tracked by one graph launch
 template <typename T>
 pic_status enqueue_batch(const BeamDev* tab, int nb, const BatchDims& bd, int shape, int n_steps,
-                         hipStream_t s) {
+                         hipStream_t s, hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
   HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
   HIP_OK(launch_batch_prologue_particles(tab, nb, bd, s), "batch");
   for (int j = 0; j < n_steps; ++j) {
     const int parity = j & 1;
     HIP_OK(launch_batch_geometry(tab, nb, s), "batch");
     HIP_OK(launch_batch_zero_rho<T>(tab, nb, bd, s), "batch");
+    // Green spectra on the auxiliary stream, concurrently with binning and deposit
+    HIP_OK(hipEventRecord(fork, s), "batch");
+    HIP_OK(hipStreamWaitEvent(aux, fork, 0), "batch");
+    HIP_OK(launch_batch_green<T>(tab, nb, bd, aux), "batch");
+    HIP_OK(hipEventRecord(join, aux), "batch");
     HIP_OK(launch_batch_particles_bin(tab, nb, bd, shape, parity, j == 0, s), "batch");
     HIP_OK(launch_batch_deposit<T>(tab, nb, bd, shape, parity, s), "batch");
-    HIP_OK(launch_batch_green<T>(tab, nb, bd, s), "batch");
+    HIP_OK(hipStreamWaitEvent(s, join, 0), "batch");
     HIP_OK(launch_batch_solve<T>(tab, nb, bd, s), "batch");
     if (j + 1 < n_steps) HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
     HIP_OK(launch_batch_gkd<T>(tab, nb, bd, shape, parity, j, n_steps, s), "batch");
@@ -471,8 +524,13 @@ struct pic_batch_s {
   BeamDev* table = nullptr;  // device, in the caller's batch workspace
   BatchDims bd;
   std::vector<std::pair<int, hipGraphExec_t>> graphs;  // one instantiated graph per step count
+  hipStream_t aux = nullptr;  // Green spectra, forked from the captured stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~pic_batch_s() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -555,6 +613,7 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   if (e == hipSuccess) e = launch_box_reset(b->box, s);
   if (e == hipSuccess) e = launch_zero<uint32_t>(b->hist, kMaxTiles, s);
   if (e == hipSuccess) e = launch_clear_status(b->geom, s);
+  if (e == hipSuccess) e = make_aux(&b->aux, &b->ev_fork, &b->ev_join);
   if (e != hipSuccess) {
     delete b;
     return fail_hip(e, "beam set-up");
@@ -821,6 +880,11 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
   HIP_OK(hipStreamSynchronize(s), "batch create");
   pic_batch bt = new (std::nothrow) pic_batch_s;
   if (!bt) return fail(PIC_EINVAL, "host allocation of the batch handle failed");
+  const hipError_t ea = make_aux(&bt->aux, &bt->ev_fork, &bt->ev_join);
+  if (ea != hipSuccess) {
+    delete bt;
+    return fail_hip(ea, "batch create");
+  }
   bt->nb = n_beams;
   bt->shape = shape;
   bt->fp32 = fp32;
@@ -841,8 +905,11 @@ pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream) {
     if (g.first == n_steps) exec = g.second;
   if (!exec) {
     HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "batch capture");
-    pic_status st = bt->fp32 ? enqueue_batch<float>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s)
-                             : enqueue_batch<double>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s);
+    pic_status st =
+        bt->fp32 ? enqueue_batch<float>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s, bt->aux,
+                                        bt->ev_fork, bt->ev_join)
+                 : enqueue_batch<double>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s,
+                                         bt->aux, bt->ev_fork, bt->ev_join);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (st != PIC_OK) {

@@ -187,6 +187,13 @@ hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd,
 template <typename T>
 hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, double k,
                         double L, T* e, hipStream_t s);
+hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c, double k,
+                            double L, double* P, hipStream_t s);
+// binned vector deposit; hipErrorInvalidConfiguration if the three windows exceed 64 KB
+template <typename T>
+hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
+                                 const int4* chunks, const uint32_t* nchunks, T* e,
+                                 hipStream_t s);
 template <typename T>
 hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int nz,
                           hipStream_t s);

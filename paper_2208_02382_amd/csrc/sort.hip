@@ -379,6 +379,83 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
   }
 }
 
+// Vector deposit e_c(node) = sum_i W(r_i - node) v_c,i of the binned rows (r_x, v_x, r_y, v_y,
+// r_z, v_z) of B (the reverse sweep's transposed gather), one chunk per workgroup: three
+// float64 LDS windows (the values have both signs), flushed with global atomics.
+template <int S, typename T>
+__device__ __forceinline__ void vdeposit_tiles_body(const double* __restrict__ B,
+                                                    const Geom* __restrict__ g, Consts c,
+                                                    SortPlan sp,
+                                                    const int4* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ nchunks,
+                                                    T* __restrict__ e, int blk, int nblk) {
+  extern __shared__ unsigned char smem_raw[];
+  double* win = reinterpret_cast<double*>(smem_raw);
+  if (g->status) return;
+  const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
+  const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
+  const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
+  const int nw = Wx * Wy * Wz;
+  const int64_t n = c.n;
+  const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
+  const uint32_t nck = *nchunks;
+  for (uint32_t ci = blk; ci < nck; ci += nblk) {
+    const int4 ch = chunks[ci];
+    const int t = ch.x;
+    const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
+    const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
+    for (int w = threadIdx.x; w < 3 * nw; w += kBlk) win[w] = 0.0;
+    __syncthreads();
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+      double wx[S + 1], wy[S + 1], wz[S + 1];
+      const int bx = stencil<S>((B[i] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((B[2 * n + i] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((B[4 * n + i] - o[2]) * ih[2], c.nz, wz);
+      const double v[3] = {B[n + i], B[3 * n + i], B[5 * n + i]};
+      const int lx = bx - ox, ly = by - oy, lz = bz - oz;
+      const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
+                          lz < sp.T[2];
+      for (int a = 0; a <= S; ++a)
+        for (int b = 0; b <= S; ++b) {
+          const double wzy = wz[a] * wy[b];
+          for (int q = 0; q <= S; ++q) {
+            const double w = wzy * wx[q];
+            if (inside) {
+              const int idx = ((lz + a) * Wy + (ly + b)) * Wx + (lx + q);
+              for (int comp = 0; comp < 3; ++comp) atomicAdd(&win[comp * nw + idx], w * v[comp]);
+            } else {
+              const int64_t node = ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + (bx + q);
+              for (int comp = 0; comp < 3; ++comp) add_global(&e[comp * ng + node], (T)(w * v[comp]));
+            }
+          }
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nw; w += kBlk) {
+      const int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
+      const int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
+      if (gx < c.nx && gy < c.ny && gz < c.nz) {
+        const int64_t node = ((int64_t)gz * c.ny + gy) * c.nx + gx;
+        for (int comp = 0; comp < 3; ++comp) {
+          const double v = win[comp * nw + w];
+          if (v != 0.0) add_global(&e[comp * ng + node], (T)v);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kBlk) void k_vdeposit_tiles(const double* __restrict__ B,
+                                                         const Geom* __restrict__ g, Consts c,
+                                                         SortPlan sp,
+                                                         const int4* __restrict__ chunks,
+                                                         const uint32_t* __restrict__ nchunks,
+                                                         T* __restrict__ e) {
+  vdeposit_tiles_body<S, T>(B, g, c, sp, chunks, nchunks, e, blockIdx.x, gridDim.x);
+}
+
 template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
                                                         const Geom* __restrict__ g, Consts c,
@@ -770,6 +847,30 @@ hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const 
                        sp, chunks, nchunks, rho);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
+                                 const int4* chunks, const uint32_t* nchunks, T* e,
+                                 hipStream_t s) {
+  const int S = c.shape;
+  const size_t lds = 3 * sizeof(double) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  const int64_t grid = sp.blocks;
+  if (S == 1)
+    hipLaunchKernelGGL((k_vdeposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g,
+                       c, sp, chunks, nchunks, e);
+  else
+    hipLaunchKernelGGL((k_vdeposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g,
+                       c, sp, chunks, nchunks, e);
+  return hipGetLastError();
+}
+
+template hipError_t launch_vdeposit_tiles<double>(const double*, const Geom*, Consts,
+                                                  const SortPlan&, const int4*, const uint32_t*,
+                                                  double*, hipStream_t);
+template hipError_t launch_vdeposit_tiles<float>(const double*, const Geom*, Consts,
+                                                 const SortPlan&, const int4*, const uint32_t*,
+                                                 float*, hipStream_t);
 
 template <typename T>
 hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
