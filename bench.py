@@ -29,13 +29,28 @@ ALGO_BYTES = {
     "deposit": 24,   # read x, y, z
     "gkd": 96,       # read and write the six coordinates
 }
-KERNEL_SOURCES = {"gkd": "paper_2208_02382_amd/csrc/sort.hip",
-                  "deposit": "paper_2208_02382_amd/csrc/sort.hip"}
+# (file, device function) whose source text the counter figures were taken on
+KERNEL_SOURCES = {"gkd": ("paper_2208_02382_amd/csrc/sort.hip", "gkd_tiles_body"),
+                  "deposit": ("paper_2208_02382_amd/csrc/sort.hip", "deposit_tiles_body")}
 
 
-def _source_hash(rel):
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def function_text(path, name):
+    """Source text of the definition of device function `name` in `path`: from the line that
+    declares it to the first closing brace in column 0 after that."""
+    lines = open(path).read().split("\n")
+    start = next(i for i, l in enumerate(lines)
+                 if ("void %s(" % name) in l and not l.rstrip().endswith(";"))
+    # include the template line above the declaration
+    if start > 0 and lines[start - 1].startswith("template"):
+        start -= 1
+    end = next(i for i in range(start, len(lines)) if lines[i] == "}")
+    return "\n".join(lines[start:end + 1])
+
+
+def _source_hash(kernel):
+    rel, func = KERNEL_SOURCES[kernel]
+    text = function_text(os.path.join(ROOT, rel), func)
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def _traffic(kernel, workload):
@@ -49,7 +64,7 @@ def _traffic(kernel, workload):
         if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256_16", "bytes_per_launch"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha256_16") != _source_hash(KERNEL_SOURCES[kernel]):
+    if rec.get("source_sha256_16") != _source_hash(kernel):
         return None
     try:
         return float(rec["bytes_per_launch"])
@@ -95,6 +110,34 @@ def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None):
         raise RuntimeError("device error flag set: %s" % pic.STATUS_NAMES.get(st, st))
     mean, cov = beam.moments()
     return beam, t1 - t0, stages, cov
+
+
+def measured_copy_gbs(nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), best of `reps`, HIP events
+    on torch's stream: the practical streaming rate next to the published peak."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
+def device_info():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+            "compute_units": p.multi_processor_count,
+            "memory_GiB": round(p.total_memory / 2**30, 1)}
 
 
 def _rms(cov):
@@ -261,6 +304,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched variant")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
     ap.add_argument("--batch-beams", type=int, default=256)
+    ap.add_argument("--only", choices=("batched", "adjoint"),
+                    help="run only this variant (for profiling it) and print its JSON")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes instead of the autotuned ones")
     ap.add_argument("--batch-steps", type=int, default=100)
@@ -270,12 +315,19 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU "
-              "sharding is a design in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+              "sharding is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads
 
     cfg = workloads.CONFIGS[args.workload]
+    if args.only == "batched":
+        print(json.dumps(run_batched(args.batch_beams, args.batch_steps, tune=not args.no_tune)),
+              flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(run_adjoint(workloads.ADJOINT)), flush=True)
+        return
     if args.copy_ref_bytes > 0:
         src = torch.ones(args.copy_ref_bytes, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -298,6 +350,10 @@ def main():
                 "algorithmic_bytes_per_launch": ALGO_BYTES[name] * cfg.n}
 
     kernels = {k: roof(k, stages) for k in ("gkd", "deposit")}
+    copy_gbs = measured_copy_gbs()
+    for k in kernels.values():
+        k["measured_copy_GBs"] = copy_gbs
+        k["frac_of_measured_copy"] = k["achieved"] / copy_gbs
     dominant = max(kernels, key=lambda k: stages[k][0])
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
 
@@ -337,6 +393,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
+        "device": device_info(),
         "config": {"workload": cfg.name, "particles": cfg.n, "grid": list(cfg.nodes),
                    "shape": "TSC" if cfg.shape == 2 else "CIC", "grid_dtype": "f64",
                    "halo_frac": cfg.halo_frac, "lattice": "thin FODO k=+-1/m, 0.5 m"},

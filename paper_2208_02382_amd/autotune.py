@@ -2,7 +2,7 @@
 workgroup count (pic_beam_desc.tile / chunk / blocks), and the workgroups per beam of a batch.
 
 Each candidate is timed on the device with the library's own tracking loop
-(pic_track_n_steps: the per-step stages, timed by the library's HIP events; pic_track_batch
+(pic_track_n_steps: the call's wall time less its once-per-call stages; pic_track_batch
 for a batch: the whole call) over a few steps of a beam of the problem's size,
 re-initialised to the same seeded state before every candidate.  The search is
 coordinate-wise: tile edge with the default work items, then the work-item size at the best
@@ -64,12 +64,14 @@ def _tile_ok(tile, nodes, shape, grid_fp32):
     return ntiles <= 4096 and win <= 65536
 
 
-# stages that run once per step (the prologue and the final reordering run once per call)
-STEP_STAGES = ("geometry", "green", "deposit", "solve", "gkd", "bin")
+# stages that run once per call, alone on the caller's stream
+CALL_STAGES = ("prologue", "unpermute")
 
 
 def _time_single(cfg, tuning, grid_fp32, steps, X):
-    """Mean time of one step's stages (HIP events around each stage) over `steps` steps."""
+    """Mean time of one step over `steps` steps: the call's wall time less its once-per-call
+    stages (timed by the library's HIP events).  Stage times are not summed, because the Green
+    spectrum overlaps the binning and deposit."""
     b = Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
              cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning)
     try:
@@ -77,9 +79,12 @@ def _time_single(cfg, tuning, grid_fp32, steps, X):
         b.track(cfg.lattice, 1)
         torch.cuda.synchronize()
         b.profile_start()
+        t0 = time.perf_counter()
         b.track(cfg.lattice, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
         stages = b.profile_read()
-        dt = sum(stages[k][0] for k in STEP_STAGES) / 1e3 / steps
+        dt = (wall - sum(stages[k][0] for k in CALL_STAGES) / 1e3) / steps
         st = b.check()
         if st != PIC_OK:
             raise RuntimeError("device error during tuning: %s" % STATUS_NAMES.get(st, st))
@@ -88,7 +93,7 @@ def _time_single(cfg, tuning, grid_fp32, steps, X):
         b.close()
 
 
-def tune(cfg, grid_fp32=False, steps=4, cache=DEFAULT_CACHE, force=False, log=None):
+def tune(cfg, grid_fp32=False, steps=6, cache=DEFAULT_CACHE, force=False, log=None):
     """Tune one problem class (cfg: n, nodes, shape, sigma_matrix, seed, halo_frac, lattice,
     species fields); returns the cache record {tile, chunk, blocks, s_per_step,
     default_s_per_step, tried}."""

@@ -217,13 +217,14 @@ __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
   }
 }
 
-// dk[slot] += sum of the per-block partials (in block order)
+// dk[slot] += sum of the per-block partials: one wave, lane l sums partials l, l + 64, ...,
+// then a fixed butterfly (the summation order does not depend on timing)
 __global__ void k_adj_dk_combine(const double* __restrict__ partial, int nblocks,
                                  double* __restrict__ dk, int slot) {
-  if (threadIdx.x != 0) return;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[b];
-  dk[slot] += s;
+  for (int b = threadIdx.x; b < nblocks; b += 64) s += partial[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (threadIdx.x == 0) dk[slot] += s;
 }
 
 // lam = dJ/dX of J = w . (sigma_x, sigma_y, eps_x, eps_y); mom = [mean 6][cov upper 21]

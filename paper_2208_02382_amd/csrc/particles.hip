@@ -363,14 +363,17 @@ __global__ __launch_bounds__(kBlock) void k_mom_sum(const double* __restrict__ X
   }
 }
 
-// combine the per-block partials of slots [s0, s1) in block order; slots 0..5 become means
+// combine the per-block partials of slot s0 + blockIdx.x (one wave per slot: lane l sums the
+// partials of blocks l, l + 64, ..., then a fixed butterfly, so the order does not depend on
+// timing); slots 0..5 become means
 __global__ void k_mom_combine(const double* partial, int nblocks, int s0, int s1, int64_t n,
                               double* out) {
-  int s = s0 + threadIdx.x;
+  const int s = s0 + blockIdx.x;
   if (s >= s1) return;
   double acc = 0.0;
-  for (int b = 0; b < nblocks; ++b) acc += partial[b * kMomentSlots + s];
-  out[s] = acc / (double)n;
+  for (int b = threadIdx.x; b < nblocks; b += 64) acc += partial[b * kMomentSlots + s];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (threadIdx.x == 0) out[s] = acc / (double)n;
 }
 
 // pass 2: per-block sums of the 21 centred products (upper triangle, row-major)
@@ -531,9 +534,9 @@ hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, int has_ne
 hipError_t launch_moments(const double* X, int64_t n, double* partial, double* out,
                           hipStream_t s) {
   hipLaunchKernelGGL(k_mom_sum, dim3(kReduceBlocks), dim3(kBlock), 0, s, X, n, partial);
-  hipLaunchKernelGGL(k_mom_combine, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 0, 6, n, out);
+  hipLaunchKernelGGL(k_mom_combine, dim3(6), dim3(64), 0, s, partial, kReduceBlocks, 0, 6, n, out);
   hipLaunchKernelGGL(k_mom_cov, dim3(kReduceBlocks), dim3(kBlock), 0, s, X, n, out, partial);
-  hipLaunchKernelGGL(k_mom_combine, dim3(1), dim3(64), 0, s, partial, kReduceBlocks, 6, 27, n,
+  hipLaunchKernelGGL(k_mom_combine, dim3(21), dim3(64), 0, s, partial, kReduceBlocks, 6, 27, n,
                      out);
   return hipGetLastError();
 }

@@ -667,6 +667,63 @@ __global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A
 }
 
 
+// Final placement through LDS.  After the bucket scatter, bucket b holds exactly the particles
+// with ids [b 2^sh, (b + 1) 2^sh) (the ids are a permutation of 0..n-1), at those same
+// positions of A.  One workgroup of kUBlk threads takes a bucket: each thread keeps the local
+// offsets (id - b 2^sh) of its kUPer items; then, row by row, the values are dropped into an
+// LDS buffer by offset, 8192 at a time, and written back to X contiguously, so every store is
+// coalesced.  Requires 2^sh <= kUBlk * kUPer (= 32768).
+constexpr int kUBlk = 1024;
+constexpr int kUPer = 32;
+constexpr int kUStage = 8192;
+
+__global__ __launch_bounds__(kUBlk) void k_unpermute_lds(const double* __restrict__ A,
+                                                         const uint32_t* __restrict__ idA,
+                                                         int64_t n, int sh,
+                                                         const Geom* __restrict__ g,
+                                                         double* __restrict__ X) {
+  __shared__ double stage[kUStage];
+  if (g->status) return;  // after a device error X keeps the caller's input
+  const int64_t b0 = (int64_t)blockIdx.x << sh;
+  const int cnt = (int)min((int64_t)1 << sh, n - b0);
+  // 16-bit offsets, two per register (2^sh <= 32768); 0xffff marks no item.  An id outside
+  // the bucket (impossible for a permutation) is dropped, so LDS stays in bounds.
+  uint32_t offp[kUPer / 2];
+#pragma unroll
+  for (int k = 0; k < kUPer; ++k) {
+    const int l = threadIdx.x + k * kUBlk;
+    uint32_t o = 0xffffu;
+    if (l < cnt) {
+      const int64_t d = (int64_t)idA[b0 + l] - b0;
+      if (d >= 0 && d < cnt) o = (uint32_t)d;
+    }
+    if (k & 1)
+      offp[k >> 1] |= o << 16;
+    else
+      offp[k >> 1] = o;
+  }
+  const int nq = (cnt + kUStage - 1) / kUStage;
+  for (int r = 0; r < 6; ++r) {
+    double v[kUPer];
+#pragma unroll
+    for (int k = 0; k < kUPer; ++k) {
+      const int l = threadIdx.x + k * kUBlk;
+      v[k] = l < cnt ? A[r * n + b0 + l] : 0.0;
+    }
+    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+      for (int k = 0; k < kUPer; ++k) {
+        const uint32_t o = (offp[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+        if (o != 0xffffu && (int)(o / kUStage) == q) stage[o % kUStage] = v[k];
+      }
+      __syncthreads();
+      const int len = min(kUStage, cnt - q * kUStage);
+      for (int t = threadIdx.x; t < len; t += kUBlk) X[r * n + b0 + q * kUStage + t] = stage[t];
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------------ batched wrappers
 // beam = blockIdx.y; the current phase-space copy of step j is XA for even j (parity 0).
 
@@ -921,7 +978,10 @@ hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, dou
                      cursor, B, idB);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, B, idB, n, g, X);
+  if (((int64_t)1 << shift) <= (int64_t)kUBlk * kUPer)
+    hipLaunchKernelGGL(k_unpermute_lds, dim3(nb), dim3(kUBlk), 0, s, B, idB, n, shift, g, X);
+  else
+    hipLaunchKernelGGL(k_unpermute, dim3(grid_stride(n)), dim3(kBlk), 0, s, B, idB, n, g, X);
   return hipGetLastError();
 }
 
