@@ -292,18 +292,72 @@ def cpu_baseline(cfg, n_sample):
                       % (n_sample, cfg.n, *cfg.nodes, "TSC" if cfg.shape == 2 else "CIC", dt)}
 
 
+def oracle_timings():
+    """The oracle (NumPy float64, one thread) on every workload: the small case in full, one
+    step of the others (a sample of the particles where the full count would take hours),
+    extrapolated to particle-steps/s; 8 beams of the batched workload; the reverse sweep on a
+    sample of the adjoint workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import workloads
+    from oracle import adjoint as oadj
+    from oracle import pic as opic
+
+    def prob(c, n):
+        return opic.make_problem(n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV,
+                                 c.nodes, c.shape)
+
+    def track_rate(c, n, steps):
+        X = opic.init_from_normals(c.sigma_matrix, workloads.draw_xi(c, n=n))
+        ks, dss = workloads.lattice_arrays(c)
+        t0 = time.perf_counter()
+        opic.track(X, ks, dss, steps, prob(c, n))
+        dt = time.perf_counter() - t0
+        return n * steps / dt, dt
+
+    out = {"cores": 1, "kind": "oracle"}
+    with threadpool_limits(limits=1):
+        r, dt = track_rate(workloads.SMALL, workloads.SMALL.n, workloads.SMALL.steps)
+        out[workloads.SMALL.name] = {"value": r, "s": dt, "sample": "full run (20 steps)"}
+        r, dt = track_rate(workloads.MEDIUM, workloads.MEDIUM.n, 1)
+        out[workloads.MEDIUM.name] = {"value": r, "s": dt, "sample": "1 step of all 1e6 particles"}
+        r, dt = track_rate(workloads.LARGE, 1_000_000, 1)
+        out[workloads.LARGE.name] = {"value": r, "s": dt,
+                                     "sample": "1 step of 1e6 of the 1e8 particles, full grid"}
+        beams = workloads.batch_beams()[:8]
+        tot_n, tot_t = 0, 0.0
+        for c in beams:
+            _, dt = track_rate(c, c.n, 1)
+            tot_n += c.n
+            tot_t += dt
+        out[workloads.BATCH_NAME] = {"value": tot_n / tot_t, "s": tot_t,
+                                     "sample": "1 step of each of the first 8 beams"}
+        c = workloads.ADJOINT
+        n = 50_000
+        X = opic.init_from_normals(c.sigma_matrix, workloads.draw_xi(c, n=n))
+        ks, dss = workloads.lattice_arrays(c)
+        t0 = time.perf_counter()
+        oadj.adjoint(X, ks, dss, 2, prob(c, n), np.ones(4))
+        dt = time.perf_counter() - t0
+        out[c.name] = {"value": n * 2 / dt, "s": dt, "unit": "particle-steps/s (forward equivalent)",
+                       "sample": "forward and reverse sweep, 2 steps of 5e4 particles, full grid"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gausshalo-1e8-128c-tsc")
-    ap.add_argument("--cpu-sample", type=int, default=200_000,
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="particles in the oracle's timed sample (0 disables)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-grid variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched variant")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
     ap.add_argument("--batch-beams", type=int, default=256)
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="time the oracle on every workload (host CPU, a few minutes) and exit")
     ap.add_argument("--only", choices=("batched", "adjoint"),
                     help="run only this variant (for profiling it) and print its JSON")
     ap.add_argument("--no-tune", action="store_true",
@@ -317,6 +371,9 @@ def main():
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU "
               "sharding is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.oracle_timings:
+        print(json.dumps({"oracle_timings": oracle_timings()}), flush=True)
+        return
     import torch
     import workloads
 
