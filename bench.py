@@ -173,7 +173,7 @@ def fp32_accuracy(cfg, steps):
             "f32_particle_steps_per_s": cfg.n * steps / t32}
 
 
-def run_batched(n_beams, steps, grid_fp32=False, tune=True):
+def run_batched(n_beams, steps, grid_fp32=False, tune=True, sequential=True):
     """The batched workload in one graph launch per call, against the same beams tracked one
     after another by pic_track_n_steps (the plain per-beam form)."""
     import torch
@@ -206,11 +206,13 @@ def run_batched(n_beams, steps, grid_fp32=False, tune=True):
     bad = [i for i, st in enumerate(batch.check()) if st != pic.PIC_OK]
     if bad:
         raise RuntimeError("device error flag set on batched beams %s" % bad[:8])
-    t0 = time.perf_counter()
-    for c, b in zip(cfgs, beams):
-        b.track(c.lattice, steps)
-    torch.cuda.synchronize()
-    dt_seq = time.perf_counter() - t0
+    dt_seq = None
+    if sequential:
+        t0 = time.perf_counter()
+        for c, b in zip(cfgs, beams):
+            b.track(c.lattice, steps)
+        torch.cuda.synchronize()
+        dt_seq = time.perf_counter() - t0
     batch.close()
     for b in beams:
         b.close()
@@ -220,8 +222,9 @@ def run_batched(n_beams, steps, grid_fp32=False, tune=True):
             "grid_dtype": "f32" if grid_fp32 else "f64", "blocks_per_beam": blocks or 256,
             "autotune": None if tune_rec is None else
             {"tried": tune_rec["tried"], "chosen": tune_rec["blocks_per_beam"]},
-            "per_beam_sequential": {"value": total * steps / dt_seq, "s": dt_seq,
-                                    "note": "same beams, one pic_track_n_steps per beam"}}
+            "per_beam_sequential": None if dt_seq is None else
+            {"value": total * steps / dt_seq, "s": dt_seq,
+             "note": "same beams, one pic_track_n_steps per beam"}}
 
 
 def run_adjoint(cfg, ckpt_every=10):
@@ -360,6 +363,8 @@ def main():
                     help="time the oracle on every workload (host CPU, a few minutes) and exit")
     ap.add_argument("--only", choices=("batched", "adjoint"),
                     help="run only this variant (for profiling it) and print its JSON")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched variant without the beam-by-beam comparison")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes instead of the autotuned ones")
     ap.add_argument("--batch-steps", type=int, default=100)
@@ -379,8 +384,8 @@ def main():
 
     cfg = workloads.CONFIGS[args.workload]
     if args.only == "batched":
-        print(json.dumps(run_batched(args.batch_beams, args.batch_steps, tune=not args.no_tune)),
-              flush=True)
+        print(json.dumps(run_batched(args.batch_beams, args.batch_steps, tune=not args.no_tune,
+                                     sequential=not args.no_sequential)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(run_adjoint(workloads.ADJOINT)), flush=True)

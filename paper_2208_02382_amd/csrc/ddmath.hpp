@@ -75,12 +75,16 @@ PIC_HD __forceinline__ ddv dd_mul_d(ddv a, double b) {
   return fast_two_sum(p.hi, p.lo);
 }
 
+// a / b: three partial quotients, each the current remainder times the double reciprocal of
+// b.hi; the remainders are formed exactly (dd arithmetic), so each step removes the previous
+// quotient's error whatever the reciprocal's rounding (one division instead of three).
 PIC_HD __forceinline__ ddv dd_div(ddv a, ddv b) {
-  double q1 = a.hi / b.hi;
+  const double rb = 1.0 / b.hi;
+  double q1 = a.hi * rb;
   ddv r = dd_sub(a, dd_mul_d(b, q1));
-  double q2 = r.hi / b.hi;
+  double q2 = r.hi * rb;
   r = dd_sub(r, dd_mul_d(b, q2));
-  double q3 = r.hi / b.hi;
+  double q3 = r.hi * rb;
   return dd_add(fast_two_sum(q1, q2), dd_make(q3));
 }
 

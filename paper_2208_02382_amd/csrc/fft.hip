@@ -102,7 +102,7 @@ __device__ __forceinline__ void dft(Cx<T>* v) {
 // written after it.
 template <typename T, int DIR, int R>
 __device__ __forceinline__ void fft_stage(Cx<T>* buf, int LB, int M, int Ns,
-                                          const typename TwT<T>::type* __restrict__ tw, int tws) {
+                                          const typename TwT<T>::type* tw, int tws) {
   const int MR = M / R;
   const int nbf = LB * MR;
   const int NT = blockDim.x;
@@ -145,8 +145,8 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int LB, int M, int Ns,
 // banks).  Twiddle exp(-2 pi i t/M) is tw[t * tws] (tws = 2 when the table belongs to a
 // transform twice as long).  Requires blockDim.x >= LB M / 4.  Ends with a barrier.
 template <typename T, int DIR>
-__device__ void fft_lds(Cx<T>* buf, int LB, const FftAxis& ax,
-                        const typename TwT<T>::type* __restrict__ tw, int tws) {
+__device__ void fft_lds(Cx<T>* buf, int LB, const FftAxis& ax, const typename TwT<T>::type* tw,
+                        int tws) {
   // the planner's radix order: all factors 4, then 2, then 3 (derived from M here, so that
   // no array is indexed at run time)
   const int M = ax.M;
@@ -166,6 +166,17 @@ __device__ void fft_lds(Cx<T>* buf, int LB, const FftAxis& ax,
     Ns *= 3;
     m /= 3;
   }
+}
+
+// Copies `count` twiddles into LDS right after the LB lines of buf (LB (M + 1) elements), so
+// that the stages read them from LDS instead of global memory; ordered before the first stage
+// by the barrier that ends the caller's load phase.
+template <typename T>
+__device__ __forceinline__ const typename TwT<T>::type* stage_twiddles(
+    Cx<T>* buf, int LB, int M, const typename TwT<T>::type* __restrict__ tw, int count) {
+  auto* twl = reinterpret_cast<typename TwT<T>::type*>(buf + LB * (M + 1));
+  for (int t = threadIdx.x; t < count; t += blockDim.x) twl[t] = tw[t];
+  return twl;
 }
 
 // cyclic index of the ghost-inclusive position p = 0..n+1 (node p - 1): M - 1 for p = 0
@@ -208,8 +219,9 @@ __device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, Fft
     double im = a1 < na ? base[(int64_t)a1 * sa + (int64_t)t * st] : 0.0;
     buf[l * (M + 1) + p] = Cx<double>{re, im};
   }
+  const double2* twl = stage_twiddles(buf, LB, M, tw, M);
   __syncthreads();
-  fft_lds<double, -1>(buf, LB, ax, tw, 1);
+  fft_lds<double, -1>(buf, LB, ax, twl, 1);
   for (int idx = threadIdx.x; idx < LB * (n + 1); idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
@@ -288,8 +300,9 @@ __device__ __forceinline__ void r2c_x_body(const Geom* __restrict__ g,
     }
     buf[l * (H + 1) + j] = v;
   }
+  const auto* twl = stage_twiddles(buf, LB, H, tw, M);
   __syncthreads();
-  fft_lds<T, -1>(buf, LB, ax, tw, 2);
+  fft_lds<T, -1>(buf, LB, ax, twl, 2);
   const int cz = MODE == 0 ? z : ghost_src(z, 2 * nz);
   for (int idx = threadIdx.x; idx < LB * (H + 1); idx += blockDim.x) {
     const int l = idx / (H + 1), k = idx - l * (H + 1);
@@ -337,8 +350,9 @@ __device__ __forceinline__ void c2c_y_body(const Geom* __restrict__ g, Cx<T>* __
     if (l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M))) v = ld(base + (int64_t)p * Kx + l);
     buf[l * (M + 1) + p] = v;
   }
+  const auto* twl = stage_twiddles(buf, LB, M, tw, M);
   __syncthreads();
-  fft_lds<T, DIR>(buf, LB, ax, tw, 1);
+  fft_lds<T, DIR>(buf, LB, ax, twl, 1);
   const int nout = STAGE == 0 ? M : out_count<MODE>(ny);
   for (int idx = threadIdx.x; idx < LB * nout; idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
@@ -377,8 +391,9 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
     if (l < nl && src_nonzero<MODE>(p, nz, M)) v = ld(base + (int64_t)p * sz + l);
     buf[l * (M + 1) + p] = v;
   }
+  const auto* twl = stage_twiddles(buf, LB, M, tw, M);
   __syncthreads();
-  fft_lds<T, -1>(buf, LB, ax, tw, 1);
+  fft_lds<T, -1>(buf, LB, ax, twl, 1);
   const int fy = fold(ky, My);
   const T* grow = gh + (int64_t)fy * Kx + a0;
   const int64_t gplane = (int64_t)(ny + 1) * Kx;
@@ -391,7 +406,7 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
     }
   }
   __syncthreads();
-  fft_lds<T, +1>(buf, LB, ax, tw, 1);
+  fft_lds<T, +1>(buf, LB, ax, twl, 1);
   for (int idx = threadIdx.x; idx < LB * out_count<MODE>(nz); idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
     if (l < nl) base[(int64_t)q * sz + l] = buf[l * (M + 1) + out_src<MODE>(q, M)];
@@ -438,8 +453,9 @@ __device__ __forceinline__ void c2r_x_body(const Geom* __restrict__ g,
     }
     buf[l * (H + 1) + k] = v;
   }
+  const auto* twl = stage_twiddles(buf, LB, H, tw, M);
   __syncthreads();
-  fft_lds<T, +1>(buf, LB, ax, tw, 2);
+  fft_lds<T, +1>(buf, LB, ax, twl, 2);
   const int px = out_count<MODE>(nx);
   T* dst = phi + ((int64_t)zz * py + r0) * px;
   for (int idx = threadIdx.x; idx < LB * px; idx += blockDim.x) {
@@ -647,7 +663,8 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
     int LB, NT;
     shape_for(p.full[a].M, ncx, &LB, &NT);
     dim3 grid((ncx + LB - 1) / LB, (unsigned)cfg[a][4]);
-    size_t lds = (size_t)LB * (p.full[a].M + 1) * sizeof(Cx<double>);
+    size_t lds = (size_t)LB * (p.full[a].M + 1) * sizeof(Cx<double>) +
+                 (size_t)p.full[a].M * sizeof(double2);
     hipLaunchKernelGGL(k_green_even_dft, grid, dim3(NT), lds, s, gd, p.full[a], p.tw[a],
                        cfg[a][0], cfg[a][1], cfg[a][2], na, LB);
     PIC_TRY(hipGetLastError());
@@ -673,27 +690,32 @@ hipError_t run_passes(const Geom* g, const FftPlan& p, int nx, int ny, int nz, c
   int LB, NT;
   size_t lds;
   shape_for(p.half_x.M, rows_y, &LB, &NT);
-  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_r2c_x<T, MODE>), dim3((rows_y + LB - 1) / LB, rows_z), dim3(NT), lds, s,
                      g, src, W, p.half_x, table<T>(p, 0), nx, ny, nz, Kx, My, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_c2c_y<T, -1, MODE, 0>), dim3((Kx + LB - 1) / LB, rows_z), dim3(NT), lds,
                      s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[2].M, Kx, &LB, &NT);
-  lds = (size_t)LB * (p.full[2].M + 1) * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[2].M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[2].M * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_zconv<T, MODE>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W,
                      gh, p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.full[1].M, Kx, &LB, &NT);
-  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_c2c_y<T, +1, MODE, 1>), dim3((Kx + LB - 1) / LB, out_z), dim3(NT), lds,
                      s, g, W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
   PIC_TRY(hipGetLastError());
   shape_for(p.half_x.M, out_y, &LB, &NT);
-  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>);
+  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_c2r_x<T, MODE>), dim3((out_y + LB - 1) / LB, out_z), dim3(NT), lds, s, g,
                      W, dst, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
   return hipGetLastError();
@@ -746,7 +768,8 @@ hipError_t launch_batch_green(const BeamDev* beams, int nb, const BatchDims& bd,
     const int ncx = (na[a] + 1) / 2;
     const int gx = ceil_div(ncx, lpb(M[a], ncx));
     hipLaunchKernelGGL(k_green_even_dft_batch, dim3(gx, npl[a], nb), dim3(1024),
-                       (size_t)kLdsElems * sizeof(Cx<double>), s, beams, a);
+                       (size_t)kLdsElems * sizeof(Cx<double>) + 512 * sizeof(double2), s, beams,
+                       a);
     PIC_TRY(hipGetLastError());
   }
   const int64_t total = (int64_t)ex * ey * ez;
@@ -758,7 +781,8 @@ template <typename T>
 hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s) {
   const int nx = bd.max_nx, ny = bd.max_ny, nz = bd.max_nz;
   const int Kx = nx + 1, My = 2 * ny;
-  const size_t lds = (size_t)kLdsElems * sizeof(Cx<T>);
+  // lines plus a twiddle table of at most 512 entries (2 n <= 512)
+  const size_t lds = (size_t)kLdsElems * sizeof(Cx<T>) + 512 * sizeof(typename TwT<T>::type);
   hipLaunchKernelGGL((k_r2c_x_batch<T>), dim3(ceil_div(ny, lpb(nx, ny)), nz, nb), dim3(1024), lds,
                      s, beams);
   PIC_TRY(hipGetLastError());

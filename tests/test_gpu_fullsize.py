@@ -1,0 +1,137 @@
+"""GPU parity at the full workload sizes, in the launch configuration the bench times, on outputs
+the oracle can compute one by one.
+
+* 1e8 particles, 128^3, TSC with halo (the bench's workload and autotuned launch shapes): one
+  step on the GPU; the oracle deposits all particles (in chunks), solves on the full grid and
+  pushes a random sample of particles, which must agree within 1e-12 of each coordinate's rms.
+  The float32-grid variant at the same size: rms sizes and emittances within 1e-5 of float64.
+* The batched workload (256 beams, 6.5e7 particles, one graph): two steps; its four smallest
+  beams against the oracle within 1e-12.
+* The adjoint workload (1e6 particles, 64^3, 8 quads): the reverse sweep over two steps against
+  the oracle's at the full particle count and grid.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import adjoint as oadj
+from oracle import pic as opic
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_02382_amd as p
+    return p
+
+
+def _problem(c, n=None):
+    return opic.make_problem(c.n if n is None else n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV,
+                             c.mass_MeV, c.nodes, c.shape)
+
+
+def _coord_err(Xg, Xo, scale):
+    return (np.abs(Xg - Xo).max(axis=1) / scale).max()
+
+
+def _oracle_field_chunked(X2, prob, chunk=4_000_000):
+    """The oracle's geometry, deposit (summed over particle chunks), Green's function, solve
+    and field for the kick-point positions X2."""
+    geom = opic.geometry(X2, prob)
+    Q = None
+    for s in range(0, X2.shape[1], chunk):
+        q = opic.deposit(X2[:, s:s + chunk], geom, prob)
+        Q = q if Q is None else Q + q
+    phi = opic.solve(Q, opic.green(geom, prob))
+    return geom, opic.field(phi, geom)
+
+
+def test_headline_size_one_step_on_sampled_particles(lib):
+    from paper_2208_02382_amd import autotune
+    cfg = workloads.LARGE
+    tuning = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False)
+    b = lib.Beam.from_config(cfg, tuning=tuning)
+    b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+    X0 = b.X.cpu().numpy()
+    b.track(cfg.lattice, 1)
+    X1 = b.X.cpu().numpy()
+    assert b.check() == lib.PIC_OK
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    prob = _problem(cfg)
+    k, L = cfg.lattice[0]
+    X2 = opic.drift(opic.thin_quad(X0, k), 0.5 * L, prob)
+    del X0
+    geom, E = _oracle_field_chunked(X2, prob)
+    S = np.random.default_rng(11).choice(cfg.n, 2000, replace=False)
+    Xs = X2[:, S]
+    Xo = opic.drift(opic.kick(Xs, opic.gather(E, Xs, geom, prob), L, prob), 0.5 * L, prob)
+    scale = X1[:, ::97].std(axis=1)
+    assert _coord_err(X1[:, S], Xo, scale) < TOL
+
+
+def test_headline_size_fp32_grid_moments(lib):
+    cfg = workloads.LARGE
+    m = []
+    for fp32 in (False, True):
+        b = lib.Beam.from_config(cfg, grid_fp32=fp32)
+        b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+        b.track(cfg.lattice, 2)
+        _, cov = b.moments()
+        cov = np.array(cov)
+        m.append(np.array([np.sqrt(cov[0, 0]), np.sqrt(cov[2, 2]),
+                           np.sqrt(cov[0, 0] * cov[1, 1] - cov[0, 1] ** 2),
+                           np.sqrt(cov[2, 2] * cov[3, 3] - cov[2, 3] ** 2)]))
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    assert np.all(np.abs(m[1] - m[0]) / m[0] < 1e-5)
+
+
+def test_batched_workload_smallest_beams_against_oracle(lib):
+    cfgs = workloads.batch_beams(steps=2)
+    beams = []
+    for c in cfgs:
+        b = lib.Beam.from_config(c)
+        b.init(c.sigma_matrix, seed=c.seed)
+        beams.append(b)
+    pick = sorted(range(len(cfgs)), key=lambda i: cfgs[i].n)[:4]
+    X0 = {i: beams[i].X.cpu().numpy() for i in pick}
+    batch = lib.Batch(beams, [c.lattice for c in cfgs])
+    batch.track(2)
+    torch.cuda.synchronize()
+    assert all(st == lib.PIC_OK for st in batch.check())
+    for i in pick:
+        c = cfgs[i]
+        ks, dss = workloads.lattice_arrays(c)
+        Xo = opic.track(X0[i], ks, dss, 2, _problem(c))
+        assert _coord_err(beams[i].X.cpu().numpy(), Xo, Xo.std(axis=1)) < TOL, c.name
+    batch.close()
+    for b in beams:
+        b.close()
+
+
+def test_adjoint_workload_two_steps_against_oracle(lib):
+    cfg = workloads.ADJOINT
+    xi = workloads.draw_xi(cfg)
+    b = lib.Beam.from_config(cfg)
+    b.init_from_normals(cfg.sigma_matrix, torch.from_numpy(xi).cuda())
+    X0 = b.X.cpu().numpy()
+    w = np.array([0.7, -0.4, 1.3, 0.9])
+    m, dk, lam, _ = b.track_adjoint(cfg.lattice, 2, w, ckpt_every=1)
+    ks, dss = workloads.lattice_arrays(cfg)
+    J, dko, lamo, _ = oadj.adjoint(X0, ks, dss, 2, _problem(cfg), w)
+    assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
+    dk = np.array(dk)
+    assert np.abs(dk - dko).max() < 1e-10 * np.abs(dko).max()
+    lg = lam.cpu().numpy()
+    for r in range(6):
+        scale = np.abs(lamo[r]).max()
+        if scale > 0:
+            assert np.abs(lg[r] - lamo[r]).max() < 1e-10 * scale
+    b.close()

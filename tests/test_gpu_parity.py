@@ -183,3 +183,17 @@ def test_device_errors_are_reported(lib):
     # re-initialising clears the flag
     b2.init_from_normals(cfg.sigma_matrix, torch.from_numpy(workloads.draw_xi(cfg, n=1000)).cuda())
     assert b2.check() == lib.PIC_OK
+
+
+def test_zero_charge_equals_the_linear_map(lib):
+    # a zero bunch charge deposits nothing: the space-charge kick vanishes and tracking reduces
+    # to the linear maps of the lattice
+    cfg = workloads.SMALL.with_(charge_C=0.0)
+    n = 3_001
+    b, X = _start(lib, cfg, n, (16, 16, 16), 2)
+    prob = _problem(cfg, n, (16, 16, 16), 2)
+    ks, dss = workloads.lattice_arrays(cfg)
+    b.track(cfg.lattice, 6)
+    Xo = opic.track(X, ks, dss, 6, prob, space_charge=False)
+    assert _coord_err(b.X.cpu().numpy(), Xo) < 1e-14
+    assert b.check() == lib.PIC_OK
