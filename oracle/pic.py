@@ -236,6 +236,76 @@ def track(X, ks, dss, n_steps, prob: Problem, space_charge=True):
     return X
 
 
+# ----------------------------------------------------------------------------- thick elements
+# Listing 1 of the paper builds its FODO from Drift(ds, nslice) and Quad(ds, k, nslice); with
+# space charge each element is cut into nslice slices, and each slice is the split-operator
+# step of section "Model Assumptions": the element's linear map over half the slice, the
+# space-charge kick over the slice, the map over the other half.  Element kinds:
+THIN, DRIFT, QUAD = 0, 1, 2   # THIN: thin quad k then the space-charge drift ds (one slice)
+
+
+def quad_matrix(k, s):
+    """(x, px) transfer matrix of a quadrupole of strength k [1/m^2] over length s, focusing
+    for k > 0 (x'' = -k x): [[cos p, sin p / sqrt k], [-sqrt k sin p, cos p]], p = sqrt(k) s;
+    cosh / sinh for k < 0; a drift for k = 0.  The y plane sees -k."""
+    if k > 0:
+        r = np.sqrt(k)
+        c, sn = np.cos(r * s), np.sin(r * s)
+        return np.array([[c, sn / r], [-r * sn, c]])
+    if k < 0:
+        r = np.sqrt(-k)
+        c, sn = np.cosh(r * s), np.sinh(r * s)
+        return np.array([[c, sn / r], [r * sn, c]])
+    return np.array([[1.0, s], [0.0, 1.0]])
+
+
+def thick_quad(X, k, s, prob: Problem):
+    """Quadrupole map over length s; the longitudinal plane drifts (z += s delta / gamma^2)."""
+    Mx, My = quad_matrix(k, s), quad_matrix(-k, s)
+    Y = X.copy()
+    Y[0] = Mx[0, 0] * X[0] + Mx[0, 1] * X[1]
+    Y[1] = Mx[1, 0] * X[0] + Mx[1, 1] * X[1]
+    Y[2] = My[0, 0] * X[2] + My[0, 1] * X[3]
+    Y[3] = My[1, 0] * X[2] + My[1, 1] * X[3]
+    Y[4] = X[4] + s * X[5] / (prob.gamma * prob.gamma)
+    return Y
+
+
+def slices(elements):
+    """Expand (kind, k, ds, nslice) elements into the per-step list (kind, k, slice length)."""
+    out = []
+    for kind, k, ds, ns in elements:
+        ns = max(int(ns), 1) if kind != THIN else 1
+        out.extend([(kind, k, ds / ns)] * ns)
+    return out
+
+
+def half_map(X, kind, k, ell, prob: Problem):
+    """The linear map of half a slice of length ell (a thin slice's first half applies its quad
+    first; its second half is the plain drift, see slice_step)."""
+    if kind == QUAD:
+        return thick_quad(X, k, 0.5 * ell, prob)
+    return drift(X, 0.5 * ell, prob)
+
+
+def slice_step(X, kind, k, ell, prob: Problem, space_charge=True):
+    if kind == THIN:
+        return step(X, k, ell, prob, space_charge)
+    X = half_map(X, kind, k, ell, prob)
+    if space_charge:
+        X = kick(X, sc_field(X, prob), ell, prob)
+    return half_map(X, kind, k, ell, prob)
+
+
+def track_elements(X, elements, n_steps, prob: Problem, space_charge=True):
+    """n_steps slices through the lattice (kind, k, ds, nslice), cycled."""
+    sl = slices(elements)
+    for j in range(n_steps):
+        kind, k, ell = sl[j % len(sl)]
+        X = slice_step(X, kind, k, ell, prob, space_charge)
+    return X
+
+
 # ----------------------------------------------------------------------------- statistics
 
 def moments(X):
