@@ -82,12 +82,23 @@ typedef struct {
                               min(work items, 4096) */
 } pic_beam_desc;
 
-/* One lattice step of pic_track_n_steps: a thin quadrupole of integrated strength k [1/m]
- * (px -= k x, py += k y) followed by a space-charge drift of length ds [m] (drift ds/2,
- * space-charge kick over ds, drift ds/2). */
+/* Lattice element kinds (Listing 1 of the paper: Drift(ds, nslice), Quad(ds, k, nslice)).
+ * pic_track_n_steps takes one step per slice, cycling over the expanded slice list; each step
+ * is the split-operator step: the slice's first half map, the space-charge kick over the
+ * slice length, the second half map.
+ *   PIC_ELEM_THIN   one step: thin quadrupole of integrated strength k [1/m] (px -= k x,
+ *                   py += k y), drift ds/2, kick over ds, drift ds/2 (nslice is ignored)
+ *   PIC_ELEM_DRIFT  nslice steps of length ds/nslice: drift, kick, drift (k is ignored)
+ *   PIC_ELEM_QUAD   nslice steps of length l = ds/nslice of a quadrupole of strength k
+ *                   [1/m^2], focusing in x for k > 0: (x, px) <- [[cos p, sin p/sqrt k],
+ *                   [-sqrt k sin p, cos p]] (x, px), p = sqrt(k) l/2, cosh/sinh in y; z drifts
+ * A zero-initialised element is PIC_ELEM_THIN. */
+enum { PIC_ELEM_THIN = 0, PIC_ELEM_DRIFT = 1, PIC_ELEM_QUAD = 2 };
 typedef struct {
-  double k;
-  double ds;
+  double k;     /* strength: [1/m] for PIC_ELEM_THIN, [1/m^2] for PIC_ELEM_QUAD */
+  double ds;    /* length [m], >= 0 */
+  int kind;     /* PIC_ELEM_* */
+  int nslice;   /* slices of a DRIFT or QUAD element, 1..1e6 */
 } pic_element;
 
 typedef struct pic_beam_s* pic_beam;
@@ -152,9 +163,11 @@ pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream);
  * d_Ep is read only by PIC_PUSH_KICK (NULL allowed otherwise). */
 pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* stream);
 
-/* evolve(): n_steps split-operator steps; step j uses lattice[j mod n_el]: thin quad k, drift
- * ds/2, space-charge kick over ds with the field of the positions at that point (geometry,
- * deposit, IGF, Poisson, field, gather), drift ds/2.  Updates X in place; the particle order
+/* evolve(): n_steps split-operator steps, one per lattice slice (see pic_element), cycling over
+ * the slices of lattice[0..n_el): the slice's first half map, the space-charge kick over the
+ * slice length with the field of the positions at that point (geometry, deposit, IGF,
+ * Poisson, field, gather), the second half map.  PIC_EINVAL for an unknown element kind, a
+ * negative or non-finite length, a non-finite strength or nslice outside 1..1e6.  Updates X in place; the particle order
  * of X is preserved (internally the particles are binned by grid tile every step in two
  * workspace copies and returned to X in the caller's order at the end of the call).  With
  * desc.space_charge = 0 only the linear maps are applied.  If the device flags an error
@@ -165,7 +178,8 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
 /* Batched tracking of many independent beams (each created with pic_beam_create, all with the
  * same shape and grid precision, space_charge = 1; grids and particle counts may differ).
  * pic_batch_create copies the beams' device descriptors and their lattices (lattices[b] has
- * n_el[b] elements, cycled over the steps) into the caller's workspace d_work
+ * n_el[b] elements, expanded into slices and cycled over the steps as in pic_track_n_steps)
+ * into the caller's workspace d_work
  * blocks_per_beam (1..65535, 0 = 256) is the workgroup count per beam of the binned deposit
  * and gather;
  * (pic_batch_workspace_bytes, 256-byte aligned) and synchronises `stream`.  The beams' handles,
@@ -174,7 +188,8 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
  * stage covering all beams; the whole n_steps loop is captured into one HIP graph on the first
  * call with that step count (on `stream`, which must not be the null stream) and replayed by
  * later calls.  Device errors are reported per beam by pic_check. */
-size_t pic_batch_workspace_bytes(int n_beams, const int* n_el);
+size_t pic_batch_workspace_bytes(int n_beams, const pic_element* const* lattices,
+                                 const int* n_el);
 pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
                             const int* n_el, int blocks_per_beam, void* d_work,
                             size_t work_bytes, void* stream, pic_batch* out);
@@ -199,7 +214,8 @@ size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt
  *                row-major 6x6 (host); only the lower triangle is a parameter of L.
  * The forward states are checkpointed every ckpt_every steps in the caller's workspace
  * d_adj_work (pic_adjoint_workspace_bytes, 256-byte aligned) and recomputed per segment.
- * Needs desc.space_charge = 1 and 1 <= n_el <= 1024.  Synchronises `stream`; returns the device
+ * Needs desc.space_charge = 1, 1 <= n_el <= 1024 and a thin-lens lattice (PIC_ELEM_THIN
+ * elements only; PIC_EUNSUPPORTED otherwise).  Synchronises `stream`; returns the device
  * error flag of any step (PIC_EDOMAIN). */
 pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              int ckpt_every, const double w[4], void* d_adj_work,

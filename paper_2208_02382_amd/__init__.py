@@ -36,8 +36,12 @@ class BeamDesc(ctypes.Structure):
                 ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int)]
 
 
+ELEM_THIN, ELEM_DRIFT, ELEM_QUAD = 0, 1, 2
+
+
 class Element(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_double), ("ds", ctypes.c_double)]
+    _fields_ = [("k", ctypes.c_double), ("ds", ctypes.c_double), ("kind", ctypes.c_int),
+                ("nslice", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -64,7 +68,8 @@ _SIGS = {
     "pic_track_adjoint": (_I, [_P, ctypes.POINTER(Element), _I, _I, _I, ctypes.POINTER(_D), _P,
                                ctypes.c_size_t, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                ctypes.POINTER(_D), _P]),
-    "pic_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I)]),
+    "pic_batch_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(ctypes.POINTER(Element)),
+                                                     ctypes.POINTER(_I)]),
     "pic_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(ctypes.POINTER(Element)),
                               ctypes.POINTER(_I), _I, _P, ctypes.c_size_t, _P,
                               ctypes.POINTER(_P)]),
@@ -238,7 +243,7 @@ class Beam:
         """Reverse sweep from the current X (= X0): returns (m, dJ/dk, dJ/dX0, dJ/dL or None)
         for J = w . (sigma_x, sigma_y, eps_x, eps_y); X holds the final state afterwards."""
         n_el = len(lattice)
-        arr = (Element * n_el)(*[Element(float(k), float(ds)) for k, ds in lattice])
+        arr = _lattice(lattice)
         nbytes = int(_lib.pic_adjoint_workspace_bytes(ctypes.byref(self.desc), int(n_steps),
                                                       int(ckpt_every)))
         if nbytes == 0:
@@ -272,8 +277,16 @@ class Beam:
         return _lib.pic_check(self._h, _stream())
 
 
+def _element(e):
+    """(k, ds): a thin-lens step; (kind, k, ds, nslice): ELEM_THIN / ELEM_DRIFT / ELEM_QUAD."""
+    if len(e) == 2:
+        return Element(float(e[0]), float(e[1]), ELEM_THIN, 1)
+    kind, k, ds, ns = e
+    return Element(float(k), float(ds), int(kind), int(ns))
+
+
 def _lattice(lattice):
-    return (Element * len(lattice))(*[Element(float(k), float(ds)) for k, ds in lattice])
+    return (Element * len(lattice))(*[_element(e) for e in lattice])
 
 
 class Batch:
@@ -292,7 +305,7 @@ class Batch:
         n_el = (_I * nb)(*[len(l) for l in lattices])
         ptrs = (ctypes.POINTER(Element) * nb)(
             *[ctypes.cast(a, ctypes.POINTER(Element)) for a in self._lats])
-        nbytes = int(_lib.pic_batch_workspace_bytes(nb, n_el))
+        nbytes = int(_lib.pic_batch_workspace_bytes(nb, ptrs, n_el))
         if nbytes == 0:
             raise PicError(PIC_EINVAL, "pic_batch_workspace_bytes")
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -264,8 +264,77 @@ pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s
   return PIC_OK;
 }
 
+// ---- lattice slices (element kinds of pic_element)
+HalfMap half_drift(double ell) {
+  HalfMap h{};
+  h.type = kHalfDrift;
+  h.ell = ell;
+  return h;
+}
+
+HalfMap half_thin(double k, double ell) {
+  HalfMap h{};
+  h.type = kHalfThinDrift;
+  h.k = k;
+  h.ell = ell;
+  return h;
+}
+
+// (x, px) map of a quadrupole of strength k over length s: focusing for k > 0
+void quad_2x2(double k, double s, double m[4]) {
+  if (k > 0) {
+    const double r = std::sqrt(k), c = std::cos(r * s), sn = std::sin(r * s);
+    m[0] = c; m[1] = sn / r; m[2] = -r * sn; m[3] = c;
+  } else if (k < 0) {
+    const double r = std::sqrt(-k), c = std::cosh(r * s), sn = std::sinh(r * s);
+    m[0] = c; m[1] = sn / r; m[2] = r * sn; m[3] = c;
+  } else {
+    m[0] = 1.0; m[1] = s; m[2] = 0.0; m[3] = 1.0;
+  }
+}
+
+HalfMap half_quad(double k, double ell) {
+  HalfMap h{};
+  h.type = kHalfMatrix;
+  quad_2x2(k, ell, h.mx);
+  quad_2x2(-k, ell, h.my);
+  h.mz = ell;
+  return h;
+}
+
+// One tracking step per slice: THIN is the thin quad k followed by the space-charge drift ds
+// (one slice); DRIFT and QUAD elements are cut into nslice slices of ds / nslice, each the
+// element map over half the slice, the kick over the slice, the map over the other half.
+pic_status expand_lattice(const pic_element* lat, int n_el, std::vector<SliceDev>& out) {
+  out.clear();
+  for (int q = 0; q < n_el; ++q) {
+    const pic_element& e = lat[q];
+    if (!std::isfinite(e.k) || !std::isfinite(e.ds) || e.ds < 0.0)
+      return fail(PIC_EINVAL, "lattice element needs finite k and ds >= 0");
+    if (e.kind == PIC_ELEM_THIN) {
+      SliceDev sl{};
+      sl.L = e.ds;
+      sl.first = half_thin(e.k, 0.5 * e.ds);
+      sl.second = half_drift(0.5 * e.ds);
+      out.push_back(sl);
+    } else if (e.kind == PIC_ELEM_DRIFT || e.kind == PIC_ELEM_QUAD) {
+      if (e.nslice < 1 || e.nslice > 1000000) return fail(PIC_EINVAL, "nslice must be 1..1e6");
+      const double ell = e.ds / e.nslice;
+      SliceDev sl{};
+      sl.L = ell;
+      sl.first = e.kind == PIC_ELEM_QUAD ? half_quad(e.k, 0.5 * ell) : half_drift(0.5 * ell);
+      sl.second = sl.first;
+      for (int r = 0; r < e.nslice; ++r) out.push_back(sl);
+    } else {
+      return fail(PIC_EINVAL, "unknown lattice element kind");
+    }
+  }
+  return PIC_OK;
+}
+
 template <typename T>
-pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, hipStream_t s) {
+pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hipStream_t s) {
+  const int ns = (int)sl.size();
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   double* A = b->XA;
   double* B = b->XB;
@@ -273,9 +342,9 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
   uint32_t* idB = b->idB;
   HIP_OK(launch_box_reset(b->box, s), "box reset");
   STAGE(b, PIC_STAGE_PROLOGUE, s,
-        launch_prologue(b->X, A, idA, lat[0].k, 0.5 * lat[0].ds, b->c, b->box, s), "prologue");
+        launch_prologue(b->X, A, idA, sl[0].first, b->c, b->box, s), "prologue");
   for (int j = 0; j < n_steps; ++j) {
-    const pic_element& e = lat[j % n_el];
+    const SliceDev& e = sl[j % ns];
     HIP_OK(b->prof.begin(PIC_STAGE_GEOMETRY, s), "profile");
     HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "geometry");
     HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "zero rho");
@@ -300,7 +369,7 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
     if (st != PIC_OK) return st;
     const int has_next = j + 1 < n_steps;
-    const pic_element& nx = lat[(j + 1) % n_el];
+    const SliceDev& nx = sl[(j + 1) % ns];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
     // the E' window of a tile must fit the 64 KB of LDS a workgroup may use
     const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
@@ -308,11 +377,11 @@ pic_status track_sc(pic_beam b, const pic_element* lat, int n_el, int n_steps, h
     if (win_bytes <= 65536)
       STAGE(b, PIC_STAGE_GKD, s,
             launch_gkd_tiles<T>(B, b->geom, (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks,
-                                e.ds, has_next, nx.k, 0.5 * nx.ds, b->box, s),
+                                e.L, e.second, has_next, nx.first, b->box, s),
             "gather-kick-drift");
     else
       STAGE(b, PIC_STAGE_GKD, s,
-            launch_gkd<T>(B, b->geom, (const T*)b->E, e.ds, has_next, nx.k, 0.5 * nx.ds, b->c,
+            launch_gkd<T>(B, b->geom, (const T*)b->E, e.L, e.second, has_next, nx.first, b->c,
                           b->box, s),
             "gather-kick-drift");
     double* tX = A; A = B; B = tX;
@@ -383,7 +452,8 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_e
   HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
                          (T*)b->phi, E, s),
          "adjoint forward");
-  HIP_OK(launch_gkd<T>(X, g, E, e.ds, 0, 0.0, 0.0, b->c, box, s), "adjoint forward");
+  HIP_OK(launch_gkd<T>(X, g, E, e.ds, half_drift(0.5 * e.ds), 0, half_drift(0.0), b->c, box, s),
+         "adjoint forward");
   return PIC_OK;
 }
 
@@ -706,21 +776,20 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
                              void* stream) {
   if (!b || !lattice) return fail(PIC_EINVAL, "NULL argument");
   if (n_el < 1 || n_steps < 0) return fail(PIC_EINVAL, "n_el must be >= 1 and n_steps >= 0");
-  for (int q = 0; q < n_el; ++q)
-    if (!std::isfinite(lattice[q].k) || !std::isfinite(lattice[q].ds))
-      return fail(PIC_EINVAL, "non-finite lattice element");
+  std::vector<SliceDev> sl;
+  const pic_status est = expand_lattice(lattice, n_el, sl);
+  if (est != PIC_OK) return est;
   if (n_steps == 0) return PIC_OK;
   hipStream_t s = S(stream);
   if (!b->d.space_charge) {
     for (int j = 0; j < n_steps; ++j) {
-      const pic_element& e = lattice[j % n_el];
-      HIP_OK(launch_quad_drift(b->X, e.k, 0.5 * e.ds, b->c, nullptr, s), "track");
-      HIP_OK(launch_push<double>(b->X, PIC_PUSH_DRIFT, 0.5 * e.ds, nullptr, b->c, s), "track");
+      const SliceDev& e = sl[j % sl.size()];
+      HIP_OK(launch_half_maps(b->X, e.first, e.second, b->c, s), "track");
     }
     return PIC_OK;
   }
-  if (b->d.grid_fp32) return track_sc<float>(b, lattice, n_el, n_steps, s);
-  return track_sc<double>(b, lattice, n_el, n_steps, s);
+  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, s);
+  return track_sc<double>(b, sl, n_steps, s);
 }
 
 pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream) {
@@ -772,6 +841,9 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
   if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
   for (int q = 0; q < n_el; ++q)
+    if (lattice[q].kind != PIC_ELEM_THIN)
+      return fail(PIC_EUNSUPPORTED, "the reverse sweep supports thin-lens (PIC_ELEM_THIN) lattices");
+  for (int q = 0; q < n_el; ++q)
     if (!std::isfinite(lattice[q].k) || !std::isfinite(lattice[q].ds))
       return fail(PIC_EINVAL, "non-finite lattice element");
   for (int q = 0; q < 4; ++q)
@@ -787,14 +859,17 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
                                d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);
 }
 
-size_t pic_batch_workspace_bytes(int n_beams, const int* n_el) {
-  if (n_beams < 1 || !n_el) return 0;
-  size_t lat = 0;
+size_t pic_batch_workspace_bytes(int n_beams, const pic_element* const* lattices,
+                                 const int* n_el) {
+  if (n_beams < 1 || !n_el || !lattices) return 0;
+  size_t nsl = 0;
+  std::vector<SliceDev> sl;
   for (int b = 0; b < n_beams; ++b) {
-    if (n_el[b] < 1) return 0;
-    lat += 2 * sizeof(double) * (size_t)n_el[b];
+    if (n_el[b] < 1 || !lattices[b]) return 0;
+    if (expand_lattice(lattices[b], n_el[b], sl) != PIC_OK) return 0;
+    nsl += sl.size();
   }
-  return align256(sizeof(BeamDev) * (size_t)n_beams) + align256(lat);
+  return align256(sizeof(BeamDev) * (size_t)n_beams) + align256(sizeof(SliceDev) * nsl);
 }
 
 pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* const* lattices,
@@ -807,14 +882,14 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
   if ((uintptr_t)d_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
   if (blocks_per_beam < 0 || blocks_per_beam > 65535)
     return fail(PIC_EINVAL, "blocks_per_beam must be 0..65535");
-  const size_t need = pic_batch_workspace_bytes(n_beams, n_el);
+  const size_t need = pic_batch_workspace_bytes(n_beams, lattices, n_el);
   if (need == 0) return fail(PIC_EINVAL, "every beam needs a lattice of >= 1 element");
   if (work_bytes < need) return fail(PIC_ENOMEM, "batch workspace smaller than pic_batch_workspace_bytes");
   const int shape = beams[0] ? beams[0]->d.shape : 0;
   const int fp32 = beams[0] ? beams[0]->d.grid_fp32 : 0;
   BatchDims bd{};
   std::vector<BeamDev> tab(n_beams);
-  std::vector<double> lat;
+  std::vector<SliceDev> all, sl;
   std::vector<size_t> lat_off(n_beams);
   for (int b = 0; b < n_beams; ++b) {
     pic_beam h = beams[b];
@@ -831,13 +906,10 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     bd.max_nz = std::max(bd.max_nz, h->d.nz);
     bd.dep_lds = std::max(bd.dep_lds, sizeof(unsigned long long) * nodes);
     bd.gkd_lds = std::max(bd.gkd_lds, 3 * win);
-    lat_off[b] = lat.size();
-    for (int q = 0; q < n_el[b]; ++q) {
-      if (!std::isfinite(lattices[b][q].k) || !std::isfinite(lattices[b][q].ds))
-        return fail(PIC_EINVAL, "non-finite lattice element");
-      lat.push_back(lattices[b][q].k);
-    }
-    for (int q = 0; q < n_el[b]; ++q) lat.push_back(lattices[b][q].ds);
+    lat_off[b] = all.size();
+    const pic_status est = expand_lattice(lattices[b], n_el[b], sl);
+    if (est != PIC_OK) return est;
+    all.insert(all.end(), sl.begin(), sl.end());
     BeamDev& d = tab[b];
     d.c = h->c;
     d.sp = h->sp;
@@ -861,21 +933,19 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     d.Gd = h->Gd;
     d.Gh = h->Gh;
     d.corners = h->corners;
-    d.n_el = n_el[b];
+    d.n_slices = (int)sl.size();
   }
   // per-beam work-list blocks of the tiled kernels: the blocks of a beam stride over its chunks
   bd.max_chunks = blocks_per_beam > 0 ? blocks_per_beam : 256;
   char* w = (char*)d_work;
   BeamDev* dtab = (BeamDev*)w;
-  double* dlat = (double*)(w + align256(sizeof(BeamDev) * (size_t)n_beams));
-  for (int b = 0; b < n_beams; ++b) {
-    tab[b].lat_k = dlat + lat_off[b];
-    tab[b].lat_ds = dlat + lat_off[b] + n_el[b];
-  }
+  SliceDev* dlat = (SliceDev*)(w + align256(sizeof(BeamDev) * (size_t)n_beams));
+  for (int b = 0; b < n_beams; ++b) tab[b].slices = dlat + lat_off[b];
   hipStream_t s = S(stream);
   HIP_OK(hipMemcpyAsync(dtab, tab.data(), sizeof(BeamDev) * tab.size(), hipMemcpyHostToDevice, s),
          "batch create");
-  HIP_OK(hipMemcpyAsync(dlat, lat.data(), sizeof(double) * lat.size(), hipMemcpyHostToDevice, s),
+  HIP_OK(hipMemcpyAsync(dlat, all.data(), sizeof(SliceDev) * all.size(), hipMemcpyHostToDevice,
+                        s),
          "batch create");
   HIP_OK(hipStreamSynchronize(s), "batch create");
   pic_batch bt = new (std::nothrow) pic_batch_s;

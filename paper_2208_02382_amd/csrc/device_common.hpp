@@ -45,6 +45,26 @@ __device__ __forceinline__ int stencil(double u, int n, double* w) {
   }
 }
 
+// One half of a slice's linear map on the phase-space point v (rows x, px, y, py, z, delta).
+__device__ __forceinline__ void apply_half(const HalfMap& h, double v[6], double inv_g2) {
+  if (h.type == kHalfMatrix) {
+    const double x = v[0], px = v[1], y = v[2], py = v[3];
+    v[0] = h.mx[0] * x + h.mx[1] * px;
+    v[1] = h.mx[2] * x + h.mx[3] * px;
+    v[2] = h.my[0] * y + h.my[1] * py;
+    v[3] = h.my[2] * y + h.my[3] * py;
+    v[4] = v[4] + h.mz * v[5] * inv_g2;
+  } else {
+    if (h.type == kHalfThinDrift) {
+      v[1] = v[1] - h.k * v[0];
+      v[3] = v[3] + h.k * v[2];
+    }
+    v[0] = v[0] + h.ell * v[1];
+    v[2] = v[2] + h.ell * v[3];
+    v[4] = v[4] + h.ell * v[5] * inv_g2;
+  }
+}
+
 // Block-wide min/max of x, y, z, then one atomic per block and axis.
 __device__ __forceinline__ void box_accumulate_block(double lo[3], double hi[3], bool bad, Box* box) {
   __shared__ double slo[3][kBoxBlock / 64], shi[3][kBoxBlock / 64];

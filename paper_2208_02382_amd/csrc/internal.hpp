@@ -70,6 +70,24 @@ struct SortPlan {
   int pad;
 };
 
+// One half of a lattice slice's linear map (applied by apply_half, device_common.hpp).  A slice
+// is the split-operator step: first half map, space-charge kick over L, second half map.
+constexpr int kHalfDrift = 0;      // x += l px, y += l py, z += l delta / gamma^2
+constexpr int kHalfThinDrift = 1;  // thin quad k (px -= k x, py += k y), then the drift l
+constexpr int kHalfMatrix = 2;     // (x, px) <- mx (x, px), (y, py) <- my (y, py),
+                                   // z += mz delta / gamma^2 (thick quadrupole)
+struct HalfMap {
+  int type;
+  int pad;
+  double k, ell;          // kHalfDrift, kHalfThinDrift
+  double mx[4], my[4];    // kHalfMatrix, row-major
+  double mz;              // kHalfMatrix
+};
+struct SliceDev {
+  double L;               // kick length
+  HalfMap first, second;
+};
+
 // Per-beam device descriptor of a batch: every batched kernel takes its beam from the grid
 // (blockIdx.y, or blockIdx.z for the two-dimensional FFT passes) and reads this.
 struct BeamDev {
@@ -95,9 +113,8 @@ struct BeamDev {
   double* Gd;
   void* Gh;
   double2* corners;
-  const double* lat_k;  // lattice of this beam (cycled over the steps)
-  const double* lat_ds;
-  int n_el;
+  const SliceDev* slices;  // lattice of this beam, one entry per slice (cycled over the steps)
+  int n_slices;
   int pad;
 };
 
@@ -123,8 +140,8 @@ template <typename T>
 hipError_t launch_push(double* X, int kind, double value, const T* Ep, Consts c, hipStream_t s);
 hipError_t launch_quad_drift(double* X, double k, double ell, Consts c, Box* box, hipStream_t s);
 template <typename T>
-hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, int has_next, double k_next,
-                      double half_next, Consts c, Box* box, hipStream_t s);
+hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, const HalfMap& second,
+                      int has_next, const HalfMap& first_next, Consts c, Box* box, hipStream_t s);
 hipError_t launch_moments(const double* X, int64_t n, double* partial, double* out,
                           hipStream_t s);
 template <typename T>
@@ -134,7 +151,7 @@ hipError_t launch_zero(T* p, int64_t count, hipStream_t s);
 // tile[a], chunk, blocks: 0 selects the default
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
                         int blocks);
-hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, double ell,
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
                            Consts c, Box* box, hipStream_t s);
 hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
                       const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
@@ -146,8 +163,12 @@ hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const 
                                 hipStream_t s);
 template <typename T>
 hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
-                            const int4* chunks, const uint32_t* nchunks, double L, int has_next,
-                            double k_next, double half_next, Box* box, hipStream_t s);
+                            const int4* chunks, const uint32_t* nchunks, double L,
+                            const HalfMap& second, int has_next, const HalfMap& first_next,
+                            Box* box, hipStream_t s);
+// both half maps of a slice without a kick (tracking without space charge)
+hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
+                            hipStream_t s);
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
                             uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
                             uint32_t* nchunks, double* B, uint32_t* idB, const Geom* g,

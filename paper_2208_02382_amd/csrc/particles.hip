@@ -299,12 +299,12 @@ __global__ __launch_bounds__(kBlock) void k_quad_drift(double* __restrict__ X, d
 }
 
 // Fused second half of step j and first half of step j+1: gather E' at the current positions,
-// kick over L, drift L/2; if has_next, thin quad k_next and drift half_next, and accumulate
-// the box of the new positions (the next step's grid).
+// kick over L, the slice's second half map; if has_next, the next slice's first half map, and
+// accumulate the box of the new positions (the next step's grid).
 template <int S, typename T>
 __global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Geom* __restrict__ g,
-                                                const T* __restrict__ E, double L, int has_next,
-                                                double k_next, double half_next, Consts c,
+                                                const T* __restrict__ E, double L, HalfMap second,
+                                                int has_next, HalfMap first_next, Consts c,
                                                 Box* box) {
   if (g->status) return;
   double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
@@ -319,10 +319,9 @@ __global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Ge
     T e[3];
     gather_one<S, T>(v[0], v[2], v[4], o, ih, E, c, e);
     sc_kick(v, (double)e[0], (double)e[1], (double)e[2], L, c);
-    drift(v, 0.5 * L, c.inv_gamma2);
+    apply_half(second, v, c.inv_gamma2);
     if (has_next) {
-      thin_quad(v, k_next);
-      drift(v, half_next, c.inv_gamma2);
+      apply_half(first_next, v, c.inv_gamma2);
       double p[3] = {v[0], v[2], v[4]};
       for (int a = 0; a < 3; ++a) {
         bad |= !isfinite(p[a]);
@@ -520,14 +519,34 @@ hipError_t launch_quad_drift(double* X, double k, double ell, Consts c, Box* box
 }
 
 template <typename T>
-hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, int has_next, double k_next,
-                      double half_next, Consts c, Box* box, hipStream_t s) {
+hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, const HalfMap& second,
+                      int has_next, const HalfMap& first_next, Consts c, Box* box, hipStream_t s) {
   if (c.shape == 1)
     hipLaunchKernelGGL((k_gkd<1, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, L,
-                       has_next, k_next, half_next, c, box);
+                       second, has_next, first_next, c, box);
   else
     hipLaunchKernelGGL((k_gkd<2, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, E, L,
-                       has_next, k_next, half_next, c, box);
+                       second, has_next, first_next, c, box);
+  return hipGetLastError();
+}
+
+// both half maps of a slice, no kick
+__global__ __launch_bounds__(kBlock) void k_half_maps(double* __restrict__ X, HalfMap first,
+                                                      HalfMap second, Consts c) {
+  const int64_t n = c.n;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    apply_half(first, v, c.inv_gamma2);
+    apply_half(second, v, c.inv_gamma2);
+    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
+  }
+}
+
+hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_half_maps, dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, first, second, c);
   return hipGetLastError();
 }
 
@@ -555,10 +574,10 @@ template hipError_t launch_gather<float>(const double*, const Geom*, const float
                                          hipStream_t);
 template hipError_t launch_push<double>(double*, int, double, const double*, Consts, hipStream_t);
 template hipError_t launch_push<float>(double*, int, double, const float*, Consts, hipStream_t);
-template hipError_t launch_gkd<double>(double*, const Geom*, const double*, double, int, double,
-                                       double, Consts, Box*, hipStream_t);
-template hipError_t launch_gkd<float>(double*, const Geom*, const float*, double, int, double,
-                                      double, Consts, Box*, hipStream_t);
+template hipError_t launch_gkd<double>(double*, const Geom*, const double*, double, const HalfMap&,
+                                       int, const HalfMap&, Consts, Box*, hipStream_t);
+template hipError_t launch_gkd<float>(double*, const Geom*, const float*, double, const HalfMap&,
+                                      int, const HalfMap&, Consts, Box*, hipStream_t);
 template hipError_t launch_zero<double>(double*, int64_t, hipStream_t);
 template hipError_t launch_zero<float>(float*, int64_t, hipStream_t);
 template hipError_t launch_zero<uint32_t>(uint32_t*, int64_t, hipStream_t);

@@ -333,6 +333,9 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
   const int nw = Wx * Wy * Wz;
+  int rowoff[S + 1][S + 1];  // window offset of stencil row (a, b)
+  for (int a = 0; a <= S; ++a)
+    for (int b = 0; b <= S; ++b) rowoff[a][b] = (a * Wy + b) * Wx;
   const int64_t n = c.n;
   const uint32_t nck = *nchunks;
   for (uint32_t ci = blk; ci < nck; ci += nblk) {
@@ -362,14 +365,15 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
         // as a two's-complement int64 by subtracting the constant's bit pattern
         constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
         constexpr unsigned long long kMagicBits = 0x4338000000000000ull;
+        unsigned long long* w0 = win + (lz * Wy + ly) * Wx + lx;
         for (int a = 0; a <= S; ++a) {
           const double wzs = qs * wz[a];
           for (int b = 0; b <= S; ++b) {
             const double wzy = wzs * wy[b];
+            unsigned long long* row = w0 + rowoff[a][b];
             for (int q = 0; q <= S; ++q) {
               const double d = __builtin_fma(wzy, wx[q], kMagic);
-              atomicAdd(&win[((lz + a) * Wy + (ly + b)) * Wx + (lx + q)],
-                        (unsigned long long)__double_as_longlong(d) - kMagicBits);
+              atomicAdd(row + q, (unsigned long long)__double_as_longlong(d) - kMagicBits);
             }
           }
         }
@@ -484,8 +488,8 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict
 
 // Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
 // workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
-// rows), the particles gather from LDS, get the space-charge kick over L and the drift L/2,
-// then (has_next) the thin quad k_next and drift half_next, and the box of the new positions
+// rows), the particles gather from LDS, get the space-charge kick over L and the slice's second
+// half map, then (has_next) the next slice's first half map, and the box of the new positions
 // is accumulated.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
@@ -496,8 +500,9 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
                                                     SortPlan sp,
                                                     const int4* __restrict__ chunks,
                                                     const uint32_t* __restrict__ nchunks,
-                                                    double L, int has_next, double k_next,
-                                                    double half_next, Box* box, int blk, int nblk) {
+                                                    double L, const HalfMap& second,
+                                                    int has_next, const HalfMap& first_next,
+                                                    Box* box, int blk, int nblk) {
   extern __shared__ unsigned char smem_raw[];
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
@@ -505,6 +510,9 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
   const int nw = Wx * Wy * Wz;
+  int rowoff[S + 1][S + 1];  // window offset of stencil row (a, b)
+  for (int a = 0; a <= S; ++a)
+    for (int b = 0; b <= S; ++b) rowoff[a][b] = (a * Wy + b) * Wx;
   const int64_t n = c.n;
   const int64_t plane = (int64_t)c.nx * c.ny * c.nz;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -543,10 +551,11 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
         lz = min(max(lz, 0), sp.T[2] - 1);
       }
       T ex = 0, ey = 0, ez = 0;
+      const T* w0 = win + (lz * Wy + ly) * Wx + lx;
       for (int a = 0; a <= S; ++a)
         for (int b = 0; b <= S; ++b) {
           const double wzy = wz[a] * wy[b];
-          const T* row = win + ((lz + a) * Wy + (ly + b)) * Wx + lx;
+          const T* row = w0 + rowoff[a][b];
           for (int q = 0; q <= S; ++q) {
             const T w = (T)(wzy * wx[q]);
             ex += w * row[q];
@@ -557,16 +566,9 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       v[1] = v[1] + c.C * (double)ex * L;
       v[3] = v[3] + c.C * (double)ey * L;
       v[5] = v[5] + c.gamma * c.C * (double)ez * L;
-      const double hl = 0.5 * L;
-      v[0] = v[0] + hl * v[1];
-      v[2] = v[2] + hl * v[3];
-      v[4] = v[4] + hl * v[5] * c.inv_gamma2;
+      apply_half(second, v, c.inv_gamma2);
       if (has_next) {
-        v[1] = v[1] - k_next * v[0];
-        v[3] = v[3] + k_next * v[2];
-        v[0] = v[0] + half_next * v[1];
-        v[2] = v[2] + half_next * v[3];
-        v[4] = v[4] + half_next * v[5] * c.inv_gamma2;
+        apply_half(first_next, v, c.inv_gamma2);
         const double p[3] = {v[0], v[2], v[4]};
         for (int a = 0; a < 3; ++a) {
           bad |= !isfinite(p[a]);
@@ -588,16 +590,18 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
                                                     SortPlan sp,
                                                     const int4* __restrict__ chunks,
                                                     const uint32_t* __restrict__ nchunks,
-                                                    double L, int has_next, double k_next,
-                                                    double half_next, Box* box) {
-  gkd_tiles_body<S, T>(B, g, E, c, sp, chunks, nchunks, L, has_next, k_next, half_next, box, blockIdx.x, gridDim.x);
+                                                    double L, HalfMap second, int has_next,
+                                                    HalfMap first_next, Box* box) {
+  gkd_tiles_body<S, T>(B, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next, box,
+                       blockIdx.x, gridDim.x);
 }
 
 // First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
 __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
                                                    double* __restrict__ A,
-                                                   uint32_t* __restrict__ idA, double k,
-                                                   double ell, Consts c, Box* box, int blk, int nblk) {
+                                                   uint32_t* __restrict__ idA,
+                                                   const HalfMap& first, Consts c, Box* box,
+                                                   int blk, int nblk) {
   const int64_t n = c.n;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
@@ -605,11 +609,7 @@ __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
        i += (int64_t)nblk * kBlk) {
     double v[6];
     for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
-    v[1] = v[1] - k * v[0];
-    v[3] = v[3] + k * v[2];
-    v[0] = v[0] + ell * v[1];
-    v[2] = v[2] + ell * v[3];
-    v[4] = v[4] + ell * v[5] * c.inv_gamma2;
+    apply_half(first, v, c.inv_gamma2);
     for (int r = 0; r < 6; ++r) A[r * n + i] = v[r];
     idA[i] = (uint32_t)i;
     double p[3] = {v[0], v[2], v[4]};
@@ -624,9 +624,9 @@ __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
 
 __global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
                                                    double* __restrict__ A,
-                                                   uint32_t* __restrict__ idA, double k,
-                                                   double ell, Consts c, Box* box) {
-  prologue_body(X, A, idA, k, ell, c, box, blockIdx.x, gridDim.x);
+                                                   uint32_t* __restrict__ idA, HalfMap first,
+                                                   Consts c, Box* box) {
+  prologue_body(X, A, idA, first, c, box, blockIdx.x, gridDim.x);
 }
 
 // Bucket keys for the return to the caller's order: key = id >> shift (at most 4096 buckets of
@@ -750,8 +750,7 @@ __device__ __forceinline__ uint32_t* nxt_id(const BeamDev& d, int parity) { retu
 
 __global__ __launch_bounds__(kBlk) void k_prologue_batch(const BeamDev* __restrict__ beams) {
   const BeamDev& d = beams[blockIdx.y];
-  prologue_body(d.X, d.XA, d.idA, d.lat_k[0], 0.5 * d.lat_ds[0], d.c, d.box, blockIdx.x,
-                gridDim.x);
+  prologue_body(d.X, d.XA, d.idA, d.slices[0].first, d.c, d.box, blockIdx.x, gridDim.x);
 }
 
 template <int S>
@@ -788,10 +787,11 @@ template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
                                                           int parity, int j, int n_steps) {
   const BeamDev& d = beams[blockIdx.y];
-  const int e = j % d.n_el, e1 = (j + 1) % d.n_el;
+  const SliceDev& sl = d.slices[j % d.n_slices];
+  const SliceDev& sn = d.slices[(j + 1) % d.n_slices];
   gkd_tiles_body<S, T>(nxt_X(d, parity), d.geom, (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
-                       d.lat_ds[e], j + 1 < n_steps, d.lat_k[e1], 0.5 * d.lat_ds[e1], d.box,
-                       blockIdx.x, gridDim.x);
+                       sl.L, sl.second, j + 1 < n_steps, sn.first, d.box, blockIdx.x,
+                       gridDim.x);
 }
 
 // reordering at the end: bucket keys of the ids, bucket offsets, bucket scatter, final scatter
@@ -873,9 +873,9 @@ SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], in
   return sp;
 }
 
-hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, double k, double ell,
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
                            Consts c, Box* box, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(grid_stride(c.n)), dim3(kBlk), 0, s, X, A, idA, k, ell, c,
+  hipLaunchKernelGGL(k_prologue, dim3(grid_stride(c.n)), dim3(kBlk), 0, s, X, A, idA, first, c,
                      box);
   return hipGetLastError();
 }
@@ -947,26 +947,29 @@ template hipError_t launch_vdeposit_tiles<float>(const double*, const Geom*, Con
 
 template <typename T>
 hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
-                            const int4* chunks, const uint32_t* nchunks, double L, int has_next,
-                            double k_next, double half_next, Box* box, hipStream_t s) {
+                            const int4* chunks, const uint32_t* nchunks, double L,
+                            const HalfMap& second, int has_next, const HalfMap& first_next,
+                            Box* box, hipStream_t s) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
   const int64_t grid = sp.blocks;
   if (S == 1)
     hipLaunchKernelGGL((k_gkd_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
-                       sp, chunks, nchunks, L, has_next, k_next, half_next, box);
+                       sp, chunks, nchunks, L, second, has_next, first_next, box);
   else
     hipLaunchKernelGGL((k_gkd_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
-                       sp, chunks, nchunks, L, has_next, k_next, half_next, box);
+                       sp, chunks, nchunks, L, second, has_next, first_next, box);
   return hipGetLastError();
 }
 
 template hipError_t launch_gkd_tiles<double>(double*, const Geom*, const double*, Consts,
                                              const SortPlan&, const int4*, const uint32_t*, double,
-                                             int, double, double, Box*, hipStream_t);
+                                             const HalfMap&, int, const HalfMap&, Box*,
+                                             hipStream_t);
 template hipError_t launch_gkd_tiles<float>(double*, const Geom*, const float*, Consts,
                                             const SortPlan&, const int4*, const uint32_t*, double,
-                                            int, double, double, Box*, hipStream_t);
+                                            const HalfMap&, int, const HalfMap&, Box*,
+                                            hipStream_t);
 
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
                             uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,

@@ -64,17 +64,41 @@ def test_tuning_fields_are_validated():
     assert pic.workspace_bytes(_desc()) == base
 
 
+def _lat_ptrs(*lats):
+    arrs = [pic._lattice(l) for l in lats]
+    ptrs = (ctypes.POINTER(pic.Element) * len(arrs))(
+        *[ctypes.cast(a, ctypes.POINTER(pic.Element)) for a in arrs])
+    return arrs, ptrs, (ctypes.c_int * len(arrs))(*[len(l) for l in lats])
+
+
 def test_batch_arguments_are_validated_without_a_device():
     lib = pic._lib
-    n_el = (ctypes.c_int * 2)(2, 0)
-    assert lib.pic_batch_workspace_bytes(2, n_el) == 0                  # an empty lattice
-    n_el[1] = 3
-    assert lib.pic_batch_workspace_bytes(2, n_el) > 0
-    assert lib.pic_batch_workspace_bytes(0, n_el) == 0
+    keep, ptrs, n_el = _lat_ptrs(((1.0, 0.5), (-1.0, 0.5)), ((1.0, 0.5),))
+    n_el[1] = 0
+    assert lib.pic_batch_workspace_bytes(2, ptrs, n_el) == 0             # an empty lattice
+    n_el[1] = 1
+    thin = lib.pic_batch_workspace_bytes(2, ptrs, n_el)
+    assert thin > 0
+    assert lib.pic_batch_workspace_bytes(0, ptrs, n_el) == 0
+    # thick elements expand into slices: a larger table
+    keep2, ptrs2, n_el2 = _lat_ptrs(((1.0, 0.5), (-1.0, 0.5)), ((2, 1.0, 1.0, 400),))
+    assert lib.pic_batch_workspace_bytes(2, ptrs2, n_el2) > thin
     out = ctypes.c_void_p()
     assert lib.pic_batch_create(None, 2, None, n_el, 0, None, 0, None, ctypes.byref(out)) \
         == pic.PIC_EINVAL
     assert lib.pic_track_batch(None, 3, None) == pic.PIC_EINVAL
+
+
+def test_lattice_elements_are_validated():
+    lib = pic._lib
+    for bad in (((5, 1.0, 1.0, 1),),           # unknown kind
+                ((2, 1.0, 1.0, 0),),           # no slices
+                ((1, 0.0, -0.5, 2),),          # negative length
+                ((2, float("nan"), 1.0, 3),)):
+        keep, ptrs, n_el = _lat_ptrs(bad)
+        assert lib.pic_batch_workspace_bytes(1, ptrs, n_el) == 0
+    keep, ptrs, n_el = _lat_ptrs(((1, 0.0, 0.25, 25), (2, 1.0, 1.0, 25)))
+    assert lib.pic_batch_workspace_bytes(1, ptrs, n_el) > 0
 
 
 def test_create_rejects_bad_arguments_without_touching_a_device():

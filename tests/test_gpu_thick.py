@@ -1,0 +1,126 @@
+"""GPU parity of thick elements (drifts and quadrupoles of finite length, cut into slices, each
+slice a half map, the space-charge kick over the slice length, and a second half map) against
+the oracle's sliced tracking.
+
+Tolerances: 1e-12 of each coordinate's rms with space charge (rounding only, as for thin
+lattices).  Without space charge every slice is two products of 2x2 matrices whose cos/sin
+and cosh/sinh entries each side computes with its own math library: rounding then grows
+linearly with the number of half maps, a few ulp each, times the ratio of the largest
+coordinate to its rms (about 4); 280 half maps give 3e-13.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import pic as opic
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_02382_amd as p
+    return p
+
+
+def _problem(cfg, n, nodes, shape):
+    return opic.make_problem(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
+                             nodes, shape)
+
+
+def _start(lib, cfg, n, nodes, shape, seed=None, space_charge=True):
+    xi = workloads.draw_xi(cfg, n=n, seed=seed)
+    b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes,
+                 space_charge=space_charge)
+    b.init_from_normals(cfg.sigma_matrix, torch.from_numpy(xi).cuda())
+    return b, opic.init_from_normals(cfg.sigma_matrix, xi)
+
+
+def _coord_err(Xg, Xo):
+    return (np.abs(Xg - Xo).max(axis=1) / Xo.std(axis=1)).max()
+
+
+# 60 slices of the 125 in a cell: the first drift, the focusing quadrupole and part of the
+# middle drift, so that both element boundaries kinds (drift to quad, quad to drift) are crossed
+@pytest.mark.parametrize("n,nodes,shape,steps", [(5_000, (16, 16, 16), 2, 60),
+                                                 (4_093, (12, 18, 24), 1, 60)])
+def test_thick_fodo_with_space_charge(lib, n, nodes, shape, steps):
+    cfg = workloads.SMALL
+    b, X = _start(lib, cfg, n, nodes, shape)
+    b.track(workloads.THICK_FODO, steps)
+    Xo = opic.track_elements(X, workloads.THICK_FODO, steps, _problem(cfg, n, nodes, shape))
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
+    assert b.check() == lib.PIC_OK
+
+
+def test_thick_fodo_cell_without_space_charge(lib):
+    # a whole cell (125 slices) and the start of the next one
+    cfg = workloads.SMALL
+    n = 3_001
+    b, X = _start(lib, cfg, n, (8, 8, 8), 1, space_charge=False)
+    b.track(workloads.THICK_FODO, 140)
+    Xo = opic.track_elements(X, workloads.THICK_FODO, 140, _problem(cfg, n, (8, 8, 8), 1),
+                             space_charge=False)
+    assert _coord_err(b.X.cpu().numpy(), Xo) < 3e-13
+
+
+def test_mixed_thin_and_thick_elements(lib):
+    # thin kicks between thick quadrupoles, one slice and several, and a zero-length drift
+    lat = ((0, 0.4, 0.2, 1), (2, -0.8, 0.6, 3), (1, 0.0, 0.0, 2), (2, 1.3, 0.3, 1), (0.5, 0.25))
+    cfg = workloads.SMALL
+    n, nodes, shape = 6_000, (16, 24, 16), 2
+    b, X = _start(lib, cfg, n, nodes, shape, seed=77)
+    steps = 17
+    b.track(lat, steps)
+    elems = [e if len(e) == 4 else (0, e[0], e[1], 1) for e in lat]
+    Xo = opic.track_elements(X, elems, steps, _problem(cfg, n, nodes, shape))
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
+
+
+def test_thin_element_form_equals_pair_form(lib):
+    cfg = workloads.SMALL
+    n, nodes = 2_000, (16, 16, 16)
+    b1, _ = _start(lib, cfg, n, nodes, 1)
+    b2, _ = _start(lib, cfg, n, nodes, 1)
+    b1.track(cfg.lattice, 6)
+    b2.track([(0, k, ds, 1) for k, ds in cfg.lattice], 6)
+    # equal up to the summation order of the float atomics that flush the deposit windows
+    assert _coord_err(b1.X.cpu().numpy(), b2.X.cpu().numpy()) < TOL
+
+
+def test_batch_with_thin_and_thick_lattices(lib):
+    lats = [workloads.THICK_FODO, ((1.0, 0.5), (-1.0, 0.5)),
+            ((2, 0.9, 0.8, 4), (1, 0.0, 0.4, 2), (2, -0.9, 0.8, 4), (1, 0.0, 0.4, 2))]
+    mix = [(3_001, (16, 16, 16)), (5_000, (24, 24, 24)), (2_500, (12, 18, 24))]
+    cfg = workloads.MEDIUM
+    shape = 2
+    beams, X0, cfgs = [], [], []
+    for i, (n, nodes) in enumerate(mix):
+        c = cfg.with_(n=n, nodes=nodes, seed=500 + i)
+        b, X = _start(lib, c, n, nodes, shape)
+        beams.append(b)
+        X0.append(X)
+        cfgs.append(c)
+    steps = 12
+    batch = lib.Batch(beams, lats)
+    batch.track(steps)
+    torch.cuda.synchronize()
+    assert all(st == lib.PIC_OK for st in batch.check())
+    for b, X, c, lat in zip(beams, X0, cfgs, lats):
+        elems = [e if len(e) == 4 else (0, e[0], e[1], 1) for e in lat]
+        Xo = opic.track_elements(X, elems, steps, _problem(c, c.n, c.nodes, shape))
+        assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
+    batch.close()
+    for b in beams:
+        b.close()
+
+
+def test_adjoint_rejects_thick_lattices(lib):
+    cfg = workloads.SMALL
+    b, _ = _start(lib, cfg, 1_000, (8, 8, 8), 1)
+    with pytest.raises(lib.PicError) as e:
+        b.track_adjoint(workloads.THICK_FODO, 4, [1.0, 0.0, 0.0, 0.0], ckpt_every=2)
+    assert e.value.status == lib.PIC_EUNSUPPORTED

@@ -54,6 +54,11 @@ class Beam:
 
 FODO = ((1.0, 0.5), (-1.0, 0.5))
 
+# The paper's FODO cell of Listing 1 with thick elements: (kind, k [1/m^2], ds [m], nslice),
+# kinds 1 = drift, 2 = quadrupole (0 is the thin-lens step of FODO above)
+THICK_FODO = ((1, 0.0, 0.25, 25), (2, 1.0, 1.0, 25), (1, 0.0, 0.5, 25), (2, -1.0, 1.0, 25),
+              (1, 0.0, 0.25, 25))
+
 SMALL = Beam("gauss-1e4-32c-cic", 10_000, (1e-3, 1e-3, 1e-3, 1e-3, 2e-3, 1e-3),
              (32, 32, 32), 1, 20, FODO, seed=1)
 MEDIUM = Beam("gauss-1e6-64c-cic", 1_000_000, (1e-3, 1e-3, 1e-3, 1e-3, 5e-3, 1e-3),
