@@ -50,7 +50,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gd, Gh, rho, phi, E;
-  size_t XA, XB, idA, idB, keys, hist, cursor, chunks, nchunks, total;
+  size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, total;
 };
 
 pic_status check_desc(const pic_beam_desc* d) {
@@ -116,7 +116,7 @@ Layout layout(const pic_beam_desc* d) {
   L.phi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   L.E = take(3 * es * nx * ny * nz);
   // tracking-loop buffers: two sorted copies of the phase space, particle ids, tile keys,
-  // tile histogram / sort cursors and the deposit work list
+  // the sort permutation, tile histogram / sort cursors and the deposit work list
   const size_t n = (size_t)d->n;
   const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks);
   L.XA = take(6 * sizeof(double) * n);
@@ -124,6 +124,7 @@ Layout layout(const pic_beam_desc* d) {
   L.idA = take(sizeof(uint32_t) * n);
   L.idB = take(sizeof(uint32_t) * n);
   L.keys = take(sizeof(uint32_t) * n);
+  L.perm = take(sizeof(uint32_t) * n);
   L.hist = take(sizeof(uint32_t) * kMaxTiles);
   L.cursor = take(sizeof(uint32_t) * kMaxTiles);
   L.chunks = take(sizeof(int4) * (size_t)sp.max_chunks);
@@ -188,6 +189,7 @@ struct pic_beam_s {
   uint32_t* idA;
   uint32_t* idB;
   uint32_t* keys;
+  uint32_t* perm;
   uint32_t* hist;
   uint32_t* cursor;
   int4* chunks;
@@ -358,12 +360,28 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
                                    b->Gd, (T*)b->Gh, b->aux),
           "green spectrum");
     HIP_OK(hipEventRecord(b->ev_join, b->aux), "join");
-    STAGE(b, PIC_STAGE_BIN, s,
-          launch_bin(A, idA, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
-                     b->nchunks, B, idB, j == 0, s),
-          "binning");
+    // the E' window of a tile must fit the 64 KB of LDS a workgroup may use
+    const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
+                             (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
+    const bool tiles = win_bytes <= 65536;
+    // After the first step A is in the previous step's tile order: only the ranking is
+    // written, and the gather-kick moves the particles (A -> B) while it updates them.  The
+    // first step moves the caller's order into tile order (A -> B) and updates B in place.
+    const bool permuted = tiles && j > 0;
+    if (permuted)
+      STAGE(b, PIC_STAGE_BIN, s,
+            launch_bin_perm(A, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
+                            b->nchunks, b->perm, s),
+            "binning");
+    else
+      STAGE(b, PIC_STAGE_BIN, s,
+            launch_bin(A, idA, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
+                       b->nchunks, B, idB, j == 0, s),
+            "binning");
+    const double* P = permuted ? A : B;  // particles the deposit reads (through perm)
     STAGE(b, PIC_STAGE_DEPOSIT, s,
-          launch_deposit_tiles<T>(B, b->geom, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
+          launch_deposit_tiles<T>(P, permuted ? b->perm : nullptr, b->geom, b->c, b->sp,
+                                  b->chunks, b->nchunks, (T*)b->rho, s),
           "deposit");
     HIP_OK(hipStreamWaitEvent(s, b->ev_join, 0), "join");
     pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
@@ -371,19 +389,19 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
     const int has_next = j + 1 < n_steps;
     const SliceDev& nx = sl[(j + 1) % ns];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
-    // the E' window of a tile must fit the 64 KB of LDS a workgroup may use
-    const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
-                             (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
-    if (win_bytes <= 65536)
+    if (tiles)
       STAGE(b, PIC_STAGE_GKD, s,
-            launch_gkd_tiles<T>(B, b->geom, (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks,
-                                e.L, e.second, has_next, nx.first, b->box, s),
+            launch_gkd_tiles<T>(B, permuted ? A : nullptr, permuted ? b->perm : nullptr,
+                                permuted ? idA : nullptr, permuted ? idB : nullptr, b->geom,
+                                (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks, e.L,
+                                e.second, has_next, nx.first, b->box, s),
             "gather-kick-drift");
     else
       STAGE(b, PIC_STAGE_GKD, s,
             launch_gkd<T>(B, b->geom, (const T*)b->E, e.L, e.second, has_next, nx.first, b->c,
                           b->box, s),
             "gather-kick-drift");
+    // B holds the updated particles in slot order
     double* tX = A; A = B; B = tX;
     uint32_t* tI = idA; idA = idB; idB = tI;
   }
@@ -445,7 +463,8 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_e
   HIP_OK(launch_bin(X, b->idA, g, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks, b->nchunks,
                     b->XB, b->idB, true, s),
          "adjoint forward");
-  HIP_OK(launch_deposit_tiles<T>(b->XB, g, b->c, b->sp, b->chunks, b->nchunks, (T*)b->rho, s),
+  HIP_OK(launch_deposit_tiles<T>(b->XB, nullptr, g, b->c, b->sp, b->chunks, b->nchunks,
+                                 (T*)b->rho, s),
          "adjoint forward");
   HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh, s),
          "adjoint forward");
@@ -663,6 +682,7 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->idA = (uint32_t*)(w + L.idA);
   b->idB = (uint32_t*)(w + L.idB);
   b->keys = (uint32_t*)(w + L.keys);
+  b->perm = (uint32_t*)(w + L.perm);
   b->hist = (uint32_t*)(w + L.hist);
   b->cursor = (uint32_t*)(w + L.cursor);
   b->chunks = (int4*)(w + L.chunks);

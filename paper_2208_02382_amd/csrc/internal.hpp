@@ -157,15 +157,24 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
                       const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
                       int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, bool staged,
                       hipStream_t s);
+// keys and work list as launch_bin, then only the ranking: perm[slot] = index in A
+hipError_t launch_bin_perm(const double* A, const Geom* g, Consts c, const SortPlan& sp,
+                           uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
+                           uint32_t* nchunks, uint32_t* perm, hipStream_t s);
+// perm == nullptr: B is in slot order; else slot i reads particle perm[i] of B
 template <typename T>
-hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
-                                const int4* chunks, const uint32_t* nchunks, T* rho,
-                                hipStream_t s);
+hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geom* g, Consts c,
+                                const SortPlan& sp, const int4* chunks, const uint32_t* nchunks,
+                                T* rho, hipStream_t s);
+// perm == nullptr: B in slot order, updated in place (src, idsrc, iddst unused); else slot i
+// reads particle perm[i] of src and id idsrc[perm[i]], and writes slot i of B and iddst
+// (src != B, idsrc != iddst)
 template <typename T>
-hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
-                            const int4* chunks, const uint32_t* nchunks, double L,
-                            const HalfMap& second, int has_next, const HalfMap& first_next,
-                            Box* box, hipStream_t s);
+hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
+                            const uint32_t* idsrc, uint32_t* iddst, const Geom* g, const T* E,
+                            Consts c, const SortPlan& sp, const int4* chunks,
+                            const uint32_t* nchunks, double L, const HalfMap& second,
+                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s);
 // both half maps of a slice without a kick (tracking without space charge)
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
                             hipStream_t s);

@@ -10,7 +10,12 @@
 //   k_scatter      moves phase space and particle ids to their sorted slots: each block
 //                  counts its keys in LDS, reserves one contiguous range per key with a single
 //                  global atomic, then ranks its particles with LDS atomics, so particles of one
-//                  key leave a block as one contiguous run;
+//                  key leave a block as one contiguous run (first step of a call, where the
+//                  caller's order is unrelated to the tiles);
+//   k_scatter_perm the same ranking without moving anything: the source index of every sorted
+//                  slot (4 B per particle instead of 104).  Later steps read the particles
+//                  through it, and the gather-kick writes the new state in sorted order, so the
+//                  phase space crosses HBM once per step fewer;
 //   k_deposit_tiles each workgroup takes a chunk, accumulates the (T + S)^3 window of its tile
 //                  with 64-bit fixed-point LDS atomics, and adds the non-zero window entries to
 //                  the charge grid with one global atomic each.
@@ -281,6 +286,43 @@ __device__ __forceinline__ void scatter_direct_body(const double* __restrict__ A
   }
 }
 
+// Ranking of one block of kItems particles as in the direct form, writing only the source
+// index of each slot: perm[slot] = i.
+__device__ __forceinline__ void scatter_perm_body(const uint32_t* __restrict__ keys,
+                                                  const Geom* __restrict__ g, int64_t n,
+                                                  int ntiles, uint32_t* __restrict__ cursor,
+                                                  uint32_t* __restrict__ perm, int blk) {
+  __shared__ uint32_t lh[kMaxTiles];
+  if (g->status) return;
+  for (int t = threadIdx.x; t < ntiles; t += kBlk) lh[t] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blk * kItems;
+  uint32_t key[kPer];
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    key[k] = i < n ? keys[i] : 0u;
+    if (i < n) atomicAdd(&lh[key[k]], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += kBlk)
+    if (lh[t]) lh[t] = atomicAdd(&cursor[t], lh[t]);
+  __syncthreads();
+  for (int k = 0; k < kPer; ++k) {
+    int64_t i = base + k * kBlk + threadIdx.x;
+    if (i < n) {
+      uint32_t pos = atomicAdd(&lh[key[k]], 1u);
+      if (pos < (uint64_t)n) perm[pos] = (uint32_t)i;  // in bounds for a consistent histogram
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlk) void k_scatter_perm(const uint32_t* __restrict__ keys,
+                                                       const Geom* __restrict__ g, int64_t n,
+                                                       int ntiles, uint32_t* __restrict__ cursor,
+                                                       uint32_t* __restrict__ perm) {
+  scatter_perm_body(keys, g, n, ntiles, cursor, perm, blockIdx.x);
+}
+
 template <bool STAGED>
 __device__ __forceinline__ void scatter_body(const double* __restrict__ A,
                                              const uint32_t* __restrict__ idA,
@@ -321,6 +363,7 @@ __device__ __forceinline__ void add_global(T* p, T v) {
 // converted to T and added to the grid with one global float atomic per non-zero node.
 template <int S, typename T>
 __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
+                                                        const uint32_t* __restrict__ perm,
                                                         const Geom* __restrict__ g, Consts c,
                                                         SortPlan sp,
                                                         const int4* __restrict__ chunks,
@@ -352,10 +395,16 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     for (int w = threadIdx.x; w < nw; w += kBlk) win[w] = 0ull;
     __syncthreads();
     for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+      // slot i holds particle perm[i] of B (B itself in slot order without a permutation)
+      int64_t r = i;
+      if (perm) {
+        r = perm[i];
+        if (r >= n) r = 0;  // impossible for a consistent ranking; keeps the read in bounds
+      }
       double wx[S + 1], wy[S + 1], wz[S + 1];
-      const int bx = stencil<S>((B[i] - o[0]) * ih[0], c.nx, wx);
-      const int by = stencil<S>((B[2 * n + i] - o[1]) * ih[1], c.ny, wy);
-      const int bz = stencil<S>((B[4 * n + i] - o[2]) * ih[2], c.nz, wz);
+      const int bx = stencil<S>((B[r] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((B[2 * n + r] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((B[4 * n + r] - o[2]) * ih[2], c.nz, wz);
       const int lx = bx - ox, ly = by - oy, lz = bz - oz;
       const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
                           lz < sp.T[2];
@@ -478,23 +527,30 @@ __global__ __launch_bounds__(kBlk) void k_vdeposit_tiles(const double* __restric
 
 template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
+                                                        const uint32_t* __restrict__ perm,
                                                         const Geom* __restrict__ g, Consts c,
                                                         SortPlan sp,
                                                         const int4* __restrict__ chunks,
                                                         const uint32_t* __restrict__ nchunks,
                                                         T* __restrict__ rho) {
-  deposit_tiles_body<S, T>(B, g, c, sp, chunks, nchunks, rho, blockIdx.x, gridDim.x);
+  deposit_tiles_body<S, T>(B, perm, g, c, sp, chunks, nchunks, rho, blockIdx.x, gridDim.x);
 }
 
 // Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
 // workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
 // rows), the particles gather from LDS, get the space-charge kick over L and the slice's second
 // half map, then (has_next) the next slice's first half map, and the box of the new positions
-// is accumulated.  The gather reads LDS only (a per-lane choice between LDS and global memory
+// is accumulated.  PERM false: B is in slot order and updated in place.  PERM true: slot i
+// reads particle perm[i] of src (and its id) and writes the new state to slot i of B, so B
+// leaves in sorted order.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
-template <int S, typename T>
+template <int S, typename T, bool PERM>
 __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
+                                                    const double* __restrict__ src,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ idsrc,
+                                                    uint32_t* __restrict__ iddst,
                                                     const Geom* __restrict__ g,
                                                     const T* __restrict__ E, Consts c,
                                                     SortPlan sp,
@@ -536,7 +592,17 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
     __syncthreads();
     for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
       double v[6];
-      for (int r = 0; r < 6; ++r) v[r] = B[r * n + i];
+      int64_t i0 = i;
+      if constexpr (PERM) {
+        i0 = perm[i];
+        if (i0 >= n) {  // impossible for a consistent ranking; keeps the reads in bounds
+          bin_fault = true;
+          i0 = 0;
+        }
+        for (int r = 0; r < 6; ++r) v[r] = src[r * n + i0];
+      } else {
+        for (int r = 0; r < 6; ++r) v[r] = B[r * n + i];
+      }
       double wx[S + 1], wy[S + 1], wz[S + 1];
       const int bx = stencil<S>((v[0] - o[0]) * ih[0], c.nx, wx);
       const int by = stencil<S>((v[2] - o[1]) * ih[1], c.ny, wy);
@@ -577,14 +643,19 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
         }
       }
       for (int r = 0; r < 6; ++r) B[r * n + i] = v[r];
+      if constexpr (PERM) iddst[i] = idsrc[i0];
     }
   }
   if (bin_fault) atomicCAS(const_cast<int*>(&g->status), 0, -7);
   if (has_next) box_accumulate_block(lo, hi, bad, box);
 }
 
-template <int S, typename T>
+template <int S, typename T, bool PERM>
 __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
+                                                    const double* __restrict__ src,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ idsrc,
+                                                    uint32_t* __restrict__ iddst,
                                                     const Geom* __restrict__ g,
                                                     const T* __restrict__ E, Consts c,
                                                     SortPlan sp,
@@ -592,8 +663,8 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
                                                     const uint32_t* __restrict__ nchunks,
                                                     double L, HalfMap second, int has_next,
                                                     HalfMap first_next, Box* box) {
-  gkd_tiles_body<S, T>(B, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next, box,
-                       blockIdx.x, gridDim.x);
+  gkd_tiles_body<S, T, PERM>(B, src, perm, idsrc, iddst, g, E, c, sp, chunks, nchunks, L, second,
+                             has_next, first_next, box, blockIdx.x, gridDim.x);
 }
 
 // First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
@@ -779,7 +850,8 @@ template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
-  deposit_tiles_body<S, T>(nxt_X(d, parity), d.geom, d.c, d.sp, d.chunks, d.nchunks, (T*)d.rho,
+  deposit_tiles_body<S, T>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
+                           (T*)d.rho,
                            blockIdx.x, gridDim.x);
 }
 
@@ -789,7 +861,8 @@ __global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restr
   const BeamDev& d = beams[blockIdx.y];
   const SliceDev& sl = d.slices[j % d.n_slices];
   const SliceDev& sn = d.slices[(j + 1) % d.n_slices];
-  gkd_tiles_body<S, T>(nxt_X(d, parity), d.geom, (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
+  gkd_tiles_body<S, T, false>(nxt_X(d, parity), nullptr, nullptr, nullptr, nullptr, d.geom,
+                              (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
                        sl.L, sl.second, j + 1 < n_steps, sn.first, d.box, blockIdx.x,
                        gridDim.x);
 }
@@ -880,10 +953,11 @@ hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const Half
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
-                      const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
-                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, bool staged,
-                      hipStream_t s) {
+namespace {
+// tile keys, histogram, sort offsets and the deposit work list of the particles in A
+hipError_t launch_keys_chunks(const double* A, const Geom* g, Consts c, const SortPlan& sp,
+                              uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
+                              uint32_t* nchunks, hipStream_t s) {
   if (c.shape == 1)
     hipLaunchKernelGGL(k_key_hist<1>, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, g, c, sp, keys,
                        hist);
@@ -894,7 +968,15 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, g, sp, hist, cursor, chunks,
                      nchunks);
-  e = hipGetLastError();
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
+                      const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
+                      int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, bool staged,
+                      hipStream_t s) {
+  hipError_t e = launch_keys_chunks(A, g, c, sp, keys, hist, cursor, chunks, nchunks, s);
   if (e != hipSuccess) return e;
   if (staged)
     hipLaunchKernelGGL(k_scatter<true>, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, idA, keys, g,
@@ -905,19 +987,29 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
   return hipGetLastError();
 }
 
+hipError_t launch_bin_perm(const double* A, const Geom* g, Consts c, const SortPlan& sp,
+                           uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
+                           uint32_t* nchunks, uint32_t* perm, hipStream_t s) {
+  hipError_t e = launch_keys_chunks(A, g, c, sp, keys, hist, cursor, chunks, nchunks, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter_perm, dim3(grid_items(c.n)), dim3(kBlk), 0, s, keys, g, c.n,
+                     sp.ntiles, cursor, perm);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_deposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
-                                const int4* chunks, const uint32_t* nchunks, T* rho,
-                                hipStream_t s) {
+hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geom* g, Consts c,
+                                const SortPlan& sp, const int4* chunks, const uint32_t* nchunks,
+                                T* rho, hipStream_t s) {
   const int S = c.shape;
   size_t lds = sizeof(unsigned long long) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
   const int64_t grid = sp.blocks;
   if (S == 1)
-    hipLaunchKernelGGL((k_deposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, c,
-                       sp, chunks, nchunks, rho);
+    hipLaunchKernelGGL((k_deposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, perm,
+                       g, c, sp, chunks, nchunks, rho);
   else
-    hipLaunchKernelGGL((k_deposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, c,
-                       sp, chunks, nchunks, rho);
+    hipLaunchKernelGGL((k_deposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, perm,
+                       g, c, sp, chunks, nchunks, rho);
   return hipGetLastError();
 }
 
@@ -946,29 +1038,37 @@ template hipError_t launch_vdeposit_tiles<float>(const double*, const Geom*, Con
                                                  float*, hipStream_t);
 
 template <typename T>
-hipError_t launch_gkd_tiles(double* B, const Geom* g, const T* E, Consts c, const SortPlan& sp,
-                            const int4* chunks, const uint32_t* nchunks, double L,
-                            const HalfMap& second, int has_next, const HalfMap& first_next,
-                            Box* box, hipStream_t s) {
+hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
+                            const uint32_t* idsrc, uint32_t* iddst, const Geom* g, const T* E,
+                            Consts c, const SortPlan& sp, const int4* chunks,
+                            const uint32_t* nchunks, double L, const HalfMap& second,
+                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  const int64_t grid = sp.blocks;
-  if (S == 1)
-    hipLaunchKernelGGL((k_gkd_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
-                       sp, chunks, nchunks, L, second, has_next, first_next, box);
-  else
-    hipLaunchKernelGGL((k_gkd_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g, E, c,
-                       sp, chunks, nchunks, L, second, has_next, first_next, box);
+  const dim3 grid((unsigned)sp.blocks);
+  if (perm && (!src || !idsrc || !iddst || src == B || idsrc == iddst))
+    return hipErrorInvalidValue;
+#define PIC_GKD(SS, PP)                                                                       \
+  hipLaunchKernelGGL((k_gkd_tiles<SS, T, PP>), grid, dim3(kBlk), lds, s, B, src, perm, idsrc, \
+                     iddst, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next, box)
+  if (S == 1) {
+    if (perm) PIC_GKD(1, true); else PIC_GKD(1, false);
+  } else {
+    if (perm) PIC_GKD(2, true); else PIC_GKD(2, false);
+  }
+#undef PIC_GKD
   return hipGetLastError();
 }
 
-template hipError_t launch_gkd_tiles<double>(double*, const Geom*, const double*, Consts,
-                                             const SortPlan&, const int4*, const uint32_t*, double,
-                                             const HalfMap&, int, const HalfMap&, Box*,
-                                             hipStream_t);
-template hipError_t launch_gkd_tiles<float>(double*, const Geom*, const float*, Consts,
-                                            const SortPlan&, const int4*, const uint32_t*, double,
-                                            const HalfMap&, int, const HalfMap&, Box*,
+template hipError_t launch_gkd_tiles<double>(double*, const double*, const uint32_t*,
+                                             const uint32_t*, uint32_t*, const Geom*,
+                                             const double*, Consts, const SortPlan&, const int4*,
+                                             const uint32_t*, double, const HalfMap&, int,
+                                             const HalfMap&, Box*, hipStream_t);
+template hipError_t launch_gkd_tiles<float>(double*, const double*, const uint32_t*,
+                                            const uint32_t*, uint32_t*, const Geom*, const float*,
+                                            Consts, const SortPlan&, const int4*, const uint32_t*,
+                                            double, const HalfMap&, int, const HalfMap&, Box*,
                                             hipStream_t);
 
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
@@ -1084,11 +1184,11 @@ template hipError_t launch_batch_gkd<double>(const BeamDev*, int, const BatchDim
 template hipError_t launch_batch_gkd<float>(const BeamDev*, int, const BatchDims&, int, int, int,
                                             int, hipStream_t);
 
-template hipError_t launch_deposit_tiles<double>(const double*, const Geom*, Consts,
-                                                 const SortPlan&, const int4*, const uint32_t*,
-                                                 double*, hipStream_t);
-template hipError_t launch_deposit_tiles<float>(const double*, const Geom*, Consts,
-                                                const SortPlan&, const int4*, const uint32_t*,
-                                                float*, hipStream_t);
+template hipError_t launch_deposit_tiles<double>(const double*, const uint32_t*, const Geom*,
+                                                 Consts, const SortPlan&, const int4*,
+                                                 const uint32_t*, double*, hipStream_t);
+template hipError_t launch_deposit_tiles<float>(const double*, const uint32_t*, const Geom*,
+                                                Consts, const SortPlan&, const int4*,
+                                                const uint32_t*, float*, hipStream_t);
 
 }  // namespace pic
