@@ -75,11 +75,17 @@ typedef struct {
   /* Launch tuning of the binned deposit and gather (0 = the library's default for each);
    * results do not depend on them beyond the float atomics' summation order. */
   int tile[3];             /* tile edge in nodes per axis for the per-step binning; the tile
-                              count prod(ceil(n_a/tile_a)) must be <= 4096; default
+                              count prod(ceil(n_a/tile_a)) must be <= 4096 and the charge
+                              window 8 prod(tile_a + shape) bytes <= 156 KB (the dynamic LDS
+                              of one workgroup); a field window 3 prod(tile_a + shape) grid
+                              elements above 156 KB makes the gather fall back to global
+                              loads; default
                               max(4, ceil(n_a/16)) */
   int chunk;               /* max particles per work item of a tile, 256..2^20; default 8192 */
   int blocks;              /* workgroups of the binned deposit and gather, 1..65535; default
                               min(work items, 4096) */
+  int threads;             /* threads per workgroup of the binned deposit and gather: a
+                              multiple of 64 in 64..1024; default 256 */
 } pic_beam_desc;
 
 /* Lattice element kinds (Listing 1 of the paper: Drift(ds, nslice), Quad(ds, k, nslice)).

@@ -33,7 +33,8 @@ class BeamDesc(ctypes.Structure):
                 ("mass_MeV", ctypes.c_double), ("shape", ctypes.c_int),
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int),
-                ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int)]
+                ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int),
+                ("threads", ctypes.c_int)]
 
 
 ELEM_THIN, ELEM_DRIFT, ELEM_QUAD = 0, 1, 2
@@ -101,14 +102,14 @@ def last_error():
 
 def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,
               space_charge=True, tuning=None):
-    """tuning: None or a dict with any of tile (3 ints), chunk, blocks (0 = default)."""
+    """tuning: None or a dict with any of tile (3 ints), chunk, blocks, threads (0 = default)."""
     nx, ny, nz = nodes
     t = tuning or {}
     tile = t.get("tile", (0, 0, 0))
     return BeamDesc(int(n), float(qm_qeeV), float(charge_C), float(kin_energy_MeV),
                     float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
                     int(bool(space_charge)), (ctypes.c_int * 3)(*[int(v) for v in tile]),
-                    int(t.get("chunk", 0)), int(t.get("blocks", 0)))
+                    int(t.get("chunk", 0)), int(t.get("blocks", 0)), int(t.get("threads", 0)))
 
 
 def workspace_bytes(desc):

@@ -1,14 +1,16 @@
-"""Autotuner of the binned deposit and gather: tile edge, particles per work item and
-workgroup count (pic_beam_desc.tile / chunk / blocks), and the workgroups per beam of a batch.
+"""Autotuner of the binned deposit and gather: tile edge, particles per work item, workgroup
+count and size (pic_beam_desc.tile / chunk / blocks / threads), and the workgroups per beam of
+a batch.
 
 Each candidate is timed on the device with the library's own tracking loop
 (pic_track_n_steps: the call's wall time less its once-per-call stages; pic_track_batch
 for a batch: the whole call) over a few steps of a beam of the problem's size,
 re-initialised to the same seeded state before every candidate.  The search is
 coordinate-wise: tile edge with the default work items, then the work-item size at the best
-tile, then the workgroup count.  Only launch shapes within the library's documented limits are
-tried (tile count <= 4096, the gather's field window within 64 KB of LDS).  Results go into a
-JSON cache keyed by problem class: particle count rounded to a power of two, grid, shape and
+tile, then the workgroup count, then the workgroup size.  Only launch shapes within the
+library's documented limits are tried (tile count <= 4096, the gather's
+field window within the 156 KB of dynamic LDS a workgroup may use).  Results go into a JSON
+cache keyed by problem class: particle count rounded to a power of two, grid, shape and
 grid precision.  Results do not depend on the tuning beyond the summation order of the float
 atomics.
 """
@@ -25,6 +27,8 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 TILES = (4, 5, 6, 8, 10, 12, 16)
 CHUNKS = (2048, 4096, 8192, 16384, 32768)
 BLOCKS = (0, 1024, 2048, 8192)          # 0: min(work items, 4096)
+THREADS = (256, 512, 1024)
+LDS_BYTES = 163840 - 4096               # dynamic LDS one workgroup may allocate
 BATCH_BLOCKS = (32, 64, 128, 256, 512)
 
 
@@ -51,7 +55,8 @@ def save(table, cache=DEFAULT_CACHE):
 def lookup(n, nodes, shape, grid_fp32, cache=DEFAULT_CACHE):
     """The cached tuning dict (tile, chunk, blocks) of this problem class, or None."""
     rec = load(cache).get(key(n, nodes, shape, grid_fp32))
-    return None if rec is None else {k: rec[k] for k in ("tile", "chunk", "blocks")}
+    return None if rec is None else {k: rec[k] for k in ("tile", "chunk", "blocks", "threads")
+                                     if k in rec}
 
 
 def _tile_ok(tile, nodes, shape, grid_fp32):
@@ -61,7 +66,7 @@ def _tile_ok(tile, nodes, shape, grid_fp32):
     for t, n in zip(tile, nodes):
         ntiles *= -(-n // t)
         win *= t + shape
-    return ntiles <= 4096 and win <= 65536
+    return ntiles <= 4096 and win <= LDS_BYTES
 
 
 # stages that run once per call, alone on the caller's stream
@@ -131,9 +136,15 @@ def tune(cfg, grid_fp32=False, steps=6, cache=DEFAULT_CACHE, force=False, log=No
         dt = run(cand)
         if dt < best_t:
             best, best_t = cand, dt
+    for th in THREADS[1:]:
+        cand = dict(best, threads=th)
+        dt = run(cand)
+        if dt < best_t:
+            best, best_t = cand, dt
     del X
     rec = {"tile": list(best.get("tile", (0, 0, 0))), "chunk": int(best.get("chunk", 0)),
-           "blocks": int(best.get("blocks", 0)), "s_per_step": best_t,
+           "blocks": int(best.get("blocks", 0)), "threads": int(best.get("threads", 0)),
+           "s_per_step": best_t,
            "default_s_per_step": default, "steps_timed": steps, "tried": tried}
     if cache:
         table = load(cache)

@@ -26,6 +26,7 @@ pic_status fail(pic_status st, const char* msg) {
 
 pic_status fail_hip(hipError_t e, const char* where) {
   g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();  // a rejected call must not fail the thread's next HIP call
   return PIC_EHIP;
 }
 
@@ -81,10 +82,12 @@ pic_status check_desc(const pic_beam_desc* d) {
   }
   if (ntiles > kMaxTiles) return fail(PIC_EINVAL, "tile count must be <= 4096");
   // the deposit's charge window of a tile lives in LDS (64 KB per workgroup)
-  if (window > 65536) return fail(PIC_EINVAL, "tile charge window exceeds 64 KB of LDS");
+  if (window > (int64_t)kMaxLdsBytes) return fail(PIC_EINVAL, "tile charge window exceeds the 156 KB of LDS a workgroup may use");
   if (d->chunk != 0 && (d->chunk < 256 || d->chunk > (1 << 20)))
     return fail(PIC_EINVAL, "chunk must be 0 or 256..2^20");
   if (d->blocks < 0 || d->blocks > 65535) return fail(PIC_EINVAL, "blocks must be 0..65535");
+  if (d->threads != 0 && (d->threads < 64 || d->threads > kMaxThreads || d->threads % 64 != 0))
+    return fail(PIC_EINVAL, "threads must be 0 or a multiple of 64 in 64..1024");
   return PIC_OK;
 }
 
@@ -118,7 +121,8 @@ Layout layout(const pic_beam_desc* d) {
   // tracking-loop buffers: two sorted copies of the phase space, particle ids, tile keys,
   // the sort permutation, tile histogram / sort cursors and the deposit work list
   const size_t n = (size_t)d->n;
-  const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks);
+  const SortPlan sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks,
+                                     d->threads);
   L.XA = take(6 * sizeof(double) * n);
   L.XB = take(6 * sizeof(double) * n);
   L.idA = take(sizeof(uint32_t) * n);
@@ -334,6 +338,19 @@ pic_status expand_lattice(const pic_element* lat, int n_el, std::vector<SliceDev
   return PIC_OK;
 }
 
+// Green spectrum of the current geometry on the auxiliary stream (joined before the solve)
+template <typename T>
+pic_status fork_green(pic_beam b, hipStream_t s) {
+  HIP_OK(hipEventRecord(b->ev_fork, s), "fork");
+  HIP_OK(hipStreamWaitEvent(b->aux, b->ev_fork, 0), "fork");
+  STAGE(b, PIC_STAGE_GREEN, b->aux,
+        launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd,
+                                 (T*)b->Gh, b->aux),
+        "green spectrum");
+  HIP_OK(hipEventRecord(b->ev_join, b->aux), "join");
+  return PIC_OK;
+}
+
 template <typename T>
 pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hipStream_t s) {
   const int ns = (int)sl.size();
@@ -345,25 +362,18 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
   HIP_OK(launch_box_reset(b->box, s), "box reset");
   STAGE(b, PIC_STAGE_PROLOGUE, s,
         launch_prologue(b->X, A, idA, sl[0].first, b->c, b->box, s), "prologue");
+  // the E' window of a tile must fit the LDS a workgroup may use
+  const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
+                           (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
+  const bool tiles = win_bytes <= kMaxLdsBytes;
   for (int j = 0; j < n_steps; ++j) {
     const SliceDev& e = sl[j % ns];
     HIP_OK(b->prof.begin(PIC_STAGE_GEOMETRY, s), "profile");
     HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "geometry");
     HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "zero rho");
     HIP_OK(b->prof.end(s), "profile");
-    // the Green spectrum depends on the geometry only: it runs on the auxiliary stream while
-    // the particles are binned and deposited
-    HIP_OK(hipEventRecord(b->ev_fork, s), "fork");
-    HIP_OK(hipStreamWaitEvent(b->aux, b->ev_fork, 0), "fork");
-    STAGE(b, PIC_STAGE_GREEN, b->aux,
-          launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners,
-                                   b->Gd, (T*)b->Gh, b->aux),
-          "green spectrum");
-    HIP_OK(hipEventRecord(b->ev_join, b->aux), "join");
-    // the E' window of a tile must fit the 64 KB of LDS a workgroup may use
-    const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
-                             (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
-    const bool tiles = win_bytes <= 65536;
+    pic_status st = fork_green<T>(b, s);
+    if (st != PIC_OK) return st;
     // After the first step A is in the previous step's tile order: only the ranking is
     // written, and the gather-kick moves the particles (A -> B) while it updates them.  The
     // first step moves the caller's order into tile order (A -> B) and updates B in place.
@@ -384,7 +394,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
                                   b->chunks, b->nchunks, (T*)b->rho, s),
           "deposit");
     HIP_OK(hipStreamWaitEvent(s, b->ev_join, 0), "join");
-    pic_status st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
+    st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
     if (st != PIC_OK) return st;
     const int has_next = j + 1 < n_steps;
     const SliceDev& nx = sl[(j + 1) % ns];
@@ -497,7 +507,8 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
   double* P = (double*)(aw + A.stage);
   // the binned vector deposit keeps three float64 windows of a tile in LDS (64 KB)
   const int S = b->d.shape;
-  const bool vtiles = 24 * (size_t)(b->sp.T[0] + S) * (b->sp.T[1] + S) * (b->sp.T[2] + S) <= 65536;
+  const bool vtiles =
+      24 * (size_t)(b->sp.T[0] + S) * (b->sp.T[1] + S) * (b->sp.T[2] + S) <= kMaxLdsBytes;
   HIP_OK(launch_zero<uint32_t>((uint32_t*)(aw + A.geoms), (int64_t)(kGeomSlot / 4) * n_steps, s),
          "adjoint setup");
   HIP_OK(launch_zero<double>(dk, kMaxLattice, s), "adjoint setup");
@@ -676,7 +687,7 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->rho = w + L.rho;
   b->phi = w + L.phi;
   b->E = w + L.E;
-  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks);
+  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks, d->threads);
   b->XA = (double*)(w + L.XA);
   b->XB = (double*)(w + L.XB);
   b->idA = (uint32_t*)(w + L.idA);
@@ -919,7 +930,8 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     const size_t es = fp32 ? 4 : 8;
     const size_t nodes = (size_t)(h->sp.T[0] + shape) * (h->sp.T[1] + shape) * (h->sp.T[2] + shape);
     const size_t win = es * nodes;
-    if (3 * win > 65536) return fail(PIC_EUNSUPPORTED, "tile window of a batched beam exceeds 64 KB");
+    if (3 * win > kMaxLdsBytes)
+      return fail(PIC_EUNSUPPORTED, "tile window of a batched beam exceeds 156 KB");
     bd.max_n = std::max<int64_t>(bd.max_n, h->d.n);
     bd.max_nx = std::max(bd.max_nx, h->d.nx);
     bd.max_ny = std::max(bd.max_ny, h->d.ny);

@@ -4,7 +4,7 @@
 
 namespace pic {
 
-constexpr int kBoxBlock = 256;   // block size of every kernel that calls box_accumulate_block
+constexpr int kBoxBlock = 1024;  // largest block size of a kernel that calls box_accumulate_block
 
 // order-preserving map of doubles to uint64 (so that integer atomic min/max order doubles)
 __device__ __forceinline__ unsigned long long ord_enc(double v) {
@@ -88,7 +88,7 @@ __device__ __forceinline__ void box_accumulate_block(double lo[3], double hi[3],
   if (threadIdx.x < 3) {
     int a = threadIdx.x;
     double l = slo[a][0], h = shi[a][0];
-    for (int q = 1; q < kBoxBlock / 64; ++q) {
+    for (int q = 1; q < (int)(blockDim.x + 63) / 64; ++q) {
       l = fmin(l, slo[a][q]);
       h = fmax(h, shi[a][q]);
     }

@@ -57,6 +57,11 @@ struct Chol {
 };
 
 constexpr int kMaxTiles = 4096;       // tiles of the per-step particle binning
+// Dynamic LDS of the binned deposit's and gather's tile windows: gfx950 gives a workgroup up to
+// 160 KB, of which 4 KB are left to the kernels' static LDS (above 64 KB a kernel's
+// dynamic-LDS attribute is raised before the launch, see lds_optin)
+constexpr size_t kMaxLdsBytes = 163840 - 4096;
+constexpr int kMaxThreads = 1024;     // workgroup size limit of the binned deposit and gather
 
 // Binning plan: tiles of T[a] cells along each axis (NT[a] tiles), work chunks of at most
 // `chunk` particles for the tiled deposit.
@@ -66,8 +71,8 @@ struct SortPlan {
   int ntiles;
   int chunk;
   int64_t max_chunks;
-  int blocks;  // workgroups of the binned deposit and gather
-  int pad;
+  int blocks;   // workgroups of the binned deposit and gather
+  int threads;  // threads per workgroup of the binned deposit and gather (64..1024)
 };
 
 // One half of a lattice slice's linear map (applied by apply_half, device_common.hpp).  A slice
@@ -150,7 +155,7 @@ hipError_t launch_zero(T* p, int64_t count, hipStream_t s);
 // ---- sort.hip
 // tile[a], chunk, blocks: 0 selects the default
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
-                        int blocks);
+                        int blocks, int threads);
 hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
                            Consts c, Box* box, hipStream_t s);
 hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,

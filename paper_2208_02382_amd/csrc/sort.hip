@@ -392,9 +392,9 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     const double qc = qa * (double)(ch.z - ch.y);
     const int k = qc > 0.0 ? min(62 - max(ilogb(qc) + 1, -960), 50 - max(ilogb(qa) + 1, -960)) : 0;
     const double qs = c.q_macro * ldexp(1.0, k), unscale = ldexp(1.0, -k);
-    for (int w = threadIdx.x; w < nw; w += kBlk) win[w] = 0ull;
+    for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) win[w] = 0ull;
     __syncthreads();
-    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
       // slot i holds particle perm[i] of B (B itself in slot order without a permutation)
       int64_t r = i;
       if (perm) {
@@ -437,7 +437,7 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
       }
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < nw; w += kBlk) {
+    for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
       const long long v = (long long)win[w];
       int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
@@ -473,9 +473,9 @@ __device__ __forceinline__ void vdeposit_tiles_body(const double* __restrict__ B
     const int t = ch.x;
     const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
     const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
-    for (int w = threadIdx.x; w < 3 * nw; w += kBlk) win[w] = 0.0;
+    for (int w = threadIdx.x; w < 3 * nw; w += (int)blockDim.x) win[w] = 0.0;
     __syncthreads();
-    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
       double wx[S + 1], wy[S + 1], wz[S + 1];
       const int bx = stencil<S>((B[i] - o[0]) * ih[0], c.nx, wx);
       const int by = stencil<S>((B[2 * n + i] - o[1]) * ih[1], c.ny, wy);
@@ -500,7 +500,7 @@ __device__ __forceinline__ void vdeposit_tiles_body(const double* __restrict__ B
         }
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < nw; w += kBlk) {
+    for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
       const int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       const int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
       if (gx < c.nx && gy < c.ny && gz < c.nz) {
@@ -516,7 +516,7 @@ __device__ __forceinline__ void vdeposit_tiles_body(const double* __restrict__ B
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_vdeposit_tiles(const double* __restrict__ B,
+__global__ __launch_bounds__(kMaxThreads) void k_vdeposit_tiles(const double* __restrict__ B,
                                                          const Geom* __restrict__ g, Consts c,
                                                          SortPlan sp,
                                                          const int4* __restrict__ chunks,
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kBlk) void k_vdeposit_tiles(const double* __restric
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_deposit_tiles(const double* __restrict__ B,
+__global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __restrict__ B,
                                                         const uint32_t* __restrict__ perm,
                                                         const Geom* __restrict__ g, Consts c,
                                                         SortPlan sp,
@@ -580,7 +580,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
     const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
     const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
     __syncthreads();  // the previous chunk's readers are done with the window
-    for (int w = threadIdx.x; w < nw; w += kBlk) {
+    for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
       int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
       bool in = gx < c.nx && gy < c.ny && gz < c.nz;
@@ -590,7 +590,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       win[2 * nw + w] = in ? E[2 * plane + gi] : T(0);
     }
     __syncthreads();
-    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += kBlk) {
+    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
       double v[6];
       int64_t i0 = i;
       if constexpr (PERM) {
@@ -651,7 +651,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
 }
 
 template <int S, typename T, bool PERM>
-__global__ __launch_bounds__(kBlk) void k_gkd_tiles(double* __restrict__ B,
+__global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles(double* __restrict__ B,
                                                     const double* __restrict__ src,
                                                     const uint32_t* __restrict__ perm,
                                                     const uint32_t* __restrict__ idsrc,
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(kBlk) void k_scatter_batch(const BeamDev* __restric
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
+__global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
   deposit_tiles_body<S, T>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __r
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
+__global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
                                                           int parity, int j, int n_steps) {
   const BeamDev& d = beams[blockIdx.y];
   const SliceDev& sl = d.slices[j % d.n_slices];
@@ -925,7 +925,7 @@ int grid_stride(int64_t n) {
 }  // namespace
 
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
-                        int blocks) {
+                        int blocks, int threads) {
   SortPlan sp;
   int nn[3] = {nx, ny, nz};
   for (int a = 0; a < 3; ++a) {
@@ -942,9 +942,27 @@ SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], in
   // the work list also serves the id buckets of the final reordering (up to kMaxTiles entries)
   if (sp.max_chunks < kMaxTiles + 1) sp.max_chunks = kMaxTiles + 1;
   sp.blocks = blocks > 0 ? blocks : (int)(items < 4096 ? items : 4096);
-  sp.pad = 0;
+  sp.threads = threads > 0 ? threads : kBlk;
   return sp;
 }
+
+namespace {
+// Dynamic LDS above 64 KB needs the kernel's limit raised first; the runtime accepts a limit up
+// to the device's 160 KB less the kernel's static LDS.
+template <typename K>
+hipError_t lds_optin(K kernel, size_t bytes) {
+  if (bytes > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+}  // namespace
+
+#define PIC_TRY_LDS(kernel, bytes)            \
+  do {                                        \
+    hipError_t e_ = lds_optin(kernel, bytes); \
+    if (e_ != hipSuccess) return e_;          \
+  } while (0)
 
 hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
                            Consts c, Box* box, hipStream_t s) {
@@ -1003,13 +1021,16 @@ hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geo
                                 T* rho, hipStream_t s) {
   const int S = c.shape;
   size_t lds = sizeof(unsigned long long) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  const int64_t grid = sp.blocks;
-  if (S == 1)
-    hipLaunchKernelGGL((k_deposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, perm,
-                       g, c, sp, chunks, nchunks, rho);
-  else
-    hipLaunchKernelGGL((k_deposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, perm,
-                       g, c, sp, chunks, nchunks, rho);
+  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
+  if (S == 1) {
+    PIC_TRY_LDS((k_deposit_tiles<1, T>), lds);
+    hipLaunchKernelGGL((k_deposit_tiles<1, T>), grid, block, lds, s, B, perm, g, c, sp, chunks,
+                       nchunks, rho);
+  } else {
+    PIC_TRY_LDS((k_deposit_tiles<2, T>), lds);
+    hipLaunchKernelGGL((k_deposit_tiles<2, T>), grid, block, lds, s, B, perm, g, c, sp, chunks,
+                       nchunks, rho);
+  }
   return hipGetLastError();
 }
 
@@ -1019,14 +1040,16 @@ hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const
                                  hipStream_t s) {
   const int S = c.shape;
   const size_t lds = 3 * sizeof(double) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  if (lds > 65536) return hipErrorInvalidConfiguration;
-  const int64_t grid = sp.blocks;
-  if (S == 1)
-    hipLaunchKernelGGL((k_vdeposit_tiles<1, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g,
-                       c, sp, chunks, nchunks, e);
-  else
-    hipLaunchKernelGGL((k_vdeposit_tiles<2, T>), dim3((unsigned)grid), dim3(kBlk), lds, s, B, g,
-                       c, sp, chunks, nchunks, e);
+  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
+  if (S == 1) {
+    PIC_TRY_LDS((k_vdeposit_tiles<1, T>), lds);
+    hipLaunchKernelGGL((k_vdeposit_tiles<1, T>), grid, block, lds, s, B, g, c, sp, chunks, nchunks,
+                       e);
+  } else {
+    PIC_TRY_LDS((k_vdeposit_tiles<2, T>), lds);
+    hipLaunchKernelGGL((k_vdeposit_tiles<2, T>), grid, block, lds, s, B, g, c, sp, chunks, nchunks,
+                       e);
+  }
   return hipGetLastError();
 }
 
@@ -1045,12 +1068,16 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
                             int has_next, const HalfMap& first_next, Box* box, hipStream_t s) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  const dim3 grid((unsigned)sp.blocks);
+  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
   if (perm && (!src || !idsrc || !iddst || src == B || idsrc == iddst))
     return hipErrorInvalidValue;
 #define PIC_GKD(SS, PP)                                                                       \
-  hipLaunchKernelGGL((k_gkd_tiles<SS, T, PP>), grid, dim3(kBlk), lds, s, B, src, perm, idsrc, \
-                     iddst, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next, box)
+  do {                                                                                        \
+    PIC_TRY_LDS((k_gkd_tiles<SS, T, PP>), lds);                                               \
+    hipLaunchKernelGGL((k_gkd_tiles<SS, T, PP>), grid, block, lds, s, B, src, perm, idsrc,    \
+                       iddst, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next,  \
+                       box);                                                                  \
+  } while (0)
   if (S == 1) {
     if (perm) PIC_GKD(1, true); else PIC_GKD(1, false);
   } else {
@@ -1136,12 +1163,15 @@ template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                                 int parity, hipStream_t s) {
   const dim3 grid(bd.max_chunks, nb);
-  if (shape == 1)
+  if (shape == 1) {
+    PIC_TRY_LDS((k_deposit_tiles_batch<1, T>), bd.dep_lds);
     hipLaunchKernelGGL((k_deposit_tiles_batch<1, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
                        parity);
-  else
+  } else {
+    PIC_TRY_LDS((k_deposit_tiles_batch<2, T>), bd.dep_lds);
     hipLaunchKernelGGL((k_deposit_tiles_batch<2, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
                        parity);
+  }
   return hipGetLastError();
 }
 
@@ -1149,12 +1179,15 @@ template <typename T>
 hipError_t launch_batch_gkd(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                             int parity, int j, int n_steps, hipStream_t s) {
   const dim3 grid(bd.max_chunks, nb);
-  if (shape == 1)
+  if (shape == 1) {
+    PIC_TRY_LDS((k_gkd_tiles_batch<1, T>), bd.gkd_lds);
     hipLaunchKernelGGL((k_gkd_tiles_batch<1, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
                        j, n_steps);
-  else
+  } else {
+    PIC_TRY_LDS((k_gkd_tiles_batch<2, T>), bd.gkd_lds);
     hipLaunchKernelGGL((k_gkd_tiles_batch<2, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
                        j, n_steps);
+  }
   return hipGetLastError();
 }
 

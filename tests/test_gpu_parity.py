@@ -31,9 +31,9 @@ def _problem(cfg, n=None, nodes=None, shape=None):
                              cfg.shape if shape is None else shape)
 
 
-def _gpu_beam(lib, cfg, n, nodes, shape, grid_fp32=False, space_charge=True):
+def _gpu_beam(lib, cfg, n, nodes, shape, grid_fp32=False, space_charge=True, tuning=None):
     return lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes,
-                    grid_fp32=grid_fp32, space_charge=space_charge)
+                    grid_fp32=grid_fp32, space_charge=space_charge, tuning=tuning)
 
 
 def _start(lib, cfg, n, nodes, shape, seed=None, **kw):
@@ -196,4 +196,18 @@ def test_zero_charge_equals_the_linear_map(lib):
     b.track(cfg.lattice, 6)
     Xo = opic.track(X, ks, dss, 6, prob, space_charge=False)
     assert _coord_err(b.X.cpu().numpy(), Xo) < 1e-14
+    assert b.check() == lib.PIC_OK
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7])
+def test_box_changing_severalfold_every_step(lib, steps):
+    # thin quads of +-12/m over 0.5 m drifts change the beam's size several-fold every step,
+    # so most particles change tile between steps
+    cfg = workloads.SMALL.with_(lattice=((-12.0, 0.5), (12.0, 0.5)))
+    n, nodes, shape = 6_007, (16, 24, 16), 2
+    b, X = _start(lib, cfg, n, nodes, shape)
+    b.track(cfg.lattice, steps)
+    ks, dss = workloads.lattice_arrays(cfg)
+    Xo = opic.track(X, ks, dss, steps, _problem(cfg, n, nodes, shape))
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
     assert b.check() == lib.PIC_OK

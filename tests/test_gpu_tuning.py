@@ -19,7 +19,9 @@ def lib():
 @pytest.mark.parametrize("tuning", [
     {"tile": (4, 4, 4), "chunk": 256, "blocks": 7},     # many work items per tile, few groups
     {"tile": (8, 6, 12), "chunk": 1024},                # uneven tiles
-    {"tile": (24, 18, 9), "blocks": 3},                 # a few large tiles
+    {"tile": (24, 18, 9), "blocks": 3},                 # a few large tiles (137 KB field window)
+    {"tile": (12, 9, 18), "threads": 1024, "chunk": 512},  # wide workgroups
+    {"threads": 64, "blocks": 5},                       # one wave per workgroup
 ])
 def test_launch_shapes_keep_parity(lib, tuning):
     cfg = workloads.SMALL
@@ -43,11 +45,11 @@ def test_autotune_cache_round_trip(lib, tmp_path):
     cfg = workloads.SMALL.with_(n=20_000)
     cache = str(tmp_path / "tuning.json")
     rec = autotune.tune(cfg, steps=1, cache=cache)
-    assert set(("tile", "chunk", "blocks", "s_per_step", "tried")) <= set(rec)
+    assert set(("tile", "chunk", "blocks", "threads", "s_per_step", "tried")) <= set(rec)
     assert rec["s_per_step"] <= rec["default_s_per_step"]
     assert len(rec["tried"]) >= 5
     t = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False, cache=cache)
-    assert t == {k: rec[k] for k in ("tile", "chunk", "blocks")}
+    assert t == {k: rec[k] for k in ("tile", "chunk", "blocks", "threads")}
     assert autotune.tune(cfg, steps=1, cache=cache)["tried"] == rec["tried"]   # served cached
     # the chosen shape is a valid description
     b = lib.Beam.from_config(cfg, tuning=t)
