@@ -24,10 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
 METRIC = "particle-steps/s, 1e8 ptcl 128^3 space-charge PIC; FP32/batched/adjoint vs plain"
-# algorithmic bytes per particle per launch (float64 phase space)
+# algorithmic bytes per particle per launch (float64 phase space) in the steady state of the
+# tracking loop, where both kernels read the particles through the step's sort permutation
+# (the first step of a call reads them in tile order: 24 and 96 B)
 ALGO_BYTES = {
-    "deposit": 24,   # read x, y, z
-    "gkd": 96,       # read and write the six coordinates
+    "deposit": 28,   # read the slot's source index and x, y, z
+    "gkd": 108,      # read the source index, the six coordinates and the id; write both
 }
 # (file, device function) whose source text the counter figures were taken on
 KERNEL_SOURCES = {"gkd": ("paper_2208_02382_amd/csrc/sort.hip", "gkd_tiles_body"),
