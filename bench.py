@@ -360,6 +360,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-grid variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched variant")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
+    ap.add_argument("--no-thick", action="store_true",
+                    help="skip the thick-element (Listing 1 FODO) variant")
     ap.add_argument("--batch-beams", type=int, default=256)
     ap.add_argument("--oracle-timings", action="store_true",
                     help="time the oracle on every workload (host CPU, a few minutes) and exit")
@@ -438,6 +440,20 @@ def main():
         del X
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if not args.no_thick:
+        # the same beam through the paper's FODO cell of thick elements (Listing 1), one step
+        # per slice (125 per cell)
+        cfg_t = cfg.with_(lattice=workloads.THICK_FODO)
+        bt, dtt, stt, _ = run_gpu(cfg_t, args.steps, args.warmup, grid_fp32=False, tuning=tuning)
+        variants["thick_fodo"] = {
+            "value": cfg.n * args.steps / dtt, "ms_per_step": dtt / args.steps * 1e3,
+            "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in stt.items()},
+            "lattice": "Listing 1 FODO: Drift 0.25, Quad(1.0, k=+1), Drift 0.5, Quad(1.0, k=-1), "
+                       "Drift 0.25, 25 slices each; steps are slices",
+            "note": "float64; same beam, grid, shape and launch shapes as the headline"}
+        bt.close()
+        del bt
+        torch.cuda.empty_cache()
     if not args.no_fp32:
         variants["fp32_grid_accuracy"] = fp32_accuracy(workloads.MEDIUM, workloads.MEDIUM.steps)
     if not args.no_batched:

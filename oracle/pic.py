@@ -306,6 +306,38 @@ def track_elements(X, elements, n_steps, prob: Problem, space_charge=True):
     return X
 
 
+# ----------------------------------------------------------------------------- distributions
+
+def sigma_from_params(sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx, muypy, mutpt):
+    """6x6 covariance (x, px, y, py, z, delta) of the distribution parameters of Listing 1
+    (`distribution.Waterbag(sigmaX, ..., muxpx, muypy, mutpt)`).  Reading (the paper prints the
+    parameters, not their definition): in each plane (u, pu) the rms size is
+    sigmaU / sqrt(1 - muupu^2), the rms momentum sigmaPu / sqrt(1 - muupu^2) and the correlation
+    coefficient -muupu; the Listing's (t, pt) pair is taken as (z, delta)."""
+    S = np.zeros((6, 6))
+    for i, (su, sp, mu) in enumerate(((sigmaX, sigmaPx, muxpx), (sigmaY, sigmaPy, muypy),
+                                      (sigmaT, sigmaPt, mutpt))):
+        if not (su > 0 and sp > 0 and abs(mu) < 1):
+            raise ValueError("sigmas must be positive and |mu| < 1")
+        c = 1.0 / np.sqrt(1.0 - mu * mu)
+        ru, rp = su * c, sp * c
+        S[2 * i, 2 * i] = ru * ru
+        S[2 * i + 1, 2 * i + 1] = rp * rp
+        S[2 * i, 2 * i + 1] = S[2 * i + 1, 2 * i] = -mu * ru * rp
+    return S
+
+
+WATERBAG_RADIUS = np.sqrt(8.0)   # a uniform 6-ball of this radius has unit covariance
+
+
+def init_waterbag(sigma6, xi_ball):
+    """Waterbag beam: uniform density inside the 6-D ellipsoid x^T Sigma^-1 x <= 8, whose
+    covariance is Sigma (reading: the paper names the distribution only).  xi_ball (6, n) are
+    points uniform in the ball of radius sqrt(8) (unit covariance); x = L xi with L the lower
+    Cholesky factor of Sigma, as for the Gaussian beam."""
+    return init_from_normals(sigma6, xi_ball)
+
+
 # ----------------------------------------------------------------------------- statistics
 
 def moments(X):

@@ -12,7 +12,12 @@ sides can be compared draw by draw): particle i, draw block c in {0, 1, 2} uses 
 Core particles: Box-Muller, xi_{2c} = sqrt(-2 ln u_a) cos(2 pi u_b),
 xi_{2c+1} = sqrt(-2 ln u_a) sin(2 pi u_b).  Halo particles: xi = -4 + 8 u.
 
-Pinned by tests/test_oracle_rng.py (Random123 known-answer vectors for Philox4x32-10).
+Waterbag particles: the six Box-Muller normals g of draw blocks 0-2 give a direction, and
+u_a of block 3 a radius: xi = sqrt(8) u_a^(1/6) g / |g|, uniform in the 6-ball of radius
+sqrt(8) (Muller's method: an isotropic direction times a radius with CDF (r/R)^6).
+
+Pinned by tests/test_oracle_rng.py (Random123 known-answer vectors for Philox4x32-10; the
+radial law, bound and covariance of the Waterbag draws).
 """
 import numpy as np
 
@@ -65,3 +70,24 @@ def beam_xi(n, seed, n_halo):
         xi[2 * c] = np.where(core, rad * np.cos(ang), -4.0 + 8.0 * ua)
         xi[2 * c + 1] = np.where(core, rad * np.sin(ang), -4.0 + 8.0 * ub)
     return xi
+
+
+def waterbag_xi(n, seed):
+    """xi (6, n) of the on-device Waterbag initialisation: uniform in the ball of radius
+    sqrt(8)."""
+    i = np.arange(n, dtype=np.uint64)
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    g = np.empty((6, n))
+    for c in range(3):
+        ctr = np.stack([i & _MASK, i >> _S32, np.full(n, c, dtype=np.uint64),
+                        np.zeros(n, dtype=np.uint64)])
+        ua, ub = uniforms(philox4x32_10(ctr, key))
+        rad = np.sqrt(-2.0 * np.log(ua))
+        ang = 2.0 * np.pi * ub
+        g[2 * c] = rad * np.cos(ang)
+        g[2 * c + 1] = rad * np.sin(ang)
+    ctr = np.stack([i & _MASK, i >> _S32, np.full(n, 3, dtype=np.uint64),
+                    np.zeros(n, dtype=np.uint64)])
+    ua, _ = uniforms(philox4x32_10(ctr, key))
+    norm = np.sqrt(np.sum(g * g, axis=0))
+    return np.sqrt(8.0) * np.power(ua, 1.0 / 6.0) * g / norm

@@ -34,3 +34,33 @@ def test_listing_beam_has_the_printed_emittance():
     # the paper prints one significant digit ("2 nm"); the parameters give it to 1e-9
     for e in (eps_x, eps_y):
         assert abs(e - g["printed_emittance_m"]) < 1e-9 * g["printed_emittance_m"]
+
+
+def test_parameter_mapping_gives_the_printed_emittance():
+    # oracle.pic.sigma_from_params on the Listing's numbers: the 2 nm emittance printed in the
+    # text, rms sizes from the parameters, correlation -mu, and the Waterbag of that covariance
+    g = json.load(open(GOLDEN))
+    S = pic.sigma_from_params(g["sigmaX"], g["sigmaY"], 1.0e-3, g["sigmaPx"], g["sigmaPy"],
+                              2.0e-3, g["muxpx"], g["muypy"], 0.0)
+    for i, mu in ((0, g["muxpx"]), (2, g["muypy"])):
+        eps = np.sqrt(np.linalg.det(S[i:i + 2, i:i + 2]))
+        assert abs(eps - g["printed_emittance_m"]) < 1e-9 * g["printed_emittance_m"]
+        rho = S[i, i + 1] / np.sqrt(S[i, i] * S[i + 1, i + 1])
+        assert abs(rho + mu) < 1e-15
+    assert S[4, 5] == 0.0 and S[4, 4] == 1e-6 and abs(S[5, 5] - 4e-6) < 1e-21
+    # a Waterbag beam of that covariance: second moments within sampling error
+    from oracle import rng
+    n = 200_000
+    X = pic.init_waterbag(S, rng.waterbag_xi(n, seed=9))
+    _, cov, m = pic.moments(X)
+    d = np.sqrt(np.diag(S))
+    assert np.all(np.abs(cov - S) / np.outer(d, d) < 5.0 / np.sqrt(n))
+    # inside the ellipsoid x^T S^-1 x <= 8
+    q = np.einsum("in,ij,jn->n", X, np.linalg.inv(S), X)
+    assert q.max() <= 8.0 * (1 + 1e-9)
+    for bad in ((0.0, 1.0, 0.1), (1.0, 1.0, 1.0)):
+        try:
+            pic.sigma_from_params(bad[0], 1, 1, bad[1], 1, 1, bad[2], 0, 0)
+            assert False
+        except ValueError:
+            pass

@@ -43,3 +43,27 @@ def test_halo_rows_uniform():
     h = xi[:, -1000:]
     assert h.min() > -4.0 and h.max() <= 4.0
     assert abs(h.var() - 64.0 / 12.0) < 0.3
+
+
+def test_waterbag_draws_fill_the_ball_uniformly():
+    # uniform in the 6-ball of radius R = sqrt(8): |xi| <= R, (|xi|/R)^6 ~ U(0, 1) (the radial
+    # law of a uniform ball), isotropic, unit covariance
+    n = 100_000
+    xi = rng.waterbag_xi(n, seed=777)
+    r = np.sqrt(np.sum(xi * xi, axis=0))
+    R = np.sqrt(8.0)
+    assert r.max() <= R * (1 + 1e-15)
+    v = np.sort((r / R) ** 6)
+    ks = np.max(np.maximum(np.arange(1, n + 1) / n - v, v - np.arange(n) / n))
+    assert ks < 1.63 / np.sqrt(n)   # Kolmogorov-Smirnov, 1 % level
+    tol = 5.0 / np.sqrt(n)
+    assert np.all(np.abs(xi.mean(axis=1)) < tol)
+    c = np.cov(xi)
+    assert np.all(np.abs(np.diag(c) - 1.0) < 3 * tol)
+    assert np.all(np.abs(c - np.diag(np.diag(c))) < tol)
+    # half the radius holds 1/64 of a uniform 6-ball
+    assert abs(np.mean(r < R / 2) - 1 / 64) < 5 * np.sqrt(1 / 64 / n)
+    # the directions are those of the Gaussian draws of the same counters
+    g = rng.beam_xi(n, seed=777, n_halo=0)
+    cos = np.sum(g * xi, axis=0) / (np.sqrt(np.sum(g * g, axis=0)) * r)
+    assert np.all(np.abs(cos - 1.0) < 1e-12)

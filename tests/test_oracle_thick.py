@@ -26,14 +26,9 @@ def _twiss(M):
 
 
 def _listing_sigma():
-    S = np.zeros((6, 6))
-    for (i, s, sp, mu) in ((0, BEAM["sigmaX"], BEAM["sigmaPx"], BEAM["muxpx"]),
-                           (2, BEAM["sigmaY"], BEAM["sigmaPy"], BEAM["muypy"])):
-        rx, rp = s / np.sqrt(1 - mu ** 2), sp / np.sqrt(1 - mu ** 2)
-        S[i, i], S[i + 1, i + 1] = rx ** 2, rp ** 2
-        S[i, i + 1] = S[i + 1, i] = -mu * rx * rp
-    S[4, 4], S[5, 5] = 1e-6, 4e-6
-    return S
+    # the Listing's Waterbag parameters (sigmaT = 1e-3, sigmaPt = 2e-3, mutpt = 0 as printed)
+    return pic.sigma_from_params(BEAM["sigmaX"], BEAM["sigmaY"], 1.0e-3, BEAM["sigmaPx"],
+                                 BEAM["sigmaPy"], 2.0e-3, BEAM["muxpx"], BEAM["muypy"], 0.0)
 
 
 def _problem():
