@@ -133,6 +133,21 @@ pic_status pic_beam_destroy(pic_beam b);
 pic_status pic_init_beam(pic_beam b, const double sigma6x6[36], uint64_t seed, double halo_frac,
                          void* stream);
 
+/* Waterbag beam (Listing 1: distribution.Waterbag): X uniform inside the 6-D ellipsoid
+ * x^T sigma^-1 x <= 8, whose covariance is sigma6x6 (row-major, symmetric positive definite;
+ * PIC_EINVAL otherwise).  x = L xi with xi uniform in the ball of radius sqrt(8): the direction
+ * of the six Box-Muller normals of pic_init_beam's draw blocks 0-2 (no halo), times
+ * sqrt(8) u^(1/6) with u the first uniform of draw block 3 of the same Philox4x32-10 stream. */
+pic_status pic_init_beam_waterbag(pic_beam b, const double sigma6x6[36], uint64_t seed,
+                                  void* stream);
+
+/* Covariance (x, px, y, py, z, delta) from the distribution parameters of Listing 1, in the
+ * order p = {sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx, muypy, mutpt}: in each
+ * plane the rms size is sigmaU/sqrt(1 - mu^2), the rms momentum sigmaPu/sqrt(1 - mu^2) and the
+ * correlation coefficient -mu; (t, pt) are taken as (z, delta).  Host only (no device, no
+ * stream).  PIC_EINVAL unless every sigma is finite and positive and |mu| < 1. */
+pic_status pic_sigma_from_params(const double params[9], double sigma6x6[36]);
+
 /* Same as pic_init_beam with caller-supplied draws: d_xi is a device array of 6*n doubles in
  * the layout of X.  Used to start the device and a reference implementation from the same
  * draws. */
@@ -180,6 +195,17 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * during the call (see pic_check), X is left as it was before the call. */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
+
+/* Slice-step diagnostics (Listing 1: set_slice_step_diagnostics(True)): as pic_track_n_steps,
+ * and after every step j the moments of the particles at the end of that step go to the device
+ * array d_diag[27*j .. 27*j+26] (27 * n_steps doubles, 8-byte aligned, caller-owned): the six
+ * means of (x, px, y, py, z, delta), then the 21 centred second moments <d_a d_b> with 1/n, for
+ * a <= b in row-major order of the upper triangle.  Each step then runs its gather-kick to
+ * the end of the step and applies the next step's first half map in a separate pass (about
+ * 190 B more HBM traffic per particle and step).  Results equal pic_track_n_steps' to rounding;
+ * the moments of step j use the same reduction as pic_moments. */
+pic_status pic_track_n_steps_diag(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                                  double* d_diag, void* stream);
 
 /* Batched tracking of many independent beams (each created with pic_beam_create, all with the
  * same shape and grid precision, space_charge = 1; grids and particle counts may differ).

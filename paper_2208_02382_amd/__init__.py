@@ -55,11 +55,14 @@ _SIGS = {
     "pic_beam_destroy": (_I, [_P]),
     "pic_init_beam": (_I, [_P, ctypes.POINTER(_D), ctypes.c_uint64, _D, _P]),
     "pic_init_beam_from_normals": (_I, [_P, ctypes.POINTER(_D), _P, _P]),
+    "pic_init_beam_waterbag": (_I, [_P, ctypes.POINTER(_D), ctypes.c_uint64, _P]),
+    "pic_sigma_from_params": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "pic_deposit": (_I, [_P, _P, _P]),
     "pic_poisson_solve": (_I, [_P, _P, _P, _P, _P]),
     "pic_gather": (_I, [_P, _P, _P, _P]),
     "pic_push": (_I, [_P, _I, _D, _P, _P]),
     "pic_track_n_steps": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P]),
+    "pic_track_n_steps_diag": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P, _P]),
     "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "pic_get_geometry": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_check": (_I, [_P, _P]),
@@ -110,6 +113,16 @@ def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid
                     float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
                     int(bool(space_charge)), (ctypes.c_int * 3)(*[int(v) for v in tile]),
                     int(t.get("chunk", 0)), int(t.get("blocks", 0)), int(t.get("threads", 0)))
+
+
+def sigma_from_params(sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx=0.0, muypy=0.0,
+                      mutpt=0.0):
+    """6x6 covariance (nested lists) from Listing 1's distribution parameters."""
+    p = (ctypes.c_double * 9)(sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx, muypy,
+                              mutpt)
+    out = (ctypes.c_double * 36)()
+    _check(_lib.pic_sigma_from_params(p, out), "pic_sigma_from_params")
+    return [list(out[r * 6:(r + 1) * 6]) for r in range(6)]
 
 
 def workspace_bytes(desc):
@@ -199,6 +212,11 @@ class Beam:
         _check(_lib.pic_init_beam(self._h, _sigma(sigma), int(seed), float(halo_frac),
                                   _stream()), "pic_init_beam")
 
+    def init_waterbag(self, sigma, seed):
+        """Uniform inside the 6-D ellipsoid x^T sigma^-1 x <= 8 (covariance sigma)."""
+        _check(_lib.pic_init_beam_waterbag(self._h, _sigma(sigma), int(seed), _stream()),
+               "pic_init_beam_waterbag")
+
     def init_from_normals(self, sigma, xi):
         assert xi.dtype == torch.float64 and xi.is_contiguous() and tuple(xi.shape) == (6, self.n)
         _check(_lib.pic_init_beam_from_normals(self._h, _sigma(sigma), _ptr(xi), _stream()),
@@ -223,11 +241,20 @@ class Beam:
     def push(self, kind, value, Ep=None):
         _check(_lib.pic_push(self._h, int(kind), float(value), _ptr(Ep), _stream()), "pic_push")
 
-    def track(self, lattice, n_steps):
-        """lattice: sequence of (k, ds) pairs, cycled over the steps."""
+    def track(self, lattice, n_steps, diagnostics=False):
+        """lattice: (k, ds) thin steps or (kind, k, ds, nslice) elements, cycled over the steps.
+        diagnostics: also return the moments at the end of every step, a float64 tensor
+        (n_steps, 27) on the device (6 means, then the 21 centred second moments, upper
+        triangle row-major)."""
         arr = _lattice(lattice)
-        _check(_lib.pic_track_n_steps(self._h, arr, len(lattice), int(n_steps), _stream()),
-               "pic_track_n_steps")
+        if not diagnostics:
+            _check(_lib.pic_track_n_steps(self._h, arr, len(lattice), int(n_steps), _stream()),
+                   "pic_track_n_steps")
+            return None
+        diag = torch.empty((max(int(n_steps), 1), 27), dtype=torch.float64, device=self.device)
+        _check(_lib.pic_track_n_steps_diag(self._h, arr, len(lattice), int(n_steps), _ptr(diag),
+                                           _stream()), "pic_track_n_steps_diag")
+        return diag[:int(n_steps)]
 
     def moments(self):
         mean = (ctypes.c_double * 6)()

@@ -351,8 +351,12 @@ pic_status fork_green(pic_beam b, hipStream_t s) {
   return PIC_OK;
 }
 
+// diag: nullptr, or a device array that receives the moments (kMomentSlots doubles) of the
+// particles at the end of every step; the gather-kick then stops at the end of the step and a
+// separate pass applies the next step's first half map.
 template <typename T>
-pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hipStream_t s) {
+pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, double* diag,
+                    hipStream_t s) {
   const int ns = (int)sl.size();
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   double* A = b->XA;
@@ -396,7 +400,8 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
     HIP_OK(hipStreamWaitEvent(s, b->ev_join, 0), "join");
     st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
     if (st != PIC_OK) return st;
-    const int has_next = j + 1 < n_steps;
+    const int more = j + 1 < n_steps;
+    const int has_next = more && !diag;  // fuse the next step's first half map
     const SliceDev& nx = sl[(j + 1) % ns];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
     if (tiles)
@@ -411,6 +416,14 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, hi
             launch_gkd<T>(B, b->geom, (const T*)b->E, e.L, e.second, has_next, nx.first, b->c,
                           b->box, s),
             "gather-kick-drift");
+    if (diag) {  // moments at the end of the step, then the next step's first half map
+      HIP_OK(launch_moments(B, b->c.n, b->mom_partial, diag + (size_t)kMomentSlots * j, s),
+             "diagnostics");
+      if (more) {
+        HIP_OK(launch_box_reset(b->box, s), "box reset");
+        HIP_OK(launch_half_box(B, nx.first, b->c, b->box, s), "diagnostics");
+      }
+    }
     // B holds the updated particles in slot order
     double* tX = A; A = B; B = tX;
     uint32_t* tI = idA; idA = idB; idB = tI;
@@ -736,8 +749,38 @@ pic_status pic_init_beam(pic_beam b, const double sigma[36], uint64_t seed, doub
   if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
   int64_t n_halo = (int64_t)std::floor(halo_frac * (double)b->d.n + 0.5);
   hipStream_t s = S(stream);
-  HIP_OK(launch_init_philox(b->X, b->d.n, n_halo, seed, L, s), "init_beam");
+  HIP_OK(launch_init_philox(b->X, b->d.n, n_halo, seed, L, 0, s), "init_beam");
   HIP_OK(launch_clear_status(b->geom, s), "init_beam");
+  return PIC_OK;
+}
+
+pic_status pic_init_beam_waterbag(pic_beam b, const double sigma[36], uint64_t seed,
+                                  void* stream) {
+  if (!b || !sigma) return fail(PIC_EINVAL, "NULL argument");
+  Chol L;
+  if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
+  hipStream_t s = S(stream);
+  HIP_OK(launch_init_philox(b->X, b->d.n, 0, seed, L, 1, s), "init_beam_waterbag");
+  HIP_OK(launch_clear_status(b->geom, s), "init_beam_waterbag");
+  return PIC_OK;
+}
+
+pic_status pic_sigma_from_params(const double p[9], double sigma[36]) {
+  if (!p || !sigma) return fail(PIC_EINVAL, "NULL argument");
+  double S[36] = {0};
+  for (int a = 0; a < 3; ++a) {
+    const double su = p[a], sp = p[3 + a], mu = p[6 + a];
+    if (!(su > 0.0) || !(sp > 0.0) || !std::isfinite(su) || !std::isfinite(sp) ||
+        !(std::fabs(mu) < 1.0))
+      return fail(PIC_EINVAL, "sigmas must be finite and positive, |mu| < 1");
+    const double c = 1.0 / std::sqrt(1.0 - mu * mu);
+    const double ru = su * c, rp = sp * c;
+    const int i = 2 * a;
+    S[i * 6 + i] = ru * ru;
+    S[(i + 1) * 6 + i + 1] = rp * rp;
+    S[i * 6 + i + 1] = S[(i + 1) * 6 + i] = -mu * ru * rp;
+  }
+  std::memcpy(sigma, S, sizeof(S));
   return PIC_OK;
 }
 
@@ -803,8 +846,9 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
   return PIC_OK;
 }
 
-pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
-                             void* stream) {
+namespace {
+pic_status track(pic_beam b, const pic_element* lattice, int n_el, int n_steps, double* diag,
+                 void* stream) {
   if (!b || !lattice) return fail(PIC_EINVAL, "NULL argument");
   if (n_el < 1 || n_steps < 0) return fail(PIC_EINVAL, "n_el must be >= 1 and n_steps >= 0");
   std::vector<SliceDev> sl;
@@ -816,11 +860,27 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
     for (int j = 0; j < n_steps; ++j) {
       const SliceDev& e = sl[j % sl.size()];
       HIP_OK(launch_half_maps(b->X, e.first, e.second, b->c, s), "track");
+      if (diag)
+        HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, diag + (size_t)kMomentSlots * j, s),
+               "diagnostics");
     }
     return PIC_OK;
   }
-  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, s);
-  return track_sc<double>(b, sl, n_steps, s);
+  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, diag, s);
+  return track_sc<double>(b, sl, n_steps, diag, s);
+}
+}  // namespace
+
+pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                             void* stream) {
+  return track(b, lattice, n_el, n_steps, nullptr, stream);
+}
+
+pic_status pic_track_n_steps_diag(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
+                                  double* d_diag, void* stream) {
+  if (!d_diag) return fail(PIC_EINVAL, "NULL diagnostics array");
+  if ((uintptr_t)d_diag & 7) return fail(PIC_EINVAL, "the diagnostics array must be 8-byte aligned");
+  return track(b, lattice, n_el, n_steps, d_diag, stream);
 }
 
 pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream) {

@@ -133,8 +133,9 @@ hipError_t launch_box_reset(Box* box, hipStream_t s);
 hipError_t launch_box(const double* X, int64_t n, Box* box, hipStream_t s);
 hipError_t launch_geometry(const Box* box, Geom* g, Consts c, hipStream_t s);
 hipError_t launch_init_normals(double* X, const double* xi, int64_t n, Chol L, hipStream_t s);
+// dist 0: Gaussian with a uniform halo of n_halo trailing particles; 1: Waterbag (n_halo 0)
 hipError_t launch_init_philox(double* X, int64_t n, int64_t n_halo, uint64_t seed, Chol L,
-                              hipStream_t s);
+                              int dist, hipStream_t s);
 hipError_t launch_clear_status(Geom* g, hipStream_t s);
 template <typename T>
 hipError_t launch_deposit(const double* X, const Geom* g, T* rho, Consts c, hipStream_t s);
@@ -183,6 +184,8 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
 // both half maps of a slice without a kick (tracking without space charge)
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
                             hipStream_t s);
+// one half map in place and the box of the new positions
+hipError_t launch_half_box(double* X, const HalfMap& h, Consts c, Box* box, hipStream_t s);
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
                             uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
                             uint32_t* nchunks, double* B, uint32_t* idB, const Geom* g,

@@ -127,13 +127,16 @@ __device__ __forceinline__ double u53(unsigned a, unsigned b) {
   return (double)k * 0x1.0p-53;
 }
 
+// dist 0: Gaussian core (Box-Muller of draw blocks 0-2) and, for i >= n_core, the uniform
+// halo in [-4, 4]^6.  dist 1: Waterbag, uniform in the 6-ball of radius sqrt(8) (unit
+// covariance): the direction of the six normals times sqrt(8) u^(1/6), u from draw block 3.
 __global__ __launch_bounds__(kBlock) void k_init_philox(double* __restrict__ X, int64_t n,
                                                         int64_t n_core, unsigned k0, unsigned k1,
-                                                        Chol L) {
+                                                        Chol L, int dist) {
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
     double v[6];
-    bool core = i < n_core;
+    bool core = dist == 1 || i < n_core;
     for (unsigned blk = 0; blk < 3; ++blk) {
       unsigned c[4] = {(unsigned)((unsigned long long)i & 0xffffffffull),
                        (unsigned)((unsigned long long)i >> 32), blk, 0u};
@@ -150,6 +153,15 @@ __global__ __launch_bounds__(kBlock) void k_init_philox(double* __restrict__ X, 
         v[2 * blk] = -4.0 + 8.0 * ua;
         v[2 * blk + 1] = -4.0 + 8.0 * ub;
       }
+    }
+    if (dist == 1) {
+      unsigned c[4] = {(unsigned)((unsigned long long)i & 0xffffffffull),
+                       (unsigned)((unsigned long long)i >> 32), 3u, 0u};
+      philox4x32_10(c, k0, k1);
+      double g2 = 0.0;
+      for (int r = 0; r < 6; ++r) g2 += v[r] * v[r];
+      const double scale = sqrt(8.0) * pow(u53(c[0], c[1]), 1.0 / 6.0) / sqrt(g2);
+      for (int r = 0; r < 6; ++r) v[r] *= scale;
     }
     for (int r = 0; r < 6; ++r) {
       double s = 0.0;
@@ -477,9 +489,9 @@ hipError_t launch_init_normals(double* X, const double* xi, int64_t n, Chol L, h
 }
 
 hipError_t launch_init_philox(double* X, int64_t n, int64_t n_halo, uint64_t seed, Chol L,
-                              hipStream_t s) {
+                              int dist, hipStream_t s) {
   hipLaunchKernelGGL(k_init_philox, dim3(grid_for(n)), dim3(kBlock), 0, s, X, n, n - n_halo,
-                     (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32), L);
+                     (unsigned)(seed & 0xffffffffull), (unsigned)(seed >> 32), L, dist);
   return hipGetLastError();
 }
 
@@ -542,6 +554,34 @@ __global__ __launch_bounds__(kBlock) void k_half_maps(double* __restrict__ X, Ha
     apply_half(second, v, c.inv_gamma2);
     for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
   }
+}
+
+// One half map in place, with the box of the new positions (the first half of a step when the
+// previous step's end state was needed on its own, for diagnostics).
+__global__ __launch_bounds__(kBlock) void k_half_box(double* __restrict__ X, HalfMap h, Consts c,
+                                                     Box* box) {
+  const int64_t n = c.n;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
+    apply_half(h, v, c.inv_gamma2);
+    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
+    const double p[3] = {v[0], v[2], v[4]};
+    for (int a = 0; a < 3; ++a) {
+      bad |= !isfinite(p[a]);
+      lo[a] = fmin(lo[a], p[a]);
+      hi[a] = fmax(hi[a], p[a]);
+    }
+  }
+  box_accumulate_block(lo, hi, bad, box);
+}
+
+hipError_t launch_half_box(double* X, const HalfMap& h, Consts c, Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_half_box, dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, h, c, box);
+  return hipGetLastError();
 }
 
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,

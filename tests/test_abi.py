@@ -21,7 +21,7 @@ def _declared():
 
 def test_header_symbols_are_exported():
     names = _declared()
-    assert len(names) == 22
+    assert len(names) == 25
     lib = ctypes.CDLL(pic.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -135,3 +135,19 @@ def test_create_reports_no_device():
     st = pic._lib.pic_beam_create(ctypes.byref(d), fake, fake, nbytes, None, ctypes.byref(h))
     assert st == pic.PIC_ENODEV
     assert h.value is None
+
+
+def test_sigma_from_params_matches_the_oracle():
+    # host-only entry point: the Listing 1 parameters and a correlated longitudinal plane
+    from oracle import pic as opic
+    import numpy as np
+    for args in ((3.9984884770e-5, 3.9984884770e-5, 1.0e-3, 2.6623538760e-5, 2.6623538760e-5,
+                  2.0e-3, -0.846574929020762, 0.846574929020762, 0.0),
+                 (1e-3, 2e-3, 3e-3, 4e-4, 5e-4, 6e-4, 0.3, -0.5, 0.7)):
+        got = np.array(pic.sigma_from_params(*args))
+        ref = opic.sigma_from_params(*args)
+        assert np.allclose(got, ref, rtol=1e-15, atol=0)
+    for bad in ((0.0, 1, 1, 1, 1, 1, 0, 0, 0), (1, 1, 1, 1, 1, 1, 1.0, 0, 0),
+                (1, 1, float("nan"), 1, 1, 1, 0, 0, 0)):
+        with pytest.raises(pic.PicError):
+            pic.sigma_from_params(*bad)

@@ -211,3 +211,45 @@ def test_box_changing_severalfold_every_step(lib, steps):
     Xo = opic.track(X, ks, dss, steps, _problem(cfg, n, nodes, shape))
     assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
     assert b.check() == lib.PIC_OK
+
+
+LISTING = dict(sigmaX=3.9984884770e-5, sigmaY=3.9984884770e-5, sigmaT=1.0e-3,
+               sigmaPx=2.6623538760e-5, sigmaPy=2.6623538760e-5, sigmaPt=2.0e-3,
+               muxpx=-0.846574929020762, muypy=0.846574929020762, mutpt=0.0)
+
+
+def test_init_waterbag_matches_oracle_generator(lib):
+    cfg = workloads.MEDIUM
+    n = 100_003
+    S = np.array(lib.sigma_from_params(**LISTING))
+    assert np.allclose(S, opic.sigma_from_params(**LISTING), rtol=1e-15, atol=0)
+    b = _gpu_beam(lib, cfg, n, cfg.nodes, 1)
+    b.init_waterbag(S, seed=31)
+    Xg = b.X.cpu().numpy()
+    X0 = opic.init_waterbag(S, orng.waterbag_xi(n, 31))
+    assert _coord_err(Xg, X0) < 1e-13
+    q = np.einsum("in,ij,jn->n", Xg, np.linalg.inv(S), Xg)
+    assert q.max() <= 8.0 * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("space_charge", [False, True])
+def test_listing_example_through_the_fodo_cell(lib, space_charge):
+    # Listing 1: 1e4 macroparticles of a Waterbag beam, 2 GeV electrons, 1 nC, TSC, the FODO
+    # cell of thick elements (125 slices)
+    mass = 0.510998950
+    n, nodes, shape, steps = 10_000, (16, 16, 16), 2, 125
+    S = opic.sigma_from_params(**LISTING)
+    b = lib.Beam(n, -1.0e-6 / mass, 1.0e-9, 2.0e3, mass, shape, nodes,
+                 space_charge=space_charge)
+    b.init_waterbag(S, seed=5)
+    X0 = b.X.cpu().numpy()
+    b.track(workloads.THICK_FODO, steps)
+    prob = opic.make_problem(n, -1.0e-6 / mass, 1.0e-9, 2.0e3, mass, nodes, shape)
+    Xo = opic.track_elements(X0, workloads.THICK_FODO, steps, prob, space_charge=space_charge)
+    Xg = b.X.cpu().numpy()
+    assert _coord_err(Xg, Xo) < (TOL if space_charge else 3e-13)
+    if not space_charge:
+        # the paper's benchmark criterion: the emittances stay constant through the cell
+        _, _, m0 = opic.moments(X0)
+        _, _, m1 = opic.moments(Xg)
+        assert np.all(np.abs(m1[2:] - m0[2:]) / m0[2:] < 1e-12)

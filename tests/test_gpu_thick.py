@@ -124,3 +124,34 @@ def test_adjoint_rejects_thick_lattices(lib):
     with pytest.raises(lib.PicError) as e:
         b.track_adjoint(workloads.THICK_FODO, 4, [1.0, 0.0, 0.0, 0.0], ckpt_every=2)
     assert e.value.status == lib.PIC_EUNSUPPORTED
+
+
+def _diag_oracle(X, elements, steps, prob, space_charge=True):
+    sl = opic.slices(elements)
+    out = []
+    for j in range(steps):
+        kind, k, ell = sl[j % len(sl)]
+        X = opic.slice_step(X, kind, k, ell, prob, space_charge)
+        mean, cov, _ = opic.moments(X)
+        out.append(np.concatenate([mean, cov[np.triu_indices(6)]]))
+    return X, np.array(out)
+
+
+@pytest.mark.parametrize("space_charge", [True, False])
+def test_slice_step_diagnostics(lib, space_charge):
+    cfg = workloads.SMALL
+    n, nodes, shape, steps = 5_000, (16, 16, 16), 2, 30
+    b, X = _start(lib, cfg, n, nodes, shape, space_charge=space_charge)
+    b2, _ = _start(lib, cfg, n, nodes, shape, space_charge=space_charge)
+    diag = b.track(workloads.THICK_FODO, steps, diagnostics=True).cpu().numpy()
+    b2.track(workloads.THICK_FODO, steps)
+    assert diag.shape == (steps, 27)
+    Xo, do = _diag_oracle(X, workloads.THICK_FODO, steps, _problem(cfg, n, nodes, shape),
+                          space_charge)
+    rms = np.sqrt(np.diag(np.cov(Xo)))
+    assert np.all(np.abs(diag[:, :6] - do[:, :6]) / rms < TOL)
+    assert np.abs(diag[:, 6:] - do[:, 6:]).max() < TOL * np.abs(do[:, 6:]).max()
+    # the end state equals tracking without diagnostics (the same arithmetic, split in two
+    # passes at the end of each step)
+    assert _coord_err(b.X.cpu().numpy(), b2.X.cpu().numpy()) < 1e-13
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
