@@ -454,6 +454,25 @@ def main():
         bt.close()
         del bt
         torch.cuda.empty_cache()
+    if not args.no_thick:
+        # slice-step diagnostics (moments after every step) on the headline workload
+        import paper_2208_02382_amd as pic
+        bd = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
+                      cfg.shape, cfg.nodes, tuning=tuning)
+        bd.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+        bd.track(cfg.lattice, args.warmup, diagnostics=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        diag = bd.track(cfg.lattice, args.steps, diagnostics=True)
+        torch.cuda.synchronize()
+        dtd = time.perf_counter() - t0
+        variants["slice_step_diagnostics"] = {
+            "value": cfg.n * args.steps / dtd, "ms_per_step": dtd / args.steps * 1e3,
+            "note": "headline workload with the 27 moments recorded after every step",
+            "last_step_rms_x_y": [float(diag[-1, 6] ** 0.5), float(diag[-1, 6 + 11] ** 0.5)]}
+        bd.close()
+        del bd, diag
+        torch.cuda.empty_cache()
     if not args.no_fp32:
         variants["fp32_grid_accuracy"] = fp32_accuracy(workloads.MEDIUM, workloads.MEDIUM.steps)
     if not args.no_batched:
