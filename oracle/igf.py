@@ -24,9 +24,14 @@ the field.  The oracle therefore evaluates F and the corner sum in double-double
 (oracle.dd) and rounds the cell average to float64 once, so the returned array is the cell
 average of 1/r to float64 rounding.
 
+The field's own cell averages (field_cell_average: the mean of u_a/|r|^3 over the cell, by the
+2-D antiderivative H of field_antiderivative) give E' without differencing phi.
+
 Pinned by tests/test_oracle_igf.py: unit-cube closed form 3 ln(2+sqrt3) - pi/2; scipy adaptive
 cubature for anisotropic cells; 50-digit mpmath corner sums for far, elongated cells;
-Gbar(d) |d| -> 1 with an O((h/d)^4) error for cubic cells.
+Gbar(d) |d| -> 1 with an O((h/d)^4) error for cubic cells.  The field kernels by
+tests/test_oracle_field.py: scipy cubature, the far-field limit, the direct sum, and the exact
+field of a uniformly charged box (30-digit mpmath).
 """
 import numpy as np
 
@@ -103,6 +108,86 @@ def cell_average(nx, ny, nz, hx, hy, hz):
     vol = dd.mul(dd.two_prod(np.float64(hx), np.float64(hy)), dd.dd(np.float64(hz)))
     vol = (np.full(D[0].shape, vol[0]), np.full(D[0].shape, vol[1]))
     return dd.to_float(dd.div(D, vol))
+
+
+def field_antiderivative(u, v, w):
+    """H(u, v, w) = v ln(w + r) + w ln(v + r) - u atan(v w / (u r)) on double-double inputs >= 0
+    (terms with a zero prefactor taken as zero): d^2 H / dv dw = 1/r, so that the cell integral
+    of u/r^3 = -d(1/r)/du is minus the alternating 8-corner sum of H."""
+    u2 = dd.mul(u, u)
+    v2 = dd.mul(v, v)
+    w2 = dd.mul(w, w)
+    r = dd.sqrt(dd.add(dd.add(u2, v2), w2))
+    uz = u[0] == 0
+    vz = v[0] == 0
+    wz = w[0] == 0
+
+    def safe(a, mask):
+        return np.where(mask, 1.0, a[0]), np.where(mask, 0.0, a[1])
+
+    def zero_where(t, mask):
+        return np.where(mask, 0.0, t[0]), np.where(mask, 0.0, t[1])
+
+    # v ln(w + r): w + r > 0 unless v = w = 0 (then u > 0 or the term is 0 anyway)
+    t1 = zero_where(dd.mul(v, dd.log(safe(dd.add(w, r), vz | (wz & uz)))), vz | (wz & uz))
+    t2 = zero_where(dd.mul(w, dd.log(safe(dd.add(v, r), wz | (vz & uz)))), wz | (vz & uz))
+    t3 = zero_where(dd.mul(u, dd.atan(dd.div(dd.mul(v, w), safe(dd.mul(u, r), uz)))), uz)
+    return dd.sub(dd.add(t1, t2), t3)
+
+
+def field_cell_average(nx, ny, nz, hx, hy, hz, axis):
+    """Kbar_a(i, j, k) = (1 / (hx hy hz)) * integral over the rest-frame cell centred at
+    (i hx, j hy, k hz) of u_a / |r|^3 (u_0 = x, u_1 = y, u_2 = z), for i = 0..nx, j = 0..ny,
+    k = 0..nz; shape (nz+1, ny+1, nx+1).  The kernel is odd along `axis` (zero at index 0 there)
+    and even along the other two, whose index-0 cells are folded with weight 2 as for Gbar.
+    Evaluated as minus the 8-corner sum of field_antiderivative in double-double, rounded to
+    float64 once (the corner sum cancels as that of Gbar does)."""
+    ex = _corner_coords(nx, hx)
+    ey = _corner_coords(ny, hy)
+    ez = _corner_coords(nz, hz)
+    shape = (nz + 2, ny + 2, nx + 2)
+    Z = tuple(np.broadcast_to(c[:, None, None], shape) for c in ez)
+    Y = tuple(np.broadcast_to(c[None, :, None], shape) for c in ey)
+    X = tuple(np.broadcast_to(c[None, None, :], shape) for c in ex)
+    U = (X, Y, Z)
+    a = axis
+    Hc = field_antiderivative(U[a], U[(a + 1) % 3], U[(a + 2) % 3])
+    D = dd.sub((Hc[0][:, :, 1:], Hc[1][:, :, 1:]), (Hc[0][:, :, :-1], Hc[1][:, :, :-1]))
+    D = dd.sub((D[0][:, 1:, :], D[1][:, 1:, :]), (D[0][:, :-1, :], D[1][:, :-1, :]))
+    D = dd.sub((D[0][1:, :, :], D[1][1:, :, :]), (D[0][:-1, :, :], D[1][:-1, :, :]))
+    w = -np.ones((nz + 1, ny + 1, nx + 1))
+    for b in range(3):
+        idx = [slice(None)] * 3
+        idx[2 - b] = 0          # array axes are (z, y, x)
+        w[tuple(idx)] *= 0.0 if b == a else 2.0
+    D = (D[0] * w, D[1] * w)
+    vol = dd.mul(dd.two_prod(np.float64(hx), np.float64(hy)), dd.dd(np.float64(hz)))
+    vol = (np.full(D[0].shape, vol[0]), np.full(D[0].shape, vol[1]))
+    return dd.to_float(dd.div(D, vol))
+
+
+def hockney_array_field(kbar, axis):
+    """Place Kbar_axis in the (2nz, 2ny, 2nx) cyclic array: even along the other axes as in
+    hockney_array, odd along `axis` (index t holds Kbar(t) for t < n, -Kbar(M - t) for t > n,
+    and 0 at t = n, an offset no output node 0..n-1 reaches)."""
+    nz, ny, nx = (s - 1 for s in kbar.shape)
+    ns = (nz, ny, nx)
+
+    def offs(n):
+        M = 2 * n
+        t = np.arange(M)
+        return np.where(t <= n, t, M - t)
+
+    full = kbar[np.ix_(offs(nz), offs(ny), offs(nx))].copy()
+    ax = 2 - axis
+    n = ns[ax]
+    M = 2 * n
+    sign = np.ones(M)
+    sign[n + 1:] = -1.0
+    sign[n] = 0.0
+    shp = [1, 1, 1]
+    shp[ax] = M
+    return full * sign.reshape(shp)
 
 
 def hockney_array(gbar):

@@ -59,6 +59,7 @@ class Problem:
     q_macro: float      # charge per macroparticle, C
     nodes: tuple        # (nx, ny, nz)
     shape: int          # 1 = CIC, 2 = TSC
+    direct_field: bool = False   # E' from the field's own IGF instead of -grad phi
 
 
 def reference(kin_energy_MeV, mass_MeV):
@@ -68,11 +69,13 @@ def reference(kin_energy_MeV, mass_MeV):
     return gamma, t * (2.0 + t)
 
 
-def make_problem(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, nodes, shape):
+def make_problem(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, nodes, shape,
+                 direct_field=False):
     gamma, gb2 = reference(kin_energy_MeV, mass_MeV)
     C = qm_qeeV / gb2
     q_macro = np.copysign(charge_C, qm_qeeV) / n
-    return Problem(gamma, gb2, C, q_macro, tuple(int(v) for v in nodes), int(shape))
+    return Problem(gamma, gb2, C, q_macro, tuple(int(v) for v in nodes), int(shape),
+                   bool(direct_field))
 
 
 def init_from_normals(sigma6, xi):
@@ -177,6 +180,31 @@ def field(phi, geom):
     return np.stack([Ex, Ey, Ez])
 
 
+def green_field(geom, prob: Problem):
+    """The three field kernels Kbar_x, Kbar_y, Kbar_z on the octant (igf.field_cell_average)."""
+    nx, ny, nz = prob.nodes
+    hx, hy, hz = geom.h_rest
+    return [igf.field_cell_average(nx, ny, nz, hx, hy, hz, a) for a in range(3)]
+
+
+def solve_field(Q, kbars):
+    """Rest-frame E' on nodes 0..n_a-1, shape (3, nz, ny, nx): the charge of every cell taken
+    as spread uniformly over the cell (the IGF reading), E'_a(n) = 1/(4 pi eps0)
+    sum_m Q_m Kbar_a(n - m), by the same zero-padded FFT convolution as solve (reading 20)."""
+    nz, ny, nx = Q.shape
+    shape = (2 * nz, 2 * ny, 2 * nx)
+    Qpad = np.zeros(shape)
+    Qpad[:nz, :ny, :nx] = Q
+    axes = (0, 1, 2)
+    Qh = np.fft.rfftn(Qpad, axes=axes)
+    out = []
+    for a in range(3):
+        K = igf.hockney_array_field(kbars[a], a)
+        conv = np.fft.irfftn(Qh * np.fft.rfftn(K, axes=axes), s=shape, axes=axes)
+        out.append(conv[:nz, :ny, :nx] / (4.0 * np.pi * EPS0))
+    return np.stack(out)
+
+
 def gather(E, X, geom, prob: Problem):
     """Field at the particles, shape (3, n)."""
     flat, w = _stencil(X, geom, prob)
@@ -190,8 +218,10 @@ def sc_field(X, prob: Problem):
     """Geometry, deposit, IGF, Poisson solve, field and gather for the positions in X."""
     geom = geometry(X, prob)
     Q = deposit(X, geom, prob)
-    phi = solve(Q, green(geom, prob))
-    E = field(phi, geom)
+    if prob.direct_field:
+        E = solve_field(Q, green_field(geom, prob))
+    else:
+        E = field(solve(Q, green(geom, prob)), geom)
     return gather(E, X, geom, prob)
 
 
