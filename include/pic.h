@@ -86,6 +86,11 @@ typedef struct {
                               min(work items, 4096) */
   int threads;             /* threads per workgroup of the binned deposit and gather: a
                               multiple of 64 in 64..1024; default 256 */
+  int direct_field;        /* 0: E' = -grad phi by centred differences of the integrated-Green's-
+                              function potential; 1: E' from the integrated Green's functions
+                              of the field itself (the cell averages of u_a/|r|^3; no
+                              differencing error), three convolutions instead of one.  1 is not
+                              supported by pic_track_adjoint or in batches (PIC_EUNSUPPORTED) */
 } pic_beam_desc;
 
 /* Lattice element kinds (Listing 1 of the paper: Drift(ds, nslice), Quad(ds, k, nslice)).
@@ -164,7 +169,10 @@ pic_status pic_deposit(pic_beam b, void* d_rho, void* stream);
  * phi_n = 1/(4 pi eps0) sum_m Q_m Gbar(n - m), Gbar the integrated Green's function (cell
  * average of 1/r over a rest-frame cell; Qiang et al., PRST-AB 9, 044204, 2006), by zero
  * padding to (2nz, 2ny, 2nx) and FFT convolution; then E' = -grad phi by centred differences
- * with spacings (hx, hy, gamma hz).  Uses the geometry of the last pic_deposit.
+ * with spacings (hx, hy, gamma hz), or, with pic_beam_desc.direct_field, E'_a = 1/(4 pi eps0)
+ * sum_m Q_m Kbar_a(n - m) with Kbar_a the cell average of u_a/|r|^3 (the exact field of the
+ * cell-uniform charge; phi is then computed only when d_phi is given).  Uses the geometry of
+ * the last pic_deposit.
  * d_rho: nx*ny*nz pic_real (coulomb per node).  d_phi: optional (NULL allowed),
  * (nx+2)*(ny+2)*(nz+2) pic_real holding phi on nodes -1..n_a (volt).  d_E: 3*nx*ny*nz
  * pic_real, component-major E'[c][k][j][i] (V/m, rest frame). */

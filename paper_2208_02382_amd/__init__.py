@@ -34,7 +34,7 @@ class BeamDesc(ctypes.Structure):
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int),
                 ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int),
-                ("threads", ctypes.c_int)]
+                ("threads", ctypes.c_int), ("direct_field", ctypes.c_int)]
 
 
 ELEM_THIN, ELEM_DRIFT, ELEM_QUAD = 0, 1, 2
@@ -104,15 +104,17 @@ def last_error():
 
 
 def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,
-              space_charge=True, tuning=None):
-    """tuning: None or a dict with any of tile (3 ints), chunk, blocks, threads (0 = default)."""
+              space_charge=True, tuning=None, direct_field=False):
+    """tuning: None or a dict with any of tile (3 ints), chunk, blocks, threads (0 = default).
+    direct_field: E' from the field's own integrated Green's functions (no differencing)."""
     nx, ny, nz = nodes
     t = tuning or {}
     tile = t.get("tile", (0, 0, 0))
     return BeamDesc(int(n), float(qm_qeeV), float(charge_C), float(kin_energy_MeV),
                     float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
                     int(bool(space_charge)), (ctypes.c_int * 3)(*[int(v) for v in tile]),
-                    int(t.get("chunk", 0)), int(t.get("blocks", 0)), int(t.get("threads", 0)))
+                    int(t.get("chunk", 0)), int(t.get("blocks", 0)), int(t.get("threads", 0)),
+                    int(bool(direct_field)))
 
 
 def sigma_from_params(sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx=0.0, muypy=0.0,
@@ -150,9 +152,10 @@ class Beam:
     """
 
     def __init__(self, n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
-                 grid_fp32=False, space_charge=True, device="cuda:0", X=None, tuning=None):
+                 grid_fp32=False, space_charge=True, device="cuda:0", X=None, tuning=None,
+                 direct_field=False):
         self.desc = make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes,
-                              grid_fp32, space_charge, tuning)
+                              grid_fp32, space_charge, tuning, direct_field)
         self.device = torch.device(device)
         self.n = int(n)
         self.nodes = tuple(int(v) for v in nodes)

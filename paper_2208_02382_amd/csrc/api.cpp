@@ -51,6 +51,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gd, Gh, rho, phi, E;
+  size_t hcorners, gd3, gh3, W2;  // direct field only (else 0-byte slots)
   size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, total;
 };
 
@@ -88,6 +89,7 @@ pic_status check_desc(const pic_beam_desc* d) {
   if (d->blocks < 0 || d->blocks > 65535) return fail(PIC_EINVAL, "blocks must be 0..65535");
   if (d->threads != 0 && (d->threads < 64 || d->threads > kMaxThreads || d->threads % 64 != 0))
     return fail(PIC_EINVAL, "threads must be 0 or a multiple of 64 in 64..1024");
+  if (d->direct_field != 0 && d->direct_field != 1) return fail(PIC_EINVAL, "direct_field must be 0 or 1");
   return PIC_OK;
 }
 
@@ -118,6 +120,12 @@ Layout layout(const pic_beam_desc* d) {
   L.rho = take(es * nx * ny * nz);
   L.phi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   L.E = take(3 * es * nx * ny * nz);
+  // the direct field's kernels: corner values, octant arrays, spectra, second work array
+  const size_t df = d->direct_field ? 1 : 0;
+  L.hcorners = take(df * 3 * sizeof(double2) * (nx + 2) * (ny + 2) * (nz + 2));
+  L.gd3 = take(df * 3 * sizeof(double) * G3);
+  L.gh3 = take(df * 3 * es * G3);
+  L.W2 = take(df * 2 * es * nz * 2 * ny * (nx + 1));
   // tracking-loop buffers: two sorted copies of the phase space, particle ids, tile keys,
   // the sort permutation, tile histogram / sort cursors and the deposit work list
   const size_t n = (size_t)d->n;
@@ -187,6 +195,10 @@ struct pic_beam_s {
   void* rho;
   void* phi;
   void* E;
+  double2* hcorners;  // direct field (pic_beam_desc.direct_field)
+  double* gd3;
+  void* gh3;
+  void* W2;
   SortPlan sp;
   double* XA;
   double* XB;
@@ -255,18 +267,31 @@ bool cholesky6(const double* A, Chol& out) {
     HIP_OK((b)->prof.end(s), "profile");        \
   } while (0)
 
+// the kernel spectra of the step's geometry: the potential's, or the three field kernels'
+template <typename T>
+hipError_t green_spectra(pic_beam b, hipStream_t s) {
+  if (b->d.direct_field)
+    return launch_green_field_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz,
+                                          b->hcorners, b->gd3, (T*)b->gh3, s);
+  return launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners,
+                                  b->Gd, (T*)b->Gh, s);
+}
+
 template <typename T>
 pic_status green_and_solve(pic_beam b, const T* rho, T* phi, T* E, hipStream_t s,
                            bool green = true) {
   if (green)
-    STAGE(b, PIC_STAGE_GREEN, s,
-          launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners,
-                                   b->Gd, (T*)b->Gh, s),
-          "green spectrum");
-  STAGE(b, PIC_STAGE_SOLVE, s,
-        launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W,
-                        (const T*)b->Gh, phi, E, s),
-        "poisson solve");
+    STAGE(b, PIC_STAGE_GREEN, s, green_spectra<T>(b, s), "green spectrum");
+  if (b->d.direct_field)
+    STAGE(b, PIC_STAGE_SOLVE, s,
+          launch_solve_field<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W, b->W2,
+                                (const T*)b->gh3, E, s),
+          "field solve");
+  else
+    STAGE(b, PIC_STAGE_SOLVE, s,
+          launch_solve<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, rho, b->W,
+                          (const T*)b->Gh, phi, E, s),
+          "poisson solve");
   return PIC_OK;
 }
 
@@ -343,10 +368,7 @@ template <typename T>
 pic_status fork_green(pic_beam b, hipStream_t s) {
   HIP_OK(hipEventRecord(b->ev_fork, s), "fork");
   HIP_OK(hipStreamWaitEvent(b->aux, b->ev_fork, 0), "fork");
-  STAGE(b, PIC_STAGE_GREEN, b->aux,
-        launch_green_spectrum<T>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd,
-                                 (T*)b->Gh, b->aux),
-        "green spectrum");
+  STAGE(b, PIC_STAGE_GREEN, b->aux, green_spectra<T>(b, b->aux), "green spectrum");
   HIP_OK(hipEventRecord(b->ev_join, b->aux), "join");
   return PIC_OK;
 }
@@ -700,6 +722,10 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->rho = w + L.rho;
   b->phi = w + L.phi;
   b->E = w + L.E;
+  b->hcorners = (double2*)(w + L.hcorners);
+  b->gd3 = (double*)(w + L.gd3);
+  b->gh3 = w + L.gh3;
+  b->W2 = w + L.W2;
   b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks, d->threads);
   b->XA = (double*)(w + L.XA);
   b->XB = (double*)(w + L.XB);
@@ -816,6 +842,22 @@ pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d
   if (!b || !d_rho || !d_E) return fail(PIC_EINVAL, "NULL argument");
   hipStream_t s = S(stream);
   void* phi = d_phi ? d_phi : b->phi;
+  if (b->d.direct_field && d_phi) {  // phi as well: the potential's spectrum and solve
+    if (b->d.grid_fp32)
+      HIP_OK((launch_green_spectrum<float>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz,
+                                          b->corners, b->Gd, (float*)b->Gh, s)), "poisson solve");
+    else
+      HIP_OK((launch_green_spectrum<double>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz,
+                                           b->corners, b->Gd, (double*)b->Gh, s)), "poisson solve");
+    if (b->d.grid_fp32)
+      HIP_OK(launch_solve<float>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz,
+                                 (const float*)d_rho, b->W, (const float*)b->Gh, (float*)d_phi,
+                                 (float*)b->E, s), "poisson solve");
+    else
+      HIP_OK(launch_solve<double>(b->geom, b->plan, b->d.nx, b->d.ny, b->d.nz,
+                                  (const double*)d_rho, b->W, (const double*)b->Gh,
+                                  (double*)d_phi, (double*)b->E, s), "poisson solve");
+  }
   if (b->d.grid_fp32)
     return green_and_solve<float>(b, (const float*)d_rho, (float*)phi, (float*)d_E, s);
   return green_and_solve<double>(b, (const double*)d_rho, (double*)phi, (double*)d_E, s);
@@ -929,6 +971,8 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (n_el < 1 || n_el > kMaxLattice || n_steps < 1 || ckpt_every < 1)
     return fail(PIC_EINVAL, "need 1 <= n_el <= 1024, n_steps >= 1, ckpt_every >= 1");
   if (!b->d.space_charge) return fail(PIC_EINVAL, "the reverse sweep needs space_charge = 1");
+  if (b->d.direct_field)
+    return fail(PIC_EUNSUPPORTED, "the reverse sweep transposes the differenced field only");
   if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
   if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
   for (int q = 0; q < n_el; ++q)
@@ -987,6 +1031,8 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     if (!h || !lattices[b]) return fail(PIC_EINVAL, "NULL beam or lattice");
     if (h->d.shape != shape || h->d.grid_fp32 != fp32 || !h->d.space_charge)
       return fail(PIC_EINVAL, "beams of a batch share shape and grid precision and need space charge");
+    if (h->d.direct_field)
+      return fail(PIC_EUNSUPPORTED, "batched beams use the differenced field");
     const size_t es = fp32 ? 4 : 8;
     const size_t nodes = (size_t)(h->sp.T[0] + shape) * (h->sp.T[1] + shape) * (h->sp.T[2] + shape);
     const size_t win = es * nodes;

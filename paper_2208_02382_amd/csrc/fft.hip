@@ -182,13 +182,14 @@ __device__ __forceinline__ const typename TwT<T>::type* stage_twiddles(
 // cyclic index of the ghost-inclusive position p = 0..n+1 (node p - 1): M - 1 for p = 0
 __device__ __forceinline__ int ghost_src(int p, int M) { return p == 0 ? M - 1 : p - 1; }
 
-// Two uses of the same passes.  MODE 0 (Poisson solve): the source lives on nodes 0..n-1 and
+// Three uses of the same passes.  MODE 0 (Poisson solve): the source lives on nodes 0..n-1 and
 // the result is kept on nodes -1..n.  MODE 1 (transposed solve of the reverse sweep): the
 // source lives on nodes -1..n (node -1 at cyclic index M - 1) and the result is kept on nodes
-// 0..n-1.  Both are exact: every source-to-output offset lies in [-n, n].
+// 0..n-1.  MODE 2 (direct field): source and result on nodes 0..n-1.  All are exact: every
+// source-to-output offset lies in [-n, n].
 template <int MODE>
 __device__ __forceinline__ bool src_nonzero(int p, int n, int M) {
-  return MODE == 0 ? p < n : (p <= n || p == M - 1);
+  return MODE != 1 ? p < n : (p <= n || p == M - 1);
 }
 template <int MODE>
 __device__ __forceinline__ int out_count(int n) { return MODE == 0 ? n + 2 : n; }
@@ -202,7 +203,11 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M / 2 ? k : M - 
 // line values g_0..g_n are extended to length M = 2n by g_t = g_{M-t}, transformed, and the
 // real outputs k = 0..n stored.  Complex line c carries real lines a = 2c (real part) and
 // a = 2c + 1 (imaginary part); line a starts at a*sa + b*sb, elements at stride st.
-__device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, FftAxis ax,
+// ODD: the odd extension g_t = -g_{M-t} (g_n = 0, an offset no output node reaches), whose
+// transform is i S_k with S real; S is stored (the factor i is applied by the product).  For
+// a packed pair Z = A + i B with A = i S_A, B = i S_B: S_A = Im Z, S_B = -Re Z.
+template <bool ODD>
+__device__ __forceinline__ void green_dft_body(double* __restrict__ gd, FftAxis ax,
                                                          const double2* __restrict__ tw,
                                                          int64_t st, int64_t sa, int64_t sb,
                                                          int na, int LB, int bx, int by, int nbx) {
@@ -214,10 +219,11 @@ __device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, Fft
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;  // consecutive threads: consecutive lines
     const int t = p <= n ? p : M - p;
+    const double sgn = ODD ? (p < n ? 1.0 : (p == n ? 0.0 : -1.0)) : 1.0;
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
     double re = a0 < na ? base[(int64_t)a0 * sa + (int64_t)t * st] : 0.0;
     double im = a1 < na ? base[(int64_t)a1 * sa + (int64_t)t * st] : 0.0;
-    buf[l * (M + 1) + p] = Cx<double>{re, im};
+    buf[l * (M + 1) + p] = Cx<double>{sgn * re, sgn * im};
   }
   const double2* twl = stage_twiddles(buf, LB, M, tw, M);
   __syncthreads();
@@ -226,16 +232,23 @@ __device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, Fft
     const int p = idx / LB, l = idx - p * LB;
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
     const Cx<double> v = buf[l * (M + 1) + p];
-    if (a0 < na) base[(int64_t)a0 * sa + (int64_t)p * st] = v.x;
-    if (a1 < na) base[(int64_t)a1 * sa + (int64_t)p * st] = v.y;
+    if (a0 < na) base[(int64_t)a0 * sa + (int64_t)p * st] = ODD ? v.y : v.x;
+    if (a1 < na) base[(int64_t)a1 * sa + (int64_t)p * st] = ODD ? -v.x : v.y;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_green_even_dft(double* __restrict__ gd, FftAxis ax,
-                                                         const double2* __restrict__ tw,
-                                                         int64_t st, int64_t sa, int64_t sb,
-                                                         int na, int LB) {
-  green_even_dft_body(gd, ax, tw, st, sa, sb, na, LB, blockIdx.x, blockIdx.y, gridDim.x);
+__device__ __forceinline__ void green_even_dft_body(double* __restrict__ gd, FftAxis ax,
+                                                    const double2* __restrict__ tw, int64_t st,
+                                                    int64_t sa, int64_t sb, int na, int LB,
+                                                    int bx, int by, int nbx) {
+  green_dft_body<false>(gd, ax, tw, st, sa, sb, na, LB, bx, by, nbx);
+}
+
+template <bool ODD>
+__global__ __launch_bounds__(1024) void k_green_dft(double* __restrict__ gd, FftAxis ax,
+                                                    const double2* __restrict__ tw, int64_t st,
+                                                    int64_t sa, int64_t sb, int na, int LB) {
+  green_dft_body<ODD>(gd, ax, tw, st, sa, sb, na, LB, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename T>
@@ -372,11 +385,16 @@ __global__ __launch_bounds__(1024) void k_c2c_y(const Geom* __restrict__ g, Cx<T
 // Along z (element stride My Kx) for lines a = kx, b = ky: forward FFT of the source's
 // non-zero inputs, product with Ghat(fold kz, fold ky, kx) (gh[(fz (ny+1) + fy)(nx+1) + kx]),
 // inverse FFT, and the out_count(n_z) kept rows written back in place.
-template <typename T, int MODE>
-__device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __restrict__ W,
+// IMAG: the kernel spectrum is i gh (an odd field kernel, see green_dft_body), odd along axis
+// `odd`: its spectrum is odd there too, so the folded value changes sign for k_y > n_y
+// (odd = 1) or k_z > n_z (odd = 2); along x only k_x <= n_x is stored, no fold.  W2: where the
+// kept rows go (W itself for the potential).
+template <typename T, int MODE, bool IMAG = false>
+__device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* W,
                                                 const T* __restrict__ gh, FftAxis ax,
                                                 const typename TwT<T>::type* __restrict__ tw,
-                                                int Kx, int My, int ny, int nz, int LB, int bx, int by, int nbx) {
+                                                int Kx, int My, int ny, int nz, int LB, int bx, int by, int nbx,
+                                                Cx<T>* W2 = nullptr, int odd = -1) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
   if (g->status) return;
@@ -385,6 +403,7 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
   const int nl = min(LB, Kx - a0);
   const int64_t sz = (int64_t)My * Kx;
   Cx<T>* base = W + (int64_t)ky * Kx + a0;
+  Cx<T>* obase = (W2 ? W2 : W) + (int64_t)ky * Kx + a0;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     Cx<T> v = {0, 0};
@@ -397,19 +416,21 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* __
   const int fy = fold(ky, My);
   const T* grow = gh + (int64_t)fy * Kx + a0;
   const int64_t gplane = (int64_t)(ny + 1) * Kx;
+  const bool flip_y = IMAG && odd == 1 && ky > ny;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
     const int p = idx / LB, l = idx - p * LB;
     if (l < nl) {
-      const T s = grow[(int64_t)fold(p, M) * gplane + l];
+      T s = grow[(int64_t)fold(p, M) * gplane + l];
+      if (IMAG && (flip_y || (odd == 2 && p > nz))) s = -s;
       Cx<T> v = buf[l * (M + 1) + p];
-      buf[l * (M + 1) + p] = Cx<T>{v.x * s, v.y * s};
+      buf[l * (M + 1) + p] = IMAG ? Cx<T>{-v.y * s, v.x * s} : Cx<T>{v.x * s, v.y * s};
     }
   }
   __syncthreads();
   fft_lds<T, +1>(buf, LB, ax, twl, 1);
   for (int idx = threadIdx.x; idx < LB * out_count<MODE>(nz); idx += blockDim.x) {
     const int q = idx / LB, l = idx - q * LB;
-    if (l < nl) base[(int64_t)q * sz + l] = buf[l * (M + 1) + out_src<MODE>(q, M)];
+    if (l < nl) obase[(int64_t)q * sz + l] = buf[l * (M + 1) + out_src<MODE>(q, M)];
   }
 }
 
@@ -419,6 +440,19 @@ __global__ __launch_bounds__(1024) void k_zconv(const Geom* __restrict__ g, Cx<T
                                                 const typename TwT<T>::type* __restrict__ tw,
                                                 int Kx, int My, int ny, int nz, int LB) {
   zconv_body<T, MODE>(g, W, gh, ax, tw, Kx, My, ny, nz, LB, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// direct field: forward z FFT of W (kept intact for the next component), product with i gh,
+// inverse z FFT, the n_z node rows into W2 [n_z][2 n_y][n_x + 1]
+template <typename T>
+__global__ __launch_bounds__(1024) void k_zconv_field(const Geom* __restrict__ g,
+                                                      Cx<T>* __restrict__ W,
+                                                      const T* __restrict__ gh, FftAxis ax,
+                                                      const typename TwT<T>::type* __restrict__ tw,
+                                                      int Kx, int My, int ny, int nz, int LB,
+                                                      Cx<T>* __restrict__ W2, int odd) {
+  zconv_body<T, 2, true>(g, W, gh, ax, tw, Kx, My, ny, nz, LB, blockIdx.x, blockIdx.y, gridDim.x,
+                         W2, odd);
 }
 
 // Inverse real transform of the kept rows (yy < out_count(n_y), zz < out_count(n_z)) of W,
@@ -647,11 +681,12 @@ hipError_t launch_twiddles(double2* tw, float2* twf, int M, hipStream_t s) {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
+namespace {
+// The three even/odd DFT passes of one octant kernel gd (odd_axis: -1 for an even kernel) and
+// the scaled conversion into gh.
 template <typename T>
-hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
-                                 double2* corners, double* gd, T* gh, hipStream_t s) {
-  PIC_TRY(launch_igf_corners(g, nx, ny, nz, corners, s));
-  PIC_TRY(launch_igf_cells(g, nx, ny, nz, corners, gd, s));
+hipError_t kernel_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz, double* gd,
+                           T* gh, int odd_axis, hipStream_t s) {
   const int ex = nx + 1, ey = ny + 1, ez = nz + 1;
   // (axis, element stride, line stride a, plane stride b, lines a, planes b)
   const int64_t cfg[3][5] = {{1, ex, (int64_t)ex * ey, ey, ez},
@@ -665,8 +700,12 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
     dim3 grid((ncx + LB - 1) / LB, (unsigned)cfg[a][4]);
     size_t lds = (size_t)LB * (p.full[a].M + 1) * sizeof(Cx<double>) +
                  (size_t)p.full[a].M * sizeof(double2);
-    hipLaunchKernelGGL(k_green_even_dft, grid, dim3(NT), lds, s, gd, p.full[a], p.tw[a],
-                       cfg[a][0], cfg[a][1], cfg[a][2], na, LB);
+    if (a == odd_axis)
+      hipLaunchKernelGGL(k_green_dft<true>, grid, dim3(NT), lds, s, gd, p.full[a], p.tw[a],
+                         cfg[a][0], cfg[a][1], cfg[a][2], na, LB);
+    else
+      hipLaunchKernelGGL(k_green_dft<false>, grid, dim3(NT), lds, s, gd, p.full[a], p.tw[a],
+                         cfg[a][0], cfg[a][1], cfg[a][2], na, LB);
     PIC_TRY(hipGetLastError());
   }
   const int64_t total = (int64_t)ex * ey * ez;
@@ -676,6 +715,26 @@ hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny
                      total, scale);
   return hipGetLastError();
 }
+}  // namespace
+
+template <typename T>
+hipError_t launch_green_field_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                       double2* hcorners, double* gd3, T* gh3, hipStream_t s) {
+  PIC_TRY(launch_igf_field(g, nx, ny, nz, hcorners, gd3, s));
+  const int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  for (int a = 0; a < 3; ++a)
+    PIC_TRY(kernel_spectrum<T>(g, p, nx, ny, nz, gd3 + a * total, gh3 + a * total, a, s));
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                 double2* corners, double* gd, T* gh, hipStream_t s) {
+  PIC_TRY(launch_igf_corners(g, nx, ny, nz, corners, s));
+  PIC_TRY(launch_igf_cells(g, nx, ny, nz, corners, gd, s));
+  return kernel_spectrum<T>(g, p, nx, ny, nz, gd, gh, -1, s);
+}
+
 
 namespace {
 
@@ -731,6 +790,65 @@ hipError_t launch_solve(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
   hipLaunchKernelGGL((k_grad<T>), dim3(grid_for(ng)), dim3(256), 0, s, g, phi, E, nx, ny, nz);
   return hipGetLastError();
 }
+
+// Direct field: forward x and y passes of rho into W, then per component the z pass with the
+// product by i Ghat_a into W2 and the inverse y and x passes into E_a (nodes 0..n-1).
+template <typename T>
+hipError_t launch_solve_field(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                              const T* rho, void* Wv, void* W2v, const T* gh3, T* E,
+                              hipStream_t s) {
+  Cx<T>* W = (Cx<T>*)Wv;
+  Cx<T>* W2 = (Cx<T>*)W2v;
+  const int My = 2 * ny, Kx = nx + 1;
+  const int64_t ng = (int64_t)nx * ny * nz, gtot = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  int LB, NT;
+  size_t lds;
+  shape_for(p.half_x.M, ny, &LB, &NT);
+  lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
+  hipLaunchKernelGGL((k_r2c_x<T, 0>), dim3((ny + LB - 1) / LB, nz), dim3(NT), lds, s, g, rho, W,
+                     p.half_x, table<T>(p, 0), nx, ny, nz, Kx, My, LB);
+  PIC_TRY(hipGetLastError());
+  shape_for(p.full[1].M, Kx, &LB, &NT);
+  lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+        (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
+  hipLaunchKernelGGL((k_c2c_y<T, -1, 0, 0>), dim3((Kx + LB - 1) / LB, nz), dim3(NT), lds, s, g,
+                     W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+  PIC_TRY(hipGetLastError());
+  for (int a = 0; a < 3; ++a) {
+    shape_for(p.full[2].M, Kx, &LB, &NT);
+    lds = (size_t)LB * (p.full[2].M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[2].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_zconv_field<T>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W,
+                       gh3 + a * gtot, p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB, W2, a);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.full[1].M, Kx, &LB, &NT);
+    lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_c2c_y<T, +1, 2, 1>), dim3((Kx + LB - 1) / LB, nz), dim3(NT), lds, s, g,
+                       W2, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.half_x.M, ny, &LB, &NT);
+    lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_c2r_x<T, 2>), dim3((ny + LB - 1) / LB, nz), dim3(NT), lds, s, g, W2,
+                       E + a * ng, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
+    PIC_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_solve_field<double>(const Geom*, const FftPlan&, int, int, int,
+                                               const double*, void*, void*, const double*,
+                                               double*, hipStream_t);
+template hipError_t launch_solve_field<float>(const Geom*, const FftPlan&, int, int, int,
+                                              const float*, void*, void*, const float*, float*,
+                                              hipStream_t);
+template hipError_t launch_green_field_spectrum<double>(const Geom*, const FftPlan&, int, int,
+                                                        int, double2*, double*, double*,
+                                                        hipStream_t);
+template hipError_t launch_green_field_spectrum<float>(const Geom*, const FftPlan&, int, int, int,
+                                                       double2*, double*, float*, hipStream_t);
 
 template <typename T>
 hipError_t launch_solve_ghost_source(const Geom* g, const FftPlan& p, int nx, int ny, int nz,

@@ -85,6 +85,69 @@ __global__ __launch_bounds__(256) void k_igf_cells_batch(const BeamDev* __restri
   igf_cells_body(d.geom, d.c.nx, d.c.ny, d.c.nz, d.corners, d.Gd, blockIdx.x, gridDim.x);
 }
 
+// The field kernels' corner values: H_x, H_y, H_z at every corner, hc[a total + t] (double
+// pairs), t = (mz (ny+2) + my)(nx+2) + mx as for F.
+__global__ __launch_bounds__(256) void k_igf_field_corners(const Geom* __restrict__ g, int nx,
+                                                           int ny, int nz,
+                                                           double2* __restrict__ hc) {
+  if (g->status) return;
+  const int cx = nx + 2, cy = ny + 2, cz = nz + 2;
+  const int64_t total = (int64_t)cx * cy * cz;
+  const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int mx = (int)(t % cx);
+    const int my = (int)((t / cx) % cy);
+    const int mz = (int)(t / ((int64_t)cx * cy));
+    ddv H[3];
+    field_antiderivatives(corner_coord(mx, hx), corner_coord(my, hy), corner_coord(mz, hz), H);
+    for (int a = 0; a < 3; ++a) hc[a * total + t] = make_double2(H[a].hi, H[a].lo);
+  }
+}
+
+// Field kernels Kbar_a(i, j, k) = (1/V) integral over the cell of u_a/r^3 on the octant,
+// gd3[a (nx+1)(ny+1)(nz+1) + (k (ny+1) + j)(nx+1) + i]: minus the 8-corner double-double sum
+// of H_a; zero on the kernel's own zero plane (it is odd along a), weight 2 per other axis
+// whose index is 0 (even there, folded); one division by the cell volume, rounded once.
+__global__ __launch_bounds__(256) void k_igf_field_cells(const Geom* __restrict__ g, int nx,
+                                                         int ny, int nz,
+                                                         const double2* __restrict__ hc,
+                                                         double* __restrict__ gd3) {
+  if (g->status) return;
+  const int cx = nx + 2, cy = ny + 2;
+  const int ex = nx + 1, ey = ny + 1;
+  const int64_t ctotal = (int64_t)cx * cy * (nz + 2);
+  const int64_t total = (int64_t)ex * ey * (nz + 1);
+  const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
+  const ddv vol = dd_mul_d(two_prod(hx, hy), hz);
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int i = (int)(t % ex);
+    const int j = (int)((t / ex) % ey);
+    const int k = (int)(t / ((int64_t)ex * ey));
+    const int idx[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+      double w = idx[a] == 0 ? 0.0 : -1.0;
+      for (int b = 0; b < 3; ++b)
+        if (b != a && idx[b] == 0) w *= 2.0;
+      double out = 0.0;
+      if (w != 0.0) {
+        const double2* h = hc + a * ctotal;
+        ddv dxy[2][2];
+        for (int c = 0; c < 2; ++c)
+          for (int b = 0; b < 2; ++b) {
+            const int64_t base = ((int64_t)(k + c) * cy + (j + b)) * cx + i;
+            const double2 f0 = h[base], f1 = h[base + 1];
+            dxy[c][b] = dd_sub(ddv{f1.x, f1.y}, ddv{f0.x, f0.y});
+          }
+        ddv d = dd_sub(dd_sub(dxy[1][1], dxy[1][0]), dd_sub(dxy[0][1], dxy[0][0]));
+        d = {d.hi * w, d.lo * w};
+        const ddv kbar = dd_div(d, vol);
+        out = kbar.hi + kbar.lo;
+      }
+      gd3[a * total + t] = out;
+    }
+  }
+}
+
 int grid_for(int64_t total) {
   int64_t b = (total + 255) / 256;
   if (b > 16384) b = 16384;
@@ -106,6 +169,19 @@ hipError_t launch_igf_cells(const Geom* g, int nx, int ny, int nz, const double2
   int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   hipLaunchKernelGGL(k_igf_cells, dim3(grid_for(total)), dim3(256), 0, s, g, nx, ny, nz, corners,
                      gd);
+  return hipGetLastError();
+}
+
+hipError_t launch_igf_field(const Geom* g, int nx, int ny, int nz, double2* hc, double* gd3,
+                            hipStream_t s) {
+  const int64_t corners = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+  hipLaunchKernelGGL(k_igf_field_corners, dim3(grid_for(corners)), dim3(256), 0, s, g, nx, ny,
+                     nz, hc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t cells = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  hipLaunchKernelGGL(k_igf_field_cells, dim3(grid_for(cells)), dim3(256), 0, s, g, nx, ny, nz, hc,
+                     gd3);
   return hipGetLastError();
 }
 

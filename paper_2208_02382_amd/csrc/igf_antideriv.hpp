@@ -25,4 +25,29 @@ PIC_HD inline ddv antiderivative(ddv x, ddv y, ddv z) {
   return dd_sub(dd_add(dd_add(t1, t2), t3), dd_add(dd_add(t4, t5), t6));
 }
 
+// The field's 2-D antiderivatives at a corner (x, y, z >= 0):
+//   H_x = y L_z + z L_y - x A_x,  H_y = z L_x + x L_z - y A_y,  H_z = x L_y + y L_x - z A_z,
+// L_u = ln(u + r), A_x = atan(y z/(x r)), A_y = atan(z x/(y r)), A_z = atan(x y/(z r)), every
+// term with a zero prefactor taken as zero.  d^2 H_x / dy dz = 1/r (likewise for y and z), so
+// the cell integral of x/r^3 = -d(1/r)/dx is minus the alternating 8-corner sum of H_x.  The
+// logarithms and arctangents are those of F: three of each per corner.
+PIC_HD inline void field_antiderivatives(ddv x, ddv y, ddv z, ddv H[3]) {
+  const bool x0 = x.hi == 0.0, y0 = y.hi == 0.0, z0 = z.hi == 0.0;
+  const ddv r = dd_sqrt(dd_add(dd_add(dd_mul(x, x), dd_mul(y, y)), dd_mul(z, z)));
+  const ddv zero = {0.0, 0.0};
+  // ln(u + r) is needed where one of the other two coordinates is non-zero, so r > 0 there
+  const ddv Lx = (y0 && z0) ? zero : dd_log(dd_add(x, r));
+  const ddv Ly = (z0 && x0) ? zero : dd_log(dd_add(y, r));
+  const ddv Lz = (x0 && y0) ? zero : dd_log(dd_add(z, r));
+  const ddv Ax = x0 ? zero : dd_atan(dd_div(dd_mul(y, z), dd_mul(x, r)));
+  const ddv Ay = y0 ? zero : dd_atan(dd_div(dd_mul(z, x), dd_mul(y, r)));
+  const ddv Az = z0 ? zero : dd_atan(dd_div(dd_mul(x, y), dd_mul(z, r)));
+  H[0] = dd_sub(dd_add(y0 ? zero : dd_mul(y, Lz), z0 ? zero : dd_mul(z, Ly)),
+                x0 ? zero : dd_mul(x, Ax));
+  H[1] = dd_sub(dd_add(z0 ? zero : dd_mul(z, Lx), x0 ? zero : dd_mul(x, Lz)),
+                y0 ? zero : dd_mul(y, Ay));
+  H[2] = dd_sub(dd_add(x0 ? zero : dd_mul(x, Ly), y0 ? zero : dd_mul(y, Lx)),
+                z0 ? zero : dd_mul(z, Az));
+}
+
 }  // namespace pic

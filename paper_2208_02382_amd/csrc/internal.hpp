@@ -245,6 +245,18 @@ hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* par
                      hipStream_t s);
 
 // ---- igf.hip
+// the field kernels: corner values of H_x, H_y, H_z (3 (nx+2)(ny+2)(nz+2) double pairs) and
+// the three octant arrays Kbar_a (3 (nx+1)(ny+1)(nz+1) doubles)
+hipError_t launch_igf_field(const Geom* g, int nx, int ny, int nz, double2* hc, double* gd3,
+                            hipStream_t s);
+// spectra of the three field kernels (gh3: 3 octant arrays, each i times the stored value)
+template <typename T>
+hipError_t launch_green_field_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                       double2* hcorners, double* gd3, T* gh3, hipStream_t s);
+// E' (3 [nz][ny][nx]) directly from rho with the field spectra; W2: [nz][2 ny][nx+1] complex
+template <typename T>
+hipError_t launch_solve_field(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                              const T* rho, void* W, void* W2, const T* gh3, T* E, hipStream_t s);
 hipError_t launch_igf_corners(const Geom* g, int nx, int ny, int nz, double2* corners,
                               hipStream_t s);
 hipError_t launch_igf_cells(const Geom* g, int nx, int ny, int nz, const double2* corners,

@@ -151,3 +151,13 @@ def test_sigma_from_params_matches_the_oracle():
                 (1, 1, float("nan"), 1, 1, 1, 0, 0, 0)):
         with pytest.raises(pic.PicError):
             pic.sigma_from_params(*bad)
+
+
+def test_direct_field_flag_is_validated():
+    base = pic.workspace_bytes(_desc())
+    # the field kernels' corners, octant arrays, spectra and a second work array
+    assert pic.workspace_bytes(_desc(direct_field=True)) > base
+    d = _desc()
+    d.direct_field = 2
+    assert pic.workspace_bytes(d) == 0
+    assert "direct_field" in pic.last_error()
