@@ -85,18 +85,19 @@ def tuned(cfg, grid_fp32, enabled):
         return None, None
     from paper_2208_02382_amd import autotune
     rec = autotune.tune(cfg, grid_fp32=grid_fp32, log=_log)
-    t = {k: rec[k] for k in ("tile", "chunk", "blocks")}
+    t = {k: rec[k] for k in ("tile", "chunk", "blocks", "threads") if k in rec}
     return t, {"tuning": t, "tuned_ms_per_step": rec["s_per_step"] * 1e3,
                "default_ms_per_step": rec["default_s_per_step"] * 1e3,
                "candidates": len(rec["tried"])}
 
 
-def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None):
+def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None, direct_field=False):
     import torch
     import paper_2208_02382_amd as pic
 
     beam = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
-                    cfg.shape, cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning)
+                    cfg.shape, cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning,
+                    direct_field=direct_field)
     beam.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
     if warmup:
         beam.track(cfg.lattice, warmup)
@@ -362,6 +363,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
     ap.add_argument("--no-thick", action="store_true",
                     help="skip the thick-element (Listing 1 FODO) variant")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the direct-field variant (E' from the field's own IGF)")
     ap.add_argument("--batch-beams", type=int, default=256)
     ap.add_argument("--oracle-timings", action="store_true",
                     help="time the oracle on every workload (host CPU, a few minutes) and exit")
@@ -472,6 +475,18 @@ def main():
             "last_step_rms_x_y": [float(diag[-1, 6] ** 0.5), float(diag[-1, 6 + 11] ** 0.5)]}
         bd.close()
         del bd, diag
+        torch.cuda.empty_cache()
+    if not args.no_direct:
+        # the headline workload with E' from the integrated Green's functions of the field
+        bf, dtf, stf, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, tuning=tuning,
+                                  direct_field=True)
+        variants["direct_field"] = {
+            "value": cfg.n * args.steps / dtf, "ms_per_step": dtf / args.steps * 1e3,
+            "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in stf.items()},
+            "note": "headline workload; three field-kernel spectra and three convolutions "
+                    "instead of the potential's, no differencing"}
+        bf.close()
+        del bf
         torch.cuda.empty_cache()
     if not args.no_fp32:
         variants["fp32_grid_accuracy"] = fp32_accuracy(workloads.MEDIUM, workloads.MEDIUM.steps)

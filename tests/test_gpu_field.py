@@ -2,7 +2,9 @@
 itself, pic_beam_desc.direct_field = 1) against the oracle's solve_field, on the same seeded
 inputs: the kernels' spectra and the three convolutions at 1e-12 of the largest field value,
 whole tracking runs at 1e-12 of the rms size per coordinate, FP32 grids within 1e-5 in the rms
-moments, and the rejection of the calls that do not support it.
+moments, and the rejection of the calls that do not support it.  At the headline grid (128^3,
+TSC) with the bench's launch shapes: one step on 2e6 particles, sampled particles against the
+oracle within 1e-12.
 """
 import numpy as np
 import pytest
@@ -142,3 +144,32 @@ def test_adjoint_and_batch_reject_the_direct_field(lib):
     with pytest.raises(lib.PicError) as e:
         lib.Batch([b], [cfg.lattice])
     assert e.value.status == lib.PIC_EUNSUPPORTED
+
+
+@pytest.mark.timeout(900)
+def test_headline_grid_one_step_on_sampled_particles(lib):
+    # the headline grid (128^3, TSC, Gaussian core with halo) and the bench's tuned launch
+    # shapes, at 2e6 particles: the field kernels' spectra and convolutions depend on the grid
+    # alone; the particle kernels are the potential path's, checked at 1e8 elsewhere
+    from paper_2208_02382_amd import autotune
+    cfg = workloads.LARGE
+    n = 2_000_000
+    tuning = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False)
+    b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
+                 cfg.nodes, tuning=tuning, direct_field=True)
+    b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+    X0 = b.X.cpu().numpy()
+    b.track(cfg.lattice, 1)
+    X1 = b.X.cpu().numpy()
+    assert b.check() == lib.PIC_OK
+    b.close()
+    prob = _problem(cfg, n, cfg.nodes, cfg.shape)
+    k, L = cfg.lattice[0]
+    X2 = opic.drift(opic.thin_quad(X0, k), 0.5 * L, prob)
+    geom = opic.geometry(X2, prob)
+    E = opic.solve_field(opic.deposit(X2, geom, prob), opic.green_field(geom, prob))
+    S = np.random.default_rng(12).choice(n, 2000, replace=False)
+    Xs = X2[:, S]
+    Xo = opic.drift(opic.kick(Xs, opic.gather(E, Xs, geom, prob), L, prob), 0.5 * L, prob)
+    scale = X1.std(axis=1)
+    assert (np.abs(X1[:, S] - Xo).max(axis=1) / scale).max() < TOL
