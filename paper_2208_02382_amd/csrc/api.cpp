@@ -52,7 +52,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gd, Gh, rho, phi, E;
   size_t hcorners, gd3, gh3, W2;  // direct field only (else 0-byte slots)
-  size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, total;
+  size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, diag_part, diag_shift, total;
 };
 
 pic_status check_desc(const pic_beam_desc* d) {
@@ -141,6 +141,9 @@ Layout layout(const pic_beam_desc* d) {
   L.cursor = take(sizeof(uint32_t) * kMaxTiles);
   L.chunks = take(sizeof(int4) * (size_t)sp.max_chunks);
   L.nchunks = take(sizeof(uint32_t));
+  // slice-step diagnostics summed inside the gather-kick: one partial per workgroup, the shift
+  L.diag_part = take(sizeof(double) * kMomentSlots * (size_t)sp.blocks);
+  L.diag_shift = take(sizeof(double) * 6);
   L.total = off;
   return L;
 }
@@ -188,6 +191,8 @@ struct pic_beam_s {
   Box* box;
   double* mom_partial;
   double* mom_out;
+  double* diag_part;   // per-workgroup moment sums of the fused slice-step diagnostics
+  double* diag_shift;
   double2* corners;
   void* W;
   double* Gd;
@@ -374,8 +379,9 @@ pic_status fork_green(pic_beam b, hipStream_t s) {
 }
 
 // diag: nullptr, or a device array that receives the moments (kMomentSlots doubles) of the
-// particles at the end of every step; the gather-kick then stops at the end of the step and a
-// separate pass applies the next step's first half map.
+// particles at the end of every step.  The binned gather-kick sums them in the same pass, about
+// the previous step's means; the unbinned fallback stops at the end of the step and separate
+// passes take the moments and apply the next step's first half map.
 template <typename T>
 pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, double* diag,
                     hipStream_t s) {
@@ -423,7 +429,8 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
     if (st != PIC_OK) return st;
     const int more = j + 1 < n_steps;
-    const int has_next = more && !diag;  // fuse the next step's first half map
+    const int has_next = more && (tiles || !diag);  // fuse the next step's first half map
+    double* diag_j = diag ? diag + (size_t)kMomentSlots * j : nullptr;
     const SliceDev& nx = sl[(j + 1) % ns];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
     if (tiles)
@@ -431,16 +438,17 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
             launch_gkd_tiles<T>(B, permuted ? A : nullptr, permuted ? b->perm : nullptr,
                                 permuted ? idA : nullptr, permuted ? idB : nullptr, b->geom,
                                 (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks, e.L,
-                                e.second, has_next, nx.first, b->box, s),
+                                e.second, has_next, nx.first, b->box, s, b->diag_part,
+                                b->diag_shift, j > 0 && diag_j ? diag_j - kMomentSlots : nullptr,
+                                diag_j),
             "gather-kick-drift");
     else
       STAGE(b, PIC_STAGE_GKD, s,
             launch_gkd<T>(B, b->geom, (const T*)b->E, e.L, e.second, has_next, nx.first, b->c,
                           b->box, s),
             "gather-kick-drift");
-    if (diag) {  // moments at the end of the step, then the next step's first half map
-      HIP_OK(launch_moments(B, b->c.n, b->mom_partial, diag + (size_t)kMomentSlots * j, s),
-             "diagnostics");
+    if (diag && !tiles) {  // moments at the end of the step, then the next first half map
+      HIP_OK(launch_moments(B, b->c.n, b->mom_partial, diag_j, s), "diagnostics");
       if (more) {
         HIP_OK(launch_box_reset(b->box, s), "box reset");
         HIP_OK(launch_half_box(B, nx.first, b->c, b->box, s), "diagnostics");
@@ -737,6 +745,8 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->cursor = (uint32_t*)(w + L.cursor);
   b->chunks = (int4*)(w + L.chunks);
   b->nchunks = (uint32_t*)(w + L.nchunks);
+  b->diag_part = (double*)(w + L.diag_part);
+  b->diag_shift = (double*)(w + L.diag_shift);
   int nn[3] = {d->nx, d->ny, d->nz};
   for (int a = 0; a < 3; ++a) {
     b->plan.full[a].M = 2 * nn[a];

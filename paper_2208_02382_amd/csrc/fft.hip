@@ -675,12 +675,6 @@ hipError_t launch_twiddles(double2* tw, float2* twf, int M, hipStream_t s) {
   return hipGetLastError();
 }
 
-#define PIC_TRY(x)                   \
-  do {                               \
-    hipError_t e_ = (x);             \
-    if (e_ != hipSuccess) return e_; \
-  } while (0)
-
 namespace {
 // The three even/odd DFT passes of one octant kernel gd (odd_axis: -1 for an even kernel) and
 // the scaled conversion into gh.

@@ -123,10 +123,17 @@ struct BeamDev {
   int pad;
 };
 
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 1024;   // partial sums for the moments reduction
 constexpr int kAdjBlocks = 1024;      // grid of the reverse-sweep particle kernels
-constexpr int kMaxLattice = 1024;     // lattice elements of the reverse sweep   // partial sums for the moments reduction
+constexpr int kMaxLattice = 1024;     // lattice elements of the reverse sweep
 constexpr int kMomentSlots = 27;      // 6 sums + 21 centred products
+
+// return a failing hipError_t from the enclosing launcher
+#define PIC_TRY(x)                   \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
 
 // ---- launch wrappers (particles.hip)
 hipError_t launch_box_reset(Box* box, hipStream_t s);
@@ -174,13 +181,18 @@ hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geo
                                 T* rho, hipStream_t s);
 // perm == nullptr: B in slot order, updated in place (src, idsrc, iddst unused); else slot i
 // reads particle perm[i] of src and id idsrc[perm[i]], and writes slot i of B and iddst
-// (src != B, idsrc != iddst)
+// (src != B, idsrc != iddst).  diag_out != nullptr: the moments (kMomentSlots doubles) of the
+// state after the second half map go to diag_out, summed in the same pass into diag_part
+// (sp.blocks * kMomentSlots doubles) about diag_shift (6 doubles, set from diag_prev, the
+// previous step's moments, or from the grid centre when diag_prev is nullptr).
 template <typename T>
 hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
                             const uint32_t* idsrc, uint32_t* iddst, const Geom* g, const T* E,
                             Consts c, const SortPlan& sp, const int4* chunks,
                             const uint32_t* nchunks, double L, const HalfMap& second,
-                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s);
+                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s,
+                            double* diag_part = nullptr, double* diag_shift = nullptr,
+                            const double* diag_prev = nullptr, double* diag_out = nullptr);
 // both half maps of a slice without a kick (tracking without space charge)
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
                             hipStream_t s);

@@ -286,6 +286,30 @@ __device__ __forceinline__ void scatter_direct_body(const double* __restrict__ A
   }
 }
 
+// LDS atomic add of 1 per active lane to lh[key], aggregated over the wave: one atomic per
+// distinct key among the active lanes (their count), each lane getting the value it would
+// have had from its own atomic in lane order.  Called by all lanes of the wave (the loop is
+// wave-uniform).  After the first step of a call the particles arrive in the previous step's
+// tile order, so a wave holds only a few distinct keys and the same-address atomics that
+// would serialise lane by lane collapse into one per key.
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* lh, uint32_t key, bool active) {
+  const int lane = (int)__lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint64_t todo = __ballot(active);
+  uint32_t out = 0u;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint32_t k0 = __shfl(key, leader);
+    const uint64_t grp = todo & __ballot(key == k0);
+    uint32_t b = 0u;
+    if (lane == leader) b = atomicAdd(&lh[k0], (uint32_t)__popcll(grp));
+    b = __shfl(b, leader);
+    if ((grp >> lane) & 1ull) out = b + (uint32_t)__popcll(grp & below);
+    todo &= ~grp;
+  }
+  return out;
+}
+
 // Ranking of one block of kItems particles as in the direct form, writing only the source
 // index of each slot: perm[slot] = i.
 __device__ __forceinline__ void scatter_perm_body(const uint32_t* __restrict__ keys,
@@ -301,7 +325,7 @@ __device__ __forceinline__ void scatter_perm_body(const uint32_t* __restrict__ k
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
     key[k] = i < n ? keys[i] : 0u;
-    if (i < n) atomicAdd(&lh[key[k]], 1u);
+    (void)wave_aggregated_add(lh, key[k], i < n);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += kBlk)
@@ -309,10 +333,9 @@ __device__ __forceinline__ void scatter_perm_body(const uint32_t* __restrict__ k
   __syncthreads();
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
-    if (i < n) {
-      uint32_t pos = atomicAdd(&lh[key[k]], 1u);
-      if (pos < (uint64_t)n) perm[pos] = (uint32_t)i;  // in bounds for a consistent histogram
-    }
+    const uint32_t pos = wave_aggregated_add(lh, key[k], i < n);
+    // in bounds for a consistent histogram
+    if (i < n && pos < (uint64_t)n) perm[pos] = (uint32_t)i;
   }
 }
 
@@ -545,7 +568,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __r
 // leaves in sorted order.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
-template <int S, typename T, bool PERM>
+// DIAG: the particles' state at the end of the step (after the second half map, before the
+// next first half map) is also summed into the block's partial moments, diag_part[blk * 27 +
+// q]: 6 sums of d = v - shift and the 21 products d_a d_b (a <= b, row-major), with the
+// 6-double shift read from diag_shift (close to the mean, so that the centred moments formed
+// from these sums lose no digits).
+template <int S, typename T, bool PERM, bool DIAG = false>
 __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
                                                     const double* __restrict__ src,
                                                     const uint32_t* __restrict__ perm,
@@ -558,10 +586,17 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
                                                     const uint32_t* __restrict__ nchunks,
                                                     double L, const HalfMap& second,
                                                     int has_next, const HalfMap& first_next,
-                                                    Box* box, int blk, int nblk) {
+                                                    Box* box, int blk, int nblk,
+                                                    double* __restrict__ diag_part = nullptr,
+                                                    const double* __restrict__ diag_shift = nullptr) {
   extern __shared__ unsigned char smem_raw[];
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
+  double sh[6], acc[DIAG ? kMomentSlots : 1];
+  if constexpr (DIAG) {
+    for (int r = 0; r < 6; ++r) sh[r] = diag_shift[r];
+    for (int q = 0; q < kMomentSlots; ++q) acc[q] = 0.0;
+  }
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
@@ -633,6 +668,16 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       v[3] = v[3] + c.C * (double)ey * L;
       v[5] = v[5] + c.gamma * c.C * (double)ez * L;
       apply_half(second, v, c.inv_gamma2);
+      if constexpr (DIAG) {
+        double d[6];
+        for (int r = 0; r < 6; ++r) {
+          d[r] = v[r] - sh[r];
+          acc[r] += d[r];
+        }
+        int q = 6;
+        for (int a = 0; a < 6; ++a)
+          for (int b = a; b < 6; ++b) acc[q++] += d[a] * d[b];
+      }
       if (has_next) {
         apply_half(first_next, v, c.inv_gamma2);
         const double p[3] = {v[0], v[2], v[4]};
@@ -648,9 +693,26 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   }
   if (bin_fault) atomicCAS(const_cast<int*>(&g->status), 0, -7);
   if (has_next) box_accumulate_block(lo, hi, bad, box);
+  if constexpr (DIAG) {
+    // wave sums, then the waves' sums through LDS (the window is free after the barrier; the
+    // launch gives at least kMaxThreads / 64 * 27 doubles)
+    for (int q = 0; q < kMomentSlots; ++q)
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    double* red = reinterpret_cast<double*>(smem_raw);
+    const int wave = threadIdx.x >> 6, nwave = (int)(blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+      for (int q = 0; q < kMomentSlots; ++q) red[wave * kMomentSlots + q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < kMomentSlots) {
+      double t = 0.0;
+      for (int w = 0; w < nwave; ++w) t += red[w * kMomentSlots + threadIdx.x];
+      diag_part[(int64_t)blk * kMomentSlots + threadIdx.x] = t;
+    }
+  }
 }
 
-template <int S, typename T, bool PERM>
+template <int S, typename T, bool PERM, bool DIAG>
 __global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles(double* __restrict__ B,
                                                     const double* __restrict__ src,
                                                     const uint32_t* __restrict__ perm,
@@ -662,9 +724,66 @@ __global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles(double* __restrict__ 
                                                     const int4* __restrict__ chunks,
                                                     const uint32_t* __restrict__ nchunks,
                                                     double L, HalfMap second, int has_next,
-                                                    HalfMap first_next, Box* box) {
-  gkd_tiles_body<S, T, PERM>(B, src, perm, idsrc, iddst, g, E, c, sp, chunks, nchunks, L, second,
-                             has_next, first_next, box, blockIdx.x, gridDim.x);
+                                                    HalfMap first_next, Box* box,
+                                                    double* __restrict__ diag_part,
+                                                    const double* __restrict__ diag_shift) {
+  gkd_tiles_body<S, T, PERM, DIAG>(B, src, perm, idsrc, iddst, g, E, c, sp, chunks, nchunks, L,
+                                   second, has_next, first_next, box, blockIdx.x, gridDim.x,
+                                   diag_part, diag_shift);
+}
+
+// The shift of the fused moment sums: the previous step's means (prev, 6 doubles), or, for the
+// first step (prev == nullptr), the centre of the step's grid for the positions and 0 for the
+// momenta.
+__global__ void k_diag_shift(const Geom* __restrict__ g, Consts c, const double* __restrict__ prev,
+                             double* __restrict__ shift) {
+  const int r = threadIdx.x;
+  if (r >= 6) return;
+  if (prev) {
+    shift[r] = prev[r];
+  } else if (r & 1) {
+    shift[r] = 0.0;
+  } else {
+    const int a = r >> 1;
+    const int na = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+    shift[r] = g->origin[a] + 0.5 * (na - 1) * g->h[a];
+  }
+}
+
+// Moments from the blocks' partial sums: one wave per slot sums the nblk partials; then
+// mean_r = shift_r + S_r / n and the centred products S_ab / n - (S_a / n)(S_b / n).  A device
+// error state (status != 0) writes NaN.
+__global__ __launch_bounds__(1024) void k_diag_combine(const Geom* __restrict__ g,
+                                                       const double* __restrict__ part, int nblk,
+                                                       const double* __restrict__ shift,
+                                                       int64_t n, double* __restrict__ out) {
+  __shared__ double tot[kMomentSlots];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwave = (int)blockDim.x >> 6;
+  for (int q = wave; q < kMomentSlots; q += nwave) {
+    double t = 0.0;
+    for (int b = lane; b < nblk; b += 64) t += part[(int64_t)b * kMomentSlots + q];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) tot[q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x >= kMomentSlots) return;
+  const int q = threadIdx.x;
+  if (g->status) {
+    out[q] = NAN;
+    return;
+  }
+  const double inv = 1.0 / (double)n;
+  if (q < 6) {
+    out[q] = shift[q] + tot[q] * inv;
+    return;
+  }
+  int a = 0, k = q - 6;
+  while (k >= 6 - a) {
+    k -= 6 - a;
+    ++a;
+  }
+  const int b = a + k;
+  out[q] = tot[q] * inv - (tot[a] * inv) * (tot[b] * inv);
 }
 
 // First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
@@ -861,7 +980,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles_batch(const BeamDev* 
   const BeamDev& d = beams[blockIdx.y];
   const SliceDev& sl = d.slices[j % d.n_slices];
   const SliceDev& sn = d.slices[(j + 1) % d.n_slices];
-  gkd_tiles_body<S, T, false>(nxt_X(d, parity), nullptr, nullptr, nullptr, nullptr, d.geom,
+  gkd_tiles_body<S, T, false, false>(nxt_X(d, parity), nullptr, nullptr, nullptr, nullptr, d.geom,
                               (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
                        sl.L, sl.second, j + 1 < n_steps, sn.first, d.box, blockIdx.x,
                        gridDim.x);
@@ -1065,38 +1184,64 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
                             const uint32_t* idsrc, uint32_t* iddst, const Geom* g, const T* E,
                             Consts c, const SortPlan& sp, const int4* chunks,
                             const uint32_t* nchunks, double L, const HalfMap& second,
-                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s) {
+                            int has_next, const HalfMap& first_next, Box* box, hipStream_t s,
+                            double* diag_part, double* diag_shift, const double* diag_prev,
+                            double* diag_out) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
   const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
   if (perm && (!src || !idsrc || !iddst || src == B || idsrc == iddst))
     return hipErrorInvalidValue;
-#define PIC_GKD(SS, PP)                                                                       \
+  const bool diag = diag_out != nullptr;
+  if (diag) {
+    if (!diag_part || !diag_shift) return hipErrorInvalidValue;
+    const size_t red = sizeof(double) * kMomentSlots * (kMaxThreads / 64);
+    if (lds < red) lds = red;
+    hipLaunchKernelGGL(k_diag_shift, dim3(1), dim3(64), 0, s, g, c, diag_prev, diag_shift);
+    PIC_TRY(hipGetLastError());
+  }
+#define PIC_GKD(SS, PP, DD)                                                                   \
   do {                                                                                        \
-    PIC_TRY_LDS((k_gkd_tiles<SS, T, PP>), lds);                                               \
-    hipLaunchKernelGGL((k_gkd_tiles<SS, T, PP>), grid, block, lds, s, B, src, perm, idsrc,    \
+    PIC_TRY_LDS((k_gkd_tiles<SS, T, PP, DD>), lds);                                           \
+    hipLaunchKernelGGL((k_gkd_tiles<SS, T, PP, DD>), grid, block, lds, s, B, src, perm, idsrc,\
                        iddst, g, E, c, sp, chunks, nchunks, L, second, has_next, first_next,  \
-                       box);                                                                  \
+                       box, diag_part, diag_shift);                                           \
   } while (0)
-  if (S == 1) {
-    if (perm) PIC_GKD(1, true); else PIC_GKD(1, false);
+  if (diag) {
+    if (S == 1) {
+      if (perm) PIC_GKD(1, true, true); else PIC_GKD(1, false, true);
+    } else {
+      if (perm) PIC_GKD(2, true, true); else PIC_GKD(2, false, true);
+    }
   } else {
-    if (perm) PIC_GKD(2, true); else PIC_GKD(2, false);
+    if (S == 1) {
+      if (perm) PIC_GKD(1, true, false); else PIC_GKD(1, false, false);
+    } else {
+      if (perm) PIC_GKD(2, true, false); else PIC_GKD(2, false, false);
+    }
   }
 #undef PIC_GKD
-  return hipGetLastError();
+  PIC_TRY(hipGetLastError());
+  if (diag) {
+    hipLaunchKernelGGL(k_diag_combine, dim3(1), dim3(1024), 0, s, g, diag_part, sp.blocks,
+                       diag_shift, c.n, diag_out);
+    PIC_TRY(hipGetLastError());
+  }
+  return hipSuccess;
 }
 
 template hipError_t launch_gkd_tiles<double>(double*, const double*, const uint32_t*,
                                              const uint32_t*, uint32_t*, const Geom*,
                                              const double*, Consts, const SortPlan&, const int4*,
                                              const uint32_t*, double, const HalfMap&, int,
-                                             const HalfMap&, Box*, hipStream_t);
+                                             const HalfMap&, Box*, hipStream_t, double*, double*,
+                                             const double*, double*);
 template hipError_t launch_gkd_tiles<float>(double*, const double*, const uint32_t*,
                                             const uint32_t*, uint32_t*, const Geom*, const float*,
                                             Consts, const SortPlan&, const int4*, const uint32_t*,
                                             double, const HalfMap&, int, const HalfMap&, Box*,
-                                            hipStream_t);
+                                            hipStream_t, double*, double*, const double*,
+                                            double*);
 
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
                             uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
