@@ -6,8 +6,12 @@ Each candidate is timed on the device with the library's own tracking loop
 (pic_track_n_steps: the call's wall time less its once-per-call stages; pic_track_batch
 for a batch: the whole call) over a few steps of a beam of the problem's size,
 re-initialised to the same seeded state before every candidate.  The search is
-coordinate-wise: tile edge with the default work items, then the work-item size at the best
-tile, then the workgroup count, then the workgroup size.  Only launch shapes within the
+coordinate-wise: tile shape with the default work items, then the work-item size at the best
+tile, then the workgroup count, then the workgroup size.  Tile shapes are cubes and slabs: a
+slab is thin along one axis and wide along the other two, so that particles moving mostly
+across the wide axes (the transverse planes of a focusing lattice, where the longitudinal
+position hardly changes within a step) leave their tile less often, and the gather reads fewer
+of them from outside the tile's own stretch of the previous order.  Only launch shapes within the
 library's documented limits are tried (tile count <= 4096, the gather's
 field window within the 156 KB of dynamic LDS a workgroup may use).  Results go into a JSON
 cache keyed by problem class: particle count rounded to a power of two, grid, shape and
@@ -25,6 +29,9 @@ from . import Batch, Beam, PIC_OK, STATUS_NAMES
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 TILES = (4, 5, 6, 8, 10, 12, 16)
+# slabs (wide, wide, thin), with the thin axis put on each of x, y and z in turn
+SLABS = ((24, 24, 2), (32, 16, 2), (16, 32, 2), (32, 32, 2), (16, 16, 4), (20, 20, 4),
+         (24, 24, 4), (32, 32, 1))
 CHUNKS = (2048, 4096, 8192, 16384, 32768)
 BLOCKS = (0, 1024, 2048, 8192)          # 0: min(work items, 4096)
 THREADS = (256, 512, 1024)
@@ -118,10 +125,17 @@ def tune(cfg, grid_fp32=False, steps=6, cache=DEFAULT_CACHE, force=False, log=No
 
     default = run({})
     best, best_t = {}, default
-    for t in TILES:
-        tile = [min(t, n) for n in cfg.nodes]
-        if not _tile_ok(tile, cfg.nodes, cfg.shape, grid_fp32):
+    shapes = [(t, t, t) for t in TILES]
+    for thin in (2, 1, 0):
+        for sl in SLABS:
+            wide = list(sl[:2])
+            shapes.append(tuple(sl[2] if a == thin else wide.pop(0) for a in range(3)))
+    seen = set()
+    for shp in shapes:
+        tile = [min(t, n) for t, n in zip(shp, cfg.nodes)]
+        if tuple(tile) in seen or not _tile_ok(tile, cfg.nodes, cfg.shape, grid_fp32):
             continue
+        seen.add(tuple(tile))
         cand = {"tile": tile}
         dt = run(cand)
         if dt < best_t:
