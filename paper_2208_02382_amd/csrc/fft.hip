@@ -216,8 +216,18 @@ __device__ __forceinline__ void green_dft_body(double* __restrict__ gd, FftAxis 
   const int M = ax.M, n = M / 2;
   const int c0 = bx * LB;  // first complex line of this block
   double* base = gd + (int64_t)by * sb;
+  // consecutive threads take consecutive elements of a line where the line is contiguous in
+  // memory (st == 1), else consecutive lines (contiguous across lines)
+  const bool efast = st == 1;
   for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
-    const int p = idx / LB, l = idx - p * LB;  // consecutive threads: consecutive lines
+    int p, l;
+    if (efast) {
+      l = idx / M;
+      p = idx - l * M;
+    } else {
+      p = idx / LB;
+      l = idx - p * LB;
+    }
     const int t = p <= n ? p : M - p;
     const double sgn = ODD ? (p < n ? 1.0 : (p == n ? 0.0 : -1.0)) : 1.0;
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
@@ -229,7 +239,14 @@ __device__ __forceinline__ void green_dft_body(double* __restrict__ gd, FftAxis 
   __syncthreads();
   fft_lds<double, -1>(buf, LB, ax, twl, 1);
   for (int idx = threadIdx.x; idx < LB * (n + 1); idx += blockDim.x) {
-    const int p = idx / LB, l = idx - p * LB;
+    int p, l;
+    if (efast) {
+      l = idx / (n + 1);
+      p = idx - l * (n + 1);
+    } else {
+      p = idx / LB;
+      l = idx - p * LB;
+    }
     const int a0 = 2 * (c0 + l), a1 = a0 + 1;
     const Cx<double> v = buf[l * (M + 1) + p];
     if (a0 < na) base[(int64_t)a0 * sa + (int64_t)p * st] = ODD ? v.y : v.x;
