@@ -155,3 +155,23 @@ def test_slice_step_diagnostics(lib, space_charge):
     # passes at the end of each step)
     assert _coord_err(b.X.cpu().numpy(), b2.X.cpu().numpy()) < 1e-13
     assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
+
+
+@pytest.mark.parametrize("offset_sigmas", [0.0, 30.0])
+def test_slice_step_diagnostics_of_an_offset_beam(lib, offset_sigmas):
+    # the moments are summed about a shift inside the gather-kick (the grid centre on the first
+    # step, the previous step's means after it): a beam centred 30 sigma off axis in x, px, y
+    # and delta keeps the centred moments at the parity bar
+    cfg = workloads.SMALL
+    n, nodes, shape, steps = 4_001, (16, 12, 16), 1, 12
+    b, X = _start(lib, cfg, n, nodes, shape)
+    off = offset_sigmas * np.sqrt(np.diag(np.array(cfg.sigma_matrix)))
+    off[3] = off[4] = 0.0
+    for r in range(6):
+        b.X[r] += float(off[r])
+    X = X + off[:, None]
+    diag = b.track(workloads.THICK_FODO, steps, diagnostics=True).cpu().numpy()
+    _, do = _diag_oracle(X, workloads.THICK_FODO, steps, _problem(cfg, n, nodes, shape))
+    rms = np.sqrt(np.diag(np.cov(X)))
+    assert np.all(np.abs(diag[:, :6] - do[:, :6]) / rms < TOL)
+    assert np.abs(diag[:, 6:] - do[:, 6:]).max() < TOL * np.abs(do[:, 6:]).max()
