@@ -72,8 +72,10 @@ typedef struct {
   int grid_fp32;           /* 0: float64 charge grid, FFT and field; 1: float32 (particles and
                               the push stay float64) */
   int space_charge;        /* 0/1 (set_space_charge); 0 makes pic_track_n_steps purely linear */
-  /* Launch tuning of the binned deposit and gather (0 = the library's default for each);
-   * results do not depend on them beyond the float atomics' summation order. */
+  /* Launch tuning of the binned deposit and gather (0 = the library's default for each).
+   * pic_track_n_steps gives the same bits for every chunk, blocks and threads; the tile shape
+   * changes only the rounding of the deposit's fixed-point charges (below 1e-13 of a
+   * macroparticle's charge per contribution). */
   int tile[3];             /* tile edge in nodes per axis for the per-step binning; the tile
                               count prod(ceil(n_a/tile_a)) must be <= 4096 and the charge
                               window 8 prod(tile_a + shape) bytes <= 156 KB (the dynamic LDS
@@ -200,7 +202,12 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * of X is preserved (internally the particles are binned by grid tile every step in two
  * workspace copies and returned to X in the caller's order at the end of the call).  With
  * desc.space_charge = 0 only the linear maps are applied.  If the device flags an error
- * during the call (see pic_check), X is left as it was before the call. */
+ * during the call (see pic_check), X is left as it was before the call.  Bitwise reproducible:
+ * the binned deposit sums each tile's charge window as 64-bit integers, exact in any order, and
+ * forms the grid from the tiles in a fixed order; reductions have a fixed shape; so repeated
+ * calls from the same state give the same bits although the order of particles within a tile
+ * and of the atomics varies.  (pic_deposit, batches and the slice-step diagnostics' moment
+ * sums are reproducible to rounding only.) */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 

@@ -52,7 +52,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   size_t geom, box, mom_partial, mom_out, tw[3], twf[3], corners, W, Gd, Gh, rho, phi, E;
   size_t hcorners, gd3, gh3, W2;  // direct field only (else 0-byte slots)
-  size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, diag_part, diag_shift, total;
+  size_t XA, XB, idA, idB, keys, perm, hist, cursor, chunks, nchunks, diag_part, diag_shift;
+  size_t tacc, tscale, total;
 };
 
 pic_status check_desc(const pic_beam_desc* d) {
@@ -144,6 +145,9 @@ Layout layout(const pic_beam_desc* d) {
   // slice-step diagnostics summed inside the gather-kick: one partial per workgroup, the shift
   L.diag_part = take(sizeof(double) * kMomentSlots * (size_t)sp.blocks);
   L.diag_shift = take(sizeof(double) * 6);
+  // the deposit's per-tile integer windows (the order-independent charge grid) and exponents
+  L.tacc = take(sizeof(uint64_t) * (size_t)sp.ntiles * tile_window_nodes(sp, d->shape));
+  L.tscale = take(sizeof(int) * kMaxTiles);
   L.total = off;
   return L;
 }
@@ -193,6 +197,8 @@ struct pic_beam_s {
   double* mom_out;
   double* diag_part;   // per-workgroup moment sums of the fused slice-step diagnostics
   double* diag_shift;
+  unsigned long long* tacc;  // per-tile integer charge windows (zero between deposits)
+  int* tscale;
   double2* corners;
   void* W;
   double* Gd;
@@ -368,6 +374,13 @@ pic_status expand_lattice(const pic_element* lat, int n_el, std::vector<SliceDev
   return PIC_OK;
 }
 
+// the deposit's per-tile integer windows start at zero (each deposit leaves them zero; a call
+// interrupted by a device error may not)
+hipError_t clear_tacc(pic_beam b, hipStream_t s) {
+  return launch_zero<double>((double*)b->tacc,
+                             (int64_t)b->sp.ntiles * tile_window_nodes(b->sp, b->d.shape), s);
+}
+
 // Green spectrum of the current geometry on the auxiliary stream (joined before the solve)
 template <typename T>
 pic_status fork_green(pic_beam b, hipStream_t s) {
@@ -392,6 +405,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
   uint32_t* idA = b->idA;
   uint32_t* idB = b->idB;
   HIP_OK(launch_box_reset(b->box, s), "box reset");
+  HIP_OK(clear_tacc(b, s), "clear");
   STAGE(b, PIC_STAGE_PROLOGUE, s,
         launch_prologue(b->X, A, idA, sl[0].first, b->c, b->box, s), "prologue");
   // the E' window of a tile must fit the LDS a workgroup may use
@@ -423,7 +437,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     const double* P = permuted ? A : B;  // particles the deposit reads (through perm)
     STAGE(b, PIC_STAGE_DEPOSIT, s,
           launch_deposit_tiles<T>(P, permuted ? b->perm : nullptr, b->geom, b->c, b->sp,
-                                  b->chunks, b->nchunks, (T*)b->rho, s),
+                                  b->chunks, b->nchunks, (T*)b->rho, s, b->tacc, b->tscale),
           "deposit");
     HIP_OK(hipStreamWaitEvent(s, b->ev_join, 0), "join");
     st = green_and_solve<T>(b, (const T*)b->rho, (T*)b->phi, (T*)b->E, s, false);
@@ -517,7 +531,7 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_e
                     b->XB, b->idB, true, s),
          "adjoint forward");
   HIP_OK(launch_deposit_tiles<T>(b->XB, nullptr, g, b->c, b->sp, b->chunks, b->nchunks,
-                                 (T*)b->rho, s),
+                                 (T*)b->rho, s, b->tacc, b->tscale),
          "adjoint forward");
   HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh, s),
          "adjoint forward");
@@ -747,6 +761,8 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->nchunks = (uint32_t*)(w + L.nchunks);
   b->diag_part = (double*)(w + L.diag_part);
   b->diag_shift = (double*)(w + L.diag_shift);
+  b->tacc = (unsigned long long*)(w + L.tacc);
+  b->tscale = (int*)(w + L.tscale);
   int nn[3] = {d->nx, d->ny, d->nz};
   for (int a = 0; a < 3; ++a) {
     b->plan.full[a].M = 2 * nn[a];
@@ -997,6 +1013,7 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (adj_work_bytes < A.total)
     return fail(PIC_ENOMEM, "reverse-sweep workspace smaller than pic_adjoint_workspace_bytes");
   hipStream_t s = S(stream);
+  HIP_OK(clear_tacc(b, s), "clear");
   if (b->d.grid_fp32)
     return track_adjoint<float>(b, lattice, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
                                 d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);

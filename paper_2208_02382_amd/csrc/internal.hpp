@@ -161,6 +161,10 @@ template <typename T>
 hipError_t launch_zero(T* p, int64_t count, hipStream_t s);
 
 // ---- sort.hip
+// nodes of one tile's deposit window, (T_x + S)(T_y + S)(T_z + S)
+inline int64_t tile_window_nodes(const SortPlan& sp, int S) {
+  return (int64_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
+}
 // tile[a], chunk, blocks: 0 selects the default
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
                         int blocks, int threads);
@@ -174,11 +178,15 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
 hipError_t launch_bin_perm(const double* A, const Geom* g, Consts c, const SortPlan& sp,
                            uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
                            uint32_t* nchunks, uint32_t* perm, hipStream_t s);
-// perm == nullptr: B is in slot order; else slot i reads particle perm[i] of B
+// perm == nullptr: B is in slot order; else slot i reads particle perm[i] of B.  tacc (with
+// tscale): the deterministic form, each tile's window summed exactly as integers in tacc
+// (ntiles * (T+S)^3 64-bit entries, all zero on entry and left zero) and the grid formed from
+// them in a fixed order; nullptr: windows added to rho with float atomics.
 template <typename T>
 hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geom* g, Consts c,
                                 const SortPlan& sp, const int4* chunks, const uint32_t* nchunks,
-                                T* rho, hipStream_t s);
+                                T* rho, hipStream_t s, unsigned long long* tacc = nullptr,
+                                int* tscale = nullptr);
 // perm == nullptr: B in slot order, updated in place (src, idsrc, iddst unused); else slot i
 // reads particle perm[i] of src and id idsrc[perm[i]], and writes slot i of B and iddst
 // (src != B, idsrc != iddst).  diag_out != nullptr: the moments (kMomentSlots doubles) of the

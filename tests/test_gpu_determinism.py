@@ -1,0 +1,56 @@
+"""Bitwise reproducibility of the tracking loop: the binned deposit sums every tile's window as
+64-bit integers (exact in any order) and forms the charge grid from them in a fixed order, the
+reductions (box, moments) have a fixed shape, and every particle's gather and push is its own.
+Two runs from the same state therefore give the same bits, although the order in which the
+ranking places particles within a tile, and the order of the atomics, differ between runs.
+The same holds across launch shapes that change the tiles' chunking but not the tiles.  (The
+fused slice-step diagnostics sum in floating point over the particles each workgroup holds, so
+they reproduce to rounding, not bit for bit.)"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2208_02382_amd as p
+    return p
+
+
+def _beam(lib, cfg, n, nodes, shape, xi, **kw):
+    b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes, **kw)
+    b.init_from_normals(cfg.sigma_matrix, xi)
+    return b
+
+
+@pytest.mark.parametrize("grid_fp32", [False, True])
+@pytest.mark.parametrize("shape", [1, 2])
+def test_two_runs_give_the_same_bits(lib, grid_fp32, shape):
+    cfg = workloads.SMALL
+    n, nodes = 30_011, (24, 18, 36)
+    xi = torch.from_numpy(workloads.draw_xi(cfg, n=n)).cuda()
+    out = []
+    for _ in range(2):
+        b = _beam(lib, cfg, n, nodes, shape, xi, grid_fp32=grid_fp32,
+                  tuning={"tile": (4, 4, 4), "chunk": 2048})
+        b.track(cfg.lattice, 12)
+        assert b.check() == lib.PIC_OK
+        out.append(b.X.clone())
+    assert torch.equal(out[0], out[1])
+
+
+def test_chunk_size_and_workgroups_do_not_change_the_bits(lib):
+    cfg = workloads.SMALL
+    n, nodes, shape = 20_000, (32, 32, 32), 2
+    xi = torch.from_numpy(workloads.draw_xi(cfg, n=n)).cuda()
+    out = []
+    for tun in ({"tile": (8, 8, 4), "chunk": 2048, "blocks": 64, "threads": 256},
+                {"tile": (8, 8, 4), "chunk": 16384, "blocks": 1024, "threads": 1024}):
+        b = _beam(lib, cfg, n, nodes, shape, xi, tuning=tun)
+        b.track(cfg.lattice, 10)
+        out.append(b.X.clone())
+    assert torch.equal(out[0], out[1])
