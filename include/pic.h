@@ -206,7 +206,8 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * the binned deposit sums each tile's charge window as 64-bit integers, exact in any order, and
  * forms the grid from the tiles in a fixed order; reductions have a fixed shape; so repeated
  * calls from the same state give the same bits although the order of particles within a tile
- * and of the atomics varies.  (pic_deposit, batches and the slice-step diagnostics' moment
+ * and of the atomics varies; the same holds for pic_track_batch, whose beams equal their
+ * pic_track_n_steps results bit for bit.  (pic_deposit and the slice-step diagnostics' moment
  * sums are reproducible to rounding only.) */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);

@@ -650,6 +650,7 @@ template <typename T>
 pic_status enqueue_batch(const BeamDev* tab, int nb, const BatchDims& bd, int shape, int n_steps,
                          hipStream_t s, hipStream_t aux, hipEvent_t fork, hipEvent_t join) {
   HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
+  HIP_OK(launch_batch_clear_tacc(tab, nb, s), "batch");
   HIP_OK(launch_batch_prologue_particles(tab, nb, bd, s), "batch");
   for (int j = 0; j < n_steps; ++j) {
     const int parity = j & 1;
@@ -1098,6 +1099,8 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     d.Gd = h->Gd;
     d.Gh = h->Gh;
     d.corners = h->corners;
+    d.tacc = h->tacc;
+    d.tscale = h->tscale;
     d.n_slices = (int)sl.size();
   }
   // per-beam work-list blocks of the tiled kernels: the blocks of a beam stride over its chunks

@@ -121,6 +121,8 @@ struct BeamDev {
   const SliceDev* slices;  // lattice of this beam, one entry per slice (cycled over the steps)
   int n_slices;
   int pad;
+  unsigned long long* tacc;  // per-tile integer charge windows and their exponents
+  int* tscale;
 };
 
 constexpr int kReduceBlocks = 1024;   // partial sums for the moments reduction
@@ -220,6 +222,8 @@ struct BatchDims {      // grid extents over the beams of a batch
 };
 hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                                       int parity, bool first, hipStream_t s);
+// every beam's per-tile integer charge windows set to zero
+hipError_t launch_batch_clear_tacc(const BeamDev* beams, int nb, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                                 int parity, hipStream_t s);

@@ -488,17 +488,16 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
 // 2^-k, to what the deposit's direct path put there, and clears the entries it read, so that
 // tacc is zero again for the next step (entries outside the grid are never written).
 template <int S, typename T>
-__global__ __launch_bounds__(256) void k_tile_reduce(const Geom* __restrict__ g, Consts c,
-                                                     SortPlan sp,
-                                                     unsigned long long* __restrict__ tacc,
-                                                     const int* __restrict__ tscale,
-                                                     T* __restrict__ rho) {
+__device__ __forceinline__ void tile_reduce_body(const Geom* __restrict__ g, Consts c,
+                                                 SortPlan sp,
+                                                 unsigned long long* __restrict__ tacc,
+                                                 const int* __restrict__ tscale,
+                                                 T* __restrict__ rho, int blk, int nblk) {
   if (g->status) return;
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
   const int64_t nw = (int64_t)Wx * Wy * Wz;
   const int64_t total = (int64_t)c.nx * c.ny * c.nz;
-  for (int64_t node = blockIdx.x * 256ll + threadIdx.x; node < total;
-       node += (int64_t)gridDim.x * 256) {
+  for (int64_t node = blk * 256ll + threadIdx.x; node < total; node += (int64_t)nblk * 256) {
     const int gx = (int)(node % c.nx), gy = (int)((node / c.nx) % c.ny),
               gz = (int)(node / ((int64_t)c.nx * c.ny));
     const int p[3] = {gx, gy, gz};
@@ -524,6 +523,15 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const Geom* __restrict__ g,
         }
     if (val != 0.0) rho[node] = (T)((double)rho[node] + val);
   }
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(256) void k_tile_reduce(const Geom* __restrict__ g, Consts c,
+                                                     SortPlan sp,
+                                                     unsigned long long* __restrict__ tacc,
+                                                     const int* __restrict__ tscale,
+                                                     T* __restrict__ rho) {
+  tile_reduce_body<S, T>(g, c, sp, tacc, tscale, rho, blockIdx.x, gridDim.x);
 }
 
 // Vector deposit e_c(node) = sum_i W(r_i - node) v_c,i of the binned rows (r_x, v_x, r_y, v_y,
@@ -1028,8 +1036,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles_batch(const BeamD
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
   deposit_tiles_body<S, T>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
-                           (T*)d.rho,
-                           blockIdx.x, gridDim.x);
+                           (T*)d.rho, blockIdx.x, gridDim.x, d.tacc, d.tscale);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(256) void k_tile_reduce_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  tile_reduce_body<S, T>(d.geom, d.c, d.sp, d.tacc, d.tscale, (T*)d.rho, blockIdx.x, gridDim.x);
+}
+
+// every beam's per-tile integer windows set to zero (once per batch call)
+__global__ __launch_bounds__(256) void k_clear_tacc_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  const int S = d.c.shape;
+  const int64_t count = (int64_t)d.sp.ntiles * (d.sp.T[0] + S) * (d.sp.T[1] + S) * (d.sp.T[2] + S);
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    d.tacc[i] = 0ull;
 }
 
 template <int S, typename T>
@@ -1378,15 +1400,26 @@ template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
                                 int parity, hipStream_t s) {
   const dim3 grid(bd.max_chunks, nb);
+  int rb = (int)(((int64_t)bd.max_nx * bd.max_ny * bd.max_nz + 255) / 256);
+  if (rb > 16384) rb = 16384;
   if (shape == 1) {
     PIC_TRY_LDS((k_deposit_tiles_batch<1, T>), bd.dep_lds);
     hipLaunchKernelGGL((k_deposit_tiles_batch<1, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
                        parity);
+    PIC_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_tile_reduce_batch<1, T>), dim3(rb, nb), dim3(256), 0, s, beams);
   } else {
     PIC_TRY_LDS((k_deposit_tiles_batch<2, T>), bd.dep_lds);
     hipLaunchKernelGGL((k_deposit_tiles_batch<2, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
                        parity);
+    PIC_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_tile_reduce_batch<2, T>), dim3(rb, nb), dim3(256), 0, s, beams);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_clear_tacc(const BeamDev* beams, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_tacc_batch, dim3(1024, nb), dim3(256), 0, s, beams);
   return hipGetLastError();
 }
 

@@ -94,8 +94,8 @@ def test_batch_matches_single_beam_path(lib):
         s.track(c.lattice, 12)
     torch.cuda.synchronize()
     for g, s in zip(gpu, single):
-        Xs = s.X.cpu().numpy()
-        assert _coord_err(g.X.cpu().numpy(), Xs) < TOL
+        # the same kernels' arithmetic and order-independent charge grids: the same bits
+        assert torch.equal(g.X, s.X)
 
 
 def test_batch_fp32_grid_moments_within_1e5(lib):

@@ -54,3 +54,21 @@ def test_chunk_size_and_workgroups_do_not_change_the_bits(lib):
         b.track(cfg.lattice, 10)
         out.append(b.X.clone())
     assert torch.equal(out[0], out[1])
+
+
+def test_batch_runs_give_the_same_bits(lib):
+    mix = [(7_001, (16, 16, 16), 1.0), (12_000, (24, 24, 24), 1.6), (3_000, (12, 18, 24), 0.7)]
+    out = []
+    for _ in range(2):
+        beams, lats = [], []
+        for j, (n, nodes, k) in enumerate(mix):
+            cfg = workloads.MEDIUM.with_(n=n, nodes=nodes, lattice=((k, 0.5), (-k, 0.5)))
+            xi = torch.from_numpy(workloads.draw_xi(cfg, n=n, seed=50 + j)).cuda()
+            beams.append(_beam(lib, cfg, n, nodes, 2, xi))
+            lats.append(cfg.lattice)
+        batch = lib.Batch(beams, lats)
+        batch.track(8)
+        torch.cuda.synchronize()
+        out.append([b.X.clone() for b in beams])
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
