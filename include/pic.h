@@ -164,7 +164,8 @@ pic_status pic_init_beam_from_normals(pic_beam b, const double sigma6x6[36], con
 /* Charge deposition (paper: "charge deposition"; shape order of Listing 1): computes the
  * geometry from the current positions, then writes the charge per node in coulomb,
  * Q_n = sum_i q_macro W(x_i - X_n) with W the CIC or TSC tensor-product B-spline, into
- * d_rho (nx*ny*nz pic_real, overwritten). */
+ * d_rho (nx*ny*nz pic_real, overwritten).  Binned as in pic_track_n_steps (tile keys and
+ * ranking in the workspace; X is not modified) and bitwise reproducible. */
 pic_status pic_deposit(pic_beam b, void* d_rho, void* stream);
 
 /* Poisson solve in the bunch rest frame (paper: "Poisson solve"; section "Model Assumptions"):
@@ -207,8 +208,8 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * forms the grid from the tiles in a fixed order; reductions have a fixed shape; so repeated
  * calls from the same state give the same bits although the order of particles within a tile
  * and of the atomics varies; the same holds for pic_track_batch, whose beams equal their
- * pic_track_n_steps results bit for bit.  (pic_deposit and the slice-step diagnostics' moment
- * sums are reproducible to rounding only.) */
+ * pic_track_n_steps results bit for bit.  (The slice-step diagnostics' moment sums are
+ * reproducible to rounding only.) */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 

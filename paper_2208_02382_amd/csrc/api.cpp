@@ -855,12 +855,22 @@ pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
   HIP_OK(launch_box_reset(b->box, s), "deposit");
   HIP_OK(launch_box(b->X, b->d.n, b->box, s), "deposit");
   HIP_OK(launch_geometry(b->box, b->geom, b->c, s), "deposit");
+  // binned as in the tracking loop: tile keys and the ranking of X (X itself is not moved),
+  // then the tiles' integer windows, so the grid does not depend on the order of the atomics
+  HIP_OK(clear_tacc(b, s), "deposit");
+  HIP_OK(launch_bin_perm(b->X, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
+                         b->nchunks, b->perm, s),
+         "deposit");
   if (b->d.grid_fp32) {
     HIP_OK(launch_zero<float>((float*)d_rho, ng, s), "deposit");
-    HIP_OK(launch_deposit<float>(b->X, b->geom, (float*)d_rho, b->c, s), "deposit");
+    HIP_OK(launch_deposit_tiles<float>(b->X, b->perm, b->geom, b->c, b->sp, b->chunks,
+                                       b->nchunks, (float*)d_rho, s, b->tacc, b->tscale),
+           "deposit");
   } else {
     HIP_OK(launch_zero<double>((double*)d_rho, ng, s), "deposit");
-    HIP_OK(launch_deposit<double>(b->X, b->geom, (double*)d_rho, b->c, s), "deposit");
+    HIP_OK(launch_deposit_tiles<double>(b->X, b->perm, b->geom, b->c, b->sp, b->chunks,
+                                        b->nchunks, (double*)d_rho, s, b->tacc, b->tscale),
+           "deposit");
   }
   return PIC_OK;
 }

@@ -147,8 +147,6 @@ hipError_t launch_init_philox(double* X, int64_t n, int64_t n_halo, uint64_t see
                               int dist, hipStream_t s);
 hipError_t launch_clear_status(Geom* g, hipStream_t s);
 template <typename T>
-hipError_t launch_deposit(const double* X, const Geom* g, T* rho, Consts c, hipStream_t s);
-template <typename T>
 hipError_t launch_gather(const double* X, const Geom* g, const T* E, T* Ep, Consts c,
                          hipStream_t s);
 template <typename T>

@@ -1,5 +1,6 @@
-// Particle kernels: beam initialisation, box reduction and geometry, charge deposition,
-// field gather, linear maps (drift, thin quadrupole, space-charge kick) and beam moments.
+// Particle kernels: beam initialisation, box reduction and geometry, field gather, linear
+// maps (drift, thin quadrupole, space-charge kick) and beam moments.  (The charge deposition
+// is binned by tile, in sort.hip.)
 //
 // Phase space is structure-of-arrays float64 X[6][n] = (x, px, y, py, z, delta); every kernel
 // walks particles with a grid-stride loop so consecutive lanes touch consecutive doubles of
@@ -171,37 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_init_philox(double* __restrict__ X, 
   }
 }
 
-// ---------------------------------------------------------------------------- deposit, gather
-
-template <typename T>
-__device__ __forceinline__ void atomic_add_grid(T* p, T v) {
-  unsafeAtomicAdd(p, v);
-}
-
-// Charge deposition with device-scope float atomics into the node array
-// rho[(k ny + j) nx + i]: Q_n += q_macro wz wy wx for the (S+1)^3 stencil nodes.
-template <int S, typename T>
-__global__ __launch_bounds__(kBlock) void k_deposit(const double* __restrict__ X,
-                                                    const Geom* __restrict__ g, T* rho,
-                                                    Consts c) {
-  if (g->status) return;
-  const double ox = g->origin[0], oy = g->origin[1], oz = g->origin[2];
-  const double ix = g->inv_h[0], iy = g->inv_h[1], iz = g->inv_h[2];
-  const int64_t n = c.n;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock) {
-    double wx[S + 1], wy[S + 1], wz[S + 1];
-    int bx = stencil<S>((X[i] - ox) * ix, c.nx, wx);
-    int by = stencil<S>((X[2 * n + i] - oy) * iy, c.ny, wy);
-    int bz = stencil<S>((X[4 * n + i] - oz) * iz, c.nz, wz);
-    for (int a = 0; a <= S; ++a)
-      for (int b = 0; b <= S; ++b) {
-        double wzy = wz[a] * wy[b];
-        T* row = rho + ((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + bx;
-        for (int q = 0; q <= S; ++q) atomic_add_grid(row + q, (T)(c.q_macro * (wzy * wx[q])));
-      }
-  }
-}
+// ---------------------------------------------------------------------------- gather
 
 // Field at the particles from E'[3][nz][ny][nx] with the deposit's weights.
 template <int S, typename T>
@@ -501,15 +472,6 @@ hipError_t launch_clear_status(Geom* g, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_deposit(const double* X, const Geom* g, T* rho, Consts c, hipStream_t s) {
-  if (c.shape == 1)
-    hipLaunchKernelGGL((k_deposit<1, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, rho, c);
-  else
-    hipLaunchKernelGGL((k_deposit<2, T>), dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, g, rho, c);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_gather(const double* X, const Geom* g, const T* E, T* Ep, Consts c,
                          hipStream_t s) {
   if (c.shape == 1)
@@ -606,8 +568,6 @@ hipError_t launch_zero(T* p, int64_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_deposit<double>(const double*, const Geom*, double*, Consts, hipStream_t);
-template hipError_t launch_deposit<float>(const double*, const Geom*, float*, Consts, hipStream_t);
 template hipError_t launch_gather<double>(const double*, const Geom*, const double*, double*,
                                           Consts, hipStream_t);
 template hipError_t launch_gather<float>(const double*, const Geom*, const float*, float*, Consts,

@@ -72,3 +72,18 @@ def test_batch_runs_give_the_same_bits(lib):
         out.append([b.X.clone() for b in beams])
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("grid_fp32", [False, True])
+def test_pic_deposit_gives_the_same_bits(lib, grid_fp32):
+    cfg = workloads.SMALL
+    n, nodes, shape = 50_003, (24, 18, 36), 2
+    xi = torch.from_numpy(workloads.draw_xi(cfg, n=n)).cuda()
+    b = _beam(lib, cfg, n, nodes, shape, xi, grid_fp32=grid_fp32)
+    r1 = b.deposit().clone()
+    # a different particle order gives the same charge grid, bit for bit
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(5)).cuda()
+    b2 = _beam(lib, cfg, n, nodes, shape, xi[:, perm].contiguous(), grid_fp32=grid_fp32)
+    r2 = b2.deposit().clone()
+    assert torch.equal(r1, b.deposit())
+    assert torch.equal(r1, r2)
