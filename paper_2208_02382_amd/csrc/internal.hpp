@@ -178,15 +178,14 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
 hipError_t launch_bin_perm(const double* A, const Geom* g, Consts c, const SortPlan& sp,
                            uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
                            uint32_t* nchunks, uint32_t* perm, hipStream_t s);
-// perm == nullptr: B is in slot order; else slot i reads particle perm[i] of B.  tacc (with
-// tscale): the deterministic form, each tile's window summed exactly as integers in tacc
-// (ntiles * (T+S)^3 64-bit entries, all zero on entry and left zero) and the grid formed from
-// them in a fixed order; nullptr: windows added to rho with float atomics.
+// perm == nullptr: B is in slot order; else slot i reads particle perm[i] of B.  Each tile's
+// window is summed exactly as integers in tacc (ntiles * (T+S)^3 64-bit entries, all zero on
+// entry and left zero; tscale: kMaxTiles exponents) and the grid rho (zeroed by the caller) is
+// formed from them in a fixed order.
 template <typename T>
 hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geom* g, Consts c,
                                 const SortPlan& sp, const int4* chunks, const uint32_t* nchunks,
-                                T* rho, hipStream_t s, unsigned long long* tacc = nullptr,
-                                int* tscale = nullptr);
+                                T* rho, hipStream_t s, unsigned long long* tacc, int* tscale);
 // perm == nullptr: B in slot order, updated in place (src, idsrc, iddst unused); else slot i
 // reads particle perm[i] of src and id idsrc[perm[i]], and writes slot i of B and iddst
 // (src != B, idsrc != iddst).  diag_out != nullptr: the moments (kMomentSlots doubles) of the

@@ -376,19 +376,17 @@ __device__ __forceinline__ void add_global(T* p, T v) {
 }
 
 // Charge of one chunk in its tile's (T + S)^3 window, accumulated in LDS as 64-bit fixed point:
-// every contribution q_m w is scaled by a power of two 2^k chosen so that the chunk's whole
-// charge |q_m| * count stays below 2^62 (no overflow in any node, whatever the order) and a
-// single contribution below 2^50, rounded to the nearest integer (error below
-// max(2^-62 count, 2^-50) |q_m|, about 2e-15 |q_m| for a full chunk) and added with integer
-// LDS atomics, which are exact, so the window sum does not depend on the order of the lanes.  Integer LDS atomics also run faster here than
-// floating-point ones (1.13 ms against 1.85 ms with float64 and 13 ms with float32 atomics
-// for 1e8 TSC particles on MI355X).  The window is then scaled back (exactly, by 2^-k),
-// converted to T and added to the grid with one global float atomic per non-zero node.
-// With tacc (the binned tracking loop), the scale is the tile's (from the tile's whole count,
-// the same for all its chunks) and the non-zero window entries are added, still as integers,
-// to the tile's own window in tacc (tacc[t nw + w], one 64-bit integer atomic each, exact in
-// any order); the tile's exponent goes to tscale[t], and k_tile_reduce forms the grid.  The
-// charge grid then does not depend on the order of the particles or of the atomics.
+// every contribution q_m w is scaled by a power of two 2^k chosen from the whole charge of the
+// chunk's tile, |q_m| * count_tile 2^k <= 2^62 (no overflow in any node, whatever the order;
+// the same k for all chunks of the tile), with a single contribution below 2^50, rounded to
+// the nearest integer (error below 2^-(k+1) |q_m|) and added with integer LDS atomics, which
+// are exact, so the window sum does not depend on the order of the lanes.  Integer LDS atomics
+// also run faster here than floating-point ones (1.13 ms against 1.85 ms with float64 and 13 ms
+// with float32 atomics for 1e8 TSC particles on MI355X).  The non-zero window entries are then
+// added, still as integers, to the tile's own window in tacc (tacc[t nw + w], one 64-bit
+// integer atomic each, exact in any order); the tile's exponent goes to tscale[t], and
+// k_tile_reduce forms the grid, which then depends neither on the order of the particles nor
+// on that of the atomics.
 template <int S, typename T>
 __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
                                                         const uint32_t* __restrict__ perm,
@@ -397,8 +395,8 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
                                                         const int4* __restrict__ chunks,
                                                         const uint32_t* __restrict__ nchunks,
                                                         T* __restrict__ rho, int blk, int nblk,
-                                                        unsigned long long* __restrict__ tacc = nullptr,
-                                                        int* __restrict__ tscale = nullptr) {
+                                                        unsigned long long* __restrict__ tacc,
+                                                        int* __restrict__ tscale) {
   extern __shared__ unsigned char smem_raw[];
   unsigned long long* win = reinterpret_cast<unsigned long long*>(smem_raw);
   if (g->status) return;
@@ -419,10 +417,10 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     // scale 2^k with |q_m| * count * 2^k <= 2^62 (no node overflows) and |q_m| 2^k <= 2^50
     // (every scaled contribution converts exactly below); a zero charge gives zero
     const double qa = fabs(c.q_macro);
-    const double qc = qa * (double)(tacc ? ch.w : ch.z - ch.y);
+    const double qc = qa * (double)ch.w;  // the tile's particle count
     const int k = qc > 0.0 ? min(62 - max(ilogb(qc) + 1, -960), 50 - max(ilogb(qa) + 1, -960)) : 0;
-    const double qs = c.q_macro * ldexp(1.0, k), unscale = ldexp(1.0, -k);
-    if (tacc && threadIdx.x == 0) tscale[t] = k;  // every chunk of the tile writes the same k
+    const double qs = c.q_macro * ldexp(1.0, k);
+    if (threadIdx.x == 0) tscale[t] = k;  // every chunk of the tile writes the same k
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) win[w] = 0ull;
     __syncthreads();
     for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
@@ -472,12 +470,8 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
       const long long v = (long long)win[w];
       int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
-      if (v != 0 && gx < c.nx && gy < c.ny && gz < c.nz) {
-        if (tacc)
-          atomicAdd(&tacc[(int64_t)t * nw + w], (unsigned long long)v);
-        else
-          add_global(&rho[((int64_t)gz * c.ny + gy) * c.nx + gx], (T)((double)v * unscale));
-      }
+      if (v != 0 && gx < c.nx && gy < c.ny && gz < c.nz)
+        atomicAdd(&tacc[(int64_t)t * nw + w], (unsigned long long)v);
     }
     __syncthreads();
   }
@@ -1221,7 +1215,7 @@ hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geo
   const int S = c.shape;
   size_t lds = sizeof(unsigned long long) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
   const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
-  if (tacc && !tscale) return hipErrorInvalidValue;
+  if (!tacc || !tscale) return hipErrorInvalidValue;
   const int64_t nodes = (int64_t)c.nx * c.ny * c.nz;
   int rb = (int)((nodes + 255) / 256);
   if (rb > 16384) rb = 16384;
