@@ -83,7 +83,7 @@ pic_status check_desc(const pic_beam_desc* d) {
     window *= t + d->shape;
   }
   if (ntiles > kMaxTiles) return fail(PIC_EINVAL, "tile count must be <= 4096");
-  // the deposit's charge window of a tile lives in LDS (64 KB per workgroup)
+  // the deposit's charge window of a tile lives in LDS (156 KB per workgroup)
   if (window > (int64_t)kMaxLdsBytes) return fail(PIC_EINVAL, "tile charge window exceeds the 156 KB of LDS a workgroup may use");
   if (d->chunk != 0 && (d->chunk < 256 || d->chunk > (1 << 20)))
     return fail(PIC_EINVAL, "chunk must be 0 or 256..2^20");

@@ -31,10 +31,10 @@ def _problem(cfg, n, nodes, shape):
                              nodes, shape)
 
 
-def _start(lib, cfg, n, nodes, shape, seed=None, space_charge=True):
+def _start(lib, cfg, n, nodes, shape, seed=None, space_charge=True, tuning=None):
     xi = workloads.draw_xi(cfg, n=n, seed=seed)
     b = lib.Beam(n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, shape, nodes,
-                 space_charge=space_charge)
+                 space_charge=space_charge, tuning=tuning)
     b.init_from_normals(cfg.sigma_matrix, torch.from_numpy(xi).cuda())
     return b, opic.init_from_normals(cfg.sigma_matrix, xi)
 
@@ -138,12 +138,15 @@ def _diag_oracle(X, elements, steps, prob, space_charge=True):
     return X, np.array(out)
 
 
-@pytest.mark.parametrize("space_charge", [True, False])
-def test_slice_step_diagnostics(lib, space_charge):
+@pytest.mark.parametrize("space_charge,tuning", [(True, None), (False, None),
+                                                 (True, {"tile": (16, 16, 12)})])
+def test_slice_step_diagnostics(lib, space_charge, tuning):
+    # the third case's field window (18 x 18 x 14 nodes, 109 KB in float64) fits; a tile of
+    # (16, 16, 16) would not, see the next test
     cfg = workloads.SMALL
     n, nodes, shape, steps = 5_000, (16, 16, 16), 2, 30
-    b, X = _start(lib, cfg, n, nodes, shape, space_charge=space_charge)
-    b2, _ = _start(lib, cfg, n, nodes, shape, space_charge=space_charge)
+    b, X = _start(lib, cfg, n, nodes, shape, space_charge=space_charge, tuning=tuning)
+    b2, _ = _start(lib, cfg, n, nodes, shape, space_charge=space_charge, tuning=tuning)
     diag = b.track(workloads.THICK_FODO, steps, diagnostics=True).cpu().numpy()
     b2.track(workloads.THICK_FODO, steps)
     assert diag.shape == (steps, 27)
@@ -176,3 +179,19 @@ def test_slice_step_diagnostics_of_an_offset_beam(lib, offset_sigmas):
     rms = np.sqrt(np.diag(np.cov(X)))
     assert np.all(np.abs(diag[:, :6] - do[:, :6]) / rms < TOL)
     assert np.abs(diag[:, 6:] - do[:, 6:]).max() < TOL * np.abs(do[:, 6:]).max()
+
+
+def test_slice_step_diagnostics_with_the_unbinned_gather(lib):
+    # a (24, 18, 18) tile needs a 250 KB field window, beyond LDS: the gather-kick runs
+    # unbinned, stops at the end of the step, and separate passes take the moments and apply
+    # the next first half map
+    cfg = workloads.SMALL
+    n, nodes, shape, steps = 4_001, (24, 18, 36), 2, 14
+    tun = {"tile": (24, 18, 18)}
+    b, X = _start(lib, cfg, n, nodes, shape, tuning=tun)
+    diag = b.track(workloads.THICK_FODO, steps, diagnostics=True).cpu().numpy()
+    Xo, do = _diag_oracle(X, workloads.THICK_FODO, steps, _problem(cfg, n, nodes, shape))
+    rms = np.sqrt(np.diag(np.cov(Xo)))
+    assert np.all(np.abs(diag[:, :6] - do[:, :6]) / rms < TOL)
+    assert np.abs(diag[:, 6:] - do[:, 6:]).max() < TOL * np.abs(do[:, 6:]).max()
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL

@@ -22,6 +22,7 @@ def lib():
     {"tile": (24, 18, 9), "blocks": 3},                 # a few large tiles (137 KB field window)
     {"tile": (12, 9, 18), "threads": 1024, "chunk": 512},  # wide workgroups
     {"threads": 64, "blocks": 5},                       # one wave per workgroup
+    {"tile": (24, 18, 18)},    # field window beyond LDS (250 KB): the unbinned gather-kick
 ])
 def test_launch_shapes_keep_parity(lib, tuning):
     cfg = workloads.SMALL
