@@ -19,9 +19,13 @@ in the second derivative only).  The adjoint of each linear operation is its tra
                                lam_r,i += q_m sum_n grad W(r_i - r_n) chi_n
   grad W is taken with respect to the lab position (du/dx = 1/h).
 
+* thick quadrupole half map M(k) per plane: lam <- M^T lam; dJ/dk += lam_after . (dM/dk) X_before
+  (adjoint_elements, lattices of Drift / Quad / thin elements cut into slices)
+
 Pinned by tests/test_oracle_adjoint.py: dot-product tests of every transposed operation,
-central finite differences on small beams with space charge, and the closed-form gradient of
-the zero-current (linear) map.
+central finite differences on small beams with space charge (thin lattices and lattices of
+thick elements), the closed-form gradient of the zero-current (linear) map, and the
+k-derivative of the quadrupole matrix against central differences and its k -> 0 limit.
 """
 import numpy as np
 
@@ -211,6 +215,106 @@ def adjoint(X0, ks, dss, n_steps, prob, w, geoms=None, space_charge=True):
         lam = quad_T(lam, K)
     geoms_out = [r[2] for r in rec]
     return objective(XN, w), dk, lam, geoms_out
+
+
+# ----------------------------------------------------------------------------- lattices of elements
+
+def _half_T(lam, kind, k, ell, prob):
+    """Transpose of half_map(., kind, k, ell) (drift, or the quadrupole matrix per plane with
+    the longitudinal drift) applied to lam."""
+    if kind != pic.QUAD:
+        return drift_T(lam, 0.5 * ell, prob)
+    Mx, My = pic.quad_matrix(k, 0.5 * ell), pic.quad_matrix(-k, 0.5 * ell)
+    out = lam.copy()
+    out[0] = Mx[0, 0] * lam[0] + Mx[1, 0] * lam[1]
+    out[1] = Mx[0, 1] * lam[0] + Mx[1, 1] * lam[1]
+    out[2] = My[0, 0] * lam[2] + My[1, 0] * lam[3]
+    out[3] = My[0, 1] * lam[2] + My[1, 1] * lam[3]
+    out[5] = lam[5] + 0.5 * ell * lam[4] / (prob.gamma * prob.gamma)
+    return out
+
+
+def _quad_dk(lam, X, k, ell):
+    """sum over particles of lam . (d/dk of the half quadrupole map) X: the x plane sees
+    quad_matrix(k), the y plane quad_matrix(-k), whose k-derivative is -quad_matrix_dk(-k)."""
+    Dx = pic.quad_matrix_dk(k, 0.5 * ell)
+    Dy = -pic.quad_matrix_dk(-k, 0.5 * ell)
+    return float(np.sum(lam[0] * (Dx[0, 0] * X[0] + Dx[0, 1] * X[1]) +
+                        lam[1] * (Dx[1, 0] * X[0] + Dx[1, 1] * X[1]) +
+                        lam[2] * (Dy[0, 0] * X[2] + Dy[0, 1] * X[3]) +
+                        lam[3] * (Dy[1, 0] * X[2] + Dy[1, 1] * X[3])))
+
+
+def _slices_indexed(elements):
+    """pic.slices with the index of the element each slice belongs to."""
+    out = []
+    for e, el in enumerate(elements):
+        out.extend((kind, k, ell, e) for kind, k, ell in pic.slices([el]))
+    return out
+
+
+def forward_elements(X0, elements, n_steps, prob, geoms=None, space_charge=True):
+    """Tracking as pic.track_elements (one slice per step, cycled), optionally with frozen
+    per-step geometries.  Per step: (state at the start, after the first half map, after the
+    kick, geometry, E' grid, Gbar)."""
+    sl = _slices_indexed(elements)
+    rec = []
+    X = X0
+    for j in range(n_steps):
+        kind, k, ell, _ = sl[j % len(sl)]
+        if kind == pic.THIN:
+            X1 = pic.drift(pic.thin_quad(X, k), 0.5 * ell, prob)
+        else:
+            X1 = pic.half_map(X, kind, k, ell, prob)
+        if space_charge:
+            geom = geoms[j] if geoms is not None else pic.geometry(X1, prob)
+            gbar = pic.green(geom, prob)
+            E = pic.field(pic.solve(pic.deposit(X1, geom, prob), gbar), geom)
+            X2 = pic.kick(X1, pic.gather(E, X1, geom, prob), ell, prob)
+        else:
+            geom = E = gbar = None
+            X2 = X1
+        rec.append((X, X1, X2, geom, E, gbar))
+        X = pic.drift(X2, 0.5 * ell, prob) if kind == pic.THIN else \
+            pic.half_map(X2, kind, k, ell, prob)
+    return X, rec
+
+
+def adjoint_elements(X0, elements, n_steps, prob, w, geoms=None, space_charge=True):
+    """(J, dJ/dk per element (len(elements),), dJ/dX0, per-step geometries) for a lattice of
+    (kind, k, ds, nslice) elements.  A quadrupole's strength enters both half maps of each of
+    its slices: dJ/dk gets lam_after . (dM/dk) X_before for each.  A thin element's as in
+    adjoint; drifts have no strength."""
+    XN, rec = forward_elements(X0, elements, n_steps, prob, geoms, space_charge)
+    lam = objective_grad(XN, w)
+    sl = _slices_indexed(elements)
+    dk = np.zeros(len(elements))
+    for j in range(n_steps - 1, -1, -1):
+        kind, k, ell, e = sl[j % len(sl)]
+        Xs, X1, X2, geom, E, gbar = rec[j]
+        # second half map X2 -> X_{j+1}
+        if kind == pic.QUAD:
+            dk[e] += _quad_dk(lam, X2, k, ell)
+        lam = _half_T(lam, kind, k, ell, prob)
+        if space_charge:
+            A = np.stack([prob.C * ell * lam[1], prob.C * ell * lam[3],
+                          prob.gamma * prob.C * ell * lam[5]])
+            direct = grad_gather_dot(E, A, X1, geom, prob)
+            eg = vector_deposit(A, X1, geom, prob)
+            chi = solve_ghost_source(divergence_T(eg, geom), gbar)
+            via_rho = prob.q_macro * grad_gather(chi, X1, geom, prob)
+            for c, row in enumerate((0, 2, 4)):
+                lam[row] = lam[row] + direct[c] + via_rho[c]
+        # first half map Xs -> X1
+        if kind == pic.THIN:
+            lam = drift_T(lam, 0.5 * ell, prob)
+            dk[e] += float(np.sum(-Xs[0] * lam[1] + Xs[2] * lam[3]))
+            lam = quad_T(lam, k)
+        else:
+            if kind == pic.QUAD:
+                dk[e] += _quad_dk(lam, Xs, k, ell)
+            lam = _half_T(lam, kind, k, ell, prob)
+    return objective(XN, w), dk, lam, [r[3] for r in rec]
 
 
 def cholesky_grad(L, xi, lamX0):

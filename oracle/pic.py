@@ -289,6 +289,37 @@ def quad_matrix(k, s):
     return np.array([[1.0, s], [0.0, 1.0]])
 
 
+def quad_matrix_dk(k, s):
+    """Derivative with respect to k of quad_matrix(k, s), entry by entry: from the closed forms
+    (d/dk cos(sqrt(k) s) = -s sin(sqrt(k) s) / (2 sqrt k), ...) for |k| s^2 >= 0.1, else from
+    the power series in k of cos(sqrt(k) s), sin(sqrt(k) s)/sqrt(k) and -sqrt(k) sin(sqrt(k) s),
+    which hold for either sign of k (the closed forms cancel badly near k = 0)."""
+    if abs(k) * s * s >= 0.1:
+        if k > 0:
+            r = np.sqrt(k)
+            c, sn = np.cos(r * s), np.sin(r * s)
+            dc = -s * sn / (2.0 * r)
+            return np.array([[dc, s * c / (2.0 * k) - sn / (2.0 * r ** 3)],
+                             [-sn / (2.0 * r) - 0.5 * s * c, dc]])
+        r = np.sqrt(-k)
+        c, sn = np.cosh(r * s), np.sinh(r * s)
+        dc = -s * sn / (2.0 * r)
+        return np.array([[dc, s * c / (2.0 * k) + sn / (2.0 * r ** 3)],
+                         [-sn / (2.0 * r) - 0.5 * s * c, dc]])
+    # cos = sum_m (-k)^m s^2m/(2m)!, sin/sqrt(k) = sum_m (-k)^m s^(2m+1)/(2m+1)!,
+    # -sqrt(k) sin = -sum_m (-1)^m k^(m+1) s^(2m+1)/(2m+1)!: differentiate term by term
+    d00 = d01 = d10 = 0.0
+    fact = [1.0]
+    for q in range(1, 40):
+        fact.append(fact[-1] * q)
+    for m in range(1, 16):
+        d00 += m * (-1) ** m * k ** (m - 1) * s ** (2 * m) / fact[2 * m]
+        d01 += m * (-1) ** m * k ** (m - 1) * s ** (2 * m + 1) / fact[2 * m + 1]
+    for m in range(0, 16):
+        d10 -= (m + 1) * (-1) ** m * k ** m * s ** (2 * m + 1) / fact[2 * m + 1]
+    return np.array([[d00, d01], [d10, d00]])
+
+
 def thick_quad(X, k, s, prob: Problem):
     """Quadrupole map over length s; the longitudinal plane drifts (z += s delta / gamma^2)."""
     Mx, My = quad_matrix(k, s), quad_matrix(-k, s)

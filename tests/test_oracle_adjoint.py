@@ -168,3 +168,70 @@ def test_sigma0_gradient_through_the_cholesky_factor():
         E[a, b] = E[b, a] = 1.0
         fd = (J_of(S0 + h * E) - J_of(S0 - h * E)) / (2 * h)
         assert abs(fd - G[a, b]) < 1e-5 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("k", [1.3, -0.7, 0.02, -1e-9, 0.0])
+def test_quad_matrix_k_derivative(k):
+    # against central differences of the matrix itself (series branch for |k| s^2 < 0.1)
+    s = 0.45
+    D = pic.quad_matrix_dk(k, s)
+    h = 1e-5
+    fd = (pic.quad_matrix(k + h, s) - pic.quad_matrix(k - h, s)) / (2 * h) if k != 0.0 else \
+        (pic.quad_matrix(h, s) - pic.quad_matrix(-h, s)) / (2 * h)
+    assert np.abs(D - fd).max() < 1e-8
+    if k == 0.0:   # the limit of the closed forms: [[-s^2/2, -s^3/6], [-s, -s^2/2]]
+        assert np.allclose(D, [[-s * s / 2, -s ** 3 / 6], [-s, -s * s / 2]], rtol=1e-15, atol=0)
+    # the two branches meet at |k| s^2 = 0.1
+    kb = 0.1 / (s * s)
+    for sg in (1, -1):
+        a = pic.quad_matrix_dk(sg * kb * (1 + 1e-12), s)
+        b = pic.quad_matrix_dk(sg * kb * (1 - 1e-12), s)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+THICK = [(pic.DRIFT, 0.0, 0.3, 2), (pic.QUAD, 1.4, 0.6, 3), (pic.THIN, -0.6, 0.4, 1),
+         (pic.QUAD, -1.1, 0.5, 2)]
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_thick_lattice_adjoint_matches_central_differences(shape):
+    n, steps = 300, 9
+    prob = _prob(nodes=(12, 10, 12), shape=shape, n=n)
+    X0 = _beam(n, seed=9)
+    J, dk, lam0, geoms = adj.adjoint_elements(X0, THICK, steps, prob, W4)
+
+    def J_of(els, X_=X0):
+        XN, _ = adj.forward_elements(X_, els, steps, prob, geoms=geoms)
+        return adj.objective(XN, W4)
+
+    assert abs(J_of(THICK) - J) < 1e-15 * abs(J)
+    # the same tracking as pic.track_elements when the geometry is not frozen
+    XN, _ = adj.forward_elements(X0, THICK, steps, prob)
+    assert np.array_equal(XN, pic.track_elements(X0, THICK, steps, prob))
+    assert dk[0] == 0.0                      # a drift has no strength
+    for e in (1, 2, 3):
+        h = 1e-6 * abs(THICK[e][1])
+
+        def shifted(t, e=e):
+            els = list(THICK)
+            kind, k, ds, ns = els[e]
+            els[e] = (kind, k + t, ds, ns)
+            return J_of(els)
+
+        fd = _fd(shifted, 0.0, h)
+        assert abs(fd - dk[e]) < 1e-6 * np.abs(dk).max(), e
+    D = np.random.default_rng(10).standard_normal(X0.shape) * X0.std(axis=1)[:, None]
+    fd = _fd(lambda t: J_of(THICK, X0 + t * D), 0.0, 1e-6)
+    assert abs(fd - np.sum(lam0 * D)) < 1e-6 * abs(np.sum(lam0 * D)) + 1e-12 * abs(J)
+
+
+def test_thin_elements_reduce_to_the_thin_sweep():
+    n, steps = 250, 5
+    prob = _prob(n=n)
+    X0 = _beam(n, seed=11)
+    ks = np.array([1.0, -0.8])
+    dss = np.array([0.5, 0.4])
+    J, dk, lam0, _ = adj.adjoint(X0, ks, dss, steps, prob, W4)
+    J2, dk2, lam2, _ = adj.adjoint_elements(X0, [(pic.THIN, k, d, 1) for k, d in zip(ks, dss)],
+                                            steps, prob, W4)
+    assert J2 == J and np.array_equal(dk2, dk) and np.array_equal(lam2, lam0)
