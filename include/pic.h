@@ -257,15 +257,18 @@ size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt
  * On entry X holds X0; on return X holds the final state (the forward pass, run in the
  * caller's particle order) and
  *   out_m[4]     (sigma_x, sigma_y, eps_x, eps_y) of the final state (host),
- *   dJ_dk[n_el]  dJ/dk of the lattice strengths, summed over the steps that use each (host),
+ *   dJ_dk[n_el]  dJ/dk of the lattice strengths, summed over the steps (slices) that use each:
+ *                a thin element's k [1/m] enters its quad kick, a quadrupole's k [1/m^2] both
+ *                half maps of each of its slices; drifts get 0 (host),
  *   d_lam        dJ/dX0, device array of 6*n doubles in the layout of X,
  *   dJ_dL[36]    if d_xi (device, 6*n draws with X0 = L xi) is given: dJ/dL = sum_i lam_i xi_i^T,
  *                row-major 6x6 (host); only the lower triangle is a parameter of L.
  * The forward states are checkpointed every ckpt_every steps in the caller's workspace
  * d_adj_work (pic_adjoint_workspace_bytes, 256-byte aligned) and recomputed per segment.
- * Needs desc.space_charge = 1, 1 <= n_el <= 1024 and a thin-lens lattice (PIC_ELEM_THIN
- * elements only; PIC_EUNSUPPORTED otherwise).  Synchronises `stream`; returns the device
- * error flag of any step (PIC_EDOMAIN). */
+ * Lattices as for pic_track_n_steps (thin, drift and quadrupole elements, one step per slice).
+ * Needs desc.space_charge = 1, desc.direct_field = 0 (PIC_EUNSUPPORTED) and
+ * 1 <= n_el <= 1024.  Synchronises `stream`; returns the device error flag of any step
+ * (PIC_EDOMAIN). */
 pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              int ckpt_every, const double w[4], void* d_adj_work,
                              size_t adj_work_bytes, double* d_lam, const double* d_xi,

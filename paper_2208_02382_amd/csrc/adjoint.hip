@@ -1,18 +1,20 @@
 // Reverse sweep (discrete adjoint) of the tracking loop.
 //
 // Gradients of J = w . (sigma_x, sigma_y, eps_x, eps_y) of the final beam with respect to the
-// thin-quad strengths, the initial coordinates and (given the draws xi of X0 = L xi) the
-// Cholesky factor L.  The grid geometry of every step is frozen to the forward run's.  Each
-// linear operation is replaced by its transpose:
+// lattice elements' strengths, the initial coordinates and (given the draws xi of X0 = L xi)
+// the Cholesky factor L.  The grid geometry of every step is frozen to the forward run's.  Each
+// linear operation is replaced by its transpose (apply_half_T for the half maps):
 //   drift l          lam_px += l lam_x, lam_py += l lam_y, lam_delta += (l/gamma^2) lam_z
 //   thin quad k      lam_x -= k lam_px, lam_y += k lam_py;  dJ/dk += sum(-x lam_px + y lam_py)
+//   quadrupole half map M(k) per plane: lam <- M^T lam;  dJ/dk += sum lam_after . (dM/dk) x_before
+//                    (the second half map's term from the state after it, as dM/dk M^-1 x_after)
 //   kick over L      a_i = (C L lam_px, C L lam_py, gamma C L lam_delta)
 //                    lam_r,i += sum_n grad W(r_i - r_n) (a_i . E'_n)            (k_adj_b, direct)
 //                    e = sum_i W a_i (vector deposit, k_adj_a); psi = -sum_c D_c^T e_c on nodes
 //                    -1..n (k_adj_div); chi = Gbar * psi / (4 pi eps0) on nodes 0..n-1
 //                    (transposed solve, fft.hip); lam_r,i += q_m sum_n grad W(r_i - r_n) chi_n
 // The kick-point positions are rebuilt from the stored step-start state with the same
-// expressions as the forward kernels (thin quad, then half drift).
+// expressions as the forward kernels (the slice's first half map).
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -38,15 +40,52 @@ __device__ __forceinline__ int stencil_d(double u, int n, double* w, double* dw)
   return b;
 }
 
-// kick-point position of a step-start state: thin quad k, then drift l = L/2 (positions only)
+// kick-point position of a step-start state: the slice's first half map (positions kept)
 __device__ __forceinline__ void kick_point(const double* __restrict__ X, int64_t n, int64_t i,
-                                          double k, double ell, double inv_g2, double r[3]) {
-  const double x = X[i], px = X[n + i], y = X[2 * n + i], py = X[3 * n + i];
-  const double z = X[4 * n + i], d = X[5 * n + i];
-  const double px1 = px - k * x, py1 = py + k * y;
-  r[0] = x + ell * px1;
-  r[1] = y + ell * py1;
-  r[2] = z + ell * d * inv_g2;
+                                          const HalfMap& first, double inv_g2, double r[3]) {
+  double v[6];
+  for (int q = 0; q < 6; ++q) v[q] = X[q * n + i];
+  apply_half(first, v, inv_g2);
+  r[0] = v[0];
+  r[1] = v[2];
+  r[2] = v[4];
+}
+
+// lam . (D x) summed over the (x, px) and (y, py) planes, D row-major per plane
+__device__ __forceinline__ double plane_form(const double lm[4], const double* Dx,
+                                             const double* Dy, const double v[4]) {
+  return lm[0] * (Dx[0] * v[0] + Dx[1] * v[1]) + lm[1] * (Dx[2] * v[0] + Dx[3] * v[1]) +
+         lm[2] * (Dy[0] * v[2] + Dy[1] * v[3]) + lm[3] * (Dy[2] * v[2] + Dy[3] * v[3]);
+}
+
+// one partial per block of a per-thread sum (blockDim.x == kBlk)
+__device__ __forceinline__ void block_partial(double acc, double* __restrict__ partial) {
+  __shared__ double sh[kBlk / 64];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kBlk / 64; ++q) s += sh[q];
+    partial[blockIdx.x] = s;
+  }
+}
+
+// The second half map's strength term of a quadrupole slice: sum_i lam_i . DG x_next,i with
+// DG = (d second/dk) second^-1 and x_next the state after the slice.
+__global__ __launch_bounds__(kBlk) void k_adj_dk_second(const double* __restrict__ Xn,
+                                                        const double* __restrict__ lam, Consts c,
+                                                        AdjSlice sl,
+                                                        double* __restrict__ dk_partial) {
+  const int64_t n = c.n;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlk) {
+    const double lm[4] = {lam[i], lam[n + i], lam[2 * n + i], lam[3 * n + i]};
+    const double v[4] = {Xn[i], Xn[n + i], Xn[2 * n + i], Xn[3 * n + i]};
+    acc += plane_form(lm, sl.dgx, sl.dgy, v);
+  }
+  block_partial(acc, dk_partial);
 }
 
 template <typename T>
@@ -58,25 +97,23 @@ __device__ __forceinline__ void add_global(T* p, T v) {
 template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
                                                 double* __restrict__ lam,
-                                                const Geom* __restrict__ g, Consts c, double k,
-                                                double L, T* __restrict__ e) {
+                                                const Geom* __restrict__ g, Consts c,
+                                                AdjSlice sl, T* __restrict__ e) {
   if (g->status) return;
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int64_t n = c.n;
   const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
-  const double ell = 0.5 * L;
+  const double L = sl.L;
   for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlk) {
     double r[3];
-    kick_point(X, n, i, k, ell, c.inv_gamma2, r);
-    const double lpx = lam[n + i] + ell * lam[i];
-    const double lpy = lam[3 * n + i] + ell * lam[2 * n + i];
-    const double ld = lam[5 * n + i] + ell * lam[4 * n + i] * c.inv_gamma2;
-    lam[n + i] = lpx;
-    lam[3 * n + i] = lpy;
-    lam[5 * n + i] = ld;
-    const double a[3] = {c.C * L * lpx, c.C * L * lpy, c.gamma * c.C * L * ld};
+    kick_point(X, n, i, sl.first, c.inv_gamma2, r);
+    double lm[6];
+    for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
+    apply_half_T(sl.second, lm, c.inv_gamma2);
+    for (int q = 0; q < 6; ++q) lam[q * n + i] = lm[q];
+    const double a[3] = {c.C * L * lm[1], c.C * L * lm[3], c.gamma * c.C * L * lm[5]};
     double wx[S + 1], wy[S + 1], wz[S + 1];
     const int bx = stencil<S>((r[0] - o[0]) * ih[0], c.nx, wx);
     const int by = stencil<S>((r[1] - o[1]) * ih[1], c.ny, wy);
@@ -95,32 +132,30 @@ __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
   }
 }
 
-// Pass A for the binned vector deposit: lam <- drift_T(lam, L/2), and the particle's kick-point
-// position and a = (C L lam_px, C L lam_py, gamma C L lam_delta) written as the rows
+// Pass A for the binned vector deposit: lam <- (second half map)^T lam, and the particle's
+// kick-point position and a = (C L lam_px, C L lam_py, gamma C L lam_delta) written as the rows
 // (r_x, a_x, r_y, a_y, r_z, a_z) of P, the layout the binning and the tiled deposit read.
 __global__ __launch_bounds__(kBlk) void k_adj_stage(const double* __restrict__ X,
                                                     double* __restrict__ lam,
                                                     const Geom* __restrict__ g, Consts c,
-                                                    double k, double L, double* __restrict__ P) {
+                                                    AdjSlice sl, double* __restrict__ P) {
   if (g->status) return;
   const int64_t n = c.n;
-  const double ell = 0.5 * L;
+  const double L = sl.L;
   for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlk) {
     double r[3];
-    kick_point(X, n, i, k, ell, c.inv_gamma2, r);
-    const double lpx = lam[n + i] + ell * lam[i];
-    const double lpy = lam[3 * n + i] + ell * lam[2 * n + i];
-    const double ld = lam[5 * n + i] + ell * lam[4 * n + i] * c.inv_gamma2;
-    lam[n + i] = lpx;
-    lam[3 * n + i] = lpy;
-    lam[5 * n + i] = ld;
+    kick_point(X, n, i, sl.first, c.inv_gamma2, r);
+    double lm[6];
+    for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
+    apply_half_T(sl.second, lm, c.inv_gamma2);
+    for (int q = 0; q < 6; ++q) lam[q * n + i] = lm[q];
     P[i] = r[0];
-    P[n + i] = c.C * L * lpx;
+    P[n + i] = c.C * L * lm[1];
     P[2 * n + i] = r[1];
-    P[3 * n + i] = c.C * L * lpy;
+    P[3 * n + i] = c.C * L * lm[3];
     P[4 * n + i] = r[2];
-    P[5 * n + i] = c.gamma * c.C * L * ld;
+    P[5 * n + i] = c.gamma * c.C * L * lm[5];
   }
 }
 
@@ -151,27 +186,28 @@ __global__ __launch_bounds__(kBlk) void k_adj_div(const Geom* __restrict__ g,
   }
 }
 
-// Pass B: lam_r += sum grad W (a . E') + q sum grad W chi at the kick point; lam <- drift_T(L/2);
-// dk partial += sum(-x lam_px + y lam_py) at the step start; lam <- quad_T(k).
+// Pass B: lam_r += sum grad W (a . E') + q sum grad W chi at the kick point; then the first
+// half map's strength term (thin: sum(-x lam_px + y lam_py) between the transposed drift and
+// the transposed thin quad; quadrupole: sum lam . (d first/dk) x at the step start) into the
+// block's dk partial, and lam <- (first half map)^T lam.
 template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
                                                 double* __restrict__ lam,
-                                                const Geom* __restrict__ g, Consts c, double k,
-                                                double L, const T* __restrict__ E,
+                                                const Geom* __restrict__ g, Consts c,
+                                                AdjSlice sl, const T* __restrict__ E,
                                                 const T* __restrict__ chi,
                                                 double* __restrict__ dk_partial) {
-  __shared__ double sh[kBlk / 64];
   double acc = 0.0;
   if (g->status == 0) {
     const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
     const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
     const int64_t n = c.n;
     const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
-    const double ell = 0.5 * L;
+    const double L = sl.L;
     for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlk) {
       double r[3];
-      kick_point(X, n, i, k, ell, c.inv_gamma2, r);
+      kick_point(X, n, i, sl.first, c.inv_gamma2, r);
       double lm[6];
       for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
       const double a[3] = {c.C * L * lm[1], c.C * L * lm[3], c.gamma * c.C * L * lm[5]};
@@ -195,26 +231,28 @@ __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
       lm[0] += gx;
       lm[2] += gy;
       lm[4] += gz;
-      // transposed first half drift
-      lm[1] += ell * lm[0];
-      lm[3] += ell * lm[2];
-      lm[5] += ell * lm[4] * c.inv_gamma2;
-      // strength gradient with the step-start positions, then the transposed thin quad
-      const double x = X[i], y = X[2 * n + i];
-      acc += -x * lm[1] + y * lm[3];
-      lm[0] -= k * lm[1];
-      lm[2] += k * lm[3];
+      if (sl.first.type == kHalfThinDrift) {
+        // transposed first half drift, the strength term with the step-start positions, then
+        // the transposed thin quad
+        const double ell = sl.first.ell;
+        lm[1] += ell * lm[0];
+        lm[3] += ell * lm[2];
+        lm[5] += ell * lm[4] * c.inv_gamma2;
+        const double x = X[i], y = X[2 * n + i];
+        acc += -x * lm[1] + y * lm[3];
+        lm[0] -= sl.first.k * lm[1];
+        lm[2] += sl.first.k * lm[3];
+      } else {
+        if (sl.dk_kind == kDkMatrix) {
+          const double v[4] = {X[i], X[n + i], X[2 * n + i], X[3 * n + i]};
+          acc += plane_form(lm, sl.dfx, sl.dfy, v);
+        }
+        apply_half_T(sl.first, lm, c.inv_gamma2);
+      }
       for (int q = 0; q < 6; ++q) lam[q * n + i] = lm[q];
     }
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int q = 0; q < kBlk / 64; ++q) s += sh[q];
-    dk_partial[blockIdx.x] = s;
-  }
+  block_partial(acc, dk_partial);
 }
 
 // dk[slot] += sum of the per-block partials: one wave, lane l sums partials l, l + 64, ...,
@@ -319,19 +357,31 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, double k,
-                        double L, T* e, hipStream_t s) {
-  if (c.shape == 1)
-    hipLaunchKernelGGL((k_adj_a<1, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
-  else
-    hipLaunchKernelGGL((k_adj_a<2, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, e);
+hipError_t launch_adj_dk_second(const double* Xnext, const double* lam, Consts c,
+                                const AdjSlice& sl, double* dk_partial, double* dk,
+                                hipStream_t s) {
+  if (sl.dk_kind != kDkMatrix) return hipSuccess;
+  const int nb = grid_for(c.n);
+  hipLaunchKernelGGL(k_adj_dk_second, dim3(nb), dim3(kBlk), 0, s, Xnext, lam, c, sl, dk_partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, sl.elem);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c, double k,
-                            double L, double* P, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, k, L, P);
+template <typename T>
+hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
+                        const AdjSlice& sl, T* e, hipStream_t s) {
+  if (c.shape == 1)
+    hipLaunchKernelGGL((k_adj_a<1, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, e);
+  else
+    hipLaunchKernelGGL((k_adj_a<2, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c,
+                            const AdjSlice& sl, double* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, P);
   return hipGetLastError();
 }
 
@@ -345,19 +395,18 @@ hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int
 }
 
 template <typename T>
-hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, double k, double L,
-                        const T* E, const T* chi, double* dk_partial, double* dk, int slot,
-                        hipStream_t s) {
+hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, const AdjSlice& sl,
+                        const T* E, const T* chi, double* dk_partial, double* dk, hipStream_t s) {
   const int nb = grid_for(c.n);
   if (c.shape == 1)
-    hipLaunchKernelGGL((k_adj_b<1, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, k, L, E, chi,
+    hipLaunchKernelGGL((k_adj_b<1, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, E, chi,
                        dk_partial);
   else
-    hipLaunchKernelGGL((k_adj_b<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, k, L, E, chi,
+    hipLaunchKernelGGL((k_adj_b<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, E, chi,
                        dk_partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, slot);
+  hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, sl.elem);
   return hipGetLastError();
 }
 
@@ -379,19 +428,19 @@ hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* par
   return hipGetLastError();
 }
 
-template hipError_t launch_adj_a<double>(const double*, double*, const Geom*, Consts, double,
-                                         double, double*, hipStream_t);
-template hipError_t launch_adj_a<float>(const double*, double*, const Geom*, Consts, double,
-                                        double, float*, hipStream_t);
+template hipError_t launch_adj_a<double>(const double*, double*, const Geom*, Consts,
+                                         const AdjSlice&, double*, hipStream_t);
+template hipError_t launch_adj_a<float>(const double*, double*, const Geom*, Consts,
+                                        const AdjSlice&, float*, hipStream_t);
 template hipError_t launch_adj_div<double>(const Geom*, const double*, double*, int, int, int,
                                            hipStream_t);
 template hipError_t launch_adj_div<float>(const Geom*, const float*, float*, int, int, int,
                                           hipStream_t);
-template hipError_t launch_adj_b<double>(const double*, double*, const Geom*, Consts, double,
-                                         double, const double*, const double*, double*, double*,
-                                         int, hipStream_t);
-template hipError_t launch_adj_b<float>(const double*, double*, const Geom*, Consts, double, double,
-                                        const float*, const float*, double*, double*, int,
-                                        hipStream_t);
+template hipError_t launch_adj_b<double>(const double*, double*, const Geom*, Consts,
+                                         const AdjSlice&, const double*, const double*, double*,
+                                         double*, hipStream_t);
+template hipError_t launch_adj_b<float>(const double*, double*, const Geom*, Consts,
+                                        const AdjSlice&, const float*, const float*, double*,
+                                        double*, hipStream_t);
 
 }  // namespace pic

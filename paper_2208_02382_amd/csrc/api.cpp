@@ -517,13 +517,99 @@ AdjLayout adj_layout(const pic_beam_desc* d, int n_steps, int ck) {
   return A;
 }
 
+// d/dk of quad_2x2(k, s), entry by entry: closed forms for |k| s^2 >= 0.1, else the term-by-term
+// derivative of the power series in k of cos(sqrt(k) s), sin(sqrt(k) s)/sqrt(k) and
+// -sqrt(k) sin(sqrt(k) s), valid for either sign of k
+void quad_2x2_dk(double k, double s, double d[4]) {
+  if (std::fabs(k) * s * s >= 0.1) {
+    const double r = std::sqrt(std::fabs(k));
+    if (k > 0) {
+      const double c = std::cos(r * s), sn = std::sin(r * s);
+      d[0] = d[3] = -s * sn / (2.0 * r);
+      d[1] = s * c / (2.0 * k) - sn / (2.0 * r * r * r);
+      d[2] = -sn / (2.0 * r) - 0.5 * s * c;
+    } else {
+      const double c = std::cosh(r * s), sn = std::sinh(r * s);
+      d[0] = d[3] = -s * sn / (2.0 * r);
+      d[1] = s * c / (2.0 * k) + sn / (2.0 * r * r * r);
+      d[2] = -sn / (2.0 * r) - 0.5 * s * c;
+    }
+    return;
+  }
+  // d00 = sum_{m>=1} m (-1)^m k^(m-1) s^2m / (2m)!, d01 likewise with s^(2m+1) / (2m+1)!,
+  // d10 = -sum_{m>=0} (m+1) (-1)^m k^m s^(2m+1) / (2m+1)!
+  double d00 = 0.0, d01 = 0.0, d10 = -s;
+  double f2 = 1.0, f3 = 1.0;  // (2m)!, (2m+1)!
+  double km1 = 1.0;           // k^(m-1)
+  double s2m = 1.0;           // s^2m
+  for (int m = 1; m <= 15; ++m) {
+    f2 *= (2.0 * m - 1.0) * (2.0 * m);
+    f3 *= (2.0 * m) * (2.0 * m + 1.0);
+    s2m *= s * s;
+    const double sgn = (m & 1) ? -1.0 : 1.0;
+    d00 += m * sgn * km1 * s2m / f2;
+    d01 += m * sgn * km1 * s2m * s / f3;
+    d10 -= (m + 1) * sgn * (km1 * k) * s2m * s / f3;
+    km1 *= k;
+  }
+  d[0] = d[3] = d00;
+  d[1] = d01;
+  d[2] = d10;
+}
+
+// the reverse sweep's view of a lattice: one AdjSlice per slice, as expand_lattice cuts it,
+// with the element index and the strength derivatives of the half maps
+pic_status expand_adjoint(const pic_element* lat, int n_el, std::vector<AdjSlice>& out) {
+  std::vector<SliceDev> sl;
+  const pic_status st = expand_lattice(lat, n_el, sl);
+  if (st != PIC_OK) return st;
+  out.clear();
+  size_t j = 0;
+  for (int q = 0; q < n_el; ++q) {
+    const pic_element& e = lat[q];
+    const int count = e.kind == PIC_ELEM_THIN ? 1 : e.nslice;
+    for (int r = 0; r < count; ++r, ++j) {
+      AdjSlice a{};
+      a.first = sl[j].first;
+      a.second = sl[j].second;
+      a.L = sl[j].L;
+      a.elem = q;
+      if (e.kind == PIC_ELEM_THIN) {
+        a.dk_kind = kDkThin;
+      } else if (e.kind == PIC_ELEM_QUAD) {
+        a.dk_kind = kDkMatrix;
+        const double hs = 0.5 * sl[j].L;
+        double dmy[4];
+        quad_2x2_dk(e.k, hs, a.dfx);
+        quad_2x2_dk(-e.k, hs, dmy);
+        for (int t = 0; t < 4; ++t) a.dfy[t] = -dmy[t];  // the y plane sees -k
+        // d(second)/dk (second)^-1 per plane; the 2x2 maps have unit determinant
+        const double* M[2] = {a.second.mx, a.second.my};
+        const double* D[2] = {a.dfx, a.dfy};
+        double* G[2] = {a.dgx, a.dgy};
+        for (int p = 0; p < 2; ++p) {
+          const double inv[4] = {M[p][3], -M[p][1], -M[p][2], M[p][0]};
+          G[p][0] = D[p][0] * inv[0] + D[p][1] * inv[2];
+          G[p][1] = D[p][0] * inv[1] + D[p][1] * inv[3];
+          G[p][2] = D[p][2] * inv[0] + D[p][3] * inv[2];
+          G[p][3] = D[p][2] * inv[1] + D[p][3] * inv[3];
+        }
+      } else {
+        a.dk_kind = kDkNone;
+      }
+      out.push_back(a);
+    }
+  }
+  return PIC_OK;
+}
+
 template <typename T>
-pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_element& e,
+pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const AdjSlice& e,
                                T* gh, T* E, hipStream_t s, Box* box) {
-  // thin quad + half drift (with the box when a geometry is to be computed), deposit, Green
-  // spectrum, solve, kick + half drift; g is the step's geometry slot
+  // the slice's first half map (with the box when a geometry is to be computed), deposit,
+  // Green spectrum, solve, kick and the second half map; g is the step's geometry slot
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
-  HIP_OK(launch_quad_drift(X, e.k, 0.5 * e.ds, b->c, box, s), "adjoint forward");
+  HIP_OK(launch_half_box(X, e.first, b->c, box, s), "adjoint forward");
   if (box) HIP_OK(launch_geometry(box, const_cast<Geom*>(g), b->c, s), "adjoint forward");
   HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "adjoint forward");
   // binned deposit from a tile-sorted copy (XB) of the kick-point state
@@ -538,16 +624,17 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const pic_e
   HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
                          (T*)b->phi, E, s),
          "adjoint forward");
-  HIP_OK(launch_gkd<T>(X, g, E, e.ds, half_drift(0.5 * e.ds), 0, half_drift(0.0), b->c, box, s),
+  HIP_OK(launch_gkd<T>(X, g, E, e.L, e.second, 0, half_drift(0.0), b->c, box, s),
          "adjoint forward");
   return PIC_OK;
 }
 
 template <typename T>
-pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_steps, int ck,
-                         const double w[4], char* aw, const AdjLayout& A, double* lam,
+pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, int n_steps,
+                         int ck, const double w[4], char* aw, const AdjLayout& A, double* lam,
                          const double* xi, double out_m[4], double* dJ_dk, double dJ_dL[36],
                          hipStream_t s) {
+  const size_t nsl = sl.size();
   const size_t n = (size_t)b->d.n;
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   const size_t G3 = (size_t)(b->d.nx + 1) * (b->d.ny + 1) * (b->d.nz + 1);
@@ -576,7 +663,7 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
                             hipMemcpyDeviceToDevice, s),
              "adjoint checkpoint");
     HIP_OK(launch_box_reset(b->box, s), "adjoint forward");
-    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), lat[j % n_el], (T*)b->Gh, (T*)b->E,
+    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), sl[j % nsl], (T*)b->Gh, (T*)b->E,
                                            s, b->box);
     if (st != PIC_OK) return st;
   }
@@ -594,32 +681,39 @@ pic_status track_adjoint(pic_beam b, const pic_element* lat, int n_el, int n_ste
       HIP_OK(hipMemcpyAsync(segX + 6 * n * (size_t)q, XW, 6 * sizeof(double) * n,
                             hipMemcpyDeviceToDevice, s),
              "adjoint recompute");
-      pic_status st = forward_step_frozen<T>(b, XW, geom(j), lat[j % n_el], segG + G3 * (size_t)q,
+      pic_status st = forward_step_frozen<T>(b, XW, geom(j), sl[j % nsl], segG + G3 * (size_t)q,
                                              segE + 3 * ng * (size_t)q, s, nullptr);
       if (st != PIC_OK) return st;
     }
     for (int j = c1 - 1; j >= c0; --j) {
       const int q = j - c0;
-      const pic_element& el = lat[j % n_el];
+      const AdjSlice& el = sl[j % nsl];
       const double* Xs = segX + 6 * n * (size_t)q;
+      // the state after the step: the next stored one, the next segment's checkpoint, or the
+      // final state
+      const double* Xn = j + 1 < c1 ? segX + 6 * n * (size_t)(q + 1)
+                         : j + 1 < n_steps ? ckpt + 6 * n * (size_t)(seg + 1)
+                                           : b->X;
+      HIP_OK(launch_adj_dk_second(Xn, lam, b->c, el, (double*)(aw + A.dk_part), dk, s),
+             "adjoint");
       HIP_OK(launch_zero<T>(e, 3 * ng, s), "adjoint");
       if (vtiles) {
         // kick-point positions and deposit values, tile-sorted, then the binned vector deposit
-        HIP_OK(launch_adj_stage(Xs, lam, geom(j), b->c, el.k, el.ds, P, s), "adjoint");
+        HIP_OK(launch_adj_stage(Xs, lam, geom(j), b->c, el, P, s), "adjoint");
         HIP_OK(launch_bin(P, b->idA, geom(j), b->c, b->sp, b->keys, b->hist, b->cursor,
                           b->chunks, b->nchunks, b->XB, b->idB, true, s),
                "adjoint");
         HIP_OK(launch_vdeposit_tiles<T>(b->XB, geom(j), b->c, b->sp, b->chunks, b->nchunks, e, s),
                "adjoint");
       } else {
-        HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el.k, el.ds, e, s), "adjoint");
+        HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el, e, s), "adjoint");
       }
       HIP_OK(launch_adj_div<T>(geom(j), e, psi, b->d.nx, b->d.ny, b->d.nz, s), "adjoint");
       HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi, b->W,
                                           segG + G3 * (size_t)q, chi, s),
              "adjoint");
-      HIP_OK(launch_adj_b<T>(Xs, lam, geom(j), b->c, el.k, el.ds, segE + 3 * ng * (size_t)q, chi,
-                             (double*)(aw + A.dk_part), dk, j % n_el, s),
+      HIP_OK(launch_adj_b<T>(Xs, lam, geom(j), b->c, el, segE + 3 * ng * (size_t)q, chi,
+                             (double*)(aw + A.dk_part), dk, s),
              "adjoint");
     }
   }
@@ -1012,12 +1106,9 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
     return fail(PIC_EUNSUPPORTED, "the reverse sweep transposes the differenced field only");
   if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
   if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
-  for (int q = 0; q < n_el; ++q)
-    if (lattice[q].kind != PIC_ELEM_THIN)
-      return fail(PIC_EUNSUPPORTED, "the reverse sweep supports thin-lens (PIC_ELEM_THIN) lattices");
-  for (int q = 0; q < n_el; ++q)
-    if (!std::isfinite(lattice[q].k) || !std::isfinite(lattice[q].ds))
-      return fail(PIC_EINVAL, "non-finite lattice element");
+  std::vector<AdjSlice> sl;
+  const pic_status est = expand_adjoint(lattice, n_el, sl);
+  if (est != PIC_OK) return est;
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return fail(PIC_EINVAL, "non-finite objective weight");
   AdjLayout A = adj_layout(&b->d, n_steps, ckpt_every);
@@ -1026,9 +1117,9 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   hipStream_t s = S(stream);
   HIP_OK(clear_tacc(b, s), "clear");
   if (b->d.grid_fp32)
-    return track_adjoint<float>(b, lattice, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
+    return track_adjoint<float>(b, sl, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
                                 d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);
-  return track_adjoint<double>(b, lattice, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
+  return track_adjoint<double>(b, sl, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
                                d_lam, d_xi, out_m, dJ_dk, dJ_dL, s);
 }
 

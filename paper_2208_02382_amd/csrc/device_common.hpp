@@ -65,6 +65,28 @@ __device__ __forceinline__ void apply_half(const HalfMap& h, double v[6], double
   }
 }
 
+// Transpose of apply_half on an adjoint vector lm (rows as v): the transposed matrices per
+// plane and the transposed longitudinal drift; for a thin slice's first half the transposed
+// drift, then the transposed thin quad.
+__device__ __forceinline__ void apply_half_T(const HalfMap& h, double lm[6], double inv_g2) {
+  if (h.type == kHalfMatrix) {
+    const double lx = lm[0], lpx = lm[1], ly = lm[2], lpy = lm[3];
+    lm[0] = h.mx[0] * lx + h.mx[2] * lpx;
+    lm[1] = h.mx[1] * lx + h.mx[3] * lpx;
+    lm[2] = h.my[0] * ly + h.my[2] * lpy;
+    lm[3] = h.my[1] * ly + h.my[3] * lpy;
+    lm[5] = lm[5] + h.mz * lm[4] * inv_g2;
+  } else {
+    lm[1] = lm[1] + h.ell * lm[0];
+    lm[3] = lm[3] + h.ell * lm[2];
+    lm[5] = lm[5] + h.ell * lm[4] * inv_g2;
+    if (h.type == kHalfThinDrift) {
+      lm[0] = lm[0] - h.k * lm[1];
+      lm[2] = lm[2] + h.k * lm[3];
+    }
+  }
+}
+
 // Block-wide min/max of x, y, z, then one atomic per block and axis.
 __device__ __forceinline__ void box_accumulate_block(double lo[3], double hi[3], bool bad, Box* box) {
   __shared__ double slo[3][kBoxBlock / 64], shi[3][kBoxBlock / 64];

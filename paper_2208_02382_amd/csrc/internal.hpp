@@ -93,6 +93,20 @@ struct SliceDev {
   HalfMap first, second;
 };
 
+// A slice as the reverse sweep sees it: its half maps and kick length, the lattice element
+// whose strength it uses (dJ/dk slot), and the strength derivatives of its half maps.
+constexpr int kDkNone = 0;    // no strength (drift)
+constexpr int kDkThin = 1;    // thin quad inside the first half map (kHalfThinDrift)
+constexpr int kDkMatrix = 2;  // quadrupole half maps: d(first)/dk and d(second)/dk (second)^-1
+struct AdjSlice {
+  HalfMap first, second;
+  double L;
+  int elem;
+  int dk_kind;
+  double dfx[4], dfy[4];  // d(first)/dk per plane, row-major (kDkMatrix)
+  double dgx[4], dgy[4];  // d(second)/dk times the inverse of second, per plane (kDkMatrix)
+};
+
 // Per-beam device descriptor of a batch: every batched kernel takes its beam from the grid
 // (blockIdx.y, or blockIdx.z for the two-dimensional FFT passes) and reads this.
 struct BeamDev {
@@ -151,7 +165,6 @@ hipError_t launch_gather(const double* X, const Geom* g, const T* E, T* Ep, Cons
                          hipStream_t s);
 template <typename T>
 hipError_t launch_push(double* X, int kind, double value, const T* Ep, Consts c, hipStream_t s);
-hipError_t launch_quad_drift(double* X, double k, double ell, Consts c, Box* box, hipStream_t s);
 template <typename T>
 hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, const HalfMap& second,
                       int has_next, const HalfMap& first_next, Consts c, Box* box, hipStream_t s);
@@ -203,7 +216,7 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
 // both half maps of a slice without a kick (tracking without space charge)
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
                             hipStream_t s);
-// one half map in place and the box of the new positions
+// one half map in place and (box != nullptr) the box of the new positions
 hipError_t launch_half_box(double* X, const HalfMap& h, Consts c, Box* box, hipStream_t s);
 hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, double* X,
                             uint32_t* keys, uint32_t* hist, uint32_t* cursor, int4* chunks,
@@ -243,11 +256,16 @@ template <typename T>
 hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd, hipStream_t s);
 
 // ---- adjoint.hip
+// dk[sl.elem] += sum_i lam_i . DG Xnext_i (the second half map's strength derivative, from the
+// state after it), for quadrupole slices; no-op otherwise
+hipError_t launch_adj_dk_second(const double* Xnext, const double* lam, Consts c,
+                                const AdjSlice& sl, double* dk_partial, double* dk,
+                                hipStream_t s);
 template <typename T>
-hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c, double k,
-                        double L, T* e, hipStream_t s);
-hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c, double k,
-                            double L, double* P, hipStream_t s);
+hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
+                        const AdjSlice& sl, T* e, hipStream_t s);
+hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c,
+                            const AdjSlice& sl, double* P, hipStream_t s);
 // binned vector deposit; hipErrorInvalidConfiguration if the three windows exceed 64 KB
 template <typename T>
 hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
@@ -257,9 +275,8 @@ template <typename T>
 hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int nz,
                           hipStream_t s);
 template <typename T>
-hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, double k, double L,
-                        const T* E, const T* chi, double* dk_partial, double* dk, int slot,
-                        hipStream_t s);
+hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, const AdjSlice& sl,
+                        const T* E, const T* chi, double* dk_partial, double* dk, hipStream_t s);
 hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
                            double* lam, double* out_m, hipStream_t s);
 hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* partial, double* out,

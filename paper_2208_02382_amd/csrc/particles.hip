@@ -258,29 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_push(double* __restrict__ X, int kin
   }
 }
 
-// First half of a step: thin quad k then drift l; accumulates the box of the new positions.
-__global__ __launch_bounds__(kBlock) void k_quad_drift(double* __restrict__ X, double k, double ell,
-                                                       Consts c, Box* box) {
-  const int64_t n = c.n;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  bool bad = false;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock) {
-    double v[6];
-    for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
-    thin_quad(v, k);
-    drift(v, ell, c.inv_gamma2);
-    for (int r = 0; r < 6; ++r) X[r * n + i] = v[r];
-    double p[3] = {v[0], v[2], v[4]};
-    for (int a = 0; a < 3; ++a) {
-      bad |= !isfinite(p[a]);
-      lo[a] = fmin(lo[a], p[a]);
-      hi[a] = fmax(hi[a], p[a]);
-    }
-  }
-  if (box) box_accumulate_block(lo, hi, bad, box);
-}
-
 // Fused second half of step j and first half of step j+1: gather E' at the current positions,
 // kick over L, the slice's second half map; if has_next, the next slice's first half map, and
 // accumulate the box of the new positions (the next step's grid).
@@ -487,11 +464,6 @@ hipError_t launch_push(double* X, int kind, double value, const T* Ep, Consts c,
   return hipGetLastError();
 }
 
-hipError_t launch_quad_drift(double* X, double k, double ell, Consts c, Box* box, hipStream_t s) {
-  hipLaunchKernelGGL(k_quad_drift, dim3(grid_for(c.n)), dim3(kBlock), 0, s, X, k, ell, c, box);
-  return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_gkd(double* X, const Geom* g, const T* E, double L, const HalfMap& second,
                       int has_next, const HalfMap& first_next, Consts c, Box* box, hipStream_t s) {
@@ -538,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_half_box(double* __restrict__ X, Hal
       hi[a] = fmax(hi[a], p[a]);
     }
   }
-  box_accumulate_block(lo, hi, bad, box);
+  if (box) box_accumulate_block(lo, hi, bad, box);
 }
 
 hipError_t launch_half_box(double* X, const HalfMap& h, Consts c, Box* box, hipStream_t s) {

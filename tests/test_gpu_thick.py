@@ -119,12 +119,33 @@ def test_batch_with_thin_and_thick_lattices(lib):
         b.close()
 
 
-def test_adjoint_rejects_thick_lattices(lib):
+# drifts, quadrupoles of either sign (one weak enough, |k| (l/2)^2 < 0.1, for the series form
+# of the strength derivative) and a thin element, cut into slices
+ADJ_LATTICE = [(1, 0.0, 0.3, 2), (2, 1.4, 0.6, 3), (0, -0.6, 0.4, 1), (2, -1.1, 0.5, 2),
+               (2, 0.05, 0.6, 2)]
+
+
+@pytest.mark.parametrize("shape,steps,ck", [(1, 11, 4), (2, 9, 3)])
+def test_reverse_sweep_through_thick_elements(lib, shape, steps, ck):
+    from oracle import adjoint as oadj
     cfg = workloads.SMALL
-    b, _ = _start(lib, cfg, 1_000, (8, 8, 8), 1)
-    with pytest.raises(lib.PicError) as e:
-        b.track_adjoint(workloads.THICK_FODO, 4, [1.0, 0.0, 0.0, 0.0], ckpt_every=2)
-    assert e.value.status == lib.PIC_EUNSUPPORTED
+    n, nodes = 2_500, (12, 16, 18)
+    w = np.array([0.7, -0.4, 1.3, 0.9])
+    b, X0 = _start(lib, cfg, n, nodes, shape)
+    m, dk, lam, _ = b.track_adjoint(ADJ_LATTICE, steps, w, ckpt_every=ck)
+    J, dk_o, lam_o, _ = oadj.adjoint_elements(X0, ADJ_LATTICE, steps,
+                                              _problem(cfg, n, nodes, shape), w)
+    assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
+    assert dk[0] == 0.0
+    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    lg = lam.cpu().numpy()
+    for r in range(6):
+        scale = np.abs(lam_o[r]).max()
+        if scale > 0:
+            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
+    # X holds the final state of the forward run, as pic_track_n_steps leaves it
+    Xo = opic.track_elements(X0, ADJ_LATTICE, steps, _problem(cfg, n, nodes, shape))
+    assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
 
 
 def _diag_oracle(X, elements, steps, prob, space_charge=True):
