@@ -21,11 +21,15 @@ in the second derivative only).  The adjoint of each linear operation is its tra
 
 * thick quadrupole half map M(k) per plane: lam <- M^T lam; dJ/dk += lam_after . (dM/dk) X_before
   (adjoint_elements, lattices of Drift / Quad / thin elements cut into slices)
+* with the direct field (Problem.direct_field) the charge's adjoint is chi = -1/(4 pi eps0)
+  sum_a Kbar_a * e_a (solve_field_T: the field kernels are odd along their own axis), with no
+  difference operator
 
 Pinned by tests/test_oracle_adjoint.py: dot-product tests of every transposed operation,
 central finite differences on small beams with space charge (thin lattices and lattices of
-thick elements), the closed-form gradient of the zero-current (linear) map, and the
-k-derivative of the quadrupole matrix against central differences and its k -> 0 limit.
+thick elements), the closed-form gradient of the zero-current (linear) map, the
+k-derivative of the quadrupole matrix against central differences and its k -> 0 limit, and
+the transposed field solve by a dot product and central differences with the direct field.
 """
 import numpy as np
 
@@ -111,6 +115,14 @@ def solve_ghost_source(psi, gbar):
     return conv[:nz, :ny, :nx] / (4.0 * np.pi * EPS0)
 
 
+def solve_field_T(e, kbars):
+    """Transpose of pic.solve_field: with E'_a(n) = 1/(4 pi eps0) sum_m Kbar_a(n - m) Q_m and
+    Kbar_a odd along a and even along the other axes, Qbar_m = sum_a sum_n Kbar_a(n - m) e_a(n)
+    = -1/(4 pi eps0) sum_a (Kbar_a * e_a)(m), the same zero-padded convolutions (sources and
+    outputs on nodes 0..n_a-1)."""
+    return -sum(pic.solve_field(e[a], kbars)[a] for a in range(3))
+
+
 def grad_gather(F, X, geom, prob):
     """sum_n grad W(r_i - r_n) F_n for a scalar grid F; result (3, n)."""
     flat, _, g = _stencil_grad(X, geom, prob)
@@ -165,6 +177,25 @@ def objective_grad(X, w):
 
 # ----------------------------------------------------------------------------- sweeps
 
+def _green_and_field(Q, geom, prob):
+    """The step's kernel(s) and E': the potential's Gbar and -grad phi, or (direct_field) the
+    three field kernels and their convolutions."""
+    if prob.direct_field:
+        kbars = pic.green_field(geom, prob)
+        return kbars, pic.solve_field(Q, kbars)
+    gbar = pic.green(geom, prob)
+    return gbar, pic.field(pic.solve(Q, gbar), geom)
+
+
+def _charge_adjoint(e, geom, kernel, prob):
+    """chi = dJ/dQ (per node) from the deposited adjoint field e: the transposed centred
+    difference and the transposed (ghost-source) solve, or (direct_field) the transposed field
+    convolutions."""
+    if prob.direct_field:
+        return solve_field_T(e, kernel)
+    return solve_ghost_source(divergence_T(e, geom), kernel)
+
+
 def forward(X0, ks, dss, n_steps, prob, geoms=None, space_charge=True):
     """Tracking as oracle.pic.track, optionally with frozen per-step geometries.  Returns the
     final state and, per step, (state at the step start, state at the kick point, geometry,
@@ -179,8 +210,7 @@ def forward(X0, ks, dss, n_steps, prob, geoms=None, space_charge=True):
         if space_charge:
             geom = geoms[j] if geoms is not None else pic.geometry(X2, prob)
             Q = pic.deposit(X2, geom, prob)
-            gbar = pic.green(geom, prob)
-            E = pic.field(pic.solve(Q, gbar), geom)
+            gbar, E = _green_and_field(Q, geom, prob)
             Ep = pic.gather(E, X2, geom, prob)
             X3 = pic.kick(X2, Ep, L, prob)
             rec.append((X, X2, geom, E, gbar))
@@ -206,7 +236,7 @@ def adjoint(X0, ks, dss, n_steps, prob, w, geoms=None, space_charge=True):
                           prob.gamma * prob.C * L * lam[5]])
             direct = grad_gather_dot(E, A, X2, geom, prob)
             e = vector_deposit(A, X2, geom, prob)
-            chi = solve_ghost_source(divergence_T(e, geom), gbar)
+            chi = _charge_adjoint(e, geom, gbar, prob)
             via_rho = prob.q_macro * grad_gather(chi, X2, geom, prob)
             for c, row in enumerate((0, 2, 4)):
                 lam[row] = lam[row] + direct[c] + via_rho[c]
@@ -268,8 +298,7 @@ def forward_elements(X0, elements, n_steps, prob, geoms=None, space_charge=True)
             X1 = pic.half_map(X, kind, k, ell, prob)
         if space_charge:
             geom = geoms[j] if geoms is not None else pic.geometry(X1, prob)
-            gbar = pic.green(geom, prob)
-            E = pic.field(pic.solve(pic.deposit(X1, geom, prob), gbar), geom)
+            gbar, E = _green_and_field(pic.deposit(X1, geom, prob), geom, prob)
             X2 = pic.kick(X1, pic.gather(E, X1, geom, prob), ell, prob)
         else:
             geom = E = gbar = None
@@ -301,7 +330,7 @@ def adjoint_elements(X0, elements, n_steps, prob, w, geoms=None, space_charge=Tr
                           prob.gamma * prob.C * ell * lam[5]])
             direct = grad_gather_dot(E, A, X1, geom, prob)
             eg = vector_deposit(A, X1, geom, prob)
-            chi = solve_ghost_source(divergence_T(eg, geom), gbar)
+            chi = _charge_adjoint(eg, geom, gbar, prob)
             via_rho = prob.q_macro * grad_gather(chi, X1, geom, prob)
             for c, row in enumerate((0, 2, 4)):
                 lam[row] = lam[row] + direct[c] + via_rho[c]

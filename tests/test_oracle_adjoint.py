@@ -235,3 +235,44 @@ def test_thin_elements_reduce_to_the_thin_sweep():
     J2, dk2, lam2, _ = adj.adjoint_elements(X0, [(pic.THIN, k, d, 1) for k, d in zip(ks, dss)],
                                             steps, prob, W4)
     assert J2 == J and np.array_equal(dk2, dk) and np.array_equal(lam2, lam0)
+
+
+def test_field_solve_transpose_by_dot_product():
+    rng = np.random.default_rng(12)
+    nz, ny, nx = 7, 5, 6
+    kbars = [igf.field_cell_average(nx, ny, nz, 1.0, 0.7, 2.3, a) for a in range(3)]
+    Q = rng.standard_normal((nz, ny, nx))
+    e = rng.standard_normal((3, nz, ny, nx))
+    lhs = np.sum(pic.solve_field(Q, kbars) * e)
+    rhs = np.sum(Q * adj.solve_field_T(e, kbars))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_direct_field_adjoint_matches_central_differences(shape):
+    n, steps = 300, 5
+    c = workloads.SMALL
+    prob = pic.make_problem(n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, (10, 12, 12),
+                            shape, direct_field=True)
+    X0 = _beam(n, seed=13)
+    J, dk, lam0, geoms = adj.adjoint_elements(X0, THICK, steps, prob, W4)
+
+    def J_of(els, X_=X0):
+        XN, _ = adj.forward_elements(X_, els, steps, prob, geoms=geoms)
+        return adj.objective(XN, W4)
+
+    XN, _ = adj.forward_elements(X0, THICK, steps, prob)
+    assert np.array_equal(XN, pic.track_elements(X0, THICK, steps, prob))
+    for e in (1, 2, 3):
+        h = 1e-6 * abs(THICK[e][1])
+
+        def shifted(t, e=e):
+            els = list(THICK)
+            kind, k, ds, ns = els[e]
+            els[e] = (kind, k + t, ds, ns)
+            return J_of(els)
+
+        assert abs(_fd(shifted, 0.0, h) - dk[e]) < 1e-6 * np.abs(dk).max(), e
+    D = np.random.default_rng(14).standard_normal(X0.shape) * X0.std(axis=1)[:, None]
+    fd = _fd(lambda t: J_of(THICK, X0 + t * D), 0.0, 1e-6)
+    assert abs(fd - np.sum(lam0 * D)) < 1e-6 * abs(np.sum(lam0 * D)) + 1e-12 * abs(J)
