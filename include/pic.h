@@ -92,7 +92,7 @@ typedef struct {
                               function potential; 1: E' from the integrated Green's functions
                               of the field itself (the cell averages of u_a/|r|^3; no
                               differencing error), three convolutions instead of one.  1 is not
-                              supported by pic_track_adjoint or in batches (PIC_EUNSUPPORTED) */
+                              supported in batches (PIC_EUNSUPPORTED) */
 } pic_beam_desc;
 
 /* Lattice element kinds (Listing 1 of the paper: Drift(ds, nslice), Quad(ds, k, nslice)).
@@ -266,8 +266,8 @@ size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt
  * The forward states are checkpointed every ckpt_every steps in the caller's workspace
  * d_adj_work (pic_adjoint_workspace_bytes, 256-byte aligned) and recomputed per segment.
  * Lattices as for pic_track_n_steps (thin, drift and quadrupole elements, one step per slice).
- * Needs desc.space_charge = 1, desc.direct_field = 0 (PIC_EUNSUPPORTED) and
- * 1 <= n_el <= 1024.  Synchronises `stream`; returns the device error flag of any step
+ * With desc.direct_field the charge's adjoint goes through the transposed field convolutions.
+ * Needs desc.space_charge = 1 and 1 <= n_el <= 1024.  Synchronises `stream`; returns the device error flag of any step
  * (PIC_EDOMAIN). */
 pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              int ckpt_every, const double w[4], void* d_adj_work,

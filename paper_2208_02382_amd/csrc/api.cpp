@@ -503,7 +503,7 @@ AdjLayout adj_layout(const pic_beam_desc* d, int n_steps, int ck) {
   A.ckpt = take(6 * sizeof(double) * n * (size_t)A.nseg);
   A.segX = take(6 * sizeof(double) * n * (size_t)ck);
   A.segE = take(3 * es * ng * (size_t)ck);
-  A.segG = take(es * G3 * (size_t)ck);
+  A.segG = take(es * G3 * (size_t)ck * (d->direct_field ? 3 : 1));  // the step's kernel spectra
   A.e = take(3 * es * ng);
   A.psi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   A.chi = take(es * ng);
@@ -619,11 +619,21 @@ pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const AdjSl
   HIP_OK(launch_deposit_tiles<T>(b->XB, nullptr, g, b->c, b->sp, b->chunks, b->nchunks,
                                  (T*)b->rho, s, b->tacc, b->tscale),
          "adjoint forward");
-  HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh, s),
-         "adjoint forward");
-  HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
-                         (T*)b->phi, E, s),
-         "adjoint forward");
+  if (b->d.direct_field) {  // gh holds the three field kernels' spectra
+    HIP_OK(launch_green_field_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->hcorners,
+                                          b->gd3, gh, s),
+           "adjoint forward");
+    HIP_OK(launch_solve_field<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W,
+                                 b->W2, gh, E, s),
+           "adjoint forward");
+  } else {
+    HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh,
+                                    s),
+           "adjoint forward");
+    HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
+                           (T*)b->phi, E, s),
+           "adjoint forward");
+  }
   HIP_OK(launch_gkd<T>(X, g, E, e.L, e.second, 0, half_drift(0.0), b->c, box, s),
          "adjoint forward");
   return PIC_OK;
@@ -635,9 +645,12 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
                          const double* xi, double out_m[4], double* dJ_dk, double dJ_dL[36],
                          hipStream_t s) {
   const size_t nsl = sl.size();
+  const bool direct = b->d.direct_field != 0;
   const size_t n = (size_t)b->d.n;
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
-  const size_t G3 = (size_t)(b->d.nx + 1) * (b->d.ny + 1) * (b->d.nz + 1);
+  // spectra per stored step: the potential's, or the three field kernels'
+  const size_t G3 = (size_t)(b->d.nx + 1) * (b->d.ny + 1) * (b->d.nz + 1) *
+                    (b->d.direct_field ? 3 : 1);
   auto geom = [&](int j) { return (Geom*)(aw + A.geoms + kGeomSlot * (size_t)j); };
   double* ckpt = (double*)(aw + A.ckpt);
   double* segX = (double*)(aw + A.segX);
@@ -663,8 +676,8 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
                             hipMemcpyDeviceToDevice, s),
              "adjoint checkpoint");
     HIP_OK(launch_box_reset(b->box, s), "adjoint forward");
-    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), sl[j % nsl], (T*)b->Gh, (T*)b->E,
-                                           s, b->box);
+    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), sl[j % nsl],
+                                           direct ? (T*)b->gh3 : (T*)b->Gh, (T*)b->E, s, b->box);
     if (st != PIC_OK) return st;
   }
   HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "adjoint objective");
@@ -708,10 +721,16 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
       } else {
         HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el, e, s), "adjoint");
       }
-      HIP_OK(launch_adj_div<T>(geom(j), e, psi, b->d.nx, b->d.ny, b->d.nz, s), "adjoint");
-      HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi, b->W,
-                                          segG + G3 * (size_t)q, chi, s),
-             "adjoint");
+      if (direct) {  // transposed field convolutions, b->E as their scratch
+        HIP_OK(launch_solve_field_T<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, e, b->W, b->W2,
+                                       segG + G3 * (size_t)q, (T*)b->E, chi, s),
+               "adjoint");
+      } else {
+        HIP_OK(launch_adj_div<T>(geom(j), e, psi, b->d.nx, b->d.ny, b->d.nz, s), "adjoint");
+        HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi,
+                                            b->W, segG + G3 * (size_t)q, chi, s),
+               "adjoint");
+      }
       HIP_OK(launch_adj_b<T>(Xs, lam, geom(j), b->c, el, segE + 3 * ng * (size_t)q, chi,
                              (double*)(aw + A.dk_part), dk, s),
              "adjoint");
@@ -1102,8 +1121,6 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (n_el < 1 || n_el > kMaxLattice || n_steps < 1 || ckpt_every < 1)
     return fail(PIC_EINVAL, "need 1 <= n_el <= 1024, n_steps >= 1, ckpt_every >= 1");
   if (!b->d.space_charge) return fail(PIC_EINVAL, "the reverse sweep needs space_charge = 1");
-  if (b->d.direct_field)
-    return fail(PIC_EUNSUPPORTED, "the reverse sweep transposes the differenced field only");
   if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
   if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
   std::vector<AdjSlice> sl;

@@ -849,6 +849,76 @@ hipError_t launch_solve_field(const Geom* g, const FftPlan& p, int nx, int ny, i
   return hipSuccess;
 }
 
+namespace {
+// chi = -(t_0 + t_1 + t_2) over the nodes
+template <typename T>
+__global__ __launch_bounds__(256) void k_neg_sum3(const Geom* __restrict__ g,
+                                                  const T* __restrict__ t, int64_t ng,
+                                                  T* __restrict__ chi) {
+  if (g->status) return;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < ng; i += (int64_t)gridDim.x * 256)
+    chi[i] = -(t[i] + t[ng + i] + t[2 * ng + i]);
+}
+}  // namespace
+
+// Transpose of launch_solve_field: chi = -sum_a (Kbar_a * e_a) / (4 pi eps0), each a full
+// zero-padded convolution (forward x and y passes of e_a, the z pass with i Khat_a, the inverse
+// y and x passes onto nodes 0..n-1) into tmp (3 nx ny nz), then the signed sum.
+template <typename T>
+hipError_t launch_solve_field_T(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                const T* e, void* Wv, void* W2v, const T* gh3, T* tmp, T* chi,
+                                hipStream_t s) {
+  Cx<T>* W = (Cx<T>*)Wv;
+  Cx<T>* W2 = (Cx<T>*)W2v;
+  const int My = 2 * ny, Kx = nx + 1;
+  const int64_t ng = (int64_t)nx * ny * nz, gtot = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  for (int a = 0; a < 3; ++a) {
+    int LB, NT;
+    size_t lds;
+    shape_for(p.half_x.M, ny, &LB, &NT);
+    lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_r2c_x<T, 0>), dim3((ny + LB - 1) / LB, nz), dim3(NT), lds, s, g,
+                       e + a * ng, W, p.half_x, table<T>(p, 0), nx, ny, nz, Kx, My, LB);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.full[1].M, Kx, &LB, &NT);
+    lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_c2c_y<T, -1, 0, 0>), dim3((Kx + LB - 1) / LB, nz), dim3(NT), lds, s, g,
+                       W, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.full[2].M, Kx, &LB, &NT);
+    lds = (size_t)LB * (p.full[2].M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[2].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_zconv_field<T>), dim3((Kx + LB - 1) / LB, My), dim3(NT), lds, s, g, W,
+                       gh3 + a * gtot, p.full[2], table<T>(p, 2), Kx, My, ny, nz, LB, W2, a);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.full[1].M, Kx, &LB, &NT);
+    lds = (size_t)LB * (p.full[1].M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[1].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_c2c_y<T, +1, 2, 1>), dim3((Kx + LB - 1) / LB, nz), dim3(NT), lds, s, g,
+                       W2, p.full[1], table<T>(p, 1), Kx, ny, nz, LB);
+    PIC_TRY(hipGetLastError());
+    shape_for(p.half_x.M, ny, &LB, &NT);
+    lds = (size_t)LB * (p.half_x.M + 1) * sizeof(Cx<T>) +
+          (size_t)p.full[0].M * sizeof(typename TwT<T>::type);
+    hipLaunchKernelGGL((k_c2r_x<T, 2>), dim3((ny + LB - 1) / LB, nz), dim3(NT), lds, s, g, W2,
+                       tmp + a * ng, p.half_x, table<T>(p, 0), nx, ny, Kx, My, LB);
+    PIC_TRY(hipGetLastError());
+  }
+  int64_t nbk = (ng + 255) / 256;
+  if (nbk > 16384) nbk = 16384;
+  hipLaunchKernelGGL((k_neg_sum3<T>), dim3((unsigned)nbk), dim3(256), 0, s, g, tmp, ng, chi);
+  return hipGetLastError();
+}
+
+template hipError_t launch_solve_field_T<double>(const Geom*, const FftPlan&, int, int, int,
+                                                 const double*, void*, void*, const double*,
+                                                 double*, double*, hipStream_t);
+template hipError_t launch_solve_field_T<float>(const Geom*, const FftPlan&, int, int, int,
+                                                const float*, void*, void*, const float*,
+                                                float*, float*, hipStream_t);
+
 template hipError_t launch_solve_field<double>(const Geom*, const FftPlan&, int, int, int,
                                                const double*, void*, void*, const double*,
                                                double*, hipStream_t);

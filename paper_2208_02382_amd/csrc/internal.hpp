@@ -292,6 +292,12 @@ template <typename T>
 hipError_t launch_green_field_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
                                        double2* hcorners, double* gd3, T* gh3, hipStream_t s);
 // E' (3 [nz][ny][nx]) directly from rho with the field spectra; W2: [nz][2 ny][nx+1] complex
+// the transposed direct-field solve: chi = -sum_a (Kbar_a * e_a) / (4 pi eps0) on nodes
+// 0..n-1 from the three components e[3][nz][ny][nx]; tmp holds 3 nx ny nz values
+template <typename T>
+hipError_t launch_solve_field_T(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                const T* e, void* W, void* W2, const T* gh3, T* tmp, T* chi,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_solve_field(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
                               const T* rho, void* W, void* W2, const T* gh3, T* E, hipStream_t s);

@@ -2,7 +2,8 @@
 itself, pic_beam_desc.direct_field = 1) against the oracle's solve_field, on the same seeded
 inputs: the kernels' spectra and the three convolutions at 1e-12 of the largest field value,
 whole tracking runs at 1e-12 of the rms size per coordinate, FP32 grids within 1e-5 in the rms
-moments, and the rejection of the calls that do not support it.  At the headline grid (128^3,
+moments, the reverse sweep through the transposed field solve at 1e-10, and the rejection by
+batches.  At the headline grid (128^3,
 TSC) with the bench's launch shapes: one step on 2e6 particles, sampled particles against the
 oracle within 1e-12.
 """
@@ -133,17 +134,34 @@ def test_direct_field_through_thick_elements(lib):
     assert _coord_err(b.X.cpu().numpy(), Xo) < TOL
 
 
-def test_adjoint_and_batch_reject_the_direct_field(lib):
+def test_batch_rejects_the_direct_field(lib):
     cfg = workloads.SMALL
     n, nodes, shape = CASES[0]
     b, _ = _start(lib, cfg, n, nodes, shape)
-    w = np.zeros(4)
-    with pytest.raises(lib.PicError) as e:
-        b.track_adjoint(cfg.lattice, 2, w)
-    assert e.value.status == lib.PIC_EUNSUPPORTED
     with pytest.raises(lib.PicError) as e:
         lib.Batch([b], [cfg.lattice])
     assert e.value.status == lib.PIC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("shape,ck", [(1, 3), (2, 2)])
+def test_reverse_sweep_with_the_direct_field(lib, shape, ck):
+    # the charge's adjoint through the transposed field convolutions; a lattice of thick and
+    # thin elements
+    from oracle import adjoint as oadj
+    cfg = workloads.SMALL
+    n, nodes, steps = 2_000, (12, 16, 18), 7
+    lat = [(1, 0.0, 0.3, 2), (2, 1.4, 0.6, 3), (0, -0.6, 0.4, 1)]
+    w = np.array([0.7, -0.4, 1.3, 0.9])
+    b, X0 = _start(lib, cfg, n, nodes, shape)
+    m, dk, lam, _ = b.track_adjoint(lat, steps, w, ckpt_every=ck)
+    J, dk_o, lam_o, _ = oadj.adjoint_elements(X0, lat, steps, _problem(cfg, n, nodes, shape), w)
+    assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
+    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    lg = lam.cpu().numpy()
+    for r in range(6):
+        scale = np.abs(lam_o[r]).max()
+        if scale > 0:
+            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
 
 
 @pytest.mark.timeout(900)
