@@ -53,7 +53,9 @@ typedef enum {
   PIC_ENOMEM = -2,        /* workspace too small */
   PIC_EHIP = -3,          /* a HIP runtime call failed */
   PIC_EDOMAIN = -4,       /* device flagged a non-finite coordinate or a zero-extent box */
-  PIC_EUNSUPPORTED = -5,  /* grid size whose padded FFT length is not 2^a 3^b, or > 512 */
+  PIC_EUNSUPPORTED = -5,  /* unsupported size or combination: a padded FFT length not 2^a 3^b
+                             or > 512, n >= 2^31, the direct field or an oversized tile window
+                             in a batch */
   PIC_ENODEV = -6,        /* no HIP device */
   PIC_EINTERNAL = -7      /* the device detected an inconsistency of the library's own binning */
 } pic_status;

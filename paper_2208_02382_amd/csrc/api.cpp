@@ -662,7 +662,7 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
   double* dk = (double*)(aw + A.dk);
   double* small = (double*)(aw + A.small);
   double* P = (double*)(aw + A.stage);
-  // the binned vector deposit keeps three float64 windows of a tile in LDS (64 KB)
+  // the binned vector deposit keeps three float64 windows of a tile in LDS (up to 156 KB)
   const int S = b->d.shape;
   const bool vtiles =
       24 * (size_t)(b->sp.T[0] + S) * (b->sp.T[1] + S) * (b->sp.T[2] + S) <= kMaxLdsBytes;

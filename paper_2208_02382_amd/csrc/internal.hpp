@@ -266,7 +266,7 @@ hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
                         const AdjSlice& sl, T* e, hipStream_t s);
 hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c,
                             const AdjSlice& sl, double* P, hipStream_t s);
-// binned vector deposit; hipErrorInvalidConfiguration if the three windows exceed 64 KB
+// binned vector deposit; an error if the three float64 windows exceed the LDS a workgroup may use
 template <typename T>
 hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
                                  const int4* chunks, const uint32_t* nchunks, T* e,
