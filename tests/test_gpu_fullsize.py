@@ -4,6 +4,7 @@ the oracle can compute one by one.
 * 1e8 particles, 128^3, TSC with halo (the bench's workload and autotuned launch shapes): one
   step on the GPU; the oracle deposits all particles (in chunks), solves on the full grid and
   pushes a random sample of particles, which must agree within 1e-12 of each coordinate's rms.
+  The same for one slice of the paper's thick focusing quadrupole.
   The float32-grid variant at the same size: rms sizes and emittances within 1e-5 of float64.
 * The batched workload (256 beams, 6.5e7 particles, one graph): two steps; its four smallest
   beams against the oracle within 1e-12.
@@ -71,6 +72,36 @@ def test_headline_size_one_step_on_sampled_particles(lib):
     S = np.random.default_rng(11).choice(cfg.n, 2000, replace=False)
     Xs = X2[:, S]
     Xo = opic.drift(opic.kick(Xs, opic.gather(E, Xs, geom, prob), L, prob), 0.5 * L, prob)
+    scale = X1[:, ::97].std(axis=1)
+    assert _coord_err(X1[:, S], Xo, scale) < TOL
+
+
+def test_headline_size_thick_quadrupole_slice_on_sampled_particles(lib):
+    # one slice of the paper's focusing quadrupole (Listing 1: Quad(1.0, k=1, 25 slices)) at
+    # the headline size and tuned launch shapes: quadrupole half map, kick, quadrupole half map
+    from paper_2208_02382_amd import autotune
+    cfg = workloads.LARGE
+    tuning = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False)
+    quad = (opic.QUAD, 1.0, 1.0, 25)
+    b = lib.Beam.from_config(cfg, tuning=tuning)
+    b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+    X0 = b.X.cpu().numpy()
+    b.track([quad], 1)
+    X1 = b.X.cpu().numpy()
+    assert b.check() == lib.PIC_OK
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    prob = _problem(cfg)
+    kind, k, ds, ns = quad
+    ell = ds / ns
+    X2 = opic.half_map(X0, kind, k, ell, prob)
+    del X0
+    geom, E = _oracle_field_chunked(X2, prob)
+    S = np.random.default_rng(13).choice(cfg.n, 2000, replace=False)
+    Xs = X2[:, S]
+    Xo = opic.half_map(opic.kick(Xs, opic.gather(E, Xs, geom, prob), ell, prob), kind, k, ell,
+                       prob)
     scale = X1[:, ::97].std(axis=1)
     assert _coord_err(X1[:, S], Xo, scale) < TOL
 
