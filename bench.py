@@ -10,7 +10,7 @@ Workload (default): 1e8 macroparticles, 6-D Gaussian with a 10 % uniform halo ou
 128^3 grid (256^3 padded FFT), TSC, thin-lens FODO, float64 grid; the float32-grid variant is
 timed on the same beam and reported next to it.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the library tracks a beam on one GPU.
 """
 import argparse
 import hashlib
@@ -380,8 +380,8 @@ def main():
                          "of known traffic for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU "
-              "sharding is not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: the library tracks a beam on one GPU; --gpus %d is not supported (the "
+              "multi-GPU sharding is not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.oracle_timings:
         print(json.dumps({"oracle_timings": oracle_timings()}), flush=True)
