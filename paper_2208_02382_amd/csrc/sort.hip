@@ -628,6 +628,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __r
 // leaves in sorted order.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
+// PERM with a next step: the chunk's slots [begin, end) are refilled from both ends, the
+// particles whose next kick-point position lies in the same tile of the current grid from the
+// bottom and the others from the top (one LDS atomic per wavefront and end), so that the
+// particles likely to change tile next step lie together in a short stretch of the order:
+// neighbouring tiles then read them through the next permutation from fewer cache lines.
 // DIAG: the particles' state at the end of the step (after the second half map, before the
 // next first half map) is also summed into the block's partial moments, diag_part[blk * 27 +
 // q]: 6 sums of d = v - shift and the 21 products d_a d_b (a <= b, row-major), with the
@@ -650,8 +655,10 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
                                                     double* __restrict__ diag_part = nullptr,
                                                     const double* __restrict__ diag_shift = nullptr) {
   extern __shared__ unsigned char smem_raw[];
+  __shared__ uint32_t s_up, s_down;  // the next free slot from either end of the chunk
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
+  const bool reorder = PERM && has_next;
   double sh[6], acc[DIAG ? kMomentSlots : 1];
   if constexpr (DIAG) {
     for (int r = 0; r < 6; ++r) sh[r] = diag_shift[r];
@@ -674,7 +681,11 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
     const int t = ch.x;
     const int tx = t % sp.NT[0], ty = (t / sp.NT[0]) % sp.NT[1], tz = t / (sp.NT[0] * sp.NT[1]);
     const int ox = tx * sp.T[0], oy = ty * sp.T[1], oz = tz * sp.T[2];
-    __syncthreads();  // the previous chunk's readers are done with the window
+    __syncthreads();  // the previous chunk's readers are done with the window and counters
+    if (reorder && threadIdx.x == 0) {
+      s_up = (uint32_t)ch.y;
+      s_down = (uint32_t)ch.z;
+    }
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
       int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
@@ -685,70 +696,98 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       win[2 * nw + w] = in ? E[2 * plane + gi] : T(0);
     }
     __syncthreads();
-    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
-      double v[6];
+    // every thread of the block runs the same number of rounds (the wavefront-wide slot
+    // assignment below needs all lanes); lanes past the chunk's end are inactive
+    for (int64_t ib = ch.y; ib < ch.z; ib += (int)blockDim.x) {
+      const int64_t i = ib + threadIdx.x;
+      const bool act = i < ch.z;
+      double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       int64_t i0 = i;
-      if constexpr (PERM) {
-        i0 = perm[i];
-        if (i0 >= n) {  // impossible for a consistent ranking; keeps the reads in bounds
-          bin_fault = true;
-          i0 = 0;
+      if (act) {
+        if constexpr (PERM) {
+          i0 = perm[i];
+          if (i0 >= n) {  // impossible for a consistent ranking; keeps the reads in bounds
+            bin_fault = true;
+            i0 = 0;
+          }
+          for (int r = 0; r < 6; ++r) v[r] = src[r * n + i0];
+        } else {
+          for (int r = 0; r < 6; ++r) v[r] = B[r * n + i];
         }
-        for (int r = 0; r < 6; ++r) v[r] = src[r * n + i0];
-      } else {
-        for (int r = 0; r < 6; ++r) v[r] = B[r * n + i];
-      }
-      double wx[S + 1], wy[S + 1], wz[S + 1];
-      const int bx = stencil<S>((v[0] - o[0]) * ih[0], c.nx, wx);
-      const int by = stencil<S>((v[2] - o[1]) * ih[1], c.ny, wy);
-      const int bz = stencil<S>((v[4] - o[2]) * ih[2], c.nz, wz);
-      // the binning put this particle in the chunk's tile, so its stencil lies in the window;
-      // a violation is a library fault: flagged, and the indices clamped to stay in bounds
-      int lx = bx - ox, ly = by - oy, lz = bz - oz;
-      if (lx < 0 || lx >= sp.T[0] || ly < 0 || ly >= sp.T[1] || lz < 0 || lz >= sp.T[2]) {
-        bin_fault = true;
-        lx = min(max(lx, 0), sp.T[0] - 1);
-        ly = min(max(ly, 0), sp.T[1] - 1);
-        lz = min(max(lz, 0), sp.T[2] - 1);
-      }
-      T ex = 0, ey = 0, ez = 0;
-      const T* w0 = win + (lz * Wy + ly) * Wx + lx;
-      for (int a = 0; a <= S; ++a)
-        for (int b = 0; b <= S; ++b) {
-          const double wzy = wz[a] * wy[b];
-          const T* row = w0 + rowoff[a][b];
-          for (int q = 0; q <= S; ++q) {
-            const T w = (T)(wzy * wx[q]);
-            ex += w * row[q];
-            ey += w * row[nw + q];
-            ez += w * row[2 * nw + q];
+        double wx[S + 1], wy[S + 1], wz[S + 1];
+        const int bx = stencil<S>((v[0] - o[0]) * ih[0], c.nx, wx);
+        const int by = stencil<S>((v[2] - o[1]) * ih[1], c.ny, wy);
+        const int bz = stencil<S>((v[4] - o[2]) * ih[2], c.nz, wz);
+        // the binning put this particle in the chunk's tile, so its stencil lies in the window;
+        // a violation is a library fault: flagged, and the indices clamped to stay in bounds
+        int lx = bx - ox, ly = by - oy, lz = bz - oz;
+        if (lx < 0 || lx >= sp.T[0] || ly < 0 || ly >= sp.T[1] || lz < 0 || lz >= sp.T[2]) {
+          bin_fault = true;
+          lx = min(max(lx, 0), sp.T[0] - 1);
+          ly = min(max(ly, 0), sp.T[1] - 1);
+          lz = min(max(lz, 0), sp.T[2] - 1);
+        }
+        T ex = 0, ey = 0, ez = 0;
+        const T* w0 = win + (lz * Wy + ly) * Wx + lx;
+        for (int a = 0; a <= S; ++a)
+          for (int b = 0; b <= S; ++b) {
+            const double wzy = wz[a] * wy[b];
+            const T* row = w0 + rowoff[a][b];
+            for (int q = 0; q <= S; ++q) {
+              const T w = (T)(wzy * wx[q]);
+              ex += w * row[q];
+              ey += w * row[nw + q];
+              ez += w * row[2 * nw + q];
+            }
+          }
+        v[1] = v[1] + c.C * (double)ex * L;
+        v[3] = v[3] + c.C * (double)ey * L;
+        v[5] = v[5] + c.gamma * c.C * (double)ez * L;
+        apply_half(second, v, c.inv_gamma2);
+        if constexpr (DIAG) {
+          double d[6];
+          for (int r = 0; r < 6; ++r) {
+            d[r] = v[r] - sh[r];
+            acc[r] += d[r];
+          }
+          int q = 6;
+          for (int a = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b) acc[q++] += d[a] * d[b];
+        }
+        if (has_next) {
+          apply_half(first_next, v, c.inv_gamma2);
+          const double p[3] = {v[0], v[2], v[4]};
+          for (int a = 0; a < 3; ++a) {
+            bad |= !isfinite(p[a]);
+            lo[a] = fmin(lo[a], p[a]);
+            hi[a] = fmax(hi[a], p[a]);
           }
         }
-      v[1] = v[1] + c.C * (double)ex * L;
-      v[3] = v[3] + c.C * (double)ey * L;
-      v[5] = v[5] + c.gamma * c.C * (double)ez * L;
-      apply_half(second, v, c.inv_gamma2);
-      if constexpr (DIAG) {
-        double d[6];
-        for (int r = 0; r < 6; ++r) {
-          d[r] = v[r] - sh[r];
-          acc[r] += d[r];
-        }
-        int q = 6;
-        for (int a = 0; a < 6; ++a)
-          for (int b = a; b < 6; ++b) acc[q++] += d[a] * d[b];
       }
-      if (has_next) {
-        apply_half(first_next, v, c.inv_gamma2);
-        const double p[3] = {v[0], v[2], v[4]};
-        for (int a = 0; a < 3; ++a) {
-          bad |= !isfinite(p[a]);
-          lo[a] = fmin(lo[a], p[a]);
-          hi[a] = fmax(hi[a], p[a]);
+      int64_t slot = i;
+      if (reorder) {
+        const bool stay = act && tile_key<S>(v[0], v[2], v[4], o, ih, c, sp) == (uint32_t)t;
+        const uint64_t m_s = __ballot(stay), m_m = __ballot(act && !stay);
+        const int lane = (int)__lane_id();
+        const uint64_t below = (1ull << lane) - 1ull;
+        uint32_t b_s = 0u, b_m = 0u;
+        if (lane == 0) {
+          if (m_s) b_s = atomicAdd(&s_up, (uint32_t)__popcll(m_s));
+          if (m_m) b_m = atomicSub(&s_down, (uint32_t)__popcll(m_m));
+        }
+        b_s = __shfl(b_s, 0);
+        b_m = __shfl(b_m, 0);
+        slot = stay ? (int64_t)b_s + __popcll(m_s & below)
+                    : (int64_t)b_m - __popcll(m_m) + __popcll(m_m & below);
+        if (act && (slot < ch.y || slot >= ch.z)) {  // impossible: the two ends tile the chunk
+          bin_fault = true;
+          slot = i;
         }
       }
-      for (int r = 0; r < 6; ++r) B[r * n + i] = v[r];
-      if constexpr (PERM) iddst[i] = idsrc[i0];
+      if (act) {
+        for (int r = 0; r < 6; ++r) B[r * n + slot] = v[r];
+        if constexpr (PERM) iddst[slot] = idsrc[i0];
+      }
     }
   }
   if (bin_fault) atomicCAS(const_cast<int*>(&g->status), 0, -7);
@@ -772,8 +811,13 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   }
 }
 
+// With DIAG the 27 moment sums stay in registers beside the particle's state: the kernel is
+// built for at most kDiagThreads lanes per workgroup, which doubles the registers a lane may
+// hold and keeps the sums out of scratch memory.
+constexpr int kDiagThreads = 512;
+
 template <int S, typename T, bool PERM, bool DIAG>
-__global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles(double* __restrict__ B,
+__global__ __launch_bounds__(DIAG ? kDiagThreads : kMaxThreads) void k_gkd_tiles(double* __restrict__ B,
                                                     const double* __restrict__ src,
                                                     const uint32_t* __restrict__ perm,
                                                     const uint32_t* __restrict__ idsrc,
@@ -1275,10 +1319,11 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
                             double* diag_out) {
   const int S = c.shape;
   size_t lds = 3 * sizeof(T) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
+  const bool diag = diag_out != nullptr;
+  const dim3 grid((unsigned)sp.blocks),
+      block((unsigned)(diag ? std::min(sp.threads, kDiagThreads) : sp.threads));
   if (perm && (!src || !idsrc || !iddst || src == B || idsrc == iddst))
     return hipErrorInvalidValue;
-  const bool diag = diag_out != nullptr;
   if (diag) {
     if (!diag_part || !diag_shift) return hipErrorInvalidValue;
     const size_t red = sizeof(double) * kMomentSlots * (kMaxThreads / 64);
