@@ -628,10 +628,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __r
 // leaves in sorted order.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
 // window, impossible for a consistent binning, sets status -7 (PIC_EINTERNAL).
-// PERM with a next step: the chunk's slots [begin, end) are refilled from both ends, the
-// particles whose next kick-point position lies in the same tile of the current grid from the
-// bottom and the others from the top (one LDS atomic per wavefront and end), so that the
-// particles likely to change tile next step lie together in a short stretch of the order:
+// PERM with a next step and no DIAG: the chunk's slots [begin, end) are refilled from both
+// ends, the particles whose next kick-point position lies in the same tile of the current grid
+// from the bottom and the others from the top (one LDS atomic per wavefront and end), so that
+// the particles likely to change tile next step lie together in a short stretch of the order:
 // neighbouring tiles then read them through the next permutation from fewer cache lines.
 // DIAG: the particles' state at the end of the step (after the second half map, before the
 // next first half map) is also summed into the block's partial moments, diag_part[blk * 27 +
@@ -658,7 +658,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   __shared__ uint32_t s_up, s_down;  // the next free slot from either end of the chunk
   T* win = reinterpret_cast<T*>(smem_raw);
   if (g->status) return;
-  const bool reorder = PERM && has_next;
+  const bool reorder = PERM && !DIAG && has_next;  // with DIAG it cost more time than it saved
   double sh[6], acc[DIAG ? kMomentSlots : 1];
   if constexpr (DIAG) {
     for (int r = 0; r < 6; ++r) sh[r] = diag_shift[r];
