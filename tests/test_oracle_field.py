@@ -4,6 +4,8 @@
   cells on the coordinate planes and the odd kernel's zero plane.
 * Far field: Kbar -> x/R^3 with an O((h/R)^2) error.
 * The zero-padded FFT convolution with the odd/even kernel array against the direct sum.
+* A uniformly charged ellipsoid: inside, both field paths give the linear closed form
+  E_i = rho n_i x_i / eps0 with the depolarisation factors n_i (quadrature; 1/3 for a sphere).
 * A uniformly charged box made of whole cells, whose exact field at every node follows from
   the box's own 8-corner antiderivative sum, evaluated independently in 30-digit mpmath: the
   direct-field solve reproduces it to rounding, while -grad phi by centred differences of the
@@ -172,3 +174,56 @@ def test_centred_differences_converge_to_the_direct_field():
         diffs.append(np.abs(Ed - Ef).max() / np.abs(Ef).max())
     assert 3.5 < diffs[0] / diffs[1] < 4.5
     assert diffs[1] < 1e-2
+
+
+def _depolarisation(semi):
+    # n_i = (a b c / 2) int_0^inf ds / ((s + a_i^2) sqrt((s + a^2)(s + b^2)(s + c^2))), the
+    # coefficients of the linear field inside a uniformly charged ellipsoid
+    a2 = np.asarray(semi, dtype=float) ** 2
+    root = lambda s: np.sqrt(np.prod(s + a2))
+    return np.array([0.5 * np.prod(semi) * integrate.quad(
+        lambda s, i=i: 1.0 / ((s + a2[i]) * root(s)), 0, np.inf, epsabs=0, epsrel=1e-12)[0]
+        for i in range(3)])
+
+
+def test_depolarisation_factors_of_a_sphere_and_their_sum():
+    assert np.allclose(_depolarisation((2.0, 2.0, 2.0)), 1.0 / 3.0, rtol=1e-10, atol=0)
+    assert abs(_depolarisation((12.0, 9.0, 30.0)).sum() - 1.0) < 1e-10
+
+
+def test_uniform_ellipsoid_has_the_linear_interior_field():
+    # The field inside a uniformly charged ellipsoid is E_i = rho n_i x_i / eps0 (the
+    # Kurth-like beam of a linear space-charge force). The charge per cell comes from 10^3
+    # sub-points in the cells the surface may cut, so only that staircase separates the
+    # grid solution from the closed form: about 4e-5 of the largest interior field here, while
+    # a swapped axis, a lost 4 pi or a wrong sign is off by 10 % or more.
+    nx = ny = nz = 40
+    h = np.array(H)
+    semi = np.array([12.0, 9.0, 30.0])
+    ctr = np.array([20.0, 14.0, 46.0])
+    ax = [np.arange(m) * h[a] for a, m in enumerate((nx, ny, nz))]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    u = [(X - ctr[0]) / semi[0], (Y - ctr[1]) / semi[1], (Z - ctr[2]) / semi[2]]
+    f = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    frac = (f < 1.0).astype(float)
+    # cells whose centre lies within a cell diagonal (in scaled units) of the surface
+    band = np.abs(np.sqrt(f) - 1.0) < 1.5 * np.linalg.norm(h / semi)
+    sub = (np.arange(10) + 0.5) / 10 - 0.5
+    sz, sy, sx = np.meshgrid(sub * h[2], sub * h[1], sub * h[0], indexing="ij")
+    for k, j, i in zip(*np.nonzero(band)):
+        p = (X[k, j, i] + sx - ctr[0]) / semi[0], (Y[k, j, i] + sy - ctr[1]) / semi[1], \
+            (Z[k, j, i] + sz - ctr[2]) / semi[2]
+        frac[k, j, i] = np.mean(p[0] ** 2 + p[1] ** 2 + p[2] ** 2 < 1.0)
+    rho = 1.0
+    Q = rho * frac * np.prod(h)
+    E = pic.solve_field(Q, [igf.field_cell_average(nx, ny, nz, *h, a) for a in range(3)])
+    Efd = pic.field(pic.solve(Q, igf.cell_average(nx, ny, nz, *h)),
+                    pic.Geometry(np.zeros(3), h, h))
+    n_i = _depolarisation(semi)
+    inner = f < 0.5 ** 2
+    scale = rho * max(n_i * semi) / pic.EPS0
+    for a, (g, c) in enumerate(zip((X, Y, Z), ctr)):
+        ref = rho * n_i[a] * (g - c) / pic.EPS0
+        assert np.abs(E[a][inner] - ref[inner]).max() < 3e-4 * scale, a
+        # the potential is quadratic there, so centred differences are exact up to the staircase
+        assert np.abs(Efd[a][inner] - ref[inner]).max() < 3e-4 * scale, a
