@@ -39,8 +39,11 @@ statistics (section "ImpactX") -- and the B-spline particle-shape order (Listing
 
 Pins: tests/test_oracle_pic.py (charge conservation, shape values, Hockney vs direct
 summation, analytic Gaussian-bunch field, direct Coulomb sums, momentum conservation, mirror
-symmetry, closed-form maps and phase advance, kick constant from SI units) and
-tests/test_oracle_golden.py (the paper's printed emittance).
+symmetry, closed-form maps and phase advance, kick constant from SI units),
+tests/test_oracle_golden.py (the paper's printed emittance), tests/test_oracle_field.py (the
+direct field, and the linear interior field of a uniformly charged ellipsoid) and
+tests/test_oracle_envelope.py (multi-step tracking of a cold uniform ellipsoid against its
+envelope equations).
 """
 from dataclasses import dataclass
 

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
+from ellipsoid_math import depolarisation
 from oracle import igf, pic
 
 H = (1.0, 0.7, 2.3)
@@ -176,19 +177,9 @@ def test_centred_differences_converge_to_the_direct_field():
     assert diffs[1] < 1e-2
 
 
-def _depolarisation(semi):
-    # n_i = (a b c / 2) int_0^inf ds / ((s + a_i^2) sqrt((s + a^2)(s + b^2)(s + c^2))), the
-    # coefficients of the linear field inside a uniformly charged ellipsoid
-    a2 = np.asarray(semi, dtype=float) ** 2
-    root = lambda s: np.sqrt(np.prod(s + a2))
-    return np.array([0.5 * np.prod(semi) * integrate.quad(
-        lambda s, i=i: 1.0 / ((s + a2[i]) * root(s)), 0, np.inf, epsabs=0, epsrel=1e-12)[0]
-        for i in range(3)])
-
-
 def test_depolarisation_factors_of_a_sphere_and_their_sum():
-    assert np.allclose(_depolarisation((2.0, 2.0, 2.0)), 1.0 / 3.0, rtol=1e-10, atol=0)
-    assert abs(_depolarisation((12.0, 9.0, 30.0)).sum() - 1.0) < 1e-10
+    assert np.allclose(depolarisation((2.0, 2.0, 2.0)), 1.0 / 3.0, rtol=1e-10, atol=0)
+    assert abs(depolarisation((12.0, 9.0, 30.0)).sum() - 1.0) < 1e-10
 
 
 def test_uniform_ellipsoid_has_the_linear_interior_field():
@@ -219,7 +210,7 @@ def test_uniform_ellipsoid_has_the_linear_interior_field():
     E = pic.solve_field(Q, [igf.field_cell_average(nx, ny, nz, *h, a) for a in range(3)])
     Efd = pic.field(pic.solve(Q, igf.cell_average(nx, ny, nz, *h)),
                     pic.Geometry(np.zeros(3), h, h))
-    n_i = _depolarisation(semi)
+    n_i = depolarisation(semi)
     inner = f < 0.5 ** 2
     scale = rho * max(n_i * semi) / pic.EPS0
     for a, (g, c) in enumerate(zip((X, Y, Z), ctr)):
