@@ -24,12 +24,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
 METRIC = "particle-steps/s, 1e8 ptcl 128^3 space-charge PIC; FP32/batched/adjoint vs plain"
-# algorithmic bytes per particle per launch (float64 phase space) in the steady state of the
-# tracking loop, where both kernels read the particles through the step's sort permutation
-# (the first step of a call reads them in tile order: 24 and 96 B)
+# algorithmic bytes per particle per launch (float64 phase space): what the method itself must
+# move, the deposit reading x, y, z and the fused gather-kick-drift reading and writing the six
+# coordinates
 ALGO_BYTES = {
-    "deposit": 28,   # read the slot's source index and x, y, z
-    "gkd": 108,      # read the source index, the six coordinates and the id; write both
+    "deposit": 24,
+    "gkd": 96,
+}
+# bytes per particle per launch the binned kernels move on top of that in the steady state of
+# the tracking loop, reported separately: the sort permutation's source index (both kernels)
+# and the particle id read and written by the gather-kick
+OVERHEAD_BYTES = {
+    "deposit": 4,
+    "gkd": 12,
 }
 # (file, device function) whose source text the counter figures were taken on
 KERNEL_SOURCES = {"gkd": ("paper_2208_02382_amd/csrc/sort.hip", "gkd_tiles_body"),
@@ -291,7 +298,12 @@ def cpu_baseline(cfg, n_sample):
             dt = go()
     else:
         dt = go()
+    try:
+        host_cpus = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        host_cpus = os.cpu_count()
     return {"value": n_sample / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "host_cpus": host_cpus, "host_cpu_count": os.cpu_count(),
             "sample": "1 oracle step (NumPy float64, 1 thread) of %d particles drawn like the "
                       "%d-particle workload, on its full %dx%dx%d grid with %s; includes the "
                       "double-double IGF and the padded FFTs; %.1f s"
@@ -416,7 +428,8 @@ def main():
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": t,
                 "kernel": name, "avg_launch_ms": avg * 1e3,
-                "algorithmic_bytes_per_launch": ALGO_BYTES[name] * cfg.n}
+                "algorithmic_bytes_per_launch": ALGO_BYTES[name] * cfg.n,
+                "overhead_bytes_per_launch": OVERHEAD_BYTES[name] * cfg.n}
 
     kernels = {k: roof(k, stages) for k in ("gkd", "deposit")}
     copy_gbs = measured_copy_gbs()

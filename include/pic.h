@@ -281,6 +281,13 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
  * error flag is set. */
 pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream);
 
+/* The objective terms of pic_track_adjoint for the current X: out_m = (sigma_x, sigma_y, eps_x,
+ * eps_y), the centred rms sizes and the geometric (unnormalised) emittances
+ * eps_x = sqrt(<dx^2><dpx^2> - <dx dpx>^2), as the paper quotes emittance (sections "Usage
+ * Example", "Benchmark: FODO Cell"), from the moments of pic_moments.  out_m is host memory.
+ * Synchronises `stream`; PIC_EDOMAIN if the device error flag is set. */
+pic_status pic_objective(pic_beam b, double out_m[4], void* stream);
+
 /* Geometry of the last deposit: out[0..2] origin (x, y, z) [m], out[3..5] lab spacings,
  * out[6..8] rest-frame spacings (hx, hy, gamma hz).  Synchronises `stream`. */
 pic_status pic_get_geometry(pic_beam b, double out[9], void* stream);

@@ -64,6 +64,7 @@ _SIGS = {
     "pic_track_n_steps": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P]),
     "pic_track_n_steps_diag": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P, _P]),
     "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    "pic_objective": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_get_geometry": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_check": (_I, [_P, _P]),
     "pic_profile_start": (_I, [_P]),
@@ -264,6 +265,12 @@ class Beam:
         cov = (ctypes.c_double * 36)()
         _check(_lib.pic_moments(self._h, mean, cov, _stream()), "pic_moments")
         return list(mean), [list(cov[r * 6:(r + 1) * 6]) for r in range(6)]
+
+    def objective(self):
+        """(sigma_x, sigma_y, eps_x, eps_y) of the current X, computed by the library."""
+        m = (ctypes.c_double * 4)()
+        _check(_lib.pic_objective(self._h, m, _stream()), "pic_objective")
+        return list(m)
 
     def geometry(self):
         out = (ctypes.c_double * 9)()

@@ -3,8 +3,8 @@
 The forward pass initialises X0 = L xi on the device (L = chol(Sigma0), from torch so that
 torch's Cholesky backward carries dJ/dL to dJ/dSigma0) and runs pic_track_n_steps; the backward
 pass re-initialises X0 and runs the library's reverse sweep (pic_track_adjoint), which returns
-dJ/dk and dJ/dL = sum_i lam0_i xi_i^T.  Argument marshalling only: the tracking, the moments and
-both reductions run in the library's kernels.
+dJ/dk and dJ/dL = sum_i lam0_i xi_i^T.  Argument marshalling only: the tracking, the moments, the
+objective terms (pic_objective) and both reductions run in the library's kernels.
 """
 import torch
 
@@ -17,13 +17,10 @@ class _Track(torch.autograd.Function):
         sigma = (L @ L.T).detach().cpu()
         beam.init_from_normals(sigma, xi)
         beam.track([(float(kk), float(d)) for kk, d in zip(k.tolist(), ds)], n_steps)
-        _, cov = beam.moments()
-        sx, sy = cov[0][0] ** 0.5, cov[2][2] ** 0.5
-        ex = (cov[0][0] * cov[1][1] - cov[0][1] ** 2) ** 0.5
-        ey = (cov[2][2] * cov[3][3] - cov[2][3] ** 2) ** 0.5
+        m = beam.objective()
         ctx.beam, ctx.xi, ctx.ds, ctx.n_steps, ctx.ck = beam, xi, ds, n_steps, ckpt_every
         ctx.save_for_backward(L, k)
-        return torch.tensor([sx, sy, ex, ey], dtype=torch.float64)
+        return torch.tensor(m, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, gm):

@@ -270,21 +270,36 @@ struct Weights {
   double w[4];
 };
 
+// covariance entry (a, b) of mom = [mean 6][cov upper 21] (upper triangle, row-major, a <= b)
+__device__ __forceinline__ double mom_cov(const double* __restrict__ mom, int a, int b) {
+  if (a > b) {
+    int t = a;
+    a = b;
+    b = t;
+  }
+  int q = 0;
+  for (int r = 0; r < a; ++r) q += 6 - r;
+  return mom[6 + q + (b - a)];
+}
+
+// The objective terms of the final beam: centred rms sizes and geometric (unnormalised)
+// emittances, eps_x = sqrt(<dx^2><dpx^2> - <dx dpx>^2) (the paper quotes the emittance in this
+// unnormalised form: sections "Usage Example" and "Benchmark: FODO Cell").  One thread.
+__global__ void k_objective(const double* __restrict__ mom, double* __restrict__ out_m) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double Sxx = mom_cov(mom, 0, 0), Sxp = mom_cov(mom, 0, 1), Spp = mom_cov(mom, 1, 1);
+  const double Syy = mom_cov(mom, 2, 2), Syq = mom_cov(mom, 2, 3), Sqq = mom_cov(mom, 3, 3);
+  out_m[0] = sqrt(Sxx);
+  out_m[1] = sqrt(Syy);
+  out_m[2] = sqrt(Sxx * Spp - Sxp * Sxp);
+  out_m[3] = sqrt(Syy * Sqq - Syq * Syq);
+}
+
 __global__ __launch_bounds__(kBlk) void k_obj_grad(const double* __restrict__ X, int64_t n,
                                                    const double* __restrict__ mom, Weights wt,
                                                    double* __restrict__ lam,
                                                    double* __restrict__ out_m) {
-  // covariance entries (upper triangle, row-major over a <= b)
-  auto cov = [&](int a, int b) {
-    if (a > b) {
-      int t = a;
-      a = b;
-      b = t;
-    }
-    int q = 0;
-    for (int r = 0; r < a; ++r) q += 6 - r;
-    return mom[6 + q + (b - a)];
-  };
+  auto cov = [&](int a, int b) { return mom_cov(mom, a, b); };
   const double Sxx = cov(0, 0), Sxp = cov(0, 1), Spp = cov(1, 1);
   const double Syy = cov(2, 2), Syq = cov(2, 3), Sqq = cov(3, 3);
   const double sx = sqrt(Sxx), sy = sqrt(Syy);
@@ -415,6 +430,11 @@ hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const 
   Weights wt;
   for (int q = 0; q < 4; ++q) wt.w[q] = w[q];
   hipLaunchKernelGGL(k_obj_grad, dim3(grid_for(n)), dim3(kBlk), 0, s, X, n, mom, wt, lam, out_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const double* mom, double* out_m, hipStream_t s) {
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, s, mom, out_m);
   return hipGetLastError();
 }
 

@@ -110,7 +110,7 @@ Layout layout(const pic_beam_desc* d) {
   L.geom = take(sizeof(Geom));
   L.box = take(sizeof(Box));
   L.mom_partial = take(sizeof(double) * kReduceBlocks * kMomentSlots);
-  L.mom_out = take(sizeof(double) * kMomentSlots);
+  L.mom_out = take(sizeof(double) * (kMomentSlots + 4));  // moments, then the objective terms
   int nn[3] = {d->nx, d->ny, d->nz};
   for (int a = 0; a < 3; ++a) L.tw[a] = take(sizeof(double2) * 2 * nn[a]);
   for (int a = 0; a < 3; ++a) L.twf[a] = take(sizeof(float2) * 2 * nn[a]);
@@ -1090,6 +1090,20 @@ pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream)
     for (int c = a; c < 6; ++c) {
       cov[a * 6 + c] = cov[c * 6 + a] = host[q++];
     }
+  return device_status(g.status);
+}
+
+pic_status pic_objective(pic_beam b, double out_m[4], void* stream) {
+  if (!b || !out_m) return fail(PIC_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "objective");
+  HIP_OK(launch_objective(b->mom_out, b->mom_out + kMomentSlots, s), "objective");
+  Geom g;
+  HIP_OK(hipMemcpyAsync(out_m, b->mom_out + kMomentSlots, 4 * sizeof(double),
+                        hipMemcpyDeviceToHost, s),
+         "objective");
+  HIP_OK(hipMemcpyAsync(&g, b->geom, sizeof(Geom), hipMemcpyDeviceToHost, s), "objective");
+  HIP_OK(hipStreamSynchronize(s), "objective");
   return device_status(g.status);
 }
 

@@ -277,6 +277,9 @@ hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int
 template <typename T>
 hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, const AdjSlice& sl,
                         const T* E, const T* chi, double* dk_partial, double* dk, hipStream_t s);
+// (sigma_x, sigma_y, eps_x, eps_y) from the moments mom (mean 6, covariance upper 21) into
+// the device array out_m[4]
+hipError_t launch_objective(const double* mom, double* out_m, hipStream_t s);
 hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
                            double* lam, double* out_m, hipStream_t s);
 hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* partial, double* out,

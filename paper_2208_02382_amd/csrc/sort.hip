@@ -408,6 +408,7 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
   for (int a = 0; a <= S; ++a)
     for (int b = 0; b <= S; ++b) rowoff[a][b] = (a * Wy + b) * Wx;
   const int64_t n = c.n;
+  bool bin_fault = false;
   const uint32_t nck = *nchunks;
   for (uint32_t ci = blk; ci < nck; ci += nblk) {
     const int4 ch = chunks[ci];
@@ -428,7 +429,10 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
       int64_t r = i;
       if (perm) {
         r = perm[i];
-        if (r >= n) r = 0;  // impossible for a consistent ranking; keeps the read in bounds
+        if (r >= n) {  // impossible for a consistent ranking: flagged, the particle skipped
+          bin_fault = true;
+          continue;
+        }
       }
       double wx[S + 1], wy[S + 1], wz[S + 1];
       const int bx = stencil<S>((B[r] - o[0]) * ih[0], c.nx, wx);
@@ -437,6 +441,10 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
       const int lx = bx - ox, ly = by - oy, lz = bz - oz;
       const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
                           lz < sp.T[2];
+      // the binning put the particle in the chunk's tile with this very stencil function, so
+      // its stencil lies in the window; a violation is a library fault, flagged as the
+      // gather-kick flags it (PIC_EINTERNAL), and the particle is not deposited
+      if (!inside) bin_fault = true;
       if (inside) {
         // q_m 2^k w rounded to the nearest integer by one fused multiply-add with 1.5 2^52
         // (the sum then has the integer in its low mantissa bits, |value| < 2^51), read back
@@ -455,14 +463,6 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
             }
           }
         }
-      } else {
-        for (int a = 0; a <= S; ++a)
-          for (int b = 0; b <= S; ++b) {
-            const double wzy = wz[a] * wy[b];
-            for (int q = 0; q <= S; ++q)
-              add_global(&rho[((int64_t)(bz + a) * c.ny + (by + b)) * c.nx + (bx + q)],
-                         (T)(c.q_macro * (wzy * wx[q])));
-          }
       }
     }
     __syncthreads();
@@ -475,6 +475,7 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     }
     __syncthreads();
   }
+  if (bin_fault) atomicCAS(const_cast<int*>(&g->status), 0, -7);
 }
 
 // The charge grid from the tiles' integer windows: every node adds, in ascending tile order

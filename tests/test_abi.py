@@ -21,7 +21,7 @@ def _declared():
 
 def test_header_symbols_are_exported():
     names = _declared()
-    assert len(names) == 25
+    assert len(names) == 26
     lib = ctypes.CDLL(pic.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -123,6 +123,7 @@ def test_create_rejects_bad_arguments_without_touching_a_device():
     assert lib.pic_track_n_steps(None, None, 0, 0, None) == pic.PIC_EINVAL
     assert lib.pic_deposit(None, None, None) == pic.PIC_EINVAL
     assert lib.pic_moments(None, None, None, None) == pic.PIC_EINVAL
+    assert lib.pic_objective(None, None, None) == pic.PIC_EINVAL
     assert lib.pic_beam_destroy(None) == pic.PIC_OK
 
 

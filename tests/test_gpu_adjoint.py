@@ -5,12 +5,15 @@ import pytest
 import torch
 
 import workloads
+from margins import check, rel_max
 from oracle import adjoint as oadj
 from oracle import pic as opic
 
 pytestmark = pytest.mark.gpu
 
 W4 = np.array([0.7, -0.4, 1.3, 0.9])
+GRAD_TOL = 1e-10
+SIGMA_TOL = 1e-9
 LATTICE = ((1.0, 0.5), (-1.0, 0.5), (0.8, 0.45))
 
 
@@ -43,14 +46,17 @@ def test_reverse_sweep_matches_oracle(lib, n, nodes, shape, steps, ck):
     J, dk_o, lam_o, _ = oadj.adjoint(X0, ks, dss, steps, prob, W4)
     _, _, m_o = opic.moments(opic.track(X0, ks, dss, steps, prob))
     assert np.allclose(m, m_o, rtol=1e-12, atol=0)
-    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    tag = "adjoint-%d-%d" % (n, shape)
+    check(tag + "-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), GRAD_TOL)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lam_o[r]).max()
         if scale > 0:
-            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
+            check(tag + "-lam%d" % r, rel_max(lg[r], lam_o[r], scale), GRAD_TOL)
     dL_o = lam_o @ xi.T
-    assert np.abs(np.array(dL) - dL_o).max() < 1e-10 * np.abs(dL_o).max()
+    check(tag + "-dL", rel_max(dL, dL_o, np.abs(dL_o).max()), GRAD_TOL)
+    # the library's objective call gives the same four terms for the final state
+    assert np.allclose(b.objective(), m_o, rtol=1e-12, atol=0)
 
 
 def test_fp32_grid_reverse_sweep_close_to_fp64_oracle(lib):
@@ -80,9 +86,9 @@ def test_autograd_gradients_match_oracle(lib):
     Jo, dk_o, lam_o, _ = oadj.adjoint(L @ xi, ks, dss, 4, prob, W4)
     G_o = oadj.cholesky_grad(L, xi, lam_o)
     assert abs(J.item() - Jo) < 1e-12 * abs(Jo)
-    assert np.abs(k.grad.numpy() - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    check("autograd-dk", rel_max(k.grad.numpy(), dk_o, np.abs(dk_o).max()), GRAD_TOL)
     # torch returns dJ/dA for the full input matrix (symmetric); the oracle's G is the gradient
     # with respect to the symmetric parameters (off-diagonal pairs move together)
     g = S0.grad.numpy()
     G_t = g + g.T - np.diag(np.diag(g))
-    assert np.abs(G_t - G_o).max() < 1e-9 * np.abs(G_o).max()
+    check("autograd-dSigma0", rel_max(G_t, G_o, np.abs(G_o).max()), SIGMA_TOL)

@@ -33,5 +33,5 @@ def test_cold_uniform_ellipsoid_on_the_gpu(lib, direct_field):
     assert (np.abs(Xg - Xo).max(axis=1) / Xo.std(axis=1)).max() < 1e-12
     c0, c = np.cov(X0, bias=True), np.cov(Xg, bias=True)
     grown = np.sqrt(np.diag(c)[[0, 2, 4]] / np.diag(c0)[[0, 2, 4]])
-    ratio = env._envelope(prob, prob.q_macro * env.N)
+    ratio = env._envelope(prob, -charge)  # the configured bunch charge, electron sign
     assert np.all(np.abs((grown - 1.0) / (ratio - 1.0) - 1.0) < 0.02), (grown, ratio)

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import workloads
+from margins import check, rel_max
 from oracle import pic as opic
 
 pytestmark = pytest.mark.gpu
@@ -156,12 +157,12 @@ def test_reverse_sweep_with_the_direct_field(lib, shape, ck):
     m, dk, lam, _ = b.track_adjoint(lat, steps, w, ckpt_every=ck)
     J, dk_o, lam_o, _ = oadj.adjoint_elements(X0, lat, steps, _problem(cfg, n, nodes, shape), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
-    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    check("field-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-10)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lam_o[r]).max()
         if scale > 0:
-            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
+            check("field-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-10)
 
 
 @pytest.mark.timeout(900)

@@ -16,6 +16,7 @@ import pytest
 import torch
 
 import workloads
+from margins import check, rel_max
 from oracle import adjoint as oadj
 from oracle import pic as opic
 
@@ -159,10 +160,10 @@ def test_adjoint_workload_two_steps_against_oracle(lib):
     J, dko, lamo, _ = oadj.adjoint(X0, ks, dss, 2, _problem(cfg), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
     dk = np.array(dk)
-    assert np.abs(dk - dko).max() < 1e-10 * np.abs(dko).max()
+    check("fullsize-adjoint-dk", rel_max(dk, dko, np.abs(dko).max()), 1e-10)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lamo[r]).max()
         if scale > 0:
-            assert np.abs(lg[r] - lamo[r]).max() < 1e-10 * scale
+            check("fullsize-adjoint-lam%d" % r, rel_max(lg[r], lamo[r], scale), 1e-10)
     b.close()

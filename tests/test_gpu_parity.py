@@ -2,9 +2,9 @@
 
 Tolerances (float64 paths): 1e-12 relative to the largest magnitude of the compared array
 (grids, fields) or to the rms size of the coordinate (particles).  The two sides differ only
-in rounding: the deposit's summation order (pic_deposit's float atomics) or its fixed-point
-rounding (the tracking loop), the FFT's operation order, libm against the device math library,
-and fused multiply-adds.
+in rounding: the deposit's fixed-point rounding (every contribution is rounded to a multiple of
+a power of two before the exact integer sums of pic_deposit and the tracking loop), the FFT's
+operation order, libm against the device math library, and fused multiply-adds.
 """
 import numpy as np
 import pytest

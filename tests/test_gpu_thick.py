@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import workloads
+from margins import check, rel_max
 from oracle import pic as opic
 
 pytestmark = pytest.mark.gpu
@@ -137,12 +138,12 @@ def test_reverse_sweep_through_thick_elements(lib, shape, steps, ck):
                                               _problem(cfg, n, nodes, shape), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
     assert dk[0] == 0.0
-    assert np.abs(np.array(dk) - dk_o).max() < 1e-10 * np.abs(dk_o).max()
+    check("thick-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-10)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lam_o[r]).max()
         if scale > 0:
-            assert np.abs(lg[r] - lam_o[r]).max() < 1e-10 * scale
+            check("thick-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-10)
     # X holds the final state of the forward run, as pic_track_n_steps leaves it
     Xo = opic.track_elements(X0, ADJ_LATTICE, steps, _problem(cfg, n, nodes, shape))
     assert _coord_err(b.X.cpu().numpy(), Xo) < TOL

@@ -56,7 +56,7 @@ def test_cold_uniform_ellipsoid_follows_its_envelope(direct_field):
     X = opic.track(X0, [0.0], [LENGTH / STEPS], STEPS, prob)
     c0, c = np.cov(X0, bias=True), np.cov(X, bias=True)
     grown = np.sqrt(np.diag(c)[[0, 2, 4]] / np.diag(c0)[[0, 2, 4]])
-    ratio = _envelope(prob, prob.q_macro * N)
+    ratio = _envelope(prob, -1e-9)  # the configured bunch charge (1 nC of electrons)
     assert np.all(ratio > 3.0)                      # a strong, three-dimensional expansion
     assert np.all(np.abs((grown - 1.0) / (ratio - 1.0) - 1.0) < 0.02), (grown, ratio)
     # the linear force keeps the cold beam cold: rms emittance far below sigma * sigma'

@@ -27,13 +27,29 @@ def _beam(n, seed=0, sig=(1e-3, 1e-3, 2e-3)):
 
 @pytest.mark.parametrize("shape", [1, 2])
 def test_charge_conservation(shape):
+    # the grid holds the configured bunch charge, 1 nC with the electron's sign (Listing 1's
+    # add_particles(qm, charge_C, ...) takes the charge magnitude and the species' q/m); the
+    # expected total is written from that configuration, not from the problem's macro charge
     prob = _prob(shape=shape, n=5000)
     X = _beam(5000)
     geom = pic.geometry(X, prob)
     Q = pic.deposit(X, geom, prob)
-    total = prob.q_macro * X.shape[1]
-    assert abs(Q.sum() - total) < 1e-14 * abs(total)
+    assert abs(Q.sum() - (-1.0e-9)) < 1e-15 * 1.0e-9
     assert np.all(Q <= 0)  # electrons
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("n", [1, 7, 5000])
+def test_one_particle_carries_the_bunch_charge_over_n(shape, n):
+    # a single particle of an n-particle bunch deposits charge_C / n in total, spread by its
+    # shape over 2^3 (CIC) or 3^3 (TSC) nodes; a wrong factor or a missing 1/n fails here
+    prob = _prob(shape=shape, n=n)
+    X = _beam(50, seed=9)
+    geom = pic.geometry(X, prob)
+    for i in (0, 17, 49):
+        Q = pic.deposit(X[:, i:i + 1], geom, prob)
+        assert abs(Q.sum() - (-1.0e-9 / n)) < 1e-15 * 1.0e-9 / n
+        assert np.count_nonzero(Q) <= (shape + 1) ** 3
 
 
 def test_shape_values_at_special_points():
