@@ -183,6 +183,21 @@ struct StageProfiler {
   }
 };
 
+// The end of the last work a handle enqueued, so that its teardown can wait for it before it
+// destroys the streams, events and graph executables that work may still use.  HIP does not
+// promise that destroying a graph executable or an event in flight is safe.
+struct DoneEvent {
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  void mark(hipStream_t s) {
+    if (ev && hipEventRecord(ev, s) == hipSuccess) pending = true;
+  }
+  void wait() {
+    if (ev && pending) (void)hipEventSynchronize(ev);
+    pending = false;
+  }
+};
+
 struct pic_beam_s {
   pic_beam_desc d;
   StageProfiler prof;
@@ -224,20 +239,35 @@ struct pic_beam_s {
   // the Green spectrum of a step runs on `aux`, concurrently with the binning and deposit
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DoneEvent done;  // recorded on the caller's stream at the end of every enqueuing call
   ~pic_beam_s() {
+    // the caller's stream may still wait on ev_join and run kernels of this handle: wait for
+    // the last enqueued call and for the auxiliary stream before releasing them
+    done.wait();
+    if (aux) (void)hipStreamSynchronize(aux);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (done.ev) (void)hipEventDestroy(done.ev);
     if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
-// auxiliary stream (default priority) and fork / join events
-hipError_t make_aux(hipStream_t* aux, hipEvent_t* fork, hipEvent_t* join) {
+// auxiliary stream (default priority), fork / join events and the completion event
+hipError_t make_aux(hipStream_t* aux, hipEvent_t* fork, hipEvent_t* join, hipEvent_t* done) {
   hipError_t e = hipStreamCreateWithFlags(aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(done, hipEventDisableTiming);
   return e;
 }
+
+// records the handle's completion event on the call's stream when the call returns (whatever
+// it returns: a failed call may have enqueued part of its work)
+struct MarkDone {
+  DoneEvent& d;
+  hipStream_t s;
+  ~MarkDone() { d.mark(s); }
+};
 
 namespace {
 
@@ -794,11 +824,22 @@ struct pic_batch_s {
   std::vector<pic_beam> beams;
   BeamDev* table = nullptr;  // device, in the caller's batch workspace
   BatchDims bd;
-  std::vector<std::pair<int, hipGraphExec_t>> graphs;  // one instantiated graph per step count
+  struct Graph {
+    int n_steps;
+    hipGraphExec_t exec;
+    DoneEvent done;  // recorded after every launch of this graph, on the launch's stream
+  };
+  std::vector<Graph> graphs;  // one instantiated graph per step count
   hipStream_t aux = nullptr;  // Green spectra, forked from the captured stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~pic_batch_s() {
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    // a graph executable must not be destroyed while a launch of it may still run
+    for (auto& g : graphs) g.done.wait();
+    if (aux) (void)hipStreamSynchronize(aux);
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      if (g.done.ev) (void)hipEventDestroy(g.done.ev);
+    }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (aux) (void)hipStreamDestroy(aux);
@@ -893,11 +934,13 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   if (e == hipSuccess) e = launch_box_reset(b->box, s);
   if (e == hipSuccess) e = launch_zero<uint32_t>(b->hist, kMaxTiles, s);
   if (e == hipSuccess) e = launch_clear_status(b->geom, s);
-  if (e == hipSuccess) e = make_aux(&b->aux, &b->ev_fork, &b->ev_join);
+  if (e == hipSuccess) e = make_aux(&b->aux, &b->ev_fork, &b->ev_join, &b->done.ev);
   if (e != hipSuccess) {
+    if (b->done.ev == nullptr) (void)hipStreamSynchronize(s);  // the set-up kernels above
     delete b;
     return fail_hip(e, "beam set-up");
   }
+  b->done.mark(s);
   *out = b;
   return PIC_OK;
 }
@@ -910,6 +953,7 @@ pic_status pic_beam_destroy(pic_beam b) {
 pic_status pic_init_beam(pic_beam b, const double sigma[36], uint64_t seed, double halo_frac,
                          void* stream) {
   if (!b || !sigma) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   if (!(halo_frac >= 0.0 && halo_frac <= 1.0)) return fail(PIC_EINVAL, "halo_frac must be in [0, 1]");
   Chol L;
   if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
@@ -923,6 +967,7 @@ pic_status pic_init_beam(pic_beam b, const double sigma[36], uint64_t seed, doub
 pic_status pic_init_beam_waterbag(pic_beam b, const double sigma[36], uint64_t seed,
                                   void* stream) {
   if (!b || !sigma) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   Chol L;
   if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
   hipStream_t s = S(stream);
@@ -953,6 +998,7 @@ pic_status pic_sigma_from_params(const double p[9], double sigma[36]) {
 pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const double* d_xi,
                                       void* stream) {
   if (!b || !sigma || !d_xi) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   Chol L;
   if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
   hipStream_t s = S(stream);
@@ -963,6 +1009,7 @@ pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const 
 
 pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
   if (!b || !d_rho) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   HIP_OK(launch_box_reset(b->box, s), "deposit");
@@ -990,6 +1037,7 @@ pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
 
 pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d_E, void* stream) {
   if (!b || !d_rho || !d_E) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   void* phi = d_phi ? d_phi : b->phi;
   if (b->d.direct_field && d_phi) {  // phi as well: the potential's spectrum and solve
@@ -1015,6 +1063,7 @@ pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d
 
 pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream) {
   if (!b || !d_E || !d_Ep) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   if (b->d.grid_fp32)
     HIP_OK(launch_gather<float>(b->X, b->geom, (const float*)d_E, (float*)d_Ep, b->c, s), "gather");
@@ -1026,6 +1075,7 @@ pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream) {
 
 pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* stream) {
   if (!b) return fail(PIC_EINVAL, "NULL handle");
+  MarkDone md{b->done, S(stream)};
   if (kind != PIC_PUSH_DRIFT && kind != PIC_PUSH_THINQUAD && kind != PIC_PUSH_KICK)
     return fail(PIC_EINVAL, "unknown push kind");
   if (kind == PIC_PUSH_KICK && !d_Ep) return fail(PIC_EINVAL, "kick needs the particle field");
@@ -1042,6 +1092,7 @@ namespace {
 pic_status track(pic_beam b, const pic_element* lattice, int n_el, int n_steps, double* diag,
                  void* stream) {
   if (!b || !lattice) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   if (n_el < 1 || n_steps < 0) return fail(PIC_EINVAL, "n_el must be >= 1 and n_steps >= 0");
   std::vector<SliceDev> sl;
   const pic_status est = expand_lattice(lattice, n_el, sl);
@@ -1077,6 +1128,7 @@ pic_status pic_track_n_steps_diag(pic_beam b, const pic_element* lattice, int n_
 
 pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream) {
   if (!b || !mean || !cov) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "moments");
   double host[kMomentSlots];
@@ -1095,6 +1147,7 @@ pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream)
 
 pic_status pic_objective(pic_beam b, double out_m[4], void* stream) {
   if (!b || !out_m) return fail(PIC_EINVAL, "NULL argument");
+  MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "objective");
   HIP_OK(launch_objective(b->mom_out, b->mom_out + kMomentSlots, s), "objective");
@@ -1146,6 +1199,7 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (adj_work_bytes < A.total)
     return fail(PIC_ENOMEM, "reverse-sweep workspace smaller than pic_adjoint_workspace_bytes");
   hipStream_t s = S(stream);
+  MarkDone md{b->done, s};
   HIP_OK(clear_tacc(b, s), "clear");
   if (b->d.grid_fp32)
     return track_adjoint<float>(b, sl, n_el, n_steps, ckpt_every, w, (char*)d_adj_work, A,
@@ -1250,7 +1304,9 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
   HIP_OK(hipStreamSynchronize(s), "batch create");
   pic_batch bt = new (std::nothrow) pic_batch_s;
   if (!bt) return fail(PIC_EINVAL, "host allocation of the batch handle failed");
-  const hipError_t ea = make_aux(&bt->aux, &bt->ev_fork, &bt->ev_join);
+  hipEvent_t unused_done = nullptr;
+  const hipError_t ea = make_aux(&bt->aux, &bt->ev_fork, &bt->ev_join, &unused_done);
+  if (unused_done) (void)hipEventDestroy(unused_done);  // a batch keeps one per graph instead
   if (ea != hipSuccess) {
     delete bt;
     return fail_hip(ea, "batch create");
@@ -1270,10 +1326,11 @@ pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream) {
   if (n_steps < 1) return fail(PIC_EINVAL, "n_steps must be >= 1");
   if (!stream) return fail(PIC_EINVAL, "a batch is captured into a graph: pass a non-null stream");
   hipStream_t s = S(stream);
-  hipGraphExec_t exec = nullptr;
+  pic_batch_s::Graph* gr = nullptr;
   for (auto& g : bt->graphs)
-    if (g.first == n_steps) exec = g.second;
-  if (!exec) {
+    if (g.n_steps == n_steps) gr = &g;
+  if (!gr) {
+    hipGraphExec_t exec = nullptr;
     HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "batch capture");
     pic_status st =
         bt->fp32 ? enqueue_batch<float>(bt->table, bt->nb, bt->bd, bt->shape, n_steps, s, bt->aux,
@@ -1290,9 +1347,17 @@ pic_status pic_track_batch(pic_batch bt, int n_steps, void* stream) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail_hip(e, "batch graph instantiation");
-    bt->graphs.emplace_back(n_steps, exec);
+    hipEvent_t done = nullptr;
+    e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(exec);
+      return fail_hip(e, "batch graph event");
+    }
+    bt->graphs.push_back(pic_batch_s::Graph{n_steps, exec, DoneEvent{done, false}});
+    gr = &bt->graphs.back();
   }
-  HIP_OK(hipGraphLaunch(exec, s), "batch graph launch");
+  HIP_OK(hipGraphLaunch(gr->exec, s), "batch graph launch");
+  gr->done.mark(s);
   return PIC_OK;
 }
 

@@ -56,15 +56,15 @@ def test_chunk_size_and_workgroups_do_not_change_the_bits(lib):
     assert torch.equal(out[0], out[1])
 
 
-@pytest.mark.skip(reason="the test process ended in a host segmentation fault inside "
-                         "pic_track_batch once, right after a build that added batched "
-                         "direct-field kernels (since removed); the cause was not found, so this "
-                         "case is kept off the GPU; batches' reproducibility is covered by "
-                         "test_gpu_batch.py::test_batch_matches_single_beam_path (bit for bit)")
 def test_batch_runs_give_the_same_bits(lib):
+    # two batches of the same beams, one after the other; the first batch and its beams are torn
+    # down (Python's rebinding: after the second batch is created) before the second batch's
+    # first track() captures its graph, and the second batch is released right after its launch
+    # with no synchronisation (its teardown waits for the launch)
     mix = [(7_001, (16, 16, 16), 1.0), (12_000, (24, 24, 24), 1.6), (3_000, (12, 18, 24), 0.7)]
     out = []
-    for _ in range(2):
+    batch = None
+    for it in range(2):
         beams, lats = [], []
         for j, (n, nodes, k) in enumerate(mix):
             cfg = workloads.MEDIUM.with_(n=n, nodes=nodes, lattice=((k, 0.5), (-k, 0.5)))
@@ -73,7 +73,10 @@ def test_batch_runs_give_the_same_bits(lib):
             lats.append(cfg.lattice)
         batch = lib.Batch(beams, lats)
         batch.track(8)
+        if it == 1:
+            batch.close()
         torch.cuda.synchronize()
+        assert all(b.check() == lib.PIC_OK for b in beams)
         out.append([b.X.clone() for b in beams])
     for a, b in zip(*out):
         assert torch.equal(a, b)
