@@ -5,6 +5,9 @@ the oracle can compute one by one.
   step on the GPU; the oracle deposits all particles (in chunks), solves on the full grid and
   pushes a random sample of particles, which must agree within 1e-12 of each coordinate's rms.
   The same for one slice of the paper's thick focusing quadrupole.
+* The same grid, shape and launch shapes on 4e6 particles over 3 steps, so that the steady-state
+  path runs (ranking only, permutation reads, two-ended slot order, tiles of several work
+  items): every coordinate of every particle against the oracle's tracking.
   The float32-grid variant at the same size: rms sizes and emittances within 1e-5 of float64.
 * The batched workload (256 beams, 6.5e7 particles, one graph): two steps; its four smallest
   beams against the oracle within 1e-12.
@@ -75,6 +78,55 @@ def test_headline_size_one_step_on_sampled_particles(lib):
     Xo = opic.drift(opic.kick(Xs, opic.gather(E, Xs, geom, prob), L, prob), 0.5 * L, prob)
     scale = X1[:, ::97].std(axis=1)
     assert _coord_err(X1[:, S], Xo, scale) < TOL
+
+
+def _tile_counts(X, prob, tile):
+    """Particles per tile (tile = nodes per tile along x, y, z) of the kick-point positions X,
+    by the stencil's lowest node under the oracle's geometry: a coverage check of the test."""
+    geom = opic.geometry(X, prob)
+    ntile = [-(-n // t) for n, t in zip(prob.nodes, tile)]
+    t = []
+    for a, row in enumerate((0, 2, 4)):
+        u = (X[row] - geom.origin[a]) / geom.h[a]
+        base = np.floor(u + 0.5) - 1 if prob.shape == 2 else np.floor(u)
+        t.append(base.astype(np.int64) // tile[a])
+    return np.bincount(t[0] + ntile[0] * (t[1] + ntile[1] * t[2]))
+
+
+def test_headline_grid_steady_state_tracking_against_oracle(lib):
+    # The launch configuration the bench times (128^3 nodes, TSC, 10 % halo, the committed
+    # tuning of the 1e8-particle workload: 32 x 16 x 2 tiles, 16384 particles per work item,
+    # 512 threads) on 4e6 particles over 3 steps.  Step 1 moves the caller's particles into
+    # tile order; steps 2 and 3 take the steady-state path: ranking only, deposit and
+    # gather-kick through the permutation with the two-ended slot order, core tiles of
+    # several work items, per-tile integer windows.  Every coordinate of every particle is
+    # compared with the oracle's tracking.
+    from paper_2208_02382_amd import autotune
+    big = workloads.LARGE
+    cfg = big.with_(n=4_000_000)
+    tuning = autotune.lookup(big.n, big.nodes, big.shape, False)
+    assert tuning is not None, "no committed tuning for the 1e8 TSC workload"
+    xi = workloads.draw_xi(cfg)
+    b = lib.Beam.from_config(cfg, tuning=tuning)
+    b.init_from_normals(cfg.sigma_matrix, torch.from_numpy(xi).cuda())
+    del xi
+    X0 = b.X.cpu().numpy()
+    b.track(cfg.lattice, 3)
+    X3 = b.X.cpu().numpy()
+    assert b.check() == lib.PIC_OK
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    prob = _problem(cfg)
+    ks, dss = workloads.lattice_arrays(cfg)
+    # coverage: at the second step's kick point some tiles hold several work items
+    X1 = opic.track(X0, ks, dss, 1, prob)
+    X1k = opic.drift(opic.thin_quad(X1, ks[1]), 0.5 * dss[1], prob)
+    counts = _tile_counts(X1k, prob, tuning["tile"])
+    del X1k
+    assert counts.max() > 2 * tuning["chunk"], counts.max()
+    Xo = opic.track(X1, np.roll(ks, -1), np.roll(dss, -1), 2, prob)
+    check("headline-grid-4e6-3steps", _coord_err(X3, Xo, Xo.std(axis=1)), TOL)
 
 
 def test_headline_size_thick_quadrupole_slice_on_sampled_particles(lib):
