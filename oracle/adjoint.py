@@ -4,10 +4,14 @@ Gradients of J = sum_k w_k m_k, m = (sigma_x, sigma_y, eps_x, eps_y) of the fina
 respect to the thin-quad strengths k_j, the initial coordinates X0 and, through X0 = L xi with
 L the Cholesky factor, the initial second-moment matrix Sigma0.
 
-Reading (the paper gives no differentiation; this is the project's addition): the grid
-geometry of every step is frozen to the one of the unperturbed forward run, so the tracked map
-is smooth almost everywhere (CIC weights have kinks at nodes, TSC weights at cell boundaries
-in the second derivative only).  The adjoint of each linear operation is its transpose:
+Reading (the paper gives no differentiation; this is the project's addition): the gradient is
+that of the tracked map, whose grid geometry follows the particles: every step the box is the
+min / max of the kick-point positions, h_a = (max_a - min_a)/(n_a - 3.5) and
+origin_a = min_a - 1.25 h_a.  The map is smooth almost everywhere (CIC weights have kinks at
+nodes, TSC weights at cell boundaries in the second derivative only, and the box changes its
+extreme particle on a set of measure zero).  With per-step geometries passed in (`geoms`) the
+geometry is frozen instead and its terms below are left out.  The adjoint of each linear
+operation is its transpose:
 
 * drift l:        lam_px += l lam_x, lam_py += l lam_y, lam_delta += (l/gamma^2) lam_z
 * thin quad k:    lam_x -= k lam_px, lam_y += k lam_py;   dJ/dk += sum(-x lam_px + y lam_py)
@@ -19,6 +23,16 @@ in the second derivative only).  The adjoint of each linear operation is its tra
                                lam_r,i += q_m sum_n grad W(r_i - r_n) chi_n
   grad W is taken with respect to the lab position (du/dx = 1/h).
 
+* the geometry (geometry_adjoint): with g_i the position gradient through the weights above
+  (direct + through the charge) and u_i = (x_i - origin)/h,
+    dJ/dorigin_a = -sum_i g_i,a,   dJ/dh_a += -sum_i g_i,a u_i,a            (weights)
+    dJ/dh'_b    += -sum_n e_b(n) E'_b(n) / h'_b                            (centred difference)
+    dJ/dh'_b    += sum_n Q_n (dGbar/dh'_b * psi)_n / (4 pi eps0)           (Green's function)
+  (direct field: dJ/dh'_b = sum_a sum_n e_a(n) (dKbar_a/dh'_b * Q)(n) / (4 pi eps0)), with the
+  rest-frame cell h' = (hx, hy, gamma hz) and the kernels' h-derivatives of igf; then through
+  h_a = (max_a - min_a)/(n_a - 3.5), origin_a = min_a - 1.25 h_a onto the kick-point
+  coordinate of the particle that attains the min (the first one, as numpy's argmin) and of
+  the one that attains the max
 * thick quadrupole half map M(k) per plane: lam <- M^T lam; dJ/dk += lam_after . (dM/dk) X_before
   (adjoint_elements, lattices of Drift / Quad / thin elements cut into slices)
 * with the direct field (Problem.direct_field) the charge's adjoint is chi = -1/(4 pi eps0)
@@ -27,7 +41,7 @@ in the second derivative only).  The adjoint of each linear operation is its tra
 
 Pinned by tests/test_oracle_adjoint.py: dot-product tests of every transposed operation,
 central finite differences on small beams with space charge (thin lattices and lattices of
-thick elements), the closed-form gradient of the zero-current (linear) map, the
+thick elements), of the tracking with the geometry following the particles and with it frozen, the closed-form gradient of the zero-current (linear) map, the
 k-derivative of the quadrupole matrix against central differences and its k -> 0 limit, and
 the transposed field solve by a dot product and central differences with the direct field.
 """
@@ -175,6 +189,64 @@ def objective_grad(X, w):
     return lam
 
 
+# ----------------------------------------------------------------------------- geometry
+
+def geometry_adjoint(g, X2, geom, prob, e, E, Q, kernel):
+    """(dJ/dmin (3,), dJ/dmax (3,)) of the box of the kick-point positions X2.
+
+    g: (3, n) gradient of J with respect to the kick-point positions through the deposit's and
+    the gather's weights at fixed geometry; e: dJ/dE' on the nodes (the vector deposit of the
+    kick's adjoint); E: the step's E'; Q: its charge grid; kernel: Gbar (potential) or the
+    three Kbar_a (direct field)."""
+    nodes = np.asarray(prob.nodes, dtype=np.float64)
+    h, o, hr = geom.h, geom.origin, geom.h_rest
+    dJ_do = np.empty(3)
+    dJ_dh = np.empty(3)
+    for a, row in enumerate((0, 2, 4)):
+        u = (X2[row] - o[a]) / h[a]
+        dJ_do[a] = -np.sum(g[a])
+        dJ_dh[a] = -np.sum(g[a] * u)
+    nx, ny, nz = prob.nodes
+    dJ_dhr = np.zeros(3)
+    if prob.direct_field:
+        for b in range(3):
+            dK = [igf.field_cell_average_dh(nx, ny, nz, *hr, a, b) for a in range(3)]
+            dE = pic.solve_field(Q, dK)
+            dJ_dhr[b] = np.sum(e * dE)
+    else:
+        psi = divergence_T(e, geom)
+        for b in range(3):
+            dJ_dhr[b] = -np.sum(e[b] * E[b]) / hr[b]
+            dG = igf.cell_average_dh(nx, ny, nz, *hr, b)
+            dJ_dhr[b] += np.sum(Q * solve_ghost_source(psi, dG))
+    dJ_dh += dJ_dhr * np.array([1.0, 1.0, prob.gamma])
+    # h = (max - min)/(n - 3.5), origin = min - 1.25 h
+    dJ_dmin = dJ_do * (1.0 + 1.25 / (nodes - 3.5)) - dJ_dh / (nodes - 3.5)
+    dJ_dmax = -dJ_do * 1.25 / (nodes - 3.5) + dJ_dh / (nodes - 3.5)
+    return dJ_dmin, dJ_dmax
+
+
+def _kick_adjoint(lam, X2, geom, E, kernel, Q, ell, prob, follow_geometry):
+    """lam at the kick point: adds the kick's position terms (direct, through the charge and,
+    when the geometry follows the particles, through the box) to lam, which enters as the
+    adjoint of the state after the kick."""
+    A = np.stack([prob.C * ell * lam[1], prob.C * ell * lam[3],
+                  prob.gamma * prob.C * ell * lam[5]])
+    direct = grad_gather_dot(E, A, X2, geom, prob)
+    e = vector_deposit(A, X2, geom, prob)
+    chi = _charge_adjoint(e, geom, kernel, prob)
+    g = direct + prob.q_macro * grad_gather(chi, X2, geom, prob)
+    lam = lam.copy()
+    for c, row in enumerate((0, 2, 4)):
+        lam[row] = lam[row] + g[c]
+    if follow_geometry:
+        dmin, dmax = geometry_adjoint(g, X2, geom, prob, e, E, Q, kernel)
+        for c, row in enumerate((0, 2, 4)):
+            lam[row, np.argmin(X2[row])] += dmin[c]
+            lam[row, np.argmax(X2[row])] += dmax[c]
+    return lam
+
+
 # ----------------------------------------------------------------------------- sweeps
 
 def _green_and_field(Q, geom, prob):
@@ -199,7 +271,7 @@ def _charge_adjoint(e, geom, kernel, prob):
 def forward(X0, ks, dss, n_steps, prob, geoms=None, space_charge=True):
     """Tracking as oracle.pic.track, optionally with frozen per-step geometries.  Returns the
     final state and, per step, (state at the step start, state at the kick point, geometry,
-    E' grid)."""
+    E' grid, kernel, charge grid)."""
     rec = []
     X = X0
     n_el = len(ks)
@@ -213,10 +285,10 @@ def forward(X0, ks, dss, n_steps, prob, geoms=None, space_charge=True):
             gbar, E = _green_and_field(Q, geom, prob)
             Ep = pic.gather(E, X2, geom, prob)
             X3 = pic.kick(X2, Ep, L, prob)
-            rec.append((X, X2, geom, E, gbar))
+            rec.append((X, X2, geom, E, gbar, Q))
         else:
             X3 = X2
-            rec.append((X, X2, None, None, None))
+            rec.append((X, X2, None, None, None, None))
         X = pic.drift(X3, 0.5 * L, prob)
     return X, rec
 
@@ -229,17 +301,10 @@ def adjoint(X0, ks, dss, n_steps, prob, w, geoms=None, space_charge=True):
     dk = np.zeros(n_el)
     for j in range(n_steps - 1, -1, -1):
         K, L = ks[j % n_el], dss[j % n_el]
-        Xs, X2, geom, E, gbar = rec[j]
+        Xs, X2, geom, E, gbar, Q = rec[j]
         lam = drift_T(lam, 0.5 * L, prob)
         if space_charge:
-            A = np.stack([prob.C * L * lam[1], prob.C * L * lam[3],
-                          prob.gamma * prob.C * L * lam[5]])
-            direct = grad_gather_dot(E, A, X2, geom, prob)
-            e = vector_deposit(A, X2, geom, prob)
-            chi = _charge_adjoint(e, geom, gbar, prob)
-            via_rho = prob.q_macro * grad_gather(chi, X2, geom, prob)
-            for c, row in enumerate((0, 2, 4)):
-                lam[row] = lam[row] + direct[c] + via_rho[c]
+            lam = _kick_adjoint(lam, X2, geom, E, gbar, Q, L, prob, geoms is None)
         lam = drift_T(lam, 0.5 * L, prob)
         dk[j % n_el] += float(np.sum(-Xs[0] * lam[1] + Xs[2] * lam[3]))
         lam = quad_T(lam, K)
@@ -286,7 +351,7 @@ def _slices_indexed(elements):
 def forward_elements(X0, elements, n_steps, prob, geoms=None, space_charge=True):
     """Tracking as pic.track_elements (one slice per step, cycled), optionally with frozen
     per-step geometries.  Per step: (state at the start, after the first half map, after the
-    kick, geometry, E' grid, Gbar)."""
+    kick, geometry, E' grid, kernel, charge grid)."""
     sl = _slices_indexed(elements)
     rec = []
     X = X0
@@ -298,12 +363,13 @@ def forward_elements(X0, elements, n_steps, prob, geoms=None, space_charge=True)
             X1 = pic.half_map(X, kind, k, ell, prob)
         if space_charge:
             geom = geoms[j] if geoms is not None else pic.geometry(X1, prob)
-            gbar, E = _green_and_field(pic.deposit(X1, geom, prob), geom, prob)
+            Q = pic.deposit(X1, geom, prob)
+            gbar, E = _green_and_field(Q, geom, prob)
             X2 = pic.kick(X1, pic.gather(E, X1, geom, prob), ell, prob)
         else:
-            geom = E = gbar = None
+            geom = E = gbar = Q = None
             X2 = X1
-        rec.append((X, X1, X2, geom, E, gbar))
+        rec.append((X, X1, X2, geom, E, gbar, Q))
         X = pic.drift(X2, 0.5 * ell, prob) if kind == pic.THIN else \
             pic.half_map(X2, kind, k, ell, prob)
     return X, rec
@@ -320,20 +386,13 @@ def adjoint_elements(X0, elements, n_steps, prob, w, geoms=None, space_charge=Tr
     dk = np.zeros(len(elements))
     for j in range(n_steps - 1, -1, -1):
         kind, k, ell, e = sl[j % len(sl)]
-        Xs, X1, X2, geom, E, gbar = rec[j]
+        Xs, X1, X2, geom, E, gbar, Q = rec[j]
         # second half map X2 -> X_{j+1}
         if kind == pic.QUAD:
             dk[e] += _quad_dk(lam, X2, k, ell)
         lam = _half_T(lam, kind, k, ell, prob)
         if space_charge:
-            A = np.stack([prob.C * ell * lam[1], prob.C * ell * lam[3],
-                          prob.gamma * prob.C * ell * lam[5]])
-            direct = grad_gather_dot(E, A, X1, geom, prob)
-            eg = vector_deposit(A, X1, geom, prob)
-            chi = _charge_adjoint(eg, geom, gbar, prob)
-            via_rho = prob.q_macro * grad_gather(chi, X1, geom, prob)
-            for c, row in enumerate((0, 2, 4)):
-                lam[row] = lam[row] + direct[c] + via_rho[c]
+            lam = _kick_adjoint(lam, X1, geom, E, gbar, Q, ell, prob, geoms is None)
         # first half map Xs -> X1
         if kind == pic.THIN:
             lam = drift_T(lam, 0.5 * ell, prob)

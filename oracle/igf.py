@@ -166,6 +166,103 @@ def field_cell_average(nx, ny, nz, hx, hy, hz, axis):
     return dd.to_float(dd.div(D, vol))
 
 
+# ----------------------------------------------------------------------------- h-derivatives
+# The kernels depend on the rest-frame cell (hx, hy, hz), which the grid geometry takes from the
+# particles' box every step; the reverse sweep needs their derivatives in h.  For the cell
+# average of f over the cell centred at n h, substituting r = h s (s over the unit cell around
+# n) gives d/dh_b avg(f) = (1/h_b) avg(r_b df/dr_b), and integrating by parts in r_b,
+#     avg(r_b df/dr_b) = (1/V) [r_b (integral of f over the face normal to b)] - avg(f),
+# the bracket being the alternating sum over the two faces.  With the face integral written as
+# an alternating sum over the face's corners of a 2-D antiderivative, both parts are 8-corner
+# sums of one corner function C, so d/dh_b avg(f) = (fold / (V h_b)) * (8-corner sum of C),
+# with the same folding of index-0 cells as the kernel itself.
+
+
+def _corner_grid(nx, ny, nz, hx, hy, hz):
+    """The corner coordinates (x, y, z) of the octant's cells as broadcast double-doubles."""
+    ex = _corner_coords(nx, hx)
+    ey = _corner_coords(ny, hy)
+    ez = _corner_coords(nz, hz)
+    shape = (nz + 2, ny + 2, nx + 2)
+    Z = tuple(np.broadcast_to(c[:, None, None], shape) for c in ez)
+    Y = tuple(np.broadcast_to(c[None, :, None], shape) for c in ey)
+    X = tuple(np.broadcast_to(c[None, None, :], shape) for c in ex)
+    return X, Y, Z
+
+
+def _corner_sum_over_vh(Cc, fold, hx, hy, hz, hb):
+    """(fold / (hx hy hz hb)) * (alternating 8-corner sum of the corner values Cc), rounded to
+    float64 once; fold has the cells' shape (nz+1, ny+1, nx+1)."""
+    D = dd.sub((Cc[0][:, :, 1:], Cc[1][:, :, 1:]), (Cc[0][:, :, :-1], Cc[1][:, :, :-1]))
+    D = dd.sub((D[0][:, 1:, :], D[1][:, 1:, :]), (D[0][:, :-1, :], D[1][:, :-1, :]))
+    D = dd.sub((D[0][1:, :, :], D[1][1:, :, :]), (D[0][:-1, :, :], D[1][:-1, :, :]))
+    D = (D[0] * fold, D[1] * fold)
+    den = dd.mul(dd.mul(dd.two_prod(np.float64(hx), np.float64(hy)), dd.dd(np.float64(hz))),
+                 dd.dd(np.float64(hb)))
+    den = (np.full(D[0].shape, den[0]), np.full(D[0].shape, den[1]))
+    return dd.to_float(dd.div(D, den))
+
+
+def cell_average_dh(nx, ny, nz, hx, hy, hz, b):
+    """d Gbar / d h_b (b = 0, 1, 2 for hx, hy, hz) on the octant, shape (nz+1, ny+1, nx+1).
+
+    With f = 1/r: r_b df/dr_b = -r_b^2/r^3; the face integral of 1/r is the corner sum of
+    field_antiderivative H_b (d^2 H_b / dv dw = 1/r), and the cell integral of 1/r that of F,
+    so the corner function is r_b H_b - F.  Even along every axis (index-0 cells folded with
+    weight 2).  Identity: sum_b h_b dGbar/dh_b = -Gbar (Gbar is homogeneous of degree -1)."""
+    U = _corner_grid(nx, ny, nz, hx, hy, hz)
+    Fc = antiderivative(*U)
+    Hb = field_antiderivative(U[b], U[(b + 1) % 3], U[(b + 2) % 3])
+    Cc = dd.sub(dd.mul(U[b], Hb), Fc)
+    fold = np.ones((nz + 1, ny + 1, nx + 1))
+    fold[0, :, :] *= 2.0
+    fold[:, 0, :] *= 2.0
+    fold[:, :, 0] *= 2.0
+    return _corner_sum_over_vh(Cc, fold, hx, hy, hz, (hx, hy, hz)[b])
+
+
+def field_cell_average_dh(nx, ny, nz, hx, hy, hz, axis, b):
+    """d Kbar_axis / d h_b on the octant, shape (nz+1, ny+1, nx+1), with Kbar_a the cell
+    average of u_a/|r|^3 (field_cell_average).
+
+    f = u_a/r^3.  The cell integral of f is minus the corner sum of H_a (field_antiderivative
+    with u = u_a).  The face integral normal to b: for b = a, over (v, w), of u/r^3, whose 2-D
+    antiderivative is atan(v w/(u r)); for b != a, over (u_a, u_c) (c the third axis), of
+    u_a/r^3, whose antiderivative is -ln(u_c + r).  The corner function is therefore
+    u_a atan(v w/(u_a r)) + H_a for b = a and -u_b ln(u_c + r) + H_a otherwise (a term with a
+    zero prefactor taken as zero).  Odd along `axis`, even along the others, folded as
+    Kbar_a.  Identity: sum_b h_b dKbar_a/dh_b = -2 Kbar_a (homogeneous of degree -2)."""
+    U = _corner_grid(nx, ny, nz, hx, hy, hz)
+    a = axis
+    u, v, w = U[a], U[(a + 1) % 3], U[(a + 2) % 3]
+    Ha = field_antiderivative(u, v, w)
+    r = dd.sqrt(dd.add(dd.add(dd.mul(u, u), dd.mul(v, v)), dd.mul(w, w)))
+
+    def zero_where(t, mask):
+        return np.where(mask, 0.0, t[0]), np.where(mask, 0.0, t[1])
+
+    def safe(t, mask):
+        return np.where(mask, 1.0, t[0]), np.where(mask, 0.0, t[1])
+
+    if b == a:
+        uz = u[0] == 0
+        t = zero_where(dd.mul(u, dd.atan(dd.div(dd.mul(v, w), safe(dd.mul(u, r), uz)))), uz)
+    else:
+        c = 3 - a - b
+        ub, uc = U[b], U[c]
+        bz = ub[0] == 0
+        # u_c + r > 0 unless u_c = r = 0, where u_b = 0 too
+        t = zero_where(dd.mul(ub, dd.log(safe(dd.add(uc, r), bz))), bz)
+        t = (-t[0], -t[1])
+    Cc = dd.add(t, Ha)
+    fold = np.ones((nz + 1, ny + 1, nx + 1))
+    for q in range(3):
+        idx = [slice(None)] * 3
+        idx[2 - q] = 0          # array axes are (z, y, x)
+        fold[tuple(idx)] *= 0.0 if q == a else 2.0
+    return _corner_sum_over_vh(Cc, fold, hx, hy, hz, (hx, hy, hz)[b])
+
+
 def hockney_array_field(kbar, axis):
     """Place Kbar_axis in the (2nz, 2ny, 2nx) cyclic array: even along the other axes as in
     hockney_array, odd along `axis` (index t holds Kbar(t) for t < n, -Kbar(M - t) for t > n,
