@@ -288,6 +288,20 @@ pic_status pic_moments(pic_beam b, double mean[6], double cov[36], void* stream)
  * Synchronises `stream`; PIC_EDOMAIN if the device error flag is set. */
 pic_status pic_objective(pic_beam b, double out_m[4], void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): the beam statistics of pic_moments for a phase-space array
+ * d_X (6*n doubles in the layout of X, device, 8-byte aligned, 1 <= n < 2^31) with no handle
+ * and no workspace.  d_out (device, 27 doubles, 8-byte aligned, caller-owned) receives the six
+ * means of (x, px, y, py, z, delta), then the 21 centred second moments <d_a d_b> (1/n) for
+ * a <= b in row-major order of the upper triangle, the layout of pic_track_n_steps_diag; the
+ * values equal pic_moments' bit for bit (same kernels, same reduction shape).  The reduction's
+ * partial sums live in a fixed 221 KB device array inside the library (one per GPU, held
+ * until the process ends); the call allocates nothing, does not synchronise and only enqueues
+ * four kernels on `stream`.  Calls that overlap on one GPU (different streams without
+ * ordering) race on that array.  PIC_EINVAL for a NULL or misaligned pointer or n outside
+ * 1 .. 2^31 - 1; PIC_EHIP if a launch fails. */
+pic_status pic_moments_noalloc(const double* d_X, int64_t n, double* d_out, void* stream);
+
 /* Geometry of the last deposit: out[0..2] origin (x, y, z) [m], out[3..5] lab spacings,
  * out[6..8] rest-frame spacings (hx, hy, gamma hz).  Synchronises `stream`. */
 pic_status pic_get_geometry(pic_beam b, double out[9], void* stream);

@@ -65,6 +65,7 @@ _SIGS = {
     "pic_track_n_steps_diag": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P, _P]),
     "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "pic_objective": (_I, [_P, ctypes.POINTER(_D), _P]),
+    "pic_moments_noalloc": (_I, [_P, ctypes.c_int64, _P, _P]),
     "pic_get_geometry": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_check": (_I, [_P, _P]),
     "pic_profile_start": (_I, [_P]),
@@ -102,6 +103,20 @@ def _check(status, where):
 
 def last_error():
     return _lib.pic_last_error().decode()
+
+
+def moments_noalloc(X, out=None):
+    """pic_moments_noalloc: the 27 moments (6 means, then the 21 centred second moments, upper
+    triangle row-major) of a float64 phase-space tensor X of shape (6, n) on the device, into
+    `out` (a float64 device tensor of 27 entries, allocated here if not given), with no
+    workspace; enqueued on torch's current stream."""
+    assert X.dtype == torch.float64 and X.is_contiguous() and X.dim() == 2 and X.shape[0] == 6
+    if out is None:
+        out = torch.empty(27, dtype=torch.float64, device=X.device)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 27
+    _check(_lib.pic_moments_noalloc(_ptr(X), int(X.shape[1]), _ptr(out), _stream()),
+           "pic_moments_noalloc")
+    return out
 
 
 def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,

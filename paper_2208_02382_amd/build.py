@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 # host build of the device double-double / IGF arithmetic, for CPU unit tests only
 HOSTCHECK = os.path.join(HERE, "libpic_hostcheck.so")
-SOURCES = ["particles.hip", "sort.hip", "igf.hip", "fft.hip", "adjoint.hip", "api.cpp"]
+SOURCES = ["particles.hip", "sort.hip", "igf.hip", "fft.hip", "adjoint.hip", "noalloc.hip",
+           "api.cpp"]
 
 # -Xclang -target-feature -Xclang -packed-fp32-ops: no packed FP32 instructions are emitted.
 # -munsafe-fp-atomics: float atomic adds map to the hardware global_atomic_add_f32/f64.

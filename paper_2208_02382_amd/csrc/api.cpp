@@ -30,6 +30,15 @@ pic_status fail_hip(hipError_t e, const char* where) {
   return PIC_EHIP;
 }
 
+}  // namespace
+
+namespace pic {
+int record_failure(int status, const char* msg) { return fail((pic_status)status, msg); }
+int record_hip_failure(hipError_t e, const char* where) { return fail_hip(e, where); }
+}  // namespace pic
+
+namespace {
+
 #define HIP_OK(call, where)                       \
   do {                                            \
     hipError_t e_ = (call);                       \

@@ -144,6 +144,11 @@ constexpr int kAdjBlocks = 1024;      // grid of the reverse-sweep particle kern
 constexpr int kMaxLattice = 1024;     // lattice elements of the reverse sweep
 constexpr int kMomentSlots = 27;      // 6 sums + 21 centred products
 
+// record a failure as the calling thread's pic_last_error() message and return `status`
+// (api.cpp); the HIP form also clears the runtime's sticky error of a rejected call
+int record_failure(int status, const char* msg);
+int record_hip_failure(hipError_t e, const char* where);
+
 // return a failing hipError_t from the enclosing launcher
 #define PIC_TRY(x)                   \
   do {                               \
