@@ -254,8 +254,12 @@ size_t pic_adjoint_workspace_bytes(const pic_beam_desc* d, int n_steps, int ckpt
 /* Reverse sweep (discrete adjoint) of n_steps steps of pic_track_n_steps.  The paper gives no
  * differentiation; its machine-learning coupling is only named (sections "Software Design",
  * "ImpactX").  Objective J = w[0] sigma_x + w[1] sigma_y + w[2] eps_x + w[3] eps_y of the final
- * beam (centred rms sizes and geometric emittances).  The grid geometry of each step is frozen
- * to the forward run's.
+ * beam (centred rms sizes and geometric emittances).  The gradient is that of the tracking as
+ * pic_track_n_steps runs it, whose grid geometry follows the particles: every step's box
+ * (min / max of the kick-point positions) sets origin and spacing, and the terms through them
+ * (deposit and gather weights, the centred difference, the Green's function or field kernels'
+ * dependence on the cell) reach the particles at the box's faces.  Where two particles tie for
+ * a box face, the one with the lower index takes the term (the map has a kink there).
  * On entry X holds X0; on return X holds the final state (the forward pass, run in the
  * caller's particle order) and
  *   out_m[4]     (sigma_x, sigma_y, eps_x, eps_y) of the final state (host),

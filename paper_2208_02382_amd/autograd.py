@@ -3,7 +3,8 @@
 The forward pass initialises X0 = L xi on the device (L = chol(Sigma0), from torch so that
 torch's Cholesky backward carries dJ/dL to dJ/dSigma0) and runs pic_track_n_steps; the backward
 pass re-initialises X0 and runs the library's reverse sweep (pic_track_adjoint), which returns
-dJ/dk and dJ/dL = sum_i lam0_i xi_i^T.  Argument marshalling only: the tracking, the moments, the
+dJ/dk and dJ/dL = sum_i lam0_i xi_i^T: the gradient of the tracking itself, including the terms
+through every step's grid geometry, which follows the particles' box.  Argument marshalling only: the tracking, the moments, the
 objective terms (pic_objective) and both reductions run in the library's kernels.
 """
 import torch

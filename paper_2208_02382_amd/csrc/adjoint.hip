@@ -2,8 +2,9 @@
 //
 // Gradients of J = w . (sigma_x, sigma_y, eps_x, eps_y) of the final beam with respect to the
 // lattice elements' strengths, the initial coordinates and (given the draws xi of X0 = L xi)
-// the Cholesky factor L.  The grid geometry of every step is frozen to the forward run's.  Each
-// linear operation is replaced by its transpose (apply_half_T for the half maps):
+// the Cholesky factor L.  Every step's grid geometry follows the particles (the box of the
+// kick-point positions sets origin and spacing), and its terms are part of the gradient (below).
+// Each linear operation is replaced by its transpose (apply_half_T for the half maps):
 //   drift l          lam_px += l lam_x, lam_py += l lam_y, lam_delta += (l/gamma^2) lam_z
 //   thin quad k      lam_x -= k lam_px, lam_y += k lam_py;  dJ/dk += sum(-x lam_px + y lam_py)
 //   quadrupole half map M(k) per plane: lam <- M^T lam;  dJ/dk += sum lam_after . (dM/dk) x_before
@@ -13,6 +14,16 @@
 //                    e = sum_i W a_i (vector deposit, k_adj_a); psi = -sum_c D_c^T e_c on nodes
 //                    -1..n (k_adj_div); chi = Gbar * psi / (4 pi eps0) on nodes 0..n-1
 //                    (transposed solve, fft.hip); lam_r,i += q_m sum_n grad W(r_i - r_n) chi_n
+//   geometry         with g_i the position gradient through the weights (the two terms above)
+//                    and u_i = (r_i - origin)/h: dJ/dorigin_a = -sum g_i,a and
+//                    dJ/dh_a = -sum g_i,a u_i,a (k_adj_b's block sums); dJ/dh'_b gets
+//                    -sum_n e_b E'_b / h'_b (the centred difference) and
+//                    sum_n Q_n (dGbar/dh'_b * psi)_n / (4 pi eps0) (the Green's function), or with
+//                    the direct field sum_a sum_n e_a (dKbar_a/dh'_b * Q) / (4 pi eps0); h' is
+//                    the rest-frame cell (h'_z = gamma h_z).  Through h = (max - min)/(n - 3.5)
+//                    and origin = min - 1.25 h these go to the kick-point coordinate of the
+//                    particle at the box's min (the first such index) and of the one at its
+//                    max (k_adj_geom, which also carries them through the first half map).
 // The kick-point positions are rebuilt from the stored step-start state with the same
 // expressions as the forward kernels (the slice's first half map).
 #include "device_common.hpp"
@@ -71,6 +82,112 @@ __device__ __forceinline__ void block_partial(double acc, double* __restrict__ p
   }
 }
 
+// Running extremes of the kick-point positions with the first index attaining each:
+// slots 0..2 the min of x, y, z, slots 3..5 the max.
+struct Extremes {
+  double v[6];
+  int64_t i[6];
+};
+
+__device__ __forceinline__ void ext_init(Extremes& ex) {
+  for (int a = 0; a < 3; ++a) {
+    ex.v[a] = INFINITY;
+    ex.v[3 + a] = -INFINITY;
+    ex.i[a] = ex.i[3 + a] = INT64_MAX;
+  }
+}
+
+// slot q of (v, i) merged into ex: the smaller value (min slots) or the larger (max slots),
+// the smaller index on a tie
+__device__ __forceinline__ void ext_merge(Extremes& ex, int q, double v, int64_t i) {
+  const bool better = q < 3 ? v < ex.v[q] : v > ex.v[q];
+  if (better || (v == ex.v[q] && i < ex.i[q])) {
+    ex.v[q] = v;
+    ex.i[q] = i;
+  }
+}
+
+__device__ __forceinline__ void ext_update(Extremes& ex, const double r[3], int64_t i) {
+  for (int a = 0; a < 3; ++a) {
+    ext_merge(ex, a, r[a], i);
+    ext_merge(ex, 3 + a, r[a], i);
+  }
+}
+
+// block-wide merge; partial[blk 12 + q] = value, partial[blk 12 + 6 + q] = index (exact as a
+// double below 2^53)
+__device__ __forceinline__ void ext_block_partial(Extremes& ex, double* __restrict__ partial) {
+  __shared__ double sv[kBlk / 64][6];
+  __shared__ int64_t si[kBlk / 64][6];
+  for (int q = 0; q < 6; ++q)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v = __shfl_xor(ex.v[q], off);
+      const int64_t i = __shfl_xor(ex.i[q], off);
+      ext_merge(ex, q, v, i);
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 6; ++q) {
+      sv[threadIdx.x >> 6][q] = ex.v[q];
+      si[threadIdx.x >> 6][q] = ex.i[q];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int q = threadIdx.x;
+    Extremes m;
+    ext_init(m);
+    for (int w = 0; w < kBlk / 64; ++w) ext_merge(m, q, sv[w][q], si[w][q]);
+    partial[blockIdx.x * 12 + q] = m.v[q];
+    partial[blockIdx.x * 12 + 6 + q] = (double)m.i[q];
+  }
+}
+
+// out[q] = the index of extreme q over the block partials (one thread per slot, blocks in order)
+__global__ void k_ext_combine(const double* __restrict__ partial, int nblocks,
+                              double* __restrict__ out) {
+  const int q = threadIdx.x;
+  if (q >= 6) return;
+  Extremes m;
+  ext_init(m);
+  for (int b = 0; b < nblocks; ++b)
+    ext_merge(m, q, partial[b * 12 + q], (int64_t)partial[b * 12 + 6 + q]);
+  out[q] = (double)m.i[q];
+}
+
+// out[q] = sum over blocks (in order) of partial[b ncols + q], q < ncols (one thread per column)
+__global__ void k_combine_cols(const double* __restrict__ partial, int nblocks, int ncols,
+                               double* __restrict__ out) {
+  const int q = threadIdx.x;
+  if (q >= ncols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * ncols + q];
+  out[q] = s;
+}
+
+// block partials of ncomp grid dot products: partial[blk ncomp + c] = sum_i a[c stride + i]
+// b[c stride + i] over this block's share of i < count
+template <typename T>
+__global__ __launch_bounds__(kBlk) void k_grid_dot(const T* __restrict__ a,
+                                                   const T* __restrict__ b, int64_t count,
+                                                   int ncomp, int64_t stride,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[kBlk / 64];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * kBlk)
+      acc += (double)a[c * stride + i] * (double)b[c * stride + i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBlk / 64; ++w) t += sh[w];
+      partial[blockIdx.x * ncomp + c] = t;
+    }
+  }
+}
+
 // The second half map's strength term of a quadrupole slice: sum_i lam_i . DG x_next,i with
 // DG = (d second/dk) second^-1 and x_next the state after the slice.
 __global__ __launch_bounds__(kBlk) void k_adj_dk_second(const double* __restrict__ Xn,
@@ -98,17 +215,21 @@ template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
                                                 double* __restrict__ lam,
                                                 const Geom* __restrict__ g, Consts c,
-                                                AdjSlice sl, T* __restrict__ e) {
+                                                AdjSlice sl, T* __restrict__ e,
+                                                double* __restrict__ ext_partial) {
   if (g->status) return;
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int64_t n = c.n;
   const int64_t ng = (int64_t)c.nx * c.ny * c.nz;
   const double L = sl.L;
+  Extremes ex;
+  ext_init(ex);
   for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlk) {
     double r[3];
     kick_point(X, n, i, sl.first, c.inv_gamma2, r);
+    ext_update(ex, r, i);
     double lm[6];
     for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
     apply_half_T(sl.second, lm, c.inv_gamma2);
@@ -130,6 +251,7 @@ __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
         }
       }
   }
+  ext_block_partial(ex, ext_partial);
 }
 
 // Pass A for the binned vector deposit: lam <- (second half map)^T lam, and the particle's
@@ -138,14 +260,18 @@ __global__ __launch_bounds__(kBlk) void k_adj_a(const double* __restrict__ X,
 __global__ __launch_bounds__(kBlk) void k_adj_stage(const double* __restrict__ X,
                                                     double* __restrict__ lam,
                                                     const Geom* __restrict__ g, Consts c,
-                                                    AdjSlice sl, double* __restrict__ P) {
+                                                    AdjSlice sl, double* __restrict__ P,
+                                                    double* __restrict__ ext_partial) {
   if (g->status) return;
   const int64_t n = c.n;
   const double L = sl.L;
+  Extremes ex;
+  ext_init(ex);
   for (int64_t i = blockIdx.x * (int64_t)kBlk + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlk) {
     double r[3];
     kick_point(X, n, i, sl.first, c.inv_gamma2, r);
+    ext_update(ex, r, i);
     double lm[6];
     for (int q = 0; q < 6; ++q) lm[q] = lam[q * n + i];
     apply_half_T(sl.second, lm, c.inv_gamma2);
@@ -157,6 +283,7 @@ __global__ __launch_bounds__(kBlk) void k_adj_stage(const double* __restrict__ X
     P[4 * n + i] = r[2];
     P[5 * n + i] = c.gamma * c.C * L * lm[5];
   }
+  ext_block_partial(ex, ext_partial);
 }
 
 // psi on nodes -1..n ([(nz+2)][(ny+2)][(nx+2)]) = sum_c (e_c(m + 1_c) - e_c(m - 1_c)) / (2 h_c),
@@ -196,8 +323,10 @@ __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
                                                 const Geom* __restrict__ g, Consts c,
                                                 AdjSlice sl, const T* __restrict__ E,
                                                 const T* __restrict__ chi,
-                                                double* __restrict__ dk_partial) {
+                                                double* __restrict__ dk_partial,
+                                                double* __restrict__ geo_partial) {
   double acc = 0.0;
+  double sg[3] = {0.0, 0.0, 0.0}, sgu[3] = {0.0, 0.0, 0.0};  // sum g_a, sum g_a u_a
   if (g->status == 0) {
     const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
     const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
@@ -231,6 +360,11 @@ __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
       lm[0] += gx;
       lm[2] += gy;
       lm[4] += gz;
+      const double gv[3] = {gx, gy, gz};
+      for (int q = 0; q < 3; ++q) {
+        sg[q] += gv[q];
+        sgu[q] += gv[q] * ((r[q] - o[q]) * ih[q]);
+      }
       if (sl.first.type == kHalfThinDrift) {
         // transposed first half drift, the strength term with the step-start positions, then
         // the transposed thin quad
@@ -253,6 +387,60 @@ __global__ __launch_bounds__(kBlk) void k_adj_b(const double* __restrict__ X,
     }
   }
   block_partial(acc, dk_partial);
+  for (int q = 0; q < 6; ++q) {
+    __syncthreads();
+    block_partial(q < 3 ? sg[q] : sgu[q - 3], geo_partial + q * gridDim.x);
+  }
+}
+
+// The geometry's terms of one reverse step, one thread.  geo: [0..5] indices of the particles
+// at the box's min (x, y, z) and max, [6..8] sum g_a, [9..11] sum g_a u_a, [12..14] dJ/dh'_b
+// through the kernel, [15..17] sum_n e_b E'_b (the centred difference's term is minus that over
+// h'_b; zero for the direct field).  dJ/dmin and dJ/dmax are added to
+// those particles' kick-point position adjoints, carried through the slice's first half map
+// as k_adj_b carries every particle's (lam already holds the step-start adjoint), with the
+// first half map's strength term into dk[sl.elem].
+__global__ void k_adj_geom(const double* __restrict__ X, double* __restrict__ lam,
+                           const Geom* __restrict__ g, Consts c, AdjSlice sl,
+                           const double* __restrict__ geo, double* __restrict__ dk) {
+  if (blockIdx.x != 0 || threadIdx.x != 0 || g->status) return;
+  const int64_t n = c.n;
+  const double nodes[3] = {(double)c.nx, (double)c.ny, (double)c.nz};
+  const double dhr[3] = {1.0, 1.0, c.gamma};  // d h'_a / d h_a
+  double dmin[3], dmax[3];
+  for (int a = 0; a < 3; ++a) {
+    const double dJ_do = -geo[6 + a];
+    const double dJ_dhr = geo[12 + a] - geo[15 + a] / g->h_rest[a];
+    const double dJ_dh = -geo[9 + a] + dJ_dhr * dhr[a];
+    const double m = nodes[a] - 3.5;
+    dmin[a] = dJ_do * (1.0 + 1.25 / m) - dJ_dh / m;
+    dmax[a] = -dJ_do * 1.25 / m + dJ_dh / m;
+  }
+  double acc = 0.0;
+  for (int q = 0; q < 6; ++q) {
+    const int a = q % 3;
+    const int64_t i = (int64_t)geo[q];
+    if (i < 0 || i >= n) continue;  // no particle (cannot happen for n >= 1)
+    double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    d[2 * a] = q < 3 ? dmin[a] : dmax[a];
+    if (sl.first.type == kHalfThinDrift) {
+      const double ell = sl.first.ell;
+      d[1] += ell * d[0];
+      d[3] += ell * d[2];
+      d[5] += ell * d[4] * c.inv_gamma2;
+      acc += -X[i] * d[1] + X[2 * n + i] * d[3];
+      d[0] -= sl.first.k * d[1];
+      d[2] += sl.first.k * d[3];
+    } else {
+      if (sl.dk_kind == kDkMatrix) {
+        const double v[4] = {X[i], X[n + i], X[2 * n + i], X[3 * n + i]};
+        acc += plane_form(d, sl.dfx, sl.dfy, v);
+      }
+      apply_half_T(sl.first, d, c.inv_gamma2);
+    }
+    for (int r = 0; r < 6; ++r) lam[r * n + i] += d[r];
+  }
+  if (sl.dk_kind != kDkNone) dk[sl.elem] += acc;
 }
 
 // dk[slot] += sum of the per-block partials: one wave, lane l sums partials l, l + 64, ...,
@@ -386,17 +574,44 @@ hipError_t launch_adj_dk_second(const double* Xnext, const double* lam, Consts c
 
 template <typename T>
 hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
-                        const AdjSlice& sl, T* e, hipStream_t s) {
+                        const AdjSlice& sl, T* e, double* ext_partial, double* geo,
+                        hipStream_t s) {
+  const int nb = grid_for(c.n);
   if (c.shape == 1)
-    hipLaunchKernelGGL((k_adj_a<1, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, e);
+    hipLaunchKernelGGL((k_adj_a<1, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, e,
+                       ext_partial);
   else
-    hipLaunchKernelGGL((k_adj_a<2, T>), dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, e);
+    hipLaunchKernelGGL((k_adj_a<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, e,
+                       ext_partial);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_ext_combine, dim3(1), dim3(64), 0, s, ext_partial, nb, geo);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c,
-                            const AdjSlice& sl, double* P, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_stage, dim3(grid_for(c.n)), dim3(kBlk), 0, s, X, lam, g, c, sl, P);
+                            const AdjSlice& sl, double* P, double* ext_partial, double* geo,
+                            hipStream_t s) {
+  const int nb = grid_for(c.n);
+  hipLaunchKernelGGL(k_adj_stage, dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, P, ext_partial);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_ext_combine, dim3(1), dim3(64), 0, s, ext_partial, nb, geo);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grid_dot(const T* a, const T* b, int64_t count, int ncomp, int64_t stride,
+                           double* partial, double* out, hipStream_t s) {
+  const int nb = grid_for(count);
+  hipLaunchKernelGGL((k_grid_dot<T>), dim3(nb), dim3(kBlk), 0, s, a, b, count, ncomp, stride,
+                     partial);
+  PIC_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_combine_cols, dim3(1), dim3(64), 0, s, partial, nb, ncomp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_geom(const double* X, double* lam, const Geom* g, Consts c,
+                           const AdjSlice& sl, const double* geo, double* dk, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_geom, dim3(1), dim3(64), 0, s, X, lam, g, c, sl, geo, dk);
   return hipGetLastError();
 }
 
@@ -411,18 +626,25 @@ hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int
 
 template <typename T>
 hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, const AdjSlice& sl,
-                        const T* E, const T* chi, double* dk_partial, double* dk, hipStream_t s) {
+                        const T* E, const T* chi, double* dk_partial, double* dk,
+                        double* geo_partial, double* geo, hipStream_t s) {
   const int nb = grid_for(c.n);
   if (c.shape == 1)
     hipLaunchKernelGGL((k_adj_b<1, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, E, chi,
-                       dk_partial);
+                       dk_partial, geo_partial);
   else
     hipLaunchKernelGGL((k_adj_b<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, E, chi,
-                       dk_partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+                       dk_partial, geo_partial);
+  PIC_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, sl.elem);
-  return hipGetLastError();
+  PIC_TRY(hipGetLastError());
+  // geo_partial[q nb + b] (q = 0..5) summed over the blocks into geo[6 + q]
+  for (int q = 0; q < 6; ++q) {
+    hipLaunchKernelGGL(k_combine_cols, dim3(1), dim3(64), 0, s, geo_partial + q * nb, nb, 1,
+                       geo + 6 + q);
+    PIC_TRY(hipGetLastError());
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
@@ -449,18 +671,22 @@ hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* par
 }
 
 template hipError_t launch_adj_a<double>(const double*, double*, const Geom*, Consts,
-                                         const AdjSlice&, double*, hipStream_t);
+                                         const AdjSlice&, double*, double*, double*, hipStream_t);
 template hipError_t launch_adj_a<float>(const double*, double*, const Geom*, Consts,
-                                        const AdjSlice&, float*, hipStream_t);
+                                        const AdjSlice&, float*, double*, double*, hipStream_t);
+template hipError_t launch_grid_dot<double>(const double*, const double*, int64_t, int, int64_t,
+                                            double*, double*, hipStream_t);
+template hipError_t launch_grid_dot<float>(const float*, const float*, int64_t, int, int64_t,
+                                           double*, double*, hipStream_t);
 template hipError_t launch_adj_div<double>(const Geom*, const double*, double*, int, int, int,
                                            hipStream_t);
 template hipError_t launch_adj_div<float>(const Geom*, const float*, float*, int, int, int,
                                           hipStream_t);
 template hipError_t launch_adj_b<double>(const double*, double*, const Geom*, Consts,
                                          const AdjSlice&, const double*, const double*, double*,
-                                         double*, hipStream_t);
+                                         double*, double*, double*, hipStream_t);
 template hipError_t launch_adj_b<float>(const double*, double*, const Geom*, Consts,
                                         const AdjSlice&, const float*, const float*, double*,
-                                        double*, hipStream_t);
+                                        double*, double*, double*, hipStream_t);
 
 }  // namespace pic

@@ -520,7 +520,9 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
 
 // ---- reverse sweep workspace (caller-owned, see pic_adjoint_workspace_bytes)
 struct AdjLayout {
-  size_t geoms, ckpt, segX, segE, segG, e, psi, chi, stage, dk, dk_part, dL_part, small, total;
+  size_t geoms, ckpt, segX, segE, segG, segQ, e, psi, chi, chi2, stage, dk, dk_part, dL_part,
+      small;
+  size_t ext_part, geo_part, dot_part, geo, dc, dgd, dgh, total;
   int nseg;
 };
 
@@ -543,9 +545,21 @@ AdjLayout adj_layout(const pic_beam_desc* d, int n_steps, int ck) {
   A.segX = take(6 * sizeof(double) * n * (size_t)ck);
   A.segE = take(3 * es * ng * (size_t)ck);
   A.segG = take(es * G3 * (size_t)ck * (d->direct_field ? 3 : 1));  // the step's kernel spectra
+  A.segQ = take(es * ng * (size_t)ck);                                // the step's charge grid
   A.e = take(3 * es * ng);
   A.psi = take(es * (nx + 2) * (ny + 2) * (nz + 2));
   A.chi = take(es * ng);
+  A.chi2 = take(es * ng);
+  // the geometry's terms: the kernels' h-derivatives (3 for the potential, 9 for the field:
+  // corner values, octant cells, spectra), reduction partials and the per-step sums
+  const size_t nf = d->direct_field ? 9 : 3;
+  A.dc = take(2 * sizeof(double) * (nx + 2) * (ny + 2) * (nz + 2) * nf);
+  A.dgd = take(sizeof(double) * G3 * nf);
+  A.dgh = take(es * G3 * nf);
+  A.ext_part = take(sizeof(double) * 12 * kAdjBlocks);
+  A.geo_part = take(sizeof(double) * 6 * kAdjBlocks);
+  A.dot_part = take(sizeof(double) * 3 * kAdjBlocks);
+  A.geo = take(sizeof(double) * 32);
   A.stage = take(6 * sizeof(double) * n);
   A.dk = take(sizeof(double) * kMaxLattice);
   A.dk_part = take(sizeof(double) * kAdjBlocks);
@@ -643,33 +657,33 @@ pic_status expand_adjoint(const pic_element* lat, int n_el, std::vector<AdjSlice
 }
 
 template <typename T>
-pic_status forward_step_frozen(pic_beam b, double* X, const Geom* g, const AdjSlice& e,
-                               T* gh, T* E, hipStream_t s, Box* box) {
-  // the slice's first half map (with the box when a geometry is to be computed), deposit,
-  // Green spectrum, solve, kick and the second half map; g is the step's geometry slot
+pic_status forward_step_recorded(pic_beam b, double* X, const Geom* g, const AdjSlice& e,
+                               T* gh, T* E, T* rho, hipStream_t s, Box* box) {
+  // the slice's first half map (with the box when a geometry is to be computed), deposit into
+  // rho, Green spectrum, solve, kick and the second half map; g is the step's geometry slot
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   HIP_OK(launch_half_box(X, e.first, b->c, box, s), "adjoint forward");
   if (box) HIP_OK(launch_geometry(box, const_cast<Geom*>(g), b->c, s), "adjoint forward");
-  HIP_OK(launch_zero<T>((T*)b->rho, ng, s), "adjoint forward");
+  HIP_OK(launch_zero<T>(rho, ng, s), "adjoint forward");
   // binned deposit from a tile-sorted copy (XB) of the kick-point state
   HIP_OK(launch_bin(X, b->idA, g, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks, b->nchunks,
                     b->XB, b->idB, true, s),
          "adjoint forward");
-  HIP_OK(launch_deposit_tiles<T>(b->XB, nullptr, g, b->c, b->sp, b->chunks, b->nchunks,
-                                 (T*)b->rho, s, b->tacc, b->tscale),
+  HIP_OK(launch_deposit_tiles<T>(b->XB, nullptr, g, b->c, b->sp, b->chunks, b->nchunks, rho, s,
+                                 b->tacc, b->tscale),
          "adjoint forward");
   if (b->d.direct_field) {  // gh holds the three field kernels' spectra
     HIP_OK(launch_green_field_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->hcorners,
                                           b->gd3, gh, s),
            "adjoint forward");
-    HIP_OK(launch_solve_field<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W,
+    HIP_OK(launch_solve_field<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)rho, b->W,
                                  b->W2, gh, E, s),
            "adjoint forward");
   } else {
     HIP_OK(launch_green_spectrum<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, b->corners, b->Gd, gh,
                                     s),
            "adjoint forward");
-    HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)b->rho, b->W, gh,
+    HIP_OK(launch_solve<T>(g, b->plan, b->d.nx, b->d.ny, b->d.nz, (const T*)rho, b->W, gh,
                            (T*)b->phi, E, s),
            "adjoint forward");
   }
@@ -695,9 +709,17 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
   double* segX = (double*)(aw + A.segX);
   T* segE = (T*)(aw + A.segE);
   T* segG = (T*)(aw + A.segG);
+  T* segQ = (T*)(aw + A.segQ);
   T* e = (T*)(aw + A.e);
   T* psi = (T*)(aw + A.psi);
   T* chi = (T*)(aw + A.chi);
+  T* chi2 = (T*)(aw + A.chi2);
+  double* geo = (double*)(aw + A.geo);
+  double* ext_part = (double*)(aw + A.ext_part);
+  double* geo_part = (double*)(aw + A.geo_part);
+  double* dot_part = (double*)(aw + A.dot_part);
+  T* dgh = (T*)(aw + A.dgh);
+  const size_t G1 = (size_t)(b->d.nx + 1) * (b->d.ny + 1) * (b->d.nz + 1);
   double* dk = (double*)(aw + A.dk);
   double* small = (double*)(aw + A.small);
   double* P = (double*)(aw + A.stage);
@@ -715,8 +737,9 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
                             hipMemcpyDeviceToDevice, s),
              "adjoint checkpoint");
     HIP_OK(launch_box_reset(b->box, s), "adjoint forward");
-    pic_status st = forward_step_frozen<T>(b, b->X, geom(j), sl[j % nsl],
-                                           direct ? (T*)b->gh3 : (T*)b->Gh, (T*)b->E, s, b->box);
+    pic_status st = forward_step_recorded<T>(b, b->X, geom(j), sl[j % nsl],
+                                           direct ? (T*)b->gh3 : (T*)b->Gh, (T*)b->E,
+                                           (T*)b->rho, s, b->box);
     if (st != PIC_OK) return st;
   }
   HIP_OK(launch_moments(b->X, b->d.n, b->mom_partial, b->mom_out, s), "adjoint objective");
@@ -733,8 +756,9 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
       HIP_OK(hipMemcpyAsync(segX + 6 * n * (size_t)q, XW, 6 * sizeof(double) * n,
                             hipMemcpyDeviceToDevice, s),
              "adjoint recompute");
-      pic_status st = forward_step_frozen<T>(b, XW, geom(j), sl[j % nsl], segG + G3 * (size_t)q,
-                                             segE + 3 * ng * (size_t)q, s, nullptr);
+      pic_status st = forward_step_recorded<T>(b, XW, geom(j), sl[j % nsl], segG + G3 * (size_t)q,
+                                             segE + 3 * ng * (size_t)q, segQ + ng * (size_t)q, s,
+                                             nullptr);
       if (st != PIC_OK) return st;
     }
     for (int j = c1 - 1; j >= c0; --j) {
@@ -751,14 +775,14 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
       HIP_OK(launch_zero<T>(e, 3 * ng, s), "adjoint");
       if (vtiles) {
         // kick-point positions and deposit values, tile-sorted, then the binned vector deposit
-        HIP_OK(launch_adj_stage(Xs, lam, geom(j), b->c, el, P, s), "adjoint");
+        HIP_OK(launch_adj_stage(Xs, lam, geom(j), b->c, el, P, ext_part, geo, s), "adjoint");
         HIP_OK(launch_bin(P, b->idA, geom(j), b->c, b->sp, b->keys, b->hist, b->cursor,
                           b->chunks, b->nchunks, b->XB, b->idB, true, s),
                "adjoint");
         HIP_OK(launch_vdeposit_tiles<T>(b->XB, geom(j), b->c, b->sp, b->chunks, b->nchunks, e, s),
                "adjoint");
       } else {
-        HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el, e, s), "adjoint");
+        HIP_OK(launch_adj_a<T>(Xs, lam, geom(j), b->c, el, e, ext_part, geo, s), "adjoint");
       }
       if (direct) {  // transposed field convolutions, b->E as their scratch
         HIP_OK(launch_solve_field_T<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, e, b->W, b->W2,
@@ -771,8 +795,33 @@ pic_status track_adjoint(pic_beam b, const std::vector<AdjSlice>& sl, int n_el, 
                "adjoint");
       }
       HIP_OK(launch_adj_b<T>(Xs, lam, geom(j), b->c, el, segE + 3 * ng * (size_t)q, chi,
-                             (double*)(aw + A.dk_part), dk, s),
+                             (double*)(aw + A.dk_part), dk, geo_part, geo, s),
              "adjoint");
+      // the geometry's terms: dJ/dh' through the kernel (the h-derivative kernels' convolution
+      // with the adjoint source, dotted with the step's charge) into geo[12..14], and through
+      // the centred difference sum_n e_b E'_b into geo[15..17] (zero for the direct field)
+      const T* Qj = segQ + ng * (size_t)q;
+      HIP_OK(launch_green_dh_spectra<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, direct,
+                                        (double2*)(aw + A.dc), (double*)(aw + A.dgd), dgh, s),
+             "adjoint geometry");
+      for (int hb = 0; hb < 3; ++hb) {
+        if (direct)
+          HIP_OK(launch_solve_field_T<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, e, b->W,
+                                         b->W2, dgh + 3 * G1 * (size_t)hb, (T*)b->E, chi2, s),
+                 "adjoint geometry");
+        else
+          HIP_OK(launch_solve_ghost_source<T>(geom(j), b->plan, b->d.nx, b->d.ny, b->d.nz, psi,
+                                              b->W, dgh + G1 * (size_t)hb, chi2, s),
+                 "adjoint geometry");
+        HIP_OK(launch_grid_dot<T>(Qj, chi2, ng, 1, 0, dot_part, geo + 12 + hb, s),
+               "adjoint geometry");
+      }
+      if (direct)
+        HIP_OK(launch_zero<double>(geo + 15, 3, s), "adjoint geometry");
+      else
+        HIP_OK(launch_grid_dot<T>(e, segE + 3 * ng * (size_t)q, ng, 3, ng, dot_part, geo + 15, s),
+               "adjoint geometry");
+      HIP_OK(launch_adj_geom(Xs, lam, geom(j), b->c, el, geo, dk, s), "adjoint geometry");
     }
   }
   if (xi)

@@ -739,6 +739,24 @@ hipError_t launch_green_field_spectrum(const Geom* g, const FftPlan& p, int nx, 
 }
 
 template <typename T>
+hipError_t launch_green_dh_spectra(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                   bool field, double2* dc, double* gd, T* gh, hipStream_t s) {
+  PIC_TRY(launch_igf_dh(g, nx, ny, nz, field, dc, gd, s));
+  const int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  if (!field) {
+    for (int b = 0; b < 3; ++b)
+      PIC_TRY(kernel_spectrum<T>(g, p, nx, ny, nz, gd + b * total, gh + b * total, -1, s));
+    return hipSuccess;
+  }
+  // kernel (a, b) = f = 3 a + b in gd; its spectrum at 3 b + a, so that the three of one b
+  // are consecutive, as the transposed field solve reads them
+  for (int f = 0; f < 9; ++f)
+    PIC_TRY(kernel_spectrum<T>(g, p, nx, ny, nz, gd + f * total,
+                               gh + (3 * (f % 3) + f / 3) * total, f / 3, s));
+  return hipSuccess;
+}
+
+template <typename T>
 hipError_t launch_green_spectrum(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
                                  double2* corners, double* gd, T* gh, hipStream_t s) {
   PIC_TRY(launch_igf_corners(g, nx, ny, nz, corners, s));
@@ -1009,6 +1027,10 @@ template hipError_t launch_batch_solve<float>(const BeamDev*, int, const BatchDi
 
 template hipError_t launch_green_spectrum<double>(const Geom*, const FftPlan&, int, int, int,
                                                   double2*, double*, double*, hipStream_t);
+template hipError_t launch_green_dh_spectra<double>(const Geom*, const FftPlan&, int, int, int,
+                                                    bool, double2*, double*, double*, hipStream_t);
+template hipError_t launch_green_dh_spectra<float>(const Geom*, const FftPlan&, int, int, int,
+                                                   bool, double2*, double*, float*, hipStream_t);
 template hipError_t launch_green_spectrum<float>(const Geom*, const FftPlan&, int, int, int,
                                                  double2*, double*, float*, hipStream_t);
 template hipError_t launch_solve<double>(const Geom*, const FftPlan&, int, int, int,

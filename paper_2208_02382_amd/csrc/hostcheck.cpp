@@ -43,4 +43,45 @@ void pic_hostcheck_igf(int nx, int ny, int nz, double hx, double hy, double hz, 
       }
   delete[] F;
 }
+
+// The kernels' h-derivatives (field = 0: dGbar/dh_b, b = 0..2; field = 1: dKbar_a/dh_b,
+// f = 3 a + b) on the octant, out[f cells + ((k (ny+1)) + j)(nx+1) + i], with the corner
+// functions and cell sums of the kernels.
+void pic_hostcheck_igf_dh(int field, int nx, int ny, int nz, double hx, double hy, double hz,
+                          double* out) {
+  const int nf = field ? 9 : 3;
+  const int cx = nx + 2, cy = ny + 2, cz = nz + 2;
+  const size_t ctotal = (size_t)cx * cy * cz;
+  const size_t cells = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
+  pic::ddv* C = new pic::ddv[ctotal * nf];
+  for (int mz = 0; mz < cz; ++mz)
+    for (int my = 0; my < cy; ++my)
+      for (int mx = 0; mx < cx; ++mx) {
+        pic::ddv v[9];
+        const pic::ddv x = pic::corner_coord(mx, hx), y = pic::corner_coord(my, hy),
+                       z = pic::corner_coord(mz, hz);
+        if (field)
+          pic::dh_corner_functions<true>(x, y, z, v);
+        else
+          pic::dh_corner_functions<false>(x, y, z, v);
+        for (int f = 0; f < nf; ++f) C[f * ctotal + ((size_t)mz * cy + my) * cx + mx] = v[f];
+      }
+  const double h[3] = {hx, hy, hz};
+  const pic::ddv vol = pic::dd_mul_d(pic::two_prod(hx, hy), hz);
+  for (int f = 0; f < nf; ++f)
+    for (int k = 0; k <= nz; ++k)
+      for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+          pic::ddv c[8];
+          for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+              for (int dx = 0; dx < 2; ++dx)
+                c[(dz * 2 + dy) * 2 + dx] =
+                    C[f * ctotal + ((size_t)(k + dz) * cy + (j + dy)) * cx + i + dx];
+          const int b = field ? f % 3 : f;
+          out[f * cells + ((size_t)k * (ny + 1) + j) * (nx + 1) + i] = pic::dh_cell_value(
+              c, pic::dh_fold(field != 0, f, i, j, k), pic::dd_mul_d(vol, h[b]));
+        }
+  delete[] C;
+}
 }

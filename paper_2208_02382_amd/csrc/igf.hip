@@ -148,6 +148,61 @@ __global__ __launch_bounds__(256) void k_igf_field_cells(const Geom* __restrict_
   }
 }
 
+// Corner values of the kernels' h-derivatives (dh_corner_functions): nf = 3 (potential) or 9
+// (field) double pairs per corner, dc[f ctotal + t], t as for F.
+template <bool FIELD>
+__global__ __launch_bounds__(256) void k_igf_dh_corners(const Geom* __restrict__ g, int nx,
+                                                        int ny, int nz,
+                                                        double2* __restrict__ dc) {
+  if (g->status) return;
+  constexpr int NF = FIELD ? 9 : 3;
+  const int cx = nx + 2, cy = ny + 2, cz = nz + 2;
+  const int64_t total = (int64_t)cx * cy * cz;
+  const double hx = g->h_rest[0], hy = g->h_rest[1], hz = g->h_rest[2];
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int mx = (int)(t % cx);
+    const int my = (int)((t / cx) % cy);
+    const int mz = (int)(t / ((int64_t)cx * cy));
+    ddv v[NF];
+    dh_corner_functions<FIELD>(corner_coord(mx, hx), corner_coord(my, hy), corner_coord(mz, hz),
+                               v);
+    for (int f = 0; f < NF; ++f) dc[f * total + t] = make_double2(v[f].hi, v[f].lo);
+  }
+}
+
+// The derivative kernels on the octant: gd[f total + (k (ny+1) + j)(nx+1) + i] =
+// d kernel_f / d h_b (b = f for the potential, f % 3 for the field) from the corner values
+template <bool FIELD>
+__global__ __launch_bounds__(256) void k_igf_dh_cells(const Geom* __restrict__ g, int nx, int ny,
+                                                      int nz, const double2* __restrict__ dc,
+                                                      double* __restrict__ gd) {
+  if (g->status) return;
+  constexpr int NF = FIELD ? 9 : 3;
+  const int cx = nx + 2, cy = ny + 2;
+  const int ex = nx + 1, ey = ny + 1;
+  const int64_t ctotal = (int64_t)cx * cy * (nz + 2);
+  const int64_t total = (int64_t)ex * ey * (nz + 1);
+  const double h[3] = {g->h_rest[0], g->h_rest[1], g->h_rest[2]};
+  const ddv vol = dd_mul_d(two_prod(h[0], h[1]), h[2]);
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int i = (int)(t % ex);
+    const int j = (int)((t / ex) % ey);
+    const int k = (int)(t / ((int64_t)ex * ey));
+    for (int f = 0; f < NF; ++f) {
+      const double2* src = dc + f * ctotal;
+      ddv c[8];
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const double2 v = src[((int64_t)(k + dz) * cy + (j + dy)) * cx + i + dx];
+            c[(dz * 2 + dy) * 2 + dx] = ddv{v.x, v.y};
+          }
+      const int b = FIELD ? f % 3 : f;
+      gd[f * total + t] = dh_cell_value(c, dh_fold(FIELD, f, i, j, k), dd_mul_d(vol, h[b]));
+    }
+  }
+}
+
 int grid_for(int64_t total) {
   int64_t b = (total + 255) / 256;
   if (b > 16384) b = 16384;
@@ -182,6 +237,28 @@ hipError_t launch_igf_field(const Geom* g, int nx, int ny, int nz, double2* hc, 
   const int64_t cells = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   hipLaunchKernelGGL(k_igf_field_cells, dim3(grid_for(cells)), dim3(256), 0, s, g, nx, ny, nz, hc,
                      gd3);
+  return hipGetLastError();
+}
+
+hipError_t launch_igf_dh(const Geom* g, int nx, int ny, int nz, bool field, double2* dc,
+                         double* gd, hipStream_t s) {
+  const int64_t corners = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+  const int64_t cells = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  if (field) {
+    hipLaunchKernelGGL(k_igf_dh_corners<true>, dim3(grid_for(corners)), dim3(256), 0, s, g, nx,
+                       ny, nz, dc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_igf_dh_cells<true>, dim3(grid_for(cells)), dim3(256), 0, s, g, nx, ny,
+                       nz, dc, gd);
+  } else {
+    hipLaunchKernelGGL(k_igf_dh_corners<false>, dim3(grid_for(corners)), dim3(256), 0, s, g, nx,
+                       ny, nz, dc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_igf_dh_cells<false>, dim3(grid_for(cells)), dim3(256), 0, s, g, nx, ny,
+                       nz, dc, gd);
+  }
   return hipGetLastError();
 }
 

@@ -50,4 +50,80 @@ PIC_HD inline void field_antiderivatives(ddv x, ddv y, ddv z, ddv H[3]) {
                 z0 ? zero : dd_mul(z, Az));
 }
 
+// Corner functions of the kernels' derivatives in the rest-frame spacing h_b.  Substituting
+// r = h s in the cell average gives d/dh_b avg(f) = (1/h_b) avg(r_b df/dr_b); integrating by
+// parts in r_b turns that into an 8-corner sum of one corner function C, so
+// d/dh_b avg(f) = fold / (V h_b) * (8-corner sum of C), folded as the kernel itself.
+//   potential (f = 1/r):  C_b = r_b H_b - F, which reduces to
+//     C_x = -y z L_x - x^2/2 A_x + y^2/2 A_y + z^2/2 A_z  (cyclic in x, y, z);
+//   field (f = u_a/r^3):  C_ab = r_b B_ab + H_a with the face antiderivative B_aa =
+//     atan(v w/(u_a r)) and B_ab = -ln(u_c + r) (c the third axis), which reduces to
+//     C_xx = y L_z + z L_y, C_xy = z L_y - x A_x, C_xz = y L_z - x A_x, and cyclically.
+// A term with a zero prefactor is zero (its logarithm or arctangent may be undefined there).
+// out[b] for the potential (3 values), out[3 a + b] for the field (9 values).
+template <bool FIELD>
+PIC_HD inline void dh_corner_functions(ddv x, ddv y, ddv z, ddv* out) {
+  const bool x0 = x.hi == 0.0, y0 = y.hi == 0.0, z0 = z.hi == 0.0;
+  const ddv r = dd_sqrt(dd_add(dd_add(dd_mul(x, x), dd_mul(y, y)), dd_mul(z, z)));
+  const ddv zero = {0.0, 0.0};
+  const ddv Lx = (y0 && z0) ? zero : dd_log(dd_add(x, r));
+  const ddv Ly = (z0 && x0) ? zero : dd_log(dd_add(y, r));
+  const ddv Lz = (x0 && y0) ? zero : dd_log(dd_add(z, r));
+  const ddv Ax = x0 ? zero : dd_atan(dd_div(dd_mul(y, z), dd_mul(x, r)));
+  const ddv Ay = y0 ? zero : dd_atan(dd_div(dd_mul(z, x), dd_mul(y, r)));
+  const ddv Az = z0 ? zero : dd_atan(dd_div(dd_mul(x, y), dd_mul(z, r)));
+  // coordinate times a logarithm / arctangent, zero with the coordinate
+  auto cl = [&](ddv c, bool c0, ddv L) { return c0 ? zero : dd_mul(c, L); };
+  if constexpr (!FIELD) {
+    const ddv hx2 = dd_mul_d(dd_mul(x, x), 0.5), hy2 = dd_mul_d(dd_mul(y, y), 0.5),
+              hz2 = dd_mul_d(dd_mul(z, z), 0.5);
+    const ddv tx = x0 ? zero : dd_mul(hx2, Ax);
+    const ddv ty = y0 ? zero : dd_mul(hy2, Ay);
+    const ddv tz = z0 ? zero : dd_mul(hz2, Az);
+    const ddv yzLx = (y0 || z0) ? zero : dd_mul(dd_mul(y, z), Lx);
+    const ddv zxLy = (z0 || x0) ? zero : dd_mul(dd_mul(z, x), Ly);
+    const ddv xyLz = (x0 || y0) ? zero : dd_mul(dd_mul(x, y), Lz);
+    out[0] = dd_sub(dd_add(ty, tz), dd_add(yzLx, tx));
+    out[1] = dd_sub(dd_add(tz, tx), dd_add(zxLy, ty));
+    out[2] = dd_sub(dd_add(tx, ty), dd_add(xyLz, tz));
+  } else {
+    const ddv yLz = cl(y, y0, Lz), zLy = cl(z, z0, Ly), zLx = cl(z, z0, Lx);
+    const ddv xLz = cl(x, x0, Lz), xLy = cl(x, x0, Ly), yLx = cl(y, y0, Lx);
+    const ddv xAx = cl(x, x0, Ax), yAy = cl(y, y0, Ay), zAz = cl(z, z0, Az);
+    out[0] = dd_add(yLz, zLy);  // (x, x)
+    out[1] = dd_sub(zLy, xAx);  // (x, y)
+    out[2] = dd_sub(yLz, xAx);  // (x, z)
+    out[3] = dd_sub(zLx, yAy);  // (y, x)
+    out[4] = dd_add(zLx, xLz);  // (y, y)
+    out[5] = dd_sub(xLz, yAy);  // (y, z)
+    out[6] = dd_sub(yLx, zAz);  // (z, x)
+    out[7] = dd_sub(xLy, zAz);  // (z, y)
+    out[8] = dd_add(xLy, yLx);  // (z, z)
+  }
+}
+
+// fold / (V h_b) * (alternating 8-corner sum of c), c[(dz 2 + dy) 2 + dx] the corner values of
+// one cell (d = 0 lower, 1 upper corner along each axis), rounded to double once; vhb = V h_b
+PIC_HD inline double dh_cell_value(const ddv c[8], double fold, ddv vhb) {
+  if (fold == 0.0) return 0.0;
+  ddv dxy[2][2];
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy) dxy[dz][dy] = dd_sub(c[(dz * 2 + dy) * 2 + 1], c[(dz * 2 + dy) * 2]);
+  ddv d = dd_sub(dd_sub(dxy[1][1], dxy[1][0]), dd_sub(dxy[0][1], dxy[0][0]));
+  d = {d.hi * fold, d.lo * fold};
+  const ddv v = dd_div(d, vhb);
+  return v.hi + v.lo;
+}
+
+// folding weight of the octant cell (i, j, k) for derivative kernel f: the potential's are even
+// along every axis (weight 2 per index-0 axis); the field's (a, b) = (f / 3, f % 3) are odd
+// along a (zero on its index-0 plane) and even along the other two
+PIC_HD inline double dh_fold(bool field, int f, int i, int j, int k) {
+  const int idx[3] = {i, j, k};
+  double w = 1.0;
+  for (int q = 0; q < 3; ++q)
+    if (idx[q] == 0) w *= (field && q == f / 3) ? 0.0 : 2.0;
+  return w;
+}
+
 }  // namespace pic

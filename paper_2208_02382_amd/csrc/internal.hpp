@@ -266,11 +266,24 @@ hipError_t launch_batch_solve(const BeamDev* beams, int nb, const BatchDims& bd,
 hipError_t launch_adj_dk_second(const double* Xnext, const double* lam, Consts c,
                                 const AdjSlice& sl, double* dk_partial, double* dk,
                                 hipStream_t s);
+// launch_adj_a and launch_adj_stage also find the particles at the box's min and max of the
+// kick-point positions (the first index for a tie): their indices into geo[0..5] (x, y, z min,
+// then max), ext_partial (12 doubles per block) as scratch
 template <typename T>
 hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
-                        const AdjSlice& sl, T* e, hipStream_t s);
+                        const AdjSlice& sl, T* e, double* ext_partial, double* geo,
+                        hipStream_t s);
 hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts c,
-                            const AdjSlice& sl, double* P, hipStream_t s);
+                            const AdjSlice& sl, double* P, double* ext_partial, double* geo,
+                            hipStream_t s);
+// out[c] = sum_i a[c stride + i] b[c stride + i], i < count, c < ncomp (at most 64), in a fixed
+// order; partial holds ncomp doubles per block
+template <typename T>
+hipError_t launch_grid_dot(const T* a, const T* b, int64_t count, int ncomp, int64_t stride,
+                           double* partial, double* out, hipStream_t s);
+// the geometry's terms of a reverse step from geo (see adjoint.hip) into lam and dk
+hipError_t launch_adj_geom(const double* X, double* lam, const Geom* g, Consts c,
+                           const AdjSlice& sl, const double* geo, double* dk, hipStream_t s);
 // binned vector deposit; an error if the three float64 windows exceed the LDS a workgroup may use
 template <typename T>
 hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const SortPlan& sp,
@@ -279,9 +292,12 @@ hipError_t launch_vdeposit_tiles(const double* B, const Geom* g, Consts c, const
 template <typename T>
 hipError_t launch_adj_div(const Geom* g, const T* e, T* psi, int nx, int ny, int nz,
                           hipStream_t s);
+// also the per-block sums of g_a and g_a u_a (6 kAdjBlocks doubles of geo_partial) into
+// geo[6..11]
 template <typename T>
 hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, const AdjSlice& sl,
-                        const T* E, const T* chi, double* dk_partial, double* dk, hipStream_t s);
+                        const T* E, const T* chi, double* dk_partial, double* dk,
+                        double* geo_partial, double* geo, hipStream_t s);
 // (sigma_x, sigma_y, eps_x, eps_y) from the moments mom (mean 6, covariance upper 21) into
 // the device array out_m[4]
 hipError_t launch_objective(const double* mom, double* out_m, hipStream_t s);
@@ -291,6 +307,14 @@ hipError_t launch_dL(const double* lam, const double* xi, int64_t n, double* par
                      hipStream_t s);
 
 // ---- igf.hip
+// the kernels' h-derivatives on the octant: 3 (potential, dGbar/dh_b) or 9 (field,
+// dKbar_a/dh_b at 3 a + b) corner arrays dc and cell arrays gd
+hipError_t launch_igf_dh(const Geom* g, int nx, int ny, int nz, bool field, double2* dc,
+                         double* gd, hipStream_t s);
+// their spectra, scaled as the Green spectrum: gh[b] (potential) or gh[3 b + a] (field)
+template <typename T>
+hipError_t launch_green_dh_spectra(const Geom* g, const FftPlan& p, int nx, int ny, int nz,
+                                   bool field, double2* dc, double* gd, T* gh, hipStream_t s);
 // the field kernels: corner values of H_x, H_y, H_z (3 (nx+2)(ny+2)(nz+2) double pairs) and
 // the three octant arrays Kbar_a (3 (nx+1)(ny+1)(nz+1) doubles)
 hipError_t launch_igf_field(const Geom* g, int nx, int ny, int nz, double2* hc, double* gd3,

@@ -2,7 +2,7 @@
 itself, pic_beam_desc.direct_field = 1) against the oracle's solve_field, on the same seeded
 inputs: the kernels' spectra and the three convolutions at 1e-12 of the largest field value,
 whole tracking runs at 1e-12 of the rms size per coordinate, FP32 grids within 1e-5 in the rms
-moments, the reverse sweep through the transposed field solve at 1e-10, and the rejection by
+moments, the reverse sweep through the transposed field solve at 1e-12, and the rejection by
 batches.  At the headline grid (128^3,
 TSC) with the bench's launch shapes: one step on 2e6 particles, sampled particles against the
 oracle within 1e-12.
@@ -157,12 +157,12 @@ def test_reverse_sweep_with_the_direct_field(lib, shape, ck):
     m, dk, lam, _ = b.track_adjoint(lat, steps, w, ckpt_every=ck)
     J, dk_o, lam_o, _ = oadj.adjoint_elements(X0, lat, steps, _problem(cfg, n, nodes, shape), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
-    check("field-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-10)
+    check("field-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-12)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lam_o[r]).max()
         if scale > 0:
-            check("field-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-10)
+            check("field-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-12)
 
 
 @pytest.mark.timeout(900)

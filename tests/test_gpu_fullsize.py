@@ -26,6 +26,14 @@ from oracle import pic as opic
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+# bars of dJ/dX0 at the adjoint workload (1e6 particles, 64^3), relative to each row's largest
+# entry: 1e-12, except the z and delta rows at 5e-12 (measured 9.9e-13 and 6.4e-13 on MI355X
+# with 1e-13 or less in the other rows).  The gradient through the box carries dJ/dmin and
+# dJ/dmax of z to the two particles at the box's z faces; these are differences of grid sums
+# (charge against the h-derivative convolution, e against E', the weights' sums) that cancel
+# by two to three orders of magnitude, so the two sides' rounding differences of 1e-15 in
+# those grids reach 1e-13 .. 1e-12 there.
+LAM_BARS_1E6 = (1e-12, 1e-12, 1e-12, 1e-12, 5e-12, 5e-12)
 
 
 @pytest.fixture(scope="module")
@@ -212,10 +220,10 @@ def test_adjoint_workload_two_steps_against_oracle(lib):
     J, dko, lamo, _ = oadj.adjoint(X0, ks, dss, 2, _problem(cfg), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
     dk = np.array(dk)
-    check("fullsize-adjoint-dk", rel_max(dk, dko, np.abs(dko).max()), 1e-10)
+    check("fullsize-adjoint-dk", rel_max(dk, dko, np.abs(dko).max()), 1e-12)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lamo[r]).max()
         if scale > 0:
-            check("fullsize-adjoint-lam%d" % r, rel_max(lg[r], lamo[r], scale), 1e-10)
+            check("fullsize-adjoint-lam%d" % r, rel_max(lg[r], lamo[r], scale), LAM_BARS_1E6[r])
     b.close()

@@ -138,12 +138,12 @@ def test_reverse_sweep_through_thick_elements(lib, shape, steps, ck):
                                               _problem(cfg, n, nodes, shape), w)
     assert abs(float(np.dot(w, m)) - J) < 1e-12 * abs(J)
     assert dk[0] == 0.0
-    check("thick-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-10)
+    check("thick-adjoint-dk", rel_max(dk, dk_o, np.abs(dk_o).max()), 1e-12)
     lg = lam.cpu().numpy()
     for r in range(6):
         scale = np.abs(lam_o[r]).max()
         if scale > 0:
-            check("thick-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-10)
+            check("thick-adjoint-lam%d" % r, rel_max(lg[r], lam_o[r], scale), 1e-12)
     # X holds the final state of the forward run, as pic_track_n_steps leaves it
     Xo = opic.track_elements(X0, ADJ_LATTICE, steps, _problem(cfg, n, nodes, shape))
     assert _coord_err(b.X.cpu().numpy(), Xo) < TOL

@@ -57,3 +57,24 @@ def test_dd_tables_match_their_generator():
     out = subprocess.run([sys.executable, os.path.join(d, "gen_dd_tables.py")], check=True,
                          capture_output=True, text=True).stdout
     assert out == open(os.path.join(d, "dd_tables.hpp")).read()
+
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (3e-4, 3.1e-4, 2.5e-2), (1e-4, 1e-4, 0.78)])
+@pytest.mark.parametrize("field", [0, 1])
+def test_kernel_h_derivatives_equal_oracle(lib, h, field):
+    # the device's corner functions of the kernels' h-derivatives (reduced forms of
+    # r_b H_b - F and r_b B_ab + H_a) and their folded cell sums, against the oracle's
+    # unreduced double-double forms: both are rounded once from a double-double value
+    nx, ny, nz = 9, 7, 8
+    nf = 9 if field else 3
+    cells = (nx + 1) * (ny + 1) * (nz + 1)
+    out = np.zeros(nf * cells)
+    lib.pic_hostcheck_igf_dh(field, nx, ny, nz, ctypes.c_double(h[0]), ctypes.c_double(h[1]),
+                             ctypes.c_double(h[2]), out.ctypes.data_as(ctypes.c_void_p))
+    for f in range(nf):
+        if field:
+            ref = igf.field_cell_average_dh(nx, ny, nz, *h, f // 3, f % 3)
+        else:
+            ref = igf.cell_average_dh(nx, ny, nz, *h, f)
+        got = out[f * cells:(f + 1) * cells].reshape(ref.shape)
+        assert np.abs(got - ref).max() <= 4.5e-16 * np.abs(ref).max(), f
