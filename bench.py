@@ -142,6 +142,29 @@ def measured_copy_gbs(nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / best / 1e9
 
 
+def lds_atomic_reference(blocks=2048, threads=1024, iters=2048):
+    """Measured 64-bit LDS atomic (ds_add_u64) throughput of this GPU, in lane-atomics/s, for
+    consecutive words (no bank conflict) and for hash-scattered words (libpic_probe.so), with
+    the per-clock-per-CU figure it implies at the published 2.4 GHz over the device's CUs."""
+    import ctypes
+    import torch
+    path = os.path.join(ROOT, "paper_2208_02382_amd", "libpic_probe.so")
+    lib = ctypes.CDLL(path)
+    lib.probe_lds_u64_atomics.restype = ctypes.c_int
+    lib.probe_lds_u64_atomics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"clock_GHz": 2.4, "compute_units": cus}
+    for pattern, name in ((0, "consecutive"), (1, "scattered")):
+        ms = ctypes.c_double()
+        if lib.probe_lds_u64_atomics(pattern, blocks, threads, iters, ctypes.byref(ms)) != 0:
+            raise RuntimeError("LDS atomic probe failed")
+        rate = blocks * threads * iters / (ms.value * 1e-3)
+        out[name] = {"lane_atomics_per_s": rate,
+                     "per_clock_per_cu": rate / (cus * 2.4e9), "ms": ms.value}
+    return out
+
+
 def device_info():
     import torch
     p = torch.cuda.get_device_properties(0)
@@ -157,28 +180,41 @@ def _rms(cov):
             math.sqrt(cov[2][2] * cov[3][3] - cov[2][3] ** 2)]
 
 
+ORACLE_RECORD = os.path.join(ROOT, "tests", "golden", "gauss-1e6-64c-cic_oracle.json")
+
+
 def fp32_accuracy(cfg, steps):
-    """Relative rms size and emittance differences of the float32-grid path from the float64
-    path (itself equal to the oracle within 1e-12) after `steps` steps from the same beam."""
+    """Relative rms size and emittance errors of the float64-grid and float32-grid paths after
+    `steps` steps of `cfg` from the seeded draws, against the oracle's tracking of the same beam
+    (the stored record of tests/golden/gen_medium_oracle.py, which calls only the oracle)."""
     import torch
+    import workloads
     import paper_2208_02382_amd as pic
 
-    out = []
+    with open(ORACLE_RECORD) as f:
+        rec = json.load(f)
+    if rec["workload"] != cfg.name or str(steps) not in rec["moments"]:
+        raise RuntimeError("no stored oracle record for %s after %d steps" % (cfg.name, steps))
+    m_oracle = rec["moments"][str(steps)]["objective"]
+    xi = torch.from_numpy(workloads.draw_xi(cfg)).cuda()
+    out = {}
     for fp32 in (False, True):
         b = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
                      cfg.shape, cfg.nodes, grid_fp32=fp32)
-        b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
+        b.init_from_normals(cfg.sigma_matrix, xi)
         t0 = time.perf_counter()
         b.track(cfg.lattice, steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         _, cov = b.moments()
-        out.append((_rms(cov), dt))
+        err = [abs(a - o) / abs(o) for a, o in zip(_rms(cov), m_oracle)]
+        out["f32" if fp32 else "f64"] = (err, dt)
         b.close()
-    (m64, t64), (m32, t32) = out
-    err = [abs(a - b) / abs(b) for a, b in zip(m32, m64)]
+    (e64, t64), (e32, t32) = out["f64"], out["f32"]
     return {"workload": cfg.name, "steps": steps,
-            "rel_err_sigx_sigy_epsx_epsy": err, "max_rel_err": max(err),
+            "reference": "FP64 oracle (stored record, tests/golden/gen_medium_oracle.py)",
+            "f32_rel_err_sigx_sigy_epsx_epsy": e32, "max_rel_err": max(e32),
+            "f64_rel_err_sigx_sigy_epsx_epsy": e64, "f64_max_rel_err": max(e64),
             "f64_particle_steps_per_s": cfg.n * steps / t64,
             "f32_particle_steps_per_s": cfg.n * steps / t32}
 
@@ -432,6 +468,17 @@ def main():
                 "overhead_bytes_per_launch": OVERHEAD_BYTES[name] * cfg.n}
 
     kernels = {k: roof(k, stages) for k in ("gkd", "deposit")}
+    # the deposit's LDS atomics: (S+1)^3 per particle, against the measured ds_add_u64 rates
+    lds_ref = lds_atomic_reference()
+    n_atomics = (cfg.shape + 1) ** 3 * cfg.n
+    dep_rate = n_atomics / (kernels["deposit"]["avg_launch_ms"] * 1e-3)
+    kernels["deposit"]["lds_atomics"] = {
+        "per_launch": n_atomics, "achieved_per_s": dep_rate,
+        "peak_consecutive_per_s": lds_ref["consecutive"]["lane_atomics_per_s"],
+        "frac_of_consecutive": dep_rate / lds_ref["consecutive"]["lane_atomics_per_s"],
+        "scattered_per_s": lds_ref["scattered"]["lane_atomics_per_s"],
+        "frac_of_scattered": dep_rate / lds_ref["scattered"]["lane_atomics_per_s"],
+        "reference": lds_ref}
     copy_gbs = measured_copy_gbs()
     for k in kernels.values():
         k["measured_copy_GBs"] = copy_gbs

@@ -14,6 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 # host build of the device double-double / IGF arithmetic, for CPU unit tests only
 HOSTCHECK = os.path.join(HERE, "libpic_hostcheck.so")
+# the bench's reference measurement of LDS atomic throughput (not part of libpic.so)
+PROBE = os.path.join(HERE, "libpic_probe.so")
 SOURCES = ["particles.hip", "sort.hip", "igf.hip", "fft.hip", "adjoint.hip", "noalloc.hip",
            "api.cpp"]
 
@@ -69,6 +71,12 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("hostcheck build failed: %s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, HOSTCHECK)
+    tmp = PROBE + ".tmp"
+    cmd = [hipcc] + FLAGS + ["-shared", os.path.join(CSRC, "probe_lds.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, PROBE)
     return LIB
 
 
