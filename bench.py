@@ -3,8 +3,11 @@
 
 One step = the whole hot path over the beam: box and grid geometry, charge deposition,
 integrated Green's function and its FFT, zero-padded FFT Poisson solve and field, fused field
-gather + space-charge kick + drifts + thin quadrupole (pic_track_n_steps).  Inputs are resident
-in HBM before the timed region (the beam is generated on the device).
+gather + space-charge kick + drifts + thin quadrupole.  Inputs are resident in HBM before the
+timed region (the beam is generated on the device).  The timed call is pic_track_n_steps_binned
+(the particles stay in the library's tile order between calls, as after the warm-up call);
+the same workload through pic_track_n_steps, which starts from and returns to the caller's
+particle order in every call, is reported next to it (variants.caller_order).
 
 Workload (default): 1e8 macroparticles, 6-D Gaussian with a 10 % uniform halo out to 4 sigma,
 128^3 grid (256^3 padded FFT), TSC, thin-lens FODO, float64 grid; the float32-grid variant is
@@ -33,11 +36,13 @@ ALGO_BYTES = {
 }
 # bytes per particle per launch the binned kernels move on top of that in the steady state of
 # the tracking loop, reported separately: the sort permutation's source index (both kernels)
-# and the particle id read and written by the gather-kick
+# and, where particle labels are carried (the caller's order), the id the gather-kick reads and
+# writes
 OVERHEAD_BYTES = {
     "deposit": 4,
-    "gkd": 12,
+    "gkd": 4,
 }
+ID_BYTES = {"deposit": 0, "gkd": 8}
 # (file, device function) whose source text the counter figures were taken on
 KERNEL_SOURCES = {"gkd": ("paper_2208_02382_amd/csrc/sort.hip", "gkd_tiles_body"),
                   "deposit": ("paper_2208_02382_amd/csrc/sort.hip", "deposit_tiles_body")}
@@ -98,7 +103,11 @@ def tuned(cfg, grid_fp32, enabled):
                "candidates": len(rec["tried"])}
 
 
-def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None, direct_field=False):
+def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None, direct_field=False,
+            binned=True):
+    """Warm-up call, then `steps` steps in one timed call: pic_track_n_steps_binned (X left in
+    the library's tile order between and after the calls) or, binned=False, pic_track_n_steps
+    (every call starts from and returns to the caller's particle order)."""
     import torch
     import paper_2208_02382_amd as pic
 
@@ -107,11 +116,11 @@ def run_gpu(cfg, steps, warmup, grid_fp32, X=None, tuning=None, direct_field=Fal
                     direct_field=direct_field)
     beam.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
     if warmup:
-        beam.track(cfg.lattice, warmup)
+        beam.track(cfg.lattice, warmup, binned=binned)
     torch.cuda.synchronize()
     beam.profile_start()
     t0 = time.perf_counter()
-    beam.track(cfg.lattice, steps)
+    beam.track(cfg.lattice, steps, binned=binned)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = beam.profile_read()
@@ -406,6 +415,12 @@ def main():
     ap.add_argument("--workload", default="gausshalo-1e8-128c-tsc")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="particles in the oracle's timed sample (0 disables)")
+    ap.add_argument("--order", choices=("binned", "caller"), default="binned",
+                    help="binned: pic_track_n_steps_binned (particles stay in the library's tile "
+                         "order between calls); caller: pic_track_n_steps (each call returns "
+                         "them to the caller's order)")
+    ap.add_argument("--no-caller-order", action="store_true",
+                    help="skip the caller-order variant of the headline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-grid variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched variant")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
@@ -453,7 +468,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     tuning, tune_info = tuned(cfg, False, not args.no_tune)
-    beam, dt, stages, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, tuning=tuning)
+    binned = args.order == "binned"
+    beam, dt, stages, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, tuning=tuning,
+                                  binned=binned)
     ps = cfg.n * args.steps / dt
 
     def roof(name, stg):
@@ -465,7 +482,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": t,
                 "kernel": name, "avg_launch_ms": avg * 1e3,
                 "algorithmic_bytes_per_launch": ALGO_BYTES[name] * cfg.n,
-                "overhead_bytes_per_launch": OVERHEAD_BYTES[name] * cfg.n}
+                "overhead_bytes_per_launch":
+                    (OVERHEAD_BYTES[name] + (0 if binned else ID_BYTES[name])) * cfg.n}
 
     kernels = {k: roof(k, stages) for k in ("gkd", "deposit")}
     # the deposit's LDS atomics: (S+1)^3 per particle, against the measured ds_add_u64 rates
@@ -487,13 +505,26 @@ def main():
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
 
     variants = {}
+    if binned and not args.no_caller_order:
+        # the same workload with every call starting from and returning to the caller's order
+        X = beam.X
+        beam.close()
+        del beam
+        bc, dtc, stc, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, X=X,
+                                  tuning=tuning, binned=False)
+        variants["caller_order"] = {
+            "value": cfg.n * args.steps / dtc, "ms_per_step": dtc / args.steps * 1e3,
+            "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in stc.items()},
+            "note": "pic_track_n_steps: the first step moves the caller's order into tile "
+                    "order and the call ends with the return to the caller's order"}
+        beam = bc
     if not args.no_fp32:
         X = beam.X
         beam.close()
         del beam
         tuning32, tune32 = tuned(cfg, True, not args.no_tune)
         b32, dt32, st32, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=True, X=X,
-                                     tuning=tuning32)
+                                     tuning=tuning32, binned=binned)
         variants["fp32_grid"] = {
             "value": cfg.n * args.steps / dt32, "ms_per_step": dt32 / args.steps * 1e3,
             "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in st32.items()},
@@ -507,7 +538,8 @@ def main():
         # the same beam through the paper's FODO cell of thick elements (Listing 1), one step
         # per slice (125 per cell)
         cfg_t = cfg.with_(lattice=workloads.THICK_FODO)
-        bt, dtt, stt, _ = run_gpu(cfg_t, args.steps, args.warmup, grid_fp32=False, tuning=tuning)
+        bt, dtt, stt, _ = run_gpu(cfg_t, args.steps, args.warmup, grid_fp32=False, tuning=tuning,
+                                  binned=binned)
         variants["thick_fodo"] = {
             "value": cfg.n * args.steps / dtt, "ms_per_step": dtt / args.steps * 1e3,
             "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in stt.items()},
@@ -539,7 +571,7 @@ def main():
     if not args.no_direct:
         # the headline workload with E' from the integrated Green's functions of the field
         bf, dtf, stf, _ = run_gpu(cfg, args.steps, args.warmup, grid_fp32=False, tuning=tuning,
-                                  direct_field=True)
+                                  direct_field=True, binned=binned)
         variants["direct_field"] = {
             "value": cfg.n * args.steps / dtf, "ms_per_step": dtf / args.steps * 1e3,
             "stage_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in stf.items()},
@@ -570,7 +602,9 @@ def main():
         "device": device_info(),
         "config": {"workload": cfg.name, "particles": cfg.n, "grid": list(cfg.nodes),
                    "shape": "TSC" if cfg.shape == 2 else "CIC", "grid_dtype": "f64",
-                   "halo_frac": cfg.halo_frac, "lattice": "thin FODO k=+-1/m, 0.5 m"},
+                   "halo_frac": cfg.halo_frac, "lattice": "thin FODO k=+-1/m, 0.5 m",
+                   "particle_order": "binned between calls (pic_track_n_steps_binned), no "
+                   "labels" if binned else "caller's order (pic_track_n_steps)"},
         "roofline": kernels[dominant],
         "autotune": tune_info,
         "kernels": kernels,

@@ -215,6 +215,20 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 
+/* evolve() without returning to the caller's particle order: as pic_track_n_steps, but X is left
+ * in the order of the last step's binning (particles grouped by grid tile), which the next
+ * call takes as its input.  d_ids (optional, device, n uint32, 4-byte aligned, caller-owned):
+ * labels that travel with the particles: on return d_ids[i] is the label that was at the index
+ * the particle now in slot i had on entry (start from 0..n-1 to follow the caller's indices;
+ * NULL: no labels, 8 bytes less traffic per particle and step).  Per call this saves the
+ * move of the caller's order into tile order on the first step (which then only ranks) and the
+ * return to the caller's order at the end (the last step's gather-kick writes X directly); the
+ * physics is the same, particle by particle and bit for bit, as pic_track_n_steps (moments,
+ * the objective and the deposit do not depend on the order).  X is left as it was if the device
+ * flags an error at any step's geometry (non-finite coordinate, zero-extent box). */
+pic_status pic_track_n_steps_binned(pic_beam b, const pic_element* lattice, int n_el,
+                                    int n_steps, uint32_t* d_ids, void* stream);
+
 /* Slice-step diagnostics (Listing 1: set_slice_step_diagnostics(True)): as pic_track_n_steps,
  * and after every step j the moments of the particles at the end of that step go to the device
  * array d_diag[27*j .. 27*j+26] (27 * n_steps doubles, 8-byte aligned, caller-owned): the six

@@ -63,6 +63,7 @@ _SIGS = {
     "pic_push": (_I, [_P, _I, _D, _P, _P]),
     "pic_track_n_steps": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P]),
     "pic_track_n_steps_diag": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P, _P]),
+    "pic_track_n_steps_binned": (_I, [_P, ctypes.POINTER(Element), _I, _I, _P, _P]),
     "pic_moments": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "pic_objective": (_I, [_P, ctypes.POINTER(_D), _P]),
     "pic_moments_noalloc": (_I, [_P, ctypes.c_int64, _P, _P]),
@@ -260,12 +261,23 @@ class Beam:
     def push(self, kind, value, Ep=None):
         _check(_lib.pic_push(self._h, int(kind), float(value), _ptr(Ep), _stream()), "pic_push")
 
-    def track(self, lattice, n_steps, diagnostics=False):
+    def track(self, lattice, n_steps, diagnostics=False, binned=False, ids=None):
         """lattice: (k, ds) thin steps or (kind, k, ds, nslice) elements, cycled over the steps.
         diagnostics: also return the moments at the end of every step, a float64 tensor
         (n_steps, 27) on the device (6 means, then the 21 centred second moments, upper
-        triangle row-major)."""
+        triangle row-major).  binned: leave X in the library's tile order
+        (pic_track_n_steps_binned); ids: optional int32/uint32 labels on the device, n entries,
+        permuted with the particles."""
         arr = _lattice(lattice)
+        if binned:
+            assert not diagnostics
+            if ids is not None:
+                assert ids.dtype in (torch.int32, torch.uint32) and ids.is_contiguous()
+                assert ids.numel() == self.n
+            _check(_lib.pic_track_n_steps_binned(self._h, arr, len(lattice), int(n_steps),
+                                                 _ptr(ids), _stream()),
+                   "pic_track_n_steps_binned")
+            return None
         if not diagnostics:
             _check(_lib.pic_track_n_steps(self._h, arr, len(lattice), int(n_steps), _stream()),
                    "pic_track_n_steps")

@@ -434,19 +434,26 @@ pic_status fork_green(pic_beam b, hipStream_t s) {
 // particles at the end of every step.  The binned gather-kick sums them in the same pass, about
 // the previous step's means; the unbinned fallback stops at the end of the step and separate
 // passes take the moments and apply the next step's first half map.
+// binned: leave X in the step's tile order instead of returning it to the caller's order; the
+// first step ranks instead of moving the particles (the input is usually the previous call's
+// tile order), the last gather-kick writes X (and ids_io, the caller's labels, when given)
+// directly.
 template <typename T>
 pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, double* diag,
-                    hipStream_t s) {
+                    hipStream_t s, bool binned = false, uint32_t* ids_io = nullptr) {
   const int ns = (int)sl.size();
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   double* A = b->XA;
   double* B = b->XB;
-  uint32_t* idA = b->idA;
-  uint32_t* idB = b->idB;
+  // without labels a binned call carries no ids
+  const bool ids = !binned || ids_io;
+  uint32_t* idA = ids ? b->idA : nullptr;
+  uint32_t* idB = ids ? b->idB : nullptr;
   HIP_OK(launch_box_reset(b->box, s), "box reset");
   HIP_OK(clear_tacc(b, s), "clear");
   STAGE(b, PIC_STAGE_PROLOGUE, s,
-        launch_prologue(b->X, A, idA, sl[0].first, b->c, b->box, s), "prologue");
+        launch_prologue(b->X, A, idA, binned ? ids_io : nullptr, sl[0].first, b->c, b->box, s),
+        "prologue");
   // the E' window of a tile must fit the LDS a workgroup may use
   const size_t win_bytes = 3 * sizeof(T) * (size_t)(b->sp.T[0] + b->d.shape) *
                            (b->sp.T[1] + b->d.shape) * (b->sp.T[2] + b->d.shape);
@@ -462,7 +469,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     // After the first step A is in the previous step's tile order: only the ranking is
     // written, and the gather-kick moves the particles (A -> B) while it updates them.  The
     // first step moves the caller's order into tile order (A -> B) and updates B in place.
-    const bool permuted = tiles && j > 0;
+    const bool permuted = tiles && (j > 0 || binned);
     if (permuted)
       STAGE(b, PIC_STAGE_BIN, s,
             launch_bin_perm(A, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
@@ -486,10 +493,15 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     double* diag_j = diag ? diag + (size_t)kMomentSlots * j : nullptr;
     const SliceDev& nx = sl[(j + 1) % ns];
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
+    // a binned call's last gather-kick writes the caller's arrays (it always reads A through
+    // the ranking, so X is written only if no step has flagged an error)
+    const bool to_caller = binned && tiles && !more;
+    double* out = to_caller ? b->X : B;
+    uint32_t* id_out = to_caller ? ids_io : idB;
     if (tiles)
       STAGE(b, PIC_STAGE_GKD, s,
-            launch_gkd_tiles<T>(B, permuted ? A : nullptr, permuted ? b->perm : nullptr,
-                                permuted ? idA : nullptr, permuted ? idB : nullptr, b->geom,
+            launch_gkd_tiles<T>(out, permuted ? A : nullptr, permuted ? b->perm : nullptr,
+                                permuted ? idA : nullptr, permuted ? id_out : nullptr, b->geom,
                                 (const T*)b->E, b->c, b->sp, b->chunks, b->nchunks, e.L,
                                 e.second, has_next, nx.first, b->box, s, b->diag_part,
                                 b->diag_shift, j > 0 && diag_j ? diag_j - kMomentSlots : nullptr,
@@ -510,6 +522,16 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     // B holds the updated particles in slot order
     double* tX = A; A = B; B = tX;
     uint32_t* tI = idA; idA = idB; idB = tI;
+  }
+  if (binned) {
+    if (!tiles) {  // the unbinned fallback leaves the state in A: copied in slot order
+      HIP_OK(launch_copy_if_ok(A, b->X, 6 * sizeof(double) * (size_t)b->c.n, b->geom, s),
+             "binned copy");
+      if (ids_io)
+        HIP_OK(launch_copy_if_ok(idA, ids_io, sizeof(uint32_t) * (size_t)b->c.n, b->geom, s),
+               "binned copy");
+    }
+    return PIC_OK;
   }
   STAGE(b, PIC_STAGE_UNPERMUTE, s,
         launch_unpermute(A, idA, b->c.n, b->X, b->keys, b->hist, b->cursor, b->chunks,
@@ -1148,7 +1170,7 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
 
 namespace {
 pic_status track(pic_beam b, const pic_element* lattice, int n_el, int n_steps, double* diag,
-                 void* stream) {
+                 void* stream, bool binned = false, uint32_t* ids_io = nullptr) {
   if (!b || !lattice) return fail(PIC_EINVAL, "NULL argument");
   MarkDone md{b->done, S(stream)};
   if (n_el < 1 || n_steps < 0) return fail(PIC_EINVAL, "n_el must be >= 1 and n_steps >= 0");
@@ -1167,14 +1189,20 @@ pic_status track(pic_beam b, const pic_element* lattice, int n_el, int n_steps, 
     }
     return PIC_OK;
   }
-  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, diag, s);
-  return track_sc<double>(b, sl, n_steps, diag, s);
+  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, diag, s, binned, ids_io);
+  return track_sc<double>(b, sl, n_steps, diag, s, binned, ids_io);
 }
 }  // namespace
 
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream) {
   return track(b, lattice, n_el, n_steps, nullptr, stream);
+}
+
+pic_status pic_track_n_steps_binned(pic_beam b, const pic_element* lattice, int n_el,
+                                    int n_steps, uint32_t* d_ids, void* stream) {
+  if (d_ids && ((uintptr_t)d_ids & 3)) return fail(PIC_EINVAL, "d_ids must be 4-byte aligned");
+  return track(b, lattice, n_el, n_steps, nullptr, stream, true, d_ids);
 }
 
 pic_status pic_track_n_steps_diag(pic_beam b, const pic_element* lattice, int n_el, int n_steps,

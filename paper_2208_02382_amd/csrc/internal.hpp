@@ -186,8 +186,10 @@ inline int64_t tile_window_nodes(const SortPlan& sp, int S) {
 // tile[a], chunk, blocks: 0 selects the default
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
                         int blocks, int threads);
-hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
-                           Consts c, Box* box, hipStream_t s);
+// A = the first half map of X with the box of its positions; idA (if given) = ids_in, or the
+// indices 0..n-1 when ids_in is nullptr
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const uint32_t* ids_in,
+                           const HalfMap& first, Consts c, Box* box, hipStream_t s);
 hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Consts c,
                       const SortPlan& sp, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
                       int4* chunks, uint32_t* nchunks, double* B, uint32_t* idB, bool staged,
@@ -206,7 +208,7 @@ hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geo
                                 T* rho, hipStream_t s, unsigned long long* tacc, int* tscale);
 // perm == nullptr: B in slot order, updated in place (src, idsrc, iddst unused); else slot i
 // reads particle perm[i] of src and id idsrc[perm[i]], and writes slot i of B and iddst
-// (src != B, idsrc != iddst).  diag_out != nullptr: the moments (kMomentSlots doubles) of the
+// (src != B, idsrc != iddst; iddst == nullptr: no ids).  diag_out != nullptr: the moments (kMomentSlots doubles) of the
 // state after the second half map go to diag_out, summed in the same pass into diag_part
 // (sp.blocks * kMomentSlots doubles) about diag_shift (6 doubles, set from diag_prev, the
 // previous step's moments, or from the grid centre when diag_prev is nullptr).
@@ -218,6 +220,9 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
                             int has_next, const HalfMap& first_next, Box* box, hipStream_t s,
                             double* diag_part = nullptr, double* diag_shift = nullptr,
                             const double* diag_prev = nullptr, double* diag_out = nullptr);
+// dst = src (bytes, a multiple of 4; both 4-byte aligned) unless the geometry's error flag is set
+hipError_t launch_copy_if_ok(const void* src, void* dst, size_t bytes, const Geom* g,
+                             hipStream_t s);
 // both half maps of a slice without a kick (tracking without space charge)
 hipError_t launch_half_maps(double* X, const HalfMap& first, const HalfMap& second, Consts c,
                             hipStream_t s);

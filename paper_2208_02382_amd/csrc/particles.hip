@@ -358,6 +358,15 @@ __global__ __launch_bounds__(kBlock) void k_mom_cov(const double* __restrict__ X
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy_if_ok(const uint32_t* __restrict__ src,
+                                                     uint32_t* __restrict__ dst, int64_t words,
+                                                     const Geom* __restrict__ g) {
+  if (g->status) return;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_zero(T* p, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count;
@@ -531,6 +540,14 @@ hipError_t launch_moments(const double* X, int64_t n, double* partial, double* o
   hipLaunchKernelGGL(k_mom_cov, dim3(kReduceBlocks), dim3(kBlock), 0, s, X, n, out, partial);
   hipLaunchKernelGGL(k_mom_combine, dim3(21), dim3(64), 0, s, partial, kReduceBlocks, 6, 27, n,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_if_ok(const void* src, void* dst, size_t bytes, const Geom* g,
+                             hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 4);
+  hipLaunchKernelGGL(k_copy_if_ok, dim3(grid_for(words)), dim3(kBlock), 0, s,
+                     (const uint32_t*)src, (uint32_t*)dst, words, g);
   return hipGetLastError();
 }
 

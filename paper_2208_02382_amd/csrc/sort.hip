@@ -787,7 +787,8 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       }
       if (act) {
         for (int r = 0; r < 6; ++r) B[r * n + slot] = v[r];
-        if constexpr (PERM) iddst[slot] = idsrc[i0];
+        if constexpr (PERM)
+          if (iddst) iddst[slot] = idsrc[i0];
       }
     }
   }
@@ -891,10 +892,12 @@ __global__ __launch_bounds__(1024) void k_diag_combine(const Geom* __restrict__ 
   out[q] = tot[q] * inv - (tot[a] * inv) * (tot[b] * inv);
 }
 
-// First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.
+// First half of the first step out of the caller's array: A = drift(quad(X)), ids, box.  The
+// ids are the caller's labels ids_in (binned order) or the indices in X; idA == nullptr: none.
 __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
                                                    double* __restrict__ A,
                                                    uint32_t* __restrict__ idA,
+                                                   const uint32_t* __restrict__ ids_in,
                                                    const HalfMap& first, Consts c, Box* box,
                                                    int blk, int nblk) {
   const int64_t n = c.n;
@@ -906,7 +909,7 @@ __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
     for (int r = 0; r < 6; ++r) v[r] = X[r * n + i];
     apply_half(first, v, c.inv_gamma2);
     for (int r = 0; r < 6; ++r) A[r * n + i] = v[r];
-    idA[i] = (uint32_t)i;
+    if (idA) idA[i] = ids_in ? ids_in[i] : (uint32_t)i;
     double p[3] = {v[0], v[2], v[4]};
     for (int a = 0; a < 3; ++a) {
       bad |= !isfinite(p[a]);
@@ -919,9 +922,10 @@ __device__ __forceinline__ void prologue_body(const double* __restrict__ X,
 
 __global__ __launch_bounds__(kBlk) void k_prologue(const double* __restrict__ X,
                                                    double* __restrict__ A,
-                                                   uint32_t* __restrict__ idA, HalfMap first,
-                                                   Consts c, Box* box) {
-  prologue_body(X, A, idA, first, c, box, blockIdx.x, gridDim.x);
+                                                   uint32_t* __restrict__ idA,
+                                                   const uint32_t* __restrict__ ids_in,
+                                                   HalfMap first, Consts c, Box* box) {
+  prologue_body(X, A, idA, ids_in, first, c, box, blockIdx.x, gridDim.x);
 }
 
 // Bucket keys for the return to the caller's order: key = id >> shift (at most 4096 buckets of
@@ -1045,7 +1049,7 @@ __device__ __forceinline__ uint32_t* nxt_id(const BeamDev& d, int parity) { retu
 
 __global__ __launch_bounds__(kBlk) void k_prologue_batch(const BeamDev* __restrict__ beams) {
   const BeamDev& d = beams[blockIdx.y];
-  prologue_body(d.X, d.XA, d.idA, d.slices[0].first, d.c, d.box, blockIdx.x, gridDim.x);
+  prologue_body(d.X, d.XA, d.idA, nullptr, d.slices[0].first, d.c, d.box, blockIdx.x, gridDim.x);
 }
 
 template <int S>
@@ -1202,10 +1206,10 @@ hipError_t lds_optin(K kernel, size_t bytes) {
     if (e_ != hipSuccess) return e_;          \
   } while (0)
 
-hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const HalfMap& first,
-                           Consts c, Box* box, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(grid_stride(c.n)), dim3(kBlk), 0, s, X, A, idA, first, c,
-                     box);
+hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const uint32_t* ids_in,
+                           const HalfMap& first, Consts c, Box* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(grid_stride(c.n)), dim3(kBlk), 0, s, X, A, idA, ids_in,
+                     first, c, box);
   return hipGetLastError();
 }
 
@@ -1323,7 +1327,8 @@ hipError_t launch_gkd_tiles(double* B, const double* src, const uint32_t* perm,
   const bool diag = diag_out != nullptr;
   const dim3 grid((unsigned)sp.blocks),
       block((unsigned)(diag ? std::min(sp.threads, kDiagThreads) : sp.threads));
-  if (perm && (!src || !idsrc || !iddst || src == B || idsrc == iddst))
+  // the ids are optional, as a pair
+  if (perm && (!src || src == B || (!idsrc != !iddst) || (idsrc && idsrc == iddst)))
     return hipErrorInvalidValue;
   if (diag) {
     if (!diag_part || !diag_shift) return hipErrorInvalidValue;
