@@ -141,26 +141,34 @@ __device__ __forceinline__ void ext_block_partial(Extremes& ex, double* __restri
   }
 }
 
-// out[q] = the index of extreme q over the block partials (one thread per slot, blocks in order)
+// out[q] = the index of extreme q = blockIdx.x over the block partials: one wave per slot, lane
+// l merging blocks l, l + 64, ..., then a butterfly; the merge (better value, lower index on a
+// tie) is a total order, so the result does not depend on the order of the merges
 __global__ void k_ext_combine(const double* __restrict__ partial, int nblocks,
                               double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= 6) return;
+  const int q = blockIdx.x;
   Extremes m;
   ext_init(m);
-  for (int b = 0; b < nblocks; ++b)
+  for (int b = threadIdx.x; b < nblocks; b += 64)
     ext_merge(m, q, partial[b * 12 + q], (int64_t)partial[b * 12 + 6 + q]);
-  out[q] = (double)m.i[q];
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v = __shfl_xor(m.v[q], off);
+    const int64_t i = __shfl_xor(m.i[q], off);
+    ext_merge(m, q, v, i);
+  }
+  if (threadIdx.x == 0) out[q] = (double)m.i[q];
 }
 
-// out[q] = sum over blocks (in order) of partial[b ncols + q], q < ncols (one thread per column)
-__global__ void k_combine_cols(const double* __restrict__ partial, int nblocks, int ncols,
-                               double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= ncols) return;
+// out[q] = sum over b < nblocks of partial[b sb + q sq] for column q = blockIdx.x: one wave per
+// column, lane l summing b = l, l + 64, ..., then a fixed butterfly (the order does not depend
+// on timing)
+__global__ void k_combine_cols(const double* __restrict__ partial, int nblocks, int64_t sb,
+                               int64_t sq, double* __restrict__ out) {
+  const int q = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[b * ncols + q];
-  out[q] = s;
+  for (int b = threadIdx.x; b < nblocks; b += 64) s += partial[b * sb + q * sq];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (threadIdx.x == 0) out[q] = s;
 }
 
 // block partials of ncomp grid dot products: partial[blk ncomp + c] = sum_i a[c stride + i]
@@ -584,7 +592,7 @@ hipError_t launch_adj_a(const double* X, double* lam, const Geom* g, Consts c,
     hipLaunchKernelGGL((k_adj_a<2, T>), dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, e,
                        ext_partial);
   PIC_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_ext_combine, dim3(1), dim3(64), 0, s, ext_partial, nb, geo);
+  hipLaunchKernelGGL(k_ext_combine, dim3(6), dim3(64), 0, s, ext_partial, nb, geo);
   return hipGetLastError();
 }
 
@@ -594,7 +602,7 @@ hipError_t launch_adj_stage(const double* X, double* lam, const Geom* g, Consts 
   const int nb = grid_for(c.n);
   hipLaunchKernelGGL(k_adj_stage, dim3(nb), dim3(kBlk), 0, s, X, lam, g, c, sl, P, ext_partial);
   PIC_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_ext_combine, dim3(1), dim3(64), 0, s, ext_partial, nb, geo);
+  hipLaunchKernelGGL(k_ext_combine, dim3(6), dim3(64), 0, s, ext_partial, nb, geo);
   return hipGetLastError();
 }
 
@@ -605,7 +613,8 @@ hipError_t launch_grid_dot(const T* a, const T* b, int64_t count, int ncomp, int
   hipLaunchKernelGGL((k_grid_dot<T>), dim3(nb), dim3(kBlk), 0, s, a, b, count, ncomp, stride,
                      partial);
   PIC_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_combine_cols, dim3(1), dim3(64), 0, s, partial, nb, ncomp, out);
+  hipLaunchKernelGGL(k_combine_cols, dim3(ncomp), dim3(64), 0, s, partial, nb, (int64_t)ncomp,
+                     (int64_t)1, out);
   return hipGetLastError();
 }
 
@@ -639,12 +648,9 @@ hipError_t launch_adj_b(const double* X, double* lam, const Geom* g, Consts c, c
   hipLaunchKernelGGL(k_adj_dk_combine, dim3(1), dim3(64), 0, s, dk_partial, nb, dk, sl.elem);
   PIC_TRY(hipGetLastError());
   // geo_partial[q nb + b] (q = 0..5) summed over the blocks into geo[6 + q]
-  for (int q = 0; q < 6; ++q) {
-    hipLaunchKernelGGL(k_combine_cols, dim3(1), dim3(64), 0, s, geo_partial + q * nb, nb, 1,
-                       geo + 6 + q);
-    PIC_TRY(hipGetLastError());
-  }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_combine_cols, dim3(6), dim3(64), 0, s, geo_partial, nb, (int64_t)1,
+                     (int64_t)nb, geo + 6);
+  return hipGetLastError();
 }
 
 hipError_t launch_obj_grad(const double* X, int64_t n, const double* mom, const double w[4],
