@@ -245,6 +245,9 @@ struct pic_beam_s {
   uint32_t* cursor;
   int4* chunks;
   uint32_t* nchunks;
+  // X is in the tile order a pic_track_n_steps_binned call left it in (the next binned call
+  // then only ranks on its first step); the initialisations reset it
+  bool x_binned = false;
   // the Green spectrum of a step runs on `aux`, concurrently with the binning and deposit
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -435,12 +438,13 @@ pic_status fork_green(pic_beam b, hipStream_t s) {
 // the previous step's means; the unbinned fallback stops at the end of the step and separate
 // passes take the moments and apply the next step's first half map.
 // binned: leave X in the step's tile order instead of returning it to the caller's order; the
-// first step ranks instead of moving the particles (the input is usually the previous call's
-// tile order), the last gather-kick writes X (and ids_io, the caller's labels, when given)
-// directly.
+// last gather-kick writes X (and ids_io, the caller's labels, when given) directly.  With
+// first_ranked (X is in the tile order of a previous binned call) the first step only ranks
+// instead of moving the particles into tile order.
 template <typename T>
 pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, double* diag,
-                    hipStream_t s, bool binned = false, uint32_t* ids_io = nullptr) {
+                    hipStream_t s, bool binned = false, uint32_t* ids_io = nullptr,
+                    bool first_ranked = false) {
   const int ns = (int)sl.size();
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
   double* A = b->XA;
@@ -469,7 +473,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     // After the first step A is in the previous step's tile order: only the ranking is
     // written, and the gather-kick moves the particles (A -> B) while it updates them.  The
     // first step moves the caller's order into tile order (A -> B) and updates B in place.
-    const bool permuted = tiles && (j > 0 || binned);
+    const bool permuted = tiles && (j > 0 || first_ranked);
     if (permuted)
       STAGE(b, PIC_STAGE_BIN, s,
             launch_bin_perm(A, b->geom, b->c, b->sp, b->keys, b->hist, b->cursor, b->chunks,
@@ -495,7 +499,7 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     if (has_next) HIP_OK(launch_box_reset(b->box, s), "box reset");
     // a binned call's last gather-kick writes the caller's arrays (it always reads A through
     // the ranking, so X is written only if no step has flagged an error)
-    const bool to_caller = binned && tiles && !more;
+    const bool to_caller = binned && permuted && !more;
     double* out = to_caller ? b->X : B;
     uint32_t* id_out = to_caller ? ids_io : idB;
     if (tiles)
@@ -524,7 +528,10 @@ pic_status track_sc(pic_beam b, const std::vector<SliceDev>& sl, int n_steps, do
     uint32_t* tI = idA; idA = idB; idB = tI;
   }
   if (binned) {
-    if (!tiles) {  // the unbinned fallback leaves the state in A: copied in slot order
+    // a last step that did not write X (a one-step call that moved the particles, or the
+    // gather's global-load fallback) leaves the state in A: copied in slot order
+    const bool last_to_caller = tiles && (n_steps > 1 || first_ranked);
+    if (!last_to_caller) {
       HIP_OK(launch_copy_if_ok(A, b->X, 6 * sizeof(double) * (size_t)b->c.n, b->geom, s),
              "binned copy");
       if (ids_io)
@@ -1041,6 +1048,7 @@ pic_status pic_init_beam(pic_beam b, const double sigma[36], uint64_t seed, doub
   hipStream_t s = S(stream);
   HIP_OK(launch_init_philox(b->X, b->d.n, n_halo, seed, L, 0, s), "init_beam");
   HIP_OK(launch_clear_status(b->geom, s), "init_beam");
+  b->x_binned = false;
   return PIC_OK;
 }
 
@@ -1053,6 +1061,7 @@ pic_status pic_init_beam_waterbag(pic_beam b, const double sigma[36], uint64_t s
   hipStream_t s = S(stream);
   HIP_OK(launch_init_philox(b->X, b->d.n, 0, seed, L, 1, s), "init_beam_waterbag");
   HIP_OK(launch_clear_status(b->geom, s), "init_beam_waterbag");
+  b->x_binned = false;
   return PIC_OK;
 }
 
@@ -1084,6 +1093,7 @@ pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const 
   hipStream_t s = S(stream);
   HIP_OK(launch_init_normals(b->X, d_xi, b->d.n, L, s), "init_beam_from_normals");
   HIP_OK(launch_clear_status(b->geom, s), "init_beam_from_normals");
+  b->x_binned = false;
   return PIC_OK;
 }
 
@@ -1189,8 +1199,12 @@ pic_status track(pic_beam b, const pic_element* lattice, int n_el, int n_steps, 
     }
     return PIC_OK;
   }
-  if (b->d.grid_fp32) return track_sc<float>(b, sl, n_steps, diag, s, binned, ids_io);
-  return track_sc<double>(b, sl, n_steps, diag, s, binned, ids_io);
+  const bool first_ranked = binned && b->x_binned;
+  const pic_status st =
+      b->d.grid_fp32 ? track_sc<float>(b, sl, n_steps, diag, s, binned, ids_io, first_ranked)
+                     : track_sc<double>(b, sl, n_steps, diag, s, binned, ids_io, first_ranked);
+  if (st == PIC_OK && binned) b->x_binned = true;
+  return st;
 }
 }  // namespace
 

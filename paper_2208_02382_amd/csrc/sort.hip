@@ -223,7 +223,8 @@ __device__ __forceinline__ void scatter_staged_body(const double* __restrict__ A
     }
   }
   __syncthreads();
-  for (int r = 0; r < 7; ++r) {
+  const int rows = idA ? 7 : 6;  // the ids travel as a seventh row when there are any
+  for (int r = 0; r < rows; ++r) {
     for (int k = 0; k < kPer; ++k) {
       const int l = k * kBlk + threadIdx.x;
       if (l < m) {
@@ -280,7 +281,7 @@ __device__ __forceinline__ void scatter_direct_body(const double* __restrict__ A
       uint32_t pos = atomicAdd(&lh[key[k]], 1u);
       if (pos < (uint64_t)n) {  // always true for a consistent histogram; keeps writes in bounds
         for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
-        idB[pos] = idA[i];
+        if (idA) idB[pos] = idA[i];
       }
     }
   }

@@ -52,6 +52,15 @@ def test_binned_calls_equal_caller_order_tracking(lib, shape, grid_fp32):
     _compare(lib, cfg, cfg.lattice, [2, 4, 2], grid_fp32=grid_fp32)
 
 
+@pytest.mark.parametrize("calls", [[1], [1, 1], [3, 1, 2]])
+def test_binned_calls_of_any_length(lib, calls):
+    # a one-element lattice keeps every split of the steps in phase; a call's first step on a
+    # beam that no binned call has ordered moves the particles into tile order (and a one-step
+    # call then copies them out), later calls only rank
+    cfg = workloads.MEDIUM.with_(n=120_000, nodes=(32, 32, 32), shape=2)
+    _compare(lib, cfg, [(1.0, 0.5)], calls)
+
+
 def test_binned_thick_lattice_and_direct_field(lib):
     cfg = workloads.MEDIUM.with_(n=100_001, nodes=(32, 32, 32), shape=2)
     lattice = workloads.THICK_FODO
