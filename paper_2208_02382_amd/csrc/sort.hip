@@ -172,6 +172,30 @@ __device__ void block_exclusive_scan_lds(uint32_t* a, int count) {
   __syncthreads();
 }
 
+// LDS atomic add of 1 per active lane to lh[key], aggregated over the wave: one atomic per
+// distinct key among the active lanes (their count), each lane getting the value it would
+// have had from its own atomic in lane order.  Called by all lanes of the wave (the loop is
+// wave-uniform).  After the first step of a call the particles arrive in the previous step's
+// tile order, so a wave holds only a few distinct keys and the same-address atomics that
+// would serialise lane by lane collapse into one per key.
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* lh, uint32_t key, bool active) {
+  const int lane = (int)__lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint64_t todo = __ballot(active);
+  uint32_t out = 0u;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;  // wave-uniform
+    const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+    const uint64_t grp = todo & __ballot(key == k0);
+    uint32_t b = 0u;
+    if (lane == leader) b = atomicAdd(&lh[k0], (uint32_t)__popcll(grp));
+    b = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
+    if ((grp >> lane) & 1ull) out = b + (uint32_t)__popcll(grp & below);
+    todo &= ~grp;
+  }
+  return out;
+}
+
 // Counting-sort scatter of one block of kItems particles, staged: the block ranks its items by
 // key in LDS (local offsets by a scan of its key counts, one global atomic per key present to
 // reserve the key's run in the output), then moves each row through LDS in ranked order, so
@@ -277,38 +301,12 @@ __device__ __forceinline__ void scatter_direct_body(const double* __restrict__ A
   __syncthreads();
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
-    if (i < n) {
-      uint32_t pos = atomicAdd(&lh[key[k]], 1u);
-      if (pos < (uint64_t)n) {  // always true for a consistent histogram; keeps writes in bounds
-        for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
-        if (idA) idB[pos] = idA[i];
-      }
+    const uint32_t pos = wave_aggregated_add(lh, key[k], i < n);
+    if (i < n && pos < (uint64_t)n) {  // in bounds for a consistent histogram
+      for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
+      if (idA) idB[pos] = idA[i];
     }
   }
-}
-
-// LDS atomic add of 1 per active lane to lh[key], aggregated over the wave: one atomic per
-// distinct key among the active lanes (their count), each lane getting the value it would
-// have had from its own atomic in lane order.  Called by all lanes of the wave (the loop is
-// wave-uniform).  After the first step of a call the particles arrive in the previous step's
-// tile order, so a wave holds only a few distinct keys and the same-address atomics that
-// would serialise lane by lane collapse into one per key.
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* lh, uint32_t key, bool active) {
-  const int lane = (int)__lane_id();
-  const uint64_t below = (1ull << lane) - 1ull;
-  uint64_t todo = __ballot(active);
-  uint32_t out = 0u;
-  while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const uint32_t k0 = __shfl(key, leader);
-    const uint64_t grp = todo & __ballot(key == k0);
-    uint32_t b = 0u;
-    if (lane == leader) b = atomicAdd(&lh[k0], (uint32_t)__popcll(grp));
-    b = __shfl(b, leader);
-    if ((grp >> lane) & 1ull) out = b + (uint32_t)__popcll(grp & below);
-    todo &= ~grp;
-  }
-  return out;
 }
 
 // Ranking of one block of kItems particles as in the direct form, writing only the source
@@ -322,12 +320,15 @@ __device__ __forceinline__ void scatter_perm_body(const uint32_t* __restrict__ k
   for (int t = threadIdx.x; t < ntiles; t += kBlk) lh[t] = 0u;
   __syncthreads();
   const int64_t base = (int64_t)blk * kItems;
+  // all of the thread's keys are loaded before the first (wave-uniform, branching) histogram
+  // add, so that the loads overlap instead of each waiting behind the previous add
   uint32_t key[kPer];
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
     key[k] = i < n ? keys[i] : 0u;
-    (void)wave_aggregated_add(lh, key[k], i < n);
   }
+  for (int k = 0; k < kPer; ++k)
+    (void)wave_aggregated_add(lh, key[k], base + k * kBlk + threadIdx.x < n);
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += kBlk)
     if (lh[t]) lh[t] = atomicAdd(&cursor[t], lh[t]);
@@ -425,28 +426,45 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     if (threadIdx.x == 0) tscale[t] = k;  // every chunk of the tile writes the same k
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) win[w] = 0ull;
     __syncthreads();
-    for (int64_t i = ch.y + threadIdx.x; i < ch.z; i += (int)blockDim.x) {
-      // slot i holds particle perm[i] of B (B itself in slot order without a permutation)
-      int64_t r = i;
-      if (perm) {
-        r = perm[i];
-        if (r >= n) {  // impossible for a consistent ranking: flagged, the particle skipped
-          bin_fault = true;
-          continue;
-        }
+    // Software-pipelined over the lane's slots i, i + stride, ...: the index of the slot two
+    // ahead and the position of the slot one ahead are loaded before the current particle's
+    // atomics are issued, so that the loads' latency overlaps the LDS work.  Slot i holds
+    // particle perm[i] of B (B itself in slot order without a permutation); an index past n,
+    // impossible for a consistent ranking, is flagged and its particle skipped.
+    const int64_t stride = (int)blockDim.x;
+    auto index_of = [&](int64_t j) -> int64_t { return perm ? (int64_t)perm[j] : j; };
+    int64_t i = ch.y + threadIdx.x;
+    int64_t r_cur = i < ch.z ? index_of(i) : 0;
+    int64_t r_next = i + stride < ch.z ? index_of(i + stride) : 0;
+    double p_cur[3] = {0.0, 0.0, 0.0};
+    if (i < ch.z && r_cur < n) {
+      p_cur[0] = B[r_cur];
+      p_cur[1] = B[2 * n + r_cur];
+      p_cur[2] = B[4 * n + r_cur];
+    }
+    for (; i < ch.z; i += stride) {
+      const bool has_next = i + stride < ch.z;
+      double p_next[3] = {0.0, 0.0, 0.0};
+      if (has_next && r_next < n) {
+        p_next[0] = B[r_next];
+        p_next[1] = B[2 * n + r_next];
+        p_next[2] = B[4 * n + r_next];
       }
+      const int64_t r_after = i + 2 * stride < ch.z ? index_of(i + 2 * stride) : 0;
+      const bool valid = r_cur < n;
+      if (!valid) bin_fault = true;
       double wx[S + 1], wy[S + 1], wz[S + 1];
-      const int bx = stencil<S>((B[r] - o[0]) * ih[0], c.nx, wx);
-      const int by = stencil<S>((B[2 * n + r] - o[1]) * ih[1], c.ny, wy);
-      const int bz = stencil<S>((B[4 * n + r] - o[2]) * ih[2], c.nz, wz);
+      const int bx = stencil<S>((p_cur[0] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((p_cur[1] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((p_cur[2] - o[2]) * ih[2], c.nz, wz);
       const int lx = bx - ox, ly = by - oy, lz = bz - oz;
       const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
                           lz < sp.T[2];
       // the binning put the particle in the chunk's tile with this very stencil function, so
       // its stencil lies in the window; a violation is a library fault, flagged as the
       // gather-kick flags it (PIC_EINTERNAL), and the particle is not deposited
-      if (!inside) bin_fault = true;
-      if (inside) {
+      if (valid && !inside) bin_fault = true;
+      if (valid && inside) {
         // q_m 2^k w rounded to the nearest integer by one fused multiply-add with 1.5 2^52
         // (the sum then has the integer in its low mantissa bits, |value| < 2^51), read back
         // as a two's-complement int64 by subtracting the constant's bit pattern
@@ -465,6 +483,9 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
           }
         }
       }
+      r_cur = r_next;
+      r_next = r_after;
+      for (int a = 0; a < 3; ++a) p_cur[a] = p_next[a];
     }
     __syncthreads();
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
@@ -1076,7 +1097,7 @@ __global__ __launch_bounds__(kBlk) void k_scatter_batch(const BeamDev* __restric
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
+__global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
   deposit_tiles_body<S, T>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
@@ -1099,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_clear_tacc_batch(const BeamDev* __restr
 }
 
 template <int S, typename T>
-__global__ __launch_bounds__(kMaxThreads) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
+__global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
                                                           int parity, int j, int n_steps) {
   const BeamDev& d = beams[blockIdx.y];
   const SliceDev& sl = d.slices[j % d.n_slices];
