@@ -426,6 +426,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint variant")
     ap.add_argument("--no-thick", action="store_true",
                     help="skip the thick-element (Listing 1 FODO) variant")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip one GPU's share of the headline at 8 GPUs (n/8 particles)")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the direct-field variant (E' from the field's own IGF)")
     ap.add_argument("--batch-beams", type=int, default=256)
@@ -567,6 +569,25 @@ def main():
             "last_step_rms_x_y": [float(diag[-1, 6] ** 0.5), float(diag[-1, 6 + 11] ** 0.5)]}
         bd.close()
         del bd, diag
+        torch.cuda.empty_cache()
+    if not args.no_shard:
+        # one GPU's share of the headline over 8 GPUs: n/8 particles on the full 128^3 grid
+        # (the sharded design replicates the grid work and all-reduces rho each step)
+        cfg_s = cfg.with_(n=cfg.n // 8)
+        bs, dts, sts, _ = run_gpu(cfg_s, args.steps, args.warmup, grid_fp32=False,
+                                  tuning=tuning, binned=binned)
+        st_s = {k: v[0] / max(v[1], 1) for k, v in sts.items()}
+        grid_bytes = 8 * cfg.nodes[0] * cfg.nodes[1] * cfg.nodes[2]
+        variants["one_gpu_share_of_8"] = {
+            "value": cfg_s.n * args.steps / dts, "ms_per_step": dts / args.steps * 1e3,
+            "particles": cfg_s.n, "stage_ms_per_launch": st_s,
+            "gkd_GBs": ALGO_BYTES["gkd"] * cfg_s.n / (st_s["gkd"] * 1e-3) / 1e9,
+            "deposit_GBs": ALGO_BYTES["deposit"] * cfg_s.n / (st_s["deposit"] * 1e-3) / 1e9,
+            "rho_allreduce_bytes": grid_bytes,
+            "note": "measured on one GPU: the per-GPU work of the particle-sharded design at 8 "
+                    "GPUs (same grid, 1/8 of the particles); the all-reduce of rho is not run"}
+        bs.close()
+        del bs
         torch.cuda.empty_cache()
     if not args.no_direct:
         # the headline workload with E' from the integrated Green's functions of the field

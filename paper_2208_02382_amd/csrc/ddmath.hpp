@@ -3,12 +3,12 @@
 // A value is an unevaluated sum hi + lo of two doubles (about 106 bits).  Error-free
 // transformations: Knuth's TwoSum and the FMA form of the exact product (a*b = p + fma(a,b,-p)).
 // Elementary functions (table-driven argument reduction, then short series):
-//   log  -- a = 2^e m, m in [1, 2); c = 1 + k/32 nearest m; log a = e ln2 + log c
-//           + 2 atanh(t), t = (m - c)/(m + c), |t| <= 1/128, atanh by 9 series terms.
-//   atan -- a > 1 uses pi/2 - atan(1/a); c = k/32 nearest the argument x in [0, 1];
-//           atan x = atan c + atan(t), t = (x - c)/(1 + x c), |t| <= 1/64, 10 series terms.
+//   log  -- a = 2^e m, m in [1, 2); c = 1 + k/256 nearest m; log a = e ln2 + log c
+//           + 2 atanh(t), t = (m - c)/(m + c), |t| <= 1/1024, atanh by 6 series terms.
+//   atan -- a > 1 uses pi/2 - atan(1/a); c = k/256 nearest the argument x in [0, 1];
+//           atan x = atan c + atan(t), t = (x - c)/(1 + x c), |t| <= 1/512, 6 series terms.
 //   sqrt -- Karp-Markstein: one correction of the double reciprocal square root.
-// The tables log(1 + k/32) and atan(k/32) (dd_tables.hpp) are double pairs from 60-digit
+// The tables log(1 + k/256) and atan(k/256) (dd_tables.hpp) are double pairs from 60-digit
 // mpmath; series truncation errors are below 1e-33 relative.
 // No fast-math and no contraction: TwoSum and FastTwoSum are exact only if every + and - is
 // rounded on its own.  hipcc contracts a*b + c into an fma by default in device code, which
@@ -102,26 +102,14 @@ constexpr double kLn2Lo = 2.31904681384629956e-17;
 constexpr double kPi2Hi = 1.57079632679489656e+00;
 constexpr double kPi2Lo = 6.12323399573676604e-17;
 
-// 1/(2k+1) for k = 0..17 as double pairs.
-constexpr double kInvOdd[18][2] = {
+// 1/(2k+1) for k = 0..5 as double pairs.
+constexpr double kInvOdd[6][2] = {
     {1.0, 0.0},
     {0.3333333333333333, 1.850371707708594e-17},
     {0.2, -1.1102230246251566e-17},
     {0.14285714285714285, 7.93016446160826e-18},
     {0.1111111111111111, 6.1679056923619804e-18},
     {0.09090909090909091, -2.523234146875356e-18},
-    {0.07692307692307693, -4.270088556250602e-18},
-    {0.06666666666666667, 9.251858538542971e-19},
-    {0.058823529411764705, 8.163404592832033e-19},
-    {0.05263157894736842, 2.921639538487254e-18},
-    {0.047619047619047616, 2.64338815386942e-18},
-    {0.043478260869565216, 1.206764157201257e-18},
-    {0.04, -8.326672684688674e-19},
-    {0.037037037037037035, 2.05596856412066e-18},
-    {0.034482758620689655, 4.785444071660157e-19},
-    {0.03225806451612903, 8.953411488912552e-19},
-    {0.030303030303030304, -8.410780489584519e-19},
-    {0.02857142857142857, 8.921435019309293e-19},
 };
 
 // natural log of a positive double-double.
@@ -130,13 +118,13 @@ PIC_HD inline ddv dd_log(ddv a) {
   std::frexp(a.hi, &e);  // a.hi = f 2^e, f in [1/2, 1)
   e -= 1;
   const ddv m = {std::ldexp(a.hi, -e), std::ldexp(a.lo, -e)};  // exact; m.hi in [1, 2)
-  const int k = (int)std::rint((m.hi - 1.0) * 32.0);           // 0..32
-  const double c = 1.0 + (double)k * 0.03125;
+  const int k = (int)std::rint((m.hi - 1.0) * 256.0);          // 0..256
+  const double c = 1.0 + (double)k * 0.00390625;
   const ddv t = dd_div(dd_sub(m, dd_make(c)), dd_add(m, dd_make(c)));
   const ddv t2 = dd_mul(t, t);
-  // atanh t = t sum_{j=0}^{8} t^(2j)/(2j+1); the first omitted term is below 1e-37 t
-  ddv p = {kInvOdd[8][0], kInvOdd[8][1]};
-  for (int j = 7; j >= 0; --j) p = dd_add(dd_mul(p, t2), ddv{kInvOdd[j][0], kInvOdd[j][1]});
+  // atanh t = t sum_{j=0}^{5} t^(2j)/(2j+1); the first omitted term is below 6e-38 t
+  ddv p = {kInvOdd[5][0], kInvOdd[5][1]};
+  for (int j = 4; j >= 0; --j) p = dd_add(dd_mul(p, t2), ddv{kInvOdd[j][0], kInvOdd[j][1]});
   const ddv at = dd_mul_d(dd_mul(t, p), 2.0);
   const ddv el2 = dd_add(two_prod((double)e, kLn2Hi), two_prod((double)e, kLn2Lo));
   return dd_add(dd_add(el2, ddv{kLogTab[k][0], kLogTab[k][1]}), at);
@@ -146,13 +134,13 @@ PIC_HD inline ddv dd_log(ddv a) {
 PIC_HD inline ddv dd_atan(ddv a) {
   const bool inv = a.hi > 1.0;
   const ddv x = inv ? dd_div(dd_make(1.0), a) : a;  // in [0, 1]
-  const int k = (int)std::rint(x.hi * 32.0);          // 0..32
-  const double c = (double)k * 0.03125;
+  const int k = (int)std::rint(x.hi * 256.0);         // 0..256
+  const double c = (double)k * 0.00390625;
   const ddv t = dd_div(dd_sub(x, dd_make(c)), dd_add(dd_make(1.0), dd_mul_d(x, c)));
   const ddv t2 = dd_mul(t, t);
-  // atan t = t sum_{j=0}^{9} (-1)^j t^(2j)/(2j+1); the first omitted term is below 1e-36 t
-  ddv p = dd_neg(ddv{kInvOdd[9][0], kInvOdd[9][1]});
-  for (int j = 8; j >= 0; --j) {
+  // atan t = t sum_{j=0}^{5} (-1)^j t^(2j)/(2j+1); the first omitted term is below 3e-34 t
+  ddv p = dd_neg(ddv{kInvOdd[5][0], kInvOdd[5][1]});
+  for (int j = 4; j >= 0; --j) {
     ddv cj = {kInvOdd[j][0], kInvOdd[j][1]};
     if (j & 1) cj = dd_neg(cj);
     p = dd_add(dd_mul(p, t2), cj);

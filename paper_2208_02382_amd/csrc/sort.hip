@@ -301,10 +301,12 @@ __device__ __forceinline__ void scatter_direct_body(const double* __restrict__ A
   __syncthreads();
   for (int k = 0; k < kPer; ++k) {
     int64_t i = base + k * kBlk + threadIdx.x;
-    const uint32_t pos = wave_aggregated_add(lh, key[k], i < n);
-    if (i < n && pos < (uint64_t)n) {  // in bounds for a consistent histogram
-      for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
-      if (idA) idB[pos] = idA[i];
+    if (i < n) {
+      uint32_t pos = atomicAdd(&lh[key[k]], 1u);
+      if (pos < (uint64_t)n) {  // always true for a consistent histogram; keeps writes in bounds
+        for (int r = 0; r < 6; ++r) B[r * n + pos] = A[r * n + i];
+        if (idA) idB[pos] = idA[i];
+      }
     }
   }
 }
