@@ -221,8 +221,10 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
  * labels that travel with the particles: on return d_ids[i] is the label that was at the index
  * the particle now in slot i had on entry (start from 0..n-1 to follow the caller's indices;
  * NULL: no labels, 8 bytes less traffic per particle and step).  Per call this saves the
- * move of the caller's order into tile order on the first step (which then only ranks) and the
- * return to the caller's order at the end (the last step's gather-kick writes X directly); the
+ * return to the caller's order at the end (the last step's gather-kick writes X directly) and,
+ * when X is still in the order a previous binned call on this handle left it in, the move into
+ * tile order on the first step, which then only ranks (the handle keeps that flag; the
+ * pic_init_beam* calls clear it, and an X in any other order is only slower, never wrong); the
  * physics is the same, particle by particle and bit for bit, as pic_track_n_steps (moments,
  * the objective and the deposit do not depend on the order).  X is left as it was if the device
  * flags an error at any step's geometry (non-finite coordinate, zero-extent box). */
