@@ -3,9 +3,10 @@ count and size (pic_beam_desc.tile / chunk / blocks / threads), and the workgrou
 a batch.
 
 Each candidate is timed on the device with the library's own tracking loop
-(pic_track_n_steps: the call's wall time less its once-per-call stages; pic_track_batch
-for a batch: the whole call) over a few steps of a beam of the problem's size,
-re-initialised to the same seeded state before every candidate.  The search is
+(pic_track_n_steps_binned in steady state: after a one-step call has moved the particles into
+tile order, the wall time of a call less its once-per-call stages; pic_track_batch for a batch:
+the whole call) over a few steps of a beam of the problem's size, re-initialised to the same
+seeded state before every candidate.  The search is
 coordinate-wise: tile shape with the default work items, then the work-item size at the best
 tile, then the workgroup count, then the workgroup size.  Tile shapes are cubes and slabs: a
 slab is thin along one axis and wide along the other two, so that particles moving mostly
@@ -15,8 +16,8 @@ of them from outside the tile's own stretch of the previous order.  Only launch 
 library's documented limits are tried (tile count <= 4096, the gather's
 field window within the 156 KB of dynamic LDS a workgroup may use).  Results go into a JSON
 cache keyed by problem class: particle count rounded to a power of two, grid, shape and
-grid precision.  Results do not depend on the tuning beyond the summation order of the float
-atomics.
+grid precision.  Results depend on the tuning only through the rounding of the deposit's
+fixed-point contributions, whose scale each tile takes from its own particle count.
 """
 import json
 import math
@@ -81,18 +82,19 @@ CALL_STAGES = ("prologue", "unpermute")
 
 
 def _time_single(cfg, tuning, grid_fp32, steps, X):
-    """Mean time of one step over `steps` steps: the call's wall time less its once-per-call
-    stages (timed by the library's HIP events).  Stage times are not summed, because the Green
-    spectrum overlaps the binning and deposit."""
+    """Mean time of one steady-state step over `steps` steps: a binned call of one step moves
+    the particles into tile order, then a binned call of `steps` steps (every step only ranks)
+    is timed, less its once-per-call stages (timed by the library's HIP events).  Stage times
+    are not summed, because the Green spectrum overlaps the binning and deposit."""
     b = Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
              cfg.nodes, grid_fp32=grid_fp32, X=X, tuning=tuning)
     try:
         b.init(cfg.sigma_matrix, seed=cfg.seed, halo_frac=cfg.halo_frac)
-        b.track(cfg.lattice, 1)
+        b.track(cfg.lattice, 1, binned=True)
         torch.cuda.synchronize()
         b.profile_start()
         t0 = time.perf_counter()
-        b.track(cfg.lattice, steps)
+        b.track(cfg.lattice, steps, binned=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         stages = b.profile_read()
