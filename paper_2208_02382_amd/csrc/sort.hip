@@ -18,7 +18,11 @@
 //                  phase space crosses HBM once per step fewer;
 //   k_deposit_tiles each workgroup takes a chunk, accumulates the (T + S)^3 window of its tile
 //                  with 64-bit fixed-point LDS atomics, and adds the non-zero window entries to
-//                  the charge grid with one global atomic each.
+//                  the tile's own 64-bit integer window in HBM with one integer atomic each;
+//   k_tile_reduce  forms the charge grid from the tiles' integer windows in a fixed order, so
+//                  the grid depends neither on the particle order nor on that of the atomics;
+//   k_gkd_tiles    the gather, kick and push of a chunk from its tile's E' window in LDS,
+//                  reading through the ranking and writing the new state in sorted order.
 #include "device_common.hpp"
 #include "internal.hpp"
 
