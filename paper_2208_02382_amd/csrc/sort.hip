@@ -150,18 +150,19 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const Geom* __restrict__ 
   build_chunks_body(g, sp, hist, cursor, chunks, nchunks);
 }
 
-// In-place exclusive scan of a[0..count) (count <= kMaxTiles) by one block of kBlk threads;
+// In-place exclusive scan of a[0..count) (count <= kMaxTiles) by one block of NT threads;
 // each thread owns a run of consecutive entries.
+template <int NT>
 __device__ void block_exclusive_scan_lds(uint32_t* a, int count) {
-  __shared__ uint32_t part[kBlk];
-  const int per = (count + kBlk - 1) / kBlk;
+  __shared__ uint32_t part[NT];
+  const int per = (count + NT - 1) / NT;
   const int b = threadIdx.x * per;
   const int e = min(b + per, count);
   uint32_t sum = 0;
   for (int t = b; t < e; ++t) sum += a[t];
   part[threadIdx.x] = sum;
   __syncthreads();
-  for (int off = 1; off < kBlk; off <<= 1) {
+  for (int off = 1; off < NT; off <<= 1) {
     const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
     __syncthreads();
     part[threadIdx.x] += add;
@@ -239,7 +240,7 @@ __device__ __forceinline__ void scatter_staged_body(const double* __restrict__ A
     delta[t] = c ? atomicAdd(&cursor[t], c) : 0u;
   }
   __syncthreads();
-  block_exclusive_scan_lds(cur, ntiles);  // cur[t] = local offset of key t
+  block_exclusive_scan_lds<kBlk>(cur, ntiles);  // cur[t] = local offset of key t
   for (int t = threadIdx.x; t < ntiles; t += kBlk) delta[t] -= cur[t];
   __syncthreads();
   uint32_t slot[kPer];
@@ -376,6 +377,95 @@ __global__ __launch_bounds__(kBlk) void k_scatter(const double* __restrict__ A,
                                                   double* __restrict__ B,
                                                   uint32_t* __restrict__ idB) {
   scatter_body<STAGED>(A, idA, keys, g, n, ntiles, cursor, B, idB, blockIdx.x, gridDim.x);
+}
+
+// The staged scatter over wide blocks, for inputs whose order is unrelated to the keys (the
+// caller's order on a call's first step, the id buckets of the final reordering).  A block of
+// kWBlk threads takes kWItems particles, four times the items of k_scatter<true>, so that every
+// key's run in the output is four times longer (at 2048 tiles about 8 particles, 64 B per row,
+// instead of 2): the runs' writes then fill whole 64-byte pieces of memory instead of a
+// fraction of one.  The ranking is that of the staged form; the rows then move through a
+// kWHalf-slot LDS buffer in two halves of the ranked slots, each item's value read from HBM in
+// the half its slot falls in.
+constexpr int kWBlk = 1024;
+constexpr int kWPer = 16;
+constexpr int kWItems = kWBlk * kWPer;  // 16384
+constexpr int kWHalf = kWItems / 2;     // slots staged per pass
+
+__global__ __launch_bounds__(kWBlk) void k_scatter_wide(const double* __restrict__ A,
+                                                        const uint32_t* __restrict__ idA,
+                                                        const uint32_t* __restrict__ keys,
+                                                        const Geom* __restrict__ g, int64_t n,
+                                                        int ntiles, uint32_t* __restrict__ cursor,
+                                                        double* __restrict__ B,
+                                                        uint32_t* __restrict__ idB) {
+  // cur/delta (ranking, 2 x kMaxTiles words) and the row buffer (kWHalf doubles) share storage
+  __shared__ __align__(16) unsigned char stage[kWHalf * sizeof(double)];
+  __shared__ uint32_t dest[kWItems];
+  static_assert(2 * kMaxTiles * sizeof(uint32_t) <= sizeof(stage), "ranking exceeds storage");
+  uint32_t* cur = reinterpret_cast<uint32_t*>(stage);
+  uint32_t* delta = cur + kMaxTiles;
+  double* rowbuf = reinterpret_cast<double*>(stage);
+  uint32_t* idbuf = reinterpret_cast<uint32_t*>(stage);
+  if (g->status) return;
+  const int64_t base = (int64_t)blockIdx.x * kWItems;
+  const int m = (int)min((int64_t)kWItems, n - base);
+  for (int t = threadIdx.x; t < ntiles; t += kWBlk) cur[t] = 0u;
+  __syncthreads();
+  uint32_t key[kWPer];
+  for (int k = 0; k < kWPer; ++k) {
+    const int l = k * kWBlk + threadIdx.x;
+    key[k] = l < m ? keys[base + l] : 0u;
+  }
+  for (int k = 0; k < kWPer; ++k)
+    if (k * kWBlk + (int)threadIdx.x < m) atomicAdd(&cur[key[k]], 1u);
+  __syncthreads();
+  // reserve each present key's run in the output
+  for (int t = threadIdx.x; t < ntiles; t += kWBlk) {
+    const uint32_t c = cur[t];
+    delta[t] = c ? atomicAdd(&cursor[t], c) : 0u;
+  }
+  __syncthreads();
+  block_exclusive_scan_lds<kWBlk>(cur, ntiles);  // cur[t] = local offset of key t
+  for (int t = threadIdx.x; t < ntiles; t += kWBlk) delta[t] -= cur[t];
+  __syncthreads();
+  uint32_t slot[kWPer];
+  for (int k = 0; k < kWPer; ++k) {
+    const int l = k * kWBlk + threadIdx.x;
+    slot[k] = 0u;
+    if (l < m) {
+      slot[k] = atomicAdd(&cur[key[k]], 1u);
+      dest[slot[k]] = delta[key[k]] + slot[k];
+    }
+  }
+  __syncthreads();  // the ranking's words are dead from here: the row buffer takes them over
+  const int rows = idA ? 7 : 6;  // the ids travel as a seventh row when there are any
+  for (int r = 0; r < rows; ++r) {
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t lo = (uint32_t)(h * kWHalf);
+      for (int k = 0; k < kWPer; ++k) {
+        const int l = k * kWBlk + threadIdx.x;
+        if (l < m && slot[k] - lo < (uint32_t)kWHalf) {
+          if (r < 6)
+            rowbuf[slot[k] - lo] = A[r * n + base + l];
+          else
+            idbuf[slot[k] - lo] = idA[base + l];
+        }
+      }
+      __syncthreads();
+      const int cnt = min(kWHalf, m - (int)lo);
+      for (int q = threadIdx.x; q < cnt; q += kWBlk) {
+        const uint32_t d = dest[lo + q];
+        if (d < (uint64_t)n) {  // always true for a consistent histogram; keeps writes in bounds
+          if (r < 6)
+            B[r * n + d] = rowbuf[q];
+          else
+            idB[d] = idbuf[q];
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 template <typename T>
@@ -1185,6 +1275,10 @@ __global__ __launch_bounds__(kBlk) void k_unpermute_batch(const BeamDev* __restr
 }
 
 int grid_items(int64_t n) { return (int)((n + kItems - 1) / kItems); }
+int grid_wide(int64_t n) { return (int)((n + kWItems - 1) / kWItems); }
+// the wide staged scatter once it still fills every CU with a block (256 CUs); below that the
+// 4096-particle blocks of k_scatter<true> keep the device busy
+bool wide_pays(int64_t n) { return grid_wide(n) >= 256; }
 
 int grid_stride(int64_t n) {
   int64_t b = (n + kBlk - 1) / kBlk;
@@ -1266,7 +1360,10 @@ hipError_t launch_bin(const double* A, const uint32_t* idA, const Geom* g, Const
                       hipStream_t s) {
   hipError_t e = launch_keys_chunks(A, g, c, sp, keys, hist, cursor, chunks, nchunks, s);
   if (e != hipSuccess) return e;
-  if (staged)
+  if (staged && wide_pays(c.n))
+    hipLaunchKernelGGL(k_scatter_wide, dim3(grid_wide(c.n)), dim3(kWBlk), 0, s, A, idA, keys, g,
+                       c.n, sp.ntiles, cursor, B, idB);
+  else if (staged)
     hipLaunchKernelGGL(k_scatter<true>, dim3(grid_items(c.n)), dim3(kBlk), 0, s, A, idA, keys, g,
                        c.n, sp.ntiles, cursor, B, idB);
   else
@@ -1430,8 +1527,12 @@ hipError_t launch_unpermute(const double* A, const uint32_t* idA, int64_t n, dou
                      nchunks);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter<true>, dim3(grid_items(n)), dim3(kBlk), 0, s, A, idA, keys, g, n, nb,
-                     cursor, B, idB);
+  if (wide_pays(n))
+    hipLaunchKernelGGL(k_scatter_wide, dim3(grid_wide(n)), dim3(kWBlk), 0, s, A, idA, keys, g, n,
+                       nb, cursor, B, idB);
+  else
+    hipLaunchKernelGGL(k_scatter<true>, dim3(grid_items(n)), dim3(kBlk), 0, s, A, idA, keys, g, n,
+                       nb, cursor, B, idB);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (((int64_t)1 << shift) <= (int64_t)kUBlk * kUPer)

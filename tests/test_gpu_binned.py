@@ -61,6 +61,13 @@ def test_binned_calls_of_any_length(lib, calls):
     _compare(lib, cfg, [(1.0, 0.5)], calls)
 
 
+def test_binned_calls_at_a_size_that_takes_the_wide_staged_scatter(lib):
+    # above 256 x 16384 particles the first step's move into tile order and the return to the
+    # caller's order use the wide (16384-particle) staged scatter blocks
+    cfg = workloads.MEDIUM.with_(n=4_300_001, nodes=(64, 64, 64), shape=2)
+    _compare(lib, cfg, cfg.lattice, [2, 2])
+
+
 def test_binned_thick_lattice_and_direct_field(lib):
     cfg = workloads.MEDIUM.with_(n=100_001, nodes=(32, 32, 32), shape=2)
     lattice = workloads.THICK_FODO
