@@ -1104,11 +1104,13 @@ __global__ __launch_bounds__(kBlk) void k_unpermute(const double* __restrict__ A
 // with ids [b 2^sh, (b + 1) 2^sh) (the ids are a permutation of 0..n-1), at those same
 // positions of A.  One workgroup of kUBlk threads takes a bucket: each thread keeps the local
 // offsets (id - b 2^sh) of its kUPer items; then, row by row, the values are dropped into an
-// LDS buffer by offset, 8192 at a time, and written back to X contiguously, so every store is
-// coalesced.  Requires 2^sh <= kUBlk * kUPer (= 32768).
+// LDS buffer at their offsets, kUStage at a time, and written back to X contiguously, so every
+// store is coalesced.  Each pass loads the row's items eight at a time (the second pass from
+// L2) instead of holding all 32 in registers, which had spilled.  Requires 2^sh <= kUBlk *
+// kUPer (= 32768).
 constexpr int kUBlk = 1024;
 constexpr int kUPer = 32;
-constexpr int kUStage = 8192;
+constexpr int kUStage = 16384;
 
 __global__ __launch_bounds__(kUBlk) void k_unpermute_lds(const double* __restrict__ A,
                                                          const uint32_t* __restrict__ idA,
@@ -1137,17 +1139,21 @@ __global__ __launch_bounds__(kUBlk) void k_unpermute_lds(const double* __restric
   }
   const int nq = (cnt + kUStage - 1) / kUStage;
   for (int r = 0; r < 6; ++r) {
-    double v[kUPer];
-#pragma unroll
-    for (int k = 0; k < kUPer; ++k) {
-      const int l = threadIdx.x + k * kUBlk;
-      v[k] = l < cnt ? A[r * n + b0 + l] : 0.0;
-    }
     for (int q = 0; q < nq; ++q) {
+      // eight loads in flight per thread, unconditional (clamped into the bucket, cnt >= 1),
+      // then the stores of the items whose offset falls in this pass
+#pragma unroll 1
+      for (int k0 = 0; k0 < kUPer; k0 += 8) {
+        double v[8];
 #pragma unroll
-      for (int k = 0; k < kUPer; ++k) {
-        const uint32_t o = (offp[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-        if (o != 0xffffu && (int)(o / kUStage) == q) stage[o % kUStage] = v[k];
+        for (int j = 0; j < 8; ++j)
+          v[j] = A[r * n + b0 + min((int)threadIdx.x + (k0 + j) * kUBlk, cnt - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = k0 + j;
+          const uint32_t o = (offp[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+          if (o != 0xffffu && (int)(o / kUStage) == q) stage[o % kUStage] = v[j];
+        }
       }
       __syncthreads();
       const int len = min(kUStage, cnt - q * kUStage);
