@@ -107,6 +107,18 @@ __device__ __forceinline__ void ext_merge(Extremes& ex, int q, double v, int64_t
   }
 }
 
+// one slot as a (value, index) pair: min slots (q < 3) keep the smaller value, max slots the
+// larger, the smaller index on a tie (the merge of ext_merge for a slot chosen at run time,
+// without an array indexed by it)
+__device__ __forceinline__ void ext_merge1(bool is_min, double& bv, int64_t& bi, double v,
+                                           int64_t i) {
+  const bool better = is_min ? v < bv : v > bv;
+  if (better || (v == bv && i < bi)) {
+    bv = v;
+    bi = i;
+  }
+}
+
 __device__ __forceinline__ void ext_update(Extremes& ex, const double r[3], int64_t i) {
   for (int a = 0; a < 3; ++a) {
     ext_merge(ex, a, r[a], i);
@@ -133,11 +145,11 @@ __device__ __forceinline__ void ext_block_partial(Extremes& ex, double* __restri
   __syncthreads();
   if (threadIdx.x < 6) {
     const int q = threadIdx.x;
-    Extremes m;
-    ext_init(m);
-    for (int w = 0; w < kBlk / 64; ++w) ext_merge(m, q, sv[w][q], si[w][q]);
-    partial[blockIdx.x * 12 + q] = m.v[q];
-    partial[blockIdx.x * 12 + 6 + q] = (double)m.i[q];
+    double bv = q < 3 ? INFINITY : -INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int w = 0; w < kBlk / 64; ++w) ext_merge1(q < 3, bv, bi, sv[w][q], si[w][q]);
+    partial[blockIdx.x * 12 + q] = bv;
+    partial[blockIdx.x * 12 + 6 + q] = (double)bi;
   }
 }
 
@@ -147,16 +159,16 @@ __device__ __forceinline__ void ext_block_partial(Extremes& ex, double* __restri
 __global__ void k_ext_combine(const double* __restrict__ partial, int nblocks,
                               double* __restrict__ out) {
   const int q = blockIdx.x;
-  Extremes m;
-  ext_init(m);
+  double bv = q < 3 ? INFINITY : -INFINITY;
+  int64_t bi = INT64_MAX;
   for (int b = threadIdx.x; b < nblocks; b += 64)
-    ext_merge(m, q, partial[b * 12 + q], (int64_t)partial[b * 12 + 6 + q]);
+    ext_merge1(q < 3, bv, bi, partial[b * 12 + q], (int64_t)partial[b * 12 + 6 + q]);
   for (int off = 32; off > 0; off >>= 1) {
-    const double v = __shfl_xor(m.v[q], off);
-    const int64_t i = __shfl_xor(m.i[q], off);
-    ext_merge(m, q, v, i);
+    const double v = __shfl_xor(bv, off);
+    const int64_t i = __shfl_xor(bi, off);
+    ext_merge1(q < 3, bv, bi, v, i);
   }
-  if (threadIdx.x == 0) out[q] = (double)m.i[q];
+  if (threadIdx.x == 0) out[q] = (double)bi;
 }
 
 // out[q] = sum over b < nblocks of partial[b sb + q sq] for column q = blockIdx.x: one wave per
@@ -537,6 +549,7 @@ __global__ __launch_bounds__(kBlk) void k_dL(const double* __restrict__ lam,
     for (int a = 0; a < 6; ++a)
       for (int b = 0; b < 6; ++b) s[a * 6 + b] += l[a] * x[b];
   }
+#pragma unroll
   for (int q = 0; q < 36; ++q) {
     double v = s[q];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
