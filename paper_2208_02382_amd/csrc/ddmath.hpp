@@ -150,4 +150,28 @@ PIC_HD inline ddv dd_atan(ddv a) {
   return r;
 }
 
+// arctangent of p/q for double-doubles p >= 0, q > 0, without forming p/q: the ratio or its
+// inverse, whichever is at most about 1, picks the table entry c = k/256 from the leading
+// parts, and atan(num/den) = atan c + atan(t) with t = (num - c den)/(den + c num), the same
+// reduced argument as dd_atan's (x - c)/(1 + x c) for x = num/den, so one division serves both
+// the ratio and the reduction.  The identity holds for any c >= 0, so a table entry chosen from
+// rounded leading parts only widens |t| by a rounding error beyond 1/512.
+PIC_HD inline ddv dd_atan2(ddv p, ddv q) {
+  const bool inv = p.hi > q.hi;
+  const ddv num = inv ? q : p, den = inv ? p : q;
+  const int k = (int)std::rint(num.hi / den.hi * 256.0);  // 0..256
+  const double c = (double)k * 0.00390625;
+  const ddv t = dd_div(dd_sub(num, dd_mul_d(den, c)), dd_add(den, dd_mul_d(num, c)));
+  const ddv t2 = dd_mul(t, t);
+  ddv s = dd_neg(ddv{kInvOdd[5][0], kInvOdd[5][1]});
+  for (int j = 4; j >= 0; --j) {
+    ddv cj = {kInvOdd[j][0], kInvOdd[j][1]};
+    if (j & 1) cj = dd_neg(cj);
+    s = dd_add(dd_mul(s, t2), cj);
+  }
+  ddv r = dd_add(ddv{kAtanTab[k][0], kAtanTab[k][1]}, dd_mul(t, s));
+  if (inv) r = dd_sub(ddv{kPi2Hi, kPi2Lo}, r);
+  return r;
+}
+
 }  // namespace pic

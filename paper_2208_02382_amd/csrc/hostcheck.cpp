@@ -14,6 +14,16 @@ void pic_hostcheck_dd(int fn, int count, const double* in, double* out) {
   }
 }
 
+// double-double atan(p/q): in[4k..4k+3] = (p.hi, p.lo, q.hi, q.lo) -> out[2k], out[2k+1]
+void pic_hostcheck_dd_atan2(int count, const double* in, double* out) {
+  for (int k = 0; k < count; ++k) {
+    pic::ddv r = pic::dd_atan2(pic::ddv{in[4 * k], in[4 * k + 1]},
+                               pic::ddv{in[4 * k + 2], in[4 * k + 3]});
+    out[2 * k] = r.hi;
+    out[2 * k + 1] = r.lo;
+  }
+}
+
 // Gbar(i, j, k) for i = 0..nx, j = 0..ny, k = 0..nz into out[((k (ny+1)) + j)(nx+1) + i],
 // with the corner values and the 8-corner difference of the kernels.
 void pic_hostcheck_igf(int nx, int ny, int nz, double hx, double hy, double hz, double* out) {

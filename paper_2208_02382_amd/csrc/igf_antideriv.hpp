@@ -19,9 +19,9 @@ PIC_HD inline ddv antiderivative(ddv x, ddv y, ddv z) {
   ddv t1 = (x0 || y0) ? zero : dd_mul(xy, dd_log(dd_add(z, r)));
   ddv t2 = (y0 || z0) ? zero : dd_mul(yz, dd_log(dd_add(x, r)));
   ddv t3 = (z0 || x0) ? zero : dd_mul(zx, dd_log(dd_add(y, r)));
-  ddv t4 = x0 ? zero : dd_mul_d(dd_mul(x2, dd_atan(dd_div(yz, dd_mul(x, r)))), 0.5);
-  ddv t5 = y0 ? zero : dd_mul_d(dd_mul(y2, dd_atan(dd_div(zx, dd_mul(y, r)))), 0.5);
-  ddv t6 = z0 ? zero : dd_mul_d(dd_mul(z2, dd_atan(dd_div(xy, dd_mul(z, r)))), 0.5);
+  ddv t4 = x0 ? zero : dd_mul_d(dd_mul(x2, dd_atan2(yz, dd_mul(x, r))), 0.5);
+  ddv t5 = y0 ? zero : dd_mul_d(dd_mul(y2, dd_atan2(zx, dd_mul(y, r))), 0.5);
+  ddv t6 = z0 ? zero : dd_mul_d(dd_mul(z2, dd_atan2(xy, dd_mul(z, r))), 0.5);
   return dd_sub(dd_add(dd_add(t1, t2), t3), dd_add(dd_add(t4, t5), t6));
 }
 
@@ -39,9 +39,9 @@ PIC_HD inline void field_antiderivatives(ddv x, ddv y, ddv z, ddv H[3]) {
   const ddv Lx = (y0 && z0) ? zero : dd_log(dd_add(x, r));
   const ddv Ly = (z0 && x0) ? zero : dd_log(dd_add(y, r));
   const ddv Lz = (x0 && y0) ? zero : dd_log(dd_add(z, r));
-  const ddv Ax = x0 ? zero : dd_atan(dd_div(dd_mul(y, z), dd_mul(x, r)));
-  const ddv Ay = y0 ? zero : dd_atan(dd_div(dd_mul(z, x), dd_mul(y, r)));
-  const ddv Az = z0 ? zero : dd_atan(dd_div(dd_mul(x, y), dd_mul(z, r)));
+  const ddv Ax = x0 ? zero : dd_atan2(dd_mul(y, z), dd_mul(x, r));
+  const ddv Ay = y0 ? zero : dd_atan2(dd_mul(z, x), dd_mul(y, r));
+  const ddv Az = z0 ? zero : dd_atan2(dd_mul(x, y), dd_mul(z, r));
   H[0] = dd_sub(dd_add(y0 ? zero : dd_mul(y, Lz), z0 ? zero : dd_mul(z, Ly)),
                 x0 ? zero : dd_mul(x, Ax));
   H[1] = dd_sub(dd_add(z0 ? zero : dd_mul(z, Lx), x0 ? zero : dd_mul(x, Lz)),
@@ -69,9 +69,9 @@ PIC_HD inline void dh_corner_functions(ddv x, ddv y, ddv z, ddv* out) {
   const ddv Lx = (y0 && z0) ? zero : dd_log(dd_add(x, r));
   const ddv Ly = (z0 && x0) ? zero : dd_log(dd_add(y, r));
   const ddv Lz = (x0 && y0) ? zero : dd_log(dd_add(z, r));
-  const ddv Ax = x0 ? zero : dd_atan(dd_div(dd_mul(y, z), dd_mul(x, r)));
-  const ddv Ay = y0 ? zero : dd_atan(dd_div(dd_mul(z, x), dd_mul(y, r)));
-  const ddv Az = z0 ? zero : dd_atan(dd_div(dd_mul(x, y), dd_mul(z, r)));
+  const ddv Ax = x0 ? zero : dd_atan2(dd_mul(y, z), dd_mul(x, r));
+  const ddv Ay = y0 ? zero : dd_atan2(dd_mul(z, x), dd_mul(y, r));
+  const ddv Az = z0 ? zero : dd_atan2(dd_mul(x, y), dd_mul(z, r));
   // coordinate times a logarithm / arctangent, zero with the coordinate
   auto cl = [&](ddv c, bool c0, ddv L) { return c0 ? zero : dd_mul(c, L); };
   if constexpr (!FIELD) {

@@ -37,6 +37,32 @@ def test_dd_functions(lib, fn, name):
     assert worst < 1e-30
 
 
+def test_dd_atan2(lib):
+    # atan(p/q) without forming p/q (the corner functions' arctangents), over ratios from 0 to
+    # 1e8, at and next to 1 (where the inverse branch takes over), against 50-digit mpmath
+    mp.mp.dps = 50
+    rng = np.random.default_rng(6)
+    m = 300
+    ratio = np.concatenate([rng.uniform(0, 1, 100) * 10.0 ** rng.integers(-8, 8, 100),
+                            1.0 + rng.uniform(-1e-15, 1e-15, 100),
+                            rng.uniform(0.0, 2.0, 98), [0.0, 1.0]])
+    q = rng.uniform(1e-4, 10.0, m)
+    p = ratio * q
+    plo = p * rng.uniform(-1e-17, 1e-17, m)
+    qlo = q * rng.uniform(-1e-17, 1e-17, m)
+    inp = np.ascontiguousarray(np.stack([p, plo, q, qlo], 1).ravel())
+    out = np.zeros(2 * m)
+    lib.pic_hostcheck_dd_atan2(m, inp.ctypes.data_as(ctypes.c_void_p),
+                               out.ctypes.data_as(ctypes.c_void_p))
+    worst = 0.0
+    for i in range(m):
+        ref = mp.atan((mp.mpf(p[i]) + mp.mpf(plo[i])) / (mp.mpf(q[i]) + mp.mpf(qlo[i])))
+        got = mp.mpf(out[2 * i]) + mp.mpf(out[2 * i + 1])
+        err = abs(got - ref) if ref == 0 else abs((got - ref) / ref)
+        worst = max(worst, err)
+    assert worst < 1e-30
+
+
 @pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (1.0, 1.0, 80.0), (3e-4, 3.1e-4, 2.5e-2),
                                (1e-4, 1e-4, 0.78)])
 def test_kernel_igf_equals_oracle(lib, h):
