@@ -3,12 +3,12 @@
 // A value is an unevaluated sum hi + lo of two doubles (about 106 bits).  Error-free
 // transformations: Knuth's TwoSum and the FMA form of the exact product (a*b = p + fma(a,b,-p)).
 // Elementary functions (table-driven argument reduction, then short series):
-//   log  -- a = 2^e m, m in [1, 2); c = 1 + k/256 nearest m; log a = e ln2 + log c
-//           + 2 atanh(t), t = (m - c)/(m + c), |t| <= 1/1024, atanh by 6 series terms.
-//   atan -- a > 1 uses pi/2 - atan(1/a); c = k/256 nearest the argument x in [0, 1];
-//           atan x = atan c + atan(t), t = (x - c)/(1 + x c), |t| <= 1/512, 6 series terms.
+//   log  -- a = 2^e m, m in [1, 2); c = 1 + k/1024 nearest m; log a = e ln2 + log c
+//           + 2 atanh(t), t = (m - c)/(m + c), |t| <= 1/4096, atanh by 5 series terms.
+//   atan -- a > 1 uses pi/2 - atan(1/a); c = k/1024 nearest the argument x in [0, 1];
+//           atan x = atan c + atan(t), t = (x - c)/(1 + x c), |t| <= 1/2048, 5 series terms.
 //   sqrt -- Karp-Markstein: one correction of the double reciprocal square root.
-// The tables log(1 + k/256) and atan(k/256) (dd_tables.hpp) are double pairs from 60-digit
+// The tables log(1 + k/1024) and atan(k/1024) (dd_tables.hpp) are double pairs from 60-digit
 // mpmath; series truncation errors are below 1e-33 relative.
 // No fast-math and no contraction: TwoSum and FastTwoSum are exact only if every + and - is
 // rounded on its own.  hipcc contracts a*b + c into an fma by default in device code, which
@@ -102,14 +102,13 @@ constexpr double kLn2Lo = 2.31904681384629956e-17;
 constexpr double kPi2Hi = 1.57079632679489656e+00;
 constexpr double kPi2Lo = 6.12323399573676604e-17;
 
-// 1/(2k+1) for k = 0..5 as double pairs.
-constexpr double kInvOdd[6][2] = {
+// 1/(2k+1) for k = 0..4 as double pairs.
+constexpr double kInvOdd[5][2] = {
     {1.0, 0.0},
     {0.3333333333333333, 1.850371707708594e-17},
     {0.2, -1.1102230246251566e-17},
     {0.14285714285714285, 7.93016446160826e-18},
     {0.1111111111111111, 6.1679056923619804e-18},
-    {0.09090909090909091, -2.523234146875356e-18},
 };
 
 // natural log of a positive double-double.
@@ -118,13 +117,13 @@ PIC_HD inline ddv dd_log(ddv a) {
   std::frexp(a.hi, &e);  // a.hi = f 2^e, f in [1/2, 1)
   e -= 1;
   const ddv m = {std::ldexp(a.hi, -e), std::ldexp(a.lo, -e)};  // exact; m.hi in [1, 2)
-  const int k = (int)std::rint((m.hi - 1.0) * 256.0);          // 0..256
-  const double c = 1.0 + (double)k * 0.00390625;
+  const int k = (int)std::rint((m.hi - 1.0) * 1024.0);         // 0..1024
+  const double c = 1.0 + (double)k * 0.0009765625;
   const ddv t = dd_div(dd_sub(m, dd_make(c)), dd_add(m, dd_make(c)));
   const ddv t2 = dd_mul(t, t);
-  // atanh t = t sum_{j=0}^{5} t^(2j)/(2j+1); the first omitted term is below 6e-38 t
-  ddv p = {kInvOdd[5][0], kInvOdd[5][1]};
-  for (int j = 4; j >= 0; --j) p = dd_add(dd_mul(p, t2), ddv{kInvOdd[j][0], kInvOdd[j][1]});
+  // atanh t = t sum_{j=0}^{4} t^(2j)/(2j+1); the first omitted term is below 8e-38 t
+  ddv p = {kInvOdd[4][0], kInvOdd[4][1]};
+  for (int j = 3; j >= 0; --j) p = dd_add(dd_mul(p, t2), ddv{kInvOdd[j][0], kInvOdd[j][1]});
   const ddv at = dd_mul_d(dd_mul(t, p), 2.0);
   const ddv el2 = dd_add(two_prod((double)e, kLn2Hi), two_prod((double)e, kLn2Lo));
   return dd_add(dd_add(el2, ddv{kLogTab[k][0], kLogTab[k][1]}), at);
@@ -134,13 +133,13 @@ PIC_HD inline ddv dd_log(ddv a) {
 PIC_HD inline ddv dd_atan(ddv a) {
   const bool inv = a.hi > 1.0;
   const ddv x = inv ? dd_div(dd_make(1.0), a) : a;  // in [0, 1]
-  const int k = (int)std::rint(x.hi * 256.0);         // 0..256
-  const double c = (double)k * 0.00390625;
+  const int k = (int)std::rint(x.hi * 1024.0);        // 0..1024
+  const double c = (double)k * 0.0009765625;
   const ddv t = dd_div(dd_sub(x, dd_make(c)), dd_add(dd_make(1.0), dd_mul_d(x, c)));
   const ddv t2 = dd_mul(t, t);
-  // atan t = t sum_{j=0}^{5} (-1)^j t^(2j)/(2j+1); the first omitted term is below 3e-34 t
-  ddv p = dd_neg(ddv{kInvOdd[5][0], kInvOdd[5][1]});
-  for (int j = 4; j >= 0; --j) {
+  // atan t = t sum_{j=0}^{4} (-1)^j t^(2j)/(2j+1); the first omitted term is below 8e-35 t
+  ddv p = ddv{kInvOdd[4][0], kInvOdd[4][1]};
+  for (int j = 3; j >= 0; --j) {
     ddv cj = {kInvOdd[j][0], kInvOdd[j][1]};
     if (j & 1) cj = dd_neg(cj);
     p = dd_add(dd_mul(p, t2), cj);
@@ -151,20 +150,20 @@ PIC_HD inline ddv dd_atan(ddv a) {
 }
 
 // arctangent of p/q for double-doubles p >= 0, q > 0, without forming p/q: the ratio or its
-// inverse, whichever is at most about 1, picks the table entry c = k/256 from the leading
+// inverse, whichever is at most about 1, picks the table entry c = k/1024 from the leading
 // parts, and atan(num/den) = atan c + atan(t) with t = (num - c den)/(den + c num), the same
 // reduced argument as dd_atan's (x - c)/(1 + x c) for x = num/den, so one division serves both
 // the ratio and the reduction.  The identity holds for any c >= 0, so a table entry chosen from
-// rounded leading parts only widens |t| by a rounding error beyond 1/512.
+// rounded leading parts only widens |t| by a rounding error beyond 1/2048.
 PIC_HD inline ddv dd_atan2(ddv p, ddv q) {
   const bool inv = p.hi > q.hi;
   const ddv num = inv ? q : p, den = inv ? p : q;
-  const int k = (int)std::rint(num.hi / den.hi * 256.0);  // 0..256
-  const double c = (double)k * 0.00390625;
+  const int k = (int)std::rint(num.hi / den.hi * 1024.0);  // 0..1024
+  const double c = (double)k * 0.0009765625;
   const ddv t = dd_div(dd_sub(num, dd_mul_d(den, c)), dd_add(den, dd_mul_d(num, c)));
   const ddv t2 = dd_mul(t, t);
-  ddv s = dd_neg(ddv{kInvOdd[5][0], kInvOdd[5][1]});
-  for (int j = 4; j >= 0; --j) {
+  ddv s = ddv{kInvOdd[4][0], kInvOdd[4][1]};
+  for (int j = 3; j >= 0; --j) {
     ddv cj = {kInvOdd[j][0], kInvOdd[j][1]};
     if (j & 1) cj = dd_neg(cj);
     s = dd_add(dd_mul(s, t2), cj);
