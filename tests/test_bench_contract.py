@@ -1,5 +1,5 @@
 """bench.py's contract on the CPU: the multi-GPU request exits with a message before any device
-call, the roofline counts the survey's algorithmic bytes (96 B per particle for the fused
+call, the roofline counts the method's algorithmic bytes (96 B per particle for the fused
 gather-kick-drift, 24 B for the deposit; the sort index reported apart), and the committed
 counter summaries parse against the kernels' source text."""
 import os
