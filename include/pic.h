@@ -24,8 +24,10 @@
  *   every CIC and TSC stencil stays on nodes 0..n_a-1 and the extreme particles sit a quarter
  *   cell from any node or cell boundary.  The rest-frame cell is (hx, hy, gamma*hz).
  * Memory: the library never allocates device memory.  The caller owns X, every grid and the
- *   workspace (size from pic_workspace_bytes), all device pointers, 256-byte aligned.  The
- *   handle (host memory) is owned by the library until pic_beam_destroy.
+ *   workspace (size from pic_workspace_bytes).  Workspaces are 256-byte aligned; X, grids and
+ *   the other arrays are aligned to their element (8 bytes for double, 4 for float and the
+ *   uint32 labels); a misaligned pointer is PIC_EINVAL.  The handle (host memory) is owned by
+ *   the library until pic_beam_destroy.
  * Streams: every call takes a hipStream_t as `void* stream` (NULL = the null stream) and only
  *   enqueues work on it, unless stated "synchronises".
  * Errors: calls return pic_status.  Argument errors are reported synchronously and leave the

@@ -1097,8 +1097,16 @@ pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const 
   return PIC_OK;
 }
 
+namespace {
+// a grid or particle-field array must be aligned to its element (pic_real)
+bool grid_misaligned(const pic_beam b, const void* p) {
+  return p && ((uintptr_t)p & (b->d.grid_fp32 ? 3u : 7u));
+}
+}  // namespace
+
 pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
   if (!b || !d_rho) return fail(PIC_EINVAL, "NULL argument");
+  if (grid_misaligned(b, d_rho)) return fail(PIC_EINVAL, "rho must be aligned to its element");
   MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   const int64_t ng = (int64_t)b->d.nx * b->d.ny * b->d.nz;
@@ -1127,6 +1135,8 @@ pic_status pic_deposit(pic_beam b, void* d_rho, void* stream) {
 
 pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d_E, void* stream) {
   if (!b || !d_rho || !d_E) return fail(PIC_EINVAL, "NULL argument");
+  if (grid_misaligned(b, d_rho) || grid_misaligned(b, d_phi) || grid_misaligned(b, d_E))
+    return fail(PIC_EINVAL, "rho, phi and E must be aligned to their element");
   MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   void* phi = d_phi ? d_phi : b->phi;
@@ -1153,6 +1163,8 @@ pic_status pic_poisson_solve(pic_beam b, const void* d_rho, void* d_phi, void* d
 
 pic_status pic_gather(pic_beam b, const void* d_E, void* d_Ep, void* stream) {
   if (!b || !d_E || !d_Ep) return fail(PIC_EINVAL, "NULL argument");
+  if (grid_misaligned(b, d_E) || grid_misaligned(b, d_Ep))
+    return fail(PIC_EINVAL, "E and Ep must be aligned to their element");
   MarkDone md{b->done, S(stream)};
   hipStream_t s = S(stream);
   if (b->d.grid_fp32)
@@ -1169,6 +1181,8 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
   if (kind != PIC_PUSH_DRIFT && kind != PIC_PUSH_THINQUAD && kind != PIC_PUSH_KICK)
     return fail(PIC_EINVAL, "unknown push kind");
   if (kind == PIC_PUSH_KICK && !d_Ep) return fail(PIC_EINVAL, "kick needs the particle field");
+  if (kind == PIC_PUSH_KICK && grid_misaligned(b, d_Ep))
+    return fail(PIC_EINVAL, "Ep must be aligned to its element");
   if (!std::isfinite(value)) return fail(PIC_EINVAL, "non-finite push parameter");
   hipStream_t s = S(stream);
   if (b->d.grid_fp32)

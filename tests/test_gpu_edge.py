@@ -69,3 +69,29 @@ def test_zero_extent_along_one_axis_is_an_error(lib):
     b.init_from_normals(sig, torch.from_numpy(xi).cuda())
     b.deposit()
     assert b.check() == lib.PIC_EDOMAIN
+
+
+@pytest.mark.parametrize("grid_fp32", [False, True])
+def test_misaligned_grid_pointers_are_rejected(lib, grid_fp32):
+    # a grid or particle-field pointer off its element's alignment is an argument error,
+    # reported before anything is enqueued
+    cfg = workloads.SMALL
+    b = lib.Beam(1000, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, 1,
+                 (8, 8, 8), grid_fp32=grid_fp32)
+    b.init(cfg.sigma_matrix, seed=1)
+    es = 4 if grid_fp32 else 8
+    raw = torch.zeros(3 * 8 ** 3 * es + 64, dtype=torch.uint8, device="cuda")
+    off = raw.data_ptr() + (es // 2)      # inside the buffer, off the element boundary
+    good = b.new_E()
+    rho = b.new_rho()
+    assert lib._lib.pic_deposit(b._h, lib.ctypes.c_void_p(off), lib._stream()) == lib.PIC_EINVAL
+    assert lib._lib.pic_poisson_solve(b._h, lib.ctypes.c_void_p(off), None,
+                                      lib._ptr(good), lib._stream()) == lib.PIC_EINVAL
+    assert lib._lib.pic_gather(b._h, lib._ptr(good), lib.ctypes.c_void_p(off),
+                               lib._stream()) == lib.PIC_EINVAL
+    assert lib._lib.pic_push(b._h, lib.PUSH_KICK, 0.1, lib.ctypes.c_void_p(off),
+                             lib._stream()) == lib.PIC_EINVAL
+    # the aligned calls still work, and nothing was flagged
+    b.deposit(rho)
+    assert b.check() == lib.PIC_OK
+    b.close()
