@@ -1087,6 +1087,7 @@ pic_status pic_sigma_from_params(const double p[9], double sigma[36]) {
 pic_status pic_init_beam_from_normals(pic_beam b, const double sigma[36], const double* d_xi,
                                       void* stream) {
   if (!b || !sigma || !d_xi) return fail(PIC_EINVAL, "NULL argument");
+  if ((uintptr_t)d_xi & 7) return fail(PIC_EINVAL, "xi must be 8-byte aligned");
   MarkDone md{b->done, S(stream)};
   Chol L;
   if (!cholesky6(sigma, L)) return fail(PIC_EINVAL, "sigma is not symmetric positive definite");
@@ -1304,6 +1305,8 @@ pic_status pic_track_adjoint(pic_beam b, const pic_element* lattice, int n_el, i
   if (!b->d.space_charge) return fail(PIC_EINVAL, "the reverse sweep needs space_charge = 1");
   if (d_xi && !dJ_dL) return fail(PIC_EINVAL, "d_xi given without dJ_dL");
   if ((uintptr_t)d_adj_work & 255) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
+  if (((uintptr_t)d_lam & 7) || ((uintptr_t)d_xi & 7))
+    return fail(PIC_EINVAL, "lam and xi must be 8-byte aligned");
   std::vector<AdjSlice> sl;
   const pic_status est = expand_adjoint(lattice, n_el, sl);
   if (est != PIC_OK) return est;
