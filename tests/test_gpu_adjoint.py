@@ -12,8 +12,8 @@ from oracle import pic as opic
 pytestmark = pytest.mark.gpu
 
 W4 = np.array([0.7, -0.4, 1.3, 0.9])
-# gradients carry the FP64 bar; measured on MI355X: 4.5e-14 .. 6.2e-14 at most over runs (lam rows of z and delta),
-# 2.3e-16 for dJ/dk and dJ/dL, 3.2e-16 for dJ/dSigma0 through autograd
+# gradients carry the FP64 bar; measured on MI355X: 4.5e-14 .. 6.2e-14 at most over runs (lam
+# rows of z and delta), 2.3e-16 for dJ/dk and dJ/dL, 3.2e-16 for dJ/dSigma0 through autograd
 GRAD_TOL = 1e-12
 SIGMA_TOL = 1e-12
 LATTICE = ((1.0, 0.5), (-1.0, 0.5), (0.8, 0.45))
