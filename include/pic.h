@@ -213,7 +213,10 @@ pic_status pic_push(pic_beam b, int kind, double value, const void* d_Ep, void* 
  * calls from the same state give the same bits although the order of particles within a tile
  * and of the atomics varies; the same holds for pic_track_batch, whose beams equal their
  * pic_track_n_steps results bit for bit.  (The slice-step diagnostics' moment sums are
- * reproducible to rounding only.) */
+ * reproducible to rounding only.)  Inside a call, a slice's second half map and the next
+ * slice's first are applied as their product (the same linear map, rounded in another order);
+ * the call's last step applies the second half map alone, so a run split into several calls
+ * equals the same run in one call to rounding, not bit for bit. */
 pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, int n_steps,
                              void* stream);
 
@@ -227,8 +230,8 @@ pic_status pic_track_n_steps(pic_beam b, const pic_element* lattice, int n_el, i
  * when X is still in the order a previous binned call on this handle left it in, the move into
  * tile order on the first step, which then only ranks (the handle keeps that flag; the
  * pic_init_beam* calls clear it, and an X in any other order is only slower, never wrong); the
- * physics is the same, particle by particle and bit for bit, as pic_track_n_steps (moments,
- * the objective and the deposit do not depend on the order).  X is left as it was if the device
+ * physics is the same, particle by particle and bit for bit, as pic_track_n_steps calls of
+ * the same step counts (moments, the objective and the deposit do not depend on the order).  X is left as it was if the device
  * flags an error at any step's geometry (non-finite coordinate, zero-extent box). */
 pic_status pic_track_n_steps_binned(pic_beam b, const pic_element* lattice, int n_el,
                                     int n_steps, uint32_t* d_ids, void* stream);

@@ -65,6 +65,62 @@ __device__ __forceinline__ void apply_half(const HalfMap& h, double v[6], double
   }
 }
 
+// The 2x2 matrix of a half map on one transverse plane (0: x, px; 1: y, py), row-major, and
+// (return value) its longitudinal coefficient c in z += c delta / gamma^2.  A thin slice's half
+// map kicks first and drifts after: px -= k x, then x += l px gives ((1 - l k, l), (-k, 1)); the
+// y plane has the opposite sign of k.
+__device__ __forceinline__ double half_plane_matrix(const HalfMap& h, int plane, double m[4]) {
+  if (h.type == kHalfMatrix) {
+    const double* src = plane ? h.my : h.mx;
+    for (int q = 0; q < 4; ++q) m[q] = src[q];
+    return h.mz;
+  }
+  const double k = h.type == kHalfThinDrift ? (plane ? -h.k : h.k) : 0.0;
+  m[0] = 1.0 - h.ell * k;
+  m[1] = h.ell;
+  m[2] = -k;
+  m[3] = 1.0;
+  return h.ell;
+}
+
+// The linear map "a, then b" (b_used false: a alone) as one matrix-type half map: the product of
+// the two matrices per plane and the sum of the longitudinal coefficients.
+__device__ __forceinline__ HalfMap half_product(const HalfMap& a, const HalfMap& b, bool b_used) {
+  HalfMap r;
+  r.type = kHalfMatrix;
+  r.pad = 0;
+  r.k = 0.0;
+  r.ell = 0.0;
+  double ma[4], mb[4];
+  r.mz = half_plane_matrix(a, 0, ma);
+  double* dst[2] = {r.mx, r.my};
+  for (int plane = 0; plane < 2; ++plane) {
+    half_plane_matrix(a, plane, ma);
+    double* m = dst[plane];
+    if (!b_used) {
+      for (int q = 0; q < 4; ++q) m[q] = ma[q];
+      continue;
+    }
+    half_plane_matrix(b, plane, mb);
+    m[0] = mb[0] * ma[0] + mb[1] * ma[2];
+    m[1] = mb[0] * ma[1] + mb[1] * ma[3];
+    m[2] = mb[2] * ma[0] + mb[3] * ma[2];
+    m[3] = mb[2] * ma[1] + mb[3] * ma[3];
+  }
+  if (b_used) r.mz += half_plane_matrix(b, 0, mb);
+  return r;
+}
+
+// apply_half for a matrix-type map, without the branch on the type
+__device__ __forceinline__ void apply_matrix(const HalfMap& h, double v[6], double inv_g2) {
+  const double x = v[0], px = v[1], y = v[2], py = v[3];
+  v[0] = h.mx[0] * x + h.mx[1] * px;
+  v[1] = h.mx[2] * x + h.mx[3] * px;
+  v[2] = h.my[0] * y + h.my[1] * py;
+  v[3] = h.my[2] * y + h.my[3] * py;
+  v[4] = v[4] + h.mz * v[5] * inv_g2;
+}
+
 // Transpose of apply_half on an adjoint vector lm (rows as v): the transposed matrices per
 // plane and the transposed longitudinal drift; for a thin slice's first half the transposed
 // drift, then the transposed thin quad.

@@ -260,13 +260,15 @@ __global__ __launch_bounds__(kBlock) void k_push(double* __restrict__ X, int kin
 
 // Fused second half of step j and first half of step j+1: gather E' at the current positions,
 // kick over L, the slice's second half map; if has_next, the next slice's first half map, and
-// accumulate the box of the new positions (the next step's grid).
+// accumulate the box of the new positions (the next step's grid).  The two half maps act as
+// their product (half_product), as in the tiled gather-kick, so both paths compute the same bits.
 template <int S, typename T>
 __global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Geom* __restrict__ g,
                                                 const T* __restrict__ E, double L, HalfMap second,
                                                 int has_next, HalfMap first_next, Consts c,
                                                 Box* box) {
   if (g->status) return;
+  const HalfMap maps = half_product(second, first_next, has_next != 0);
   double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int64_t n = c.n;
@@ -279,9 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_gkd(double* __restrict__ X, const Ge
     T e[3];
     gather_one<S, T>(v[0], v[2], v[4], o, ih, E, c, e);
     sc_kick(v, (double)e[0], (double)e[1], (double)e[2], L, c);
-    apply_half(second, v, c.inv_gamma2);
+    apply_matrix(maps, v, c.inv_gamma2);
     if (has_next) {
-      apply_half(first_next, v, c.inv_gamma2);
       double p[3] = {v[0], v[2], v[4]};
       for (int a = 0; a < 3; ++a) {
         bad |= !isfinite(p[a]);

@@ -741,8 +741,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __r
 // Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
 // workgroup: the (T + S)^3 window of E' around the chunk's tile is staged in LDS (coalesced
 // rows), the particles gather from LDS, get the space-charge kick over L and the slice's second
-// half map, then (has_next) the next slice's first half map, and the box of the new positions
-// is accumulated.  PERM false: B is in slot order and updated in place.  PERM true: slot i
+// half map, then (has_next) the next slice's first half map (without DIAG the two as one
+// product), and the box of the new positions is accumulated.  PERM false: B is in slot order and updated in place.  PERM true: slot i
 // reads particle perm[i] of src (and its id) and writes the new state to slot i of B, so B
 // leaves in sorted order.  The gather reads LDS only (a per-lane choice between LDS and global memory
 // compiles to flat loads, which go through the vector memory pipeline); a stencil outside the
@@ -783,6 +783,12 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
     for (int r = 0; r < 6; ++r) sh[r] = diag_shift[r];
     for (int q = 0; q < kMomentSlots; ++q) acc[q] = 0.0;
   }
+  // Without the moment sums, the slice's second half map and the next slice's first act back
+  // to back on the kicked state: they are applied as their product (one matrix per plane, the
+  // longitudinal coefficients summed), the same linear map in half the arithmetic and with few
+  // enough uniform values to stay in scalar registers.
+  HalfMap maps;
+  if constexpr (!DIAG) maps = half_product(second, first_next, has_next != 0);
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
@@ -794,6 +800,11 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   const int64_t plane = (int64_t)c.nx * c.ny * c.nz;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false, bin_fault = false;
+  // the thread's first window entry and the block size, both split into (x, y, z) offsets
+  const int w0x = (int)threadIdx.x % Wx, w0y = ((int)threadIdx.x / Wx) % Wy,
+            w0z = (int)threadIdx.x / (Wx * Wy);
+  const int stx = (int)blockDim.x % Wx, sty = ((int)blockDim.x / Wx) % Wy,
+            stz = (int)blockDim.x / (Wx * Wy);
   const uint32_t nck = *nchunks;
   for (uint32_t ci = blk; ci < nck; ci += nblk) {
     const int4 ch = chunks[ci];
@@ -805,14 +816,22 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       s_up = (uint32_t)ch.y;
       s_down = (uint32_t)ch.z;
     }
+    // window entry w = (wz_ Wy + wy_) Wx + wx_, stepped by the block size with carries
+    int wx_ = w0x, wy_ = w0y, wz_ = w0z;
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
-      int wx_ = w % Wx, wy_ = (w / Wx) % Wy, wz_ = w / (Wx * Wy);
       int gx = ox + wx_, gy = oy + wy_, gz = oz + wz_;
       bool in = gx < c.nx && gy < c.ny && gz < c.nz;
       int64_t gi = ((int64_t)gz * c.ny + gy) * c.nx + gx;
       win[w] = in ? E[gi] : T(0);
       win[nw + w] = in ? E[plane + gi] : T(0);
       win[2 * nw + w] = in ? E[2 * plane + gi] : T(0);
+      wx_ += stx;
+      const int cx = wx_ >= Wx;
+      wx_ -= cx ? Wx : 0;
+      wy_ += sty + cx;
+      const int cy = wy_ >= Wy;
+      wy_ -= cy ? Wy : 0;
+      wz_ += stz + cy;
     }
     __syncthreads();
     // every thread of the block runs the same number of rounds (the wavefront-wide slot
@@ -862,8 +881,8 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
         v[1] = v[1] + c.C * (double)ex * L;
         v[3] = v[3] + c.C * (double)ey * L;
         v[5] = v[5] + c.gamma * c.C * (double)ez * L;
-        apply_half(second, v, c.inv_gamma2);
         if constexpr (DIAG) {
+          apply_half(second, v, c.inv_gamma2);
           double d[6];
           for (int r = 0; r < 6; ++r) {
             d[r] = v[r] - sh[r];
@@ -872,9 +891,11 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
           int q = 6;
           for (int a = 0; a < 6; ++a)
             for (int b = a; b < 6; ++b) acc[q++] += d[a] * d[b];
+          if (has_next) apply_half(first_next, v, c.inv_gamma2);
+        } else {
+          apply_matrix(maps, v, c.inv_gamma2);
         }
         if (has_next) {
-          apply_half(first_next, v, c.inv_gamma2);
           const double p[3] = {v[0], v[2], v[4]};
           for (int a = 0; a < 3; ++a) {
             bad |= !isfinite(p[a]);
@@ -885,7 +906,16 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
       }
       int64_t slot = i;
       if (reorder) {
-        const bool stay = act && tile_key<S>(v[0], v[2], v[4], o, ih, c, sp) == (uint32_t)t;
+        // the particle keeps tile t when its new stencil base lies in t's node range: the same
+        // test as tile_key(...) == t, without the divisions
+        bool stay = false;
+        if (act) {
+          const int nx_ = base_node<S>((v[0] - o[0]) * ih[0], c.nx) - ox;
+          const int ny_ = base_node<S>((v[2] - o[1]) * ih[1], c.ny) - oy;
+          const int nz_ = base_node<S>((v[4] - o[2]) * ih[2], c.nz) - oz;
+          stay = (unsigned)nx_ < (unsigned)sp.T[0] && (unsigned)ny_ < (unsigned)sp.T[1] &&
+                 (unsigned)nz_ < (unsigned)sp.T[2];
+        }
         const uint64_t m_s = __ballot(stay), m_m = __ballot(act && !stay);
         const int lane = (int)__lane_id();
         const uint64_t below = (1ull << lane) - 1ull;

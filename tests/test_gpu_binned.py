@@ -1,7 +1,8 @@
 """pic_track_n_steps_binned (X left in the library's tile order, labels permuted with the
 particles) against pic_track_n_steps from the same beam: particle by particle and bit for bit,
 over several calls, for the binned path and for the gather's global-load fallback, and the
-error contract (X untouched after a device error)."""
+error contract (X untouched after a device error).  A run split into calls equals the same run
+in one call to rounding."""
 import numpy as np
 import pytest
 import torch
@@ -25,10 +26,13 @@ def _beam(lib, cfg, tuning=None, grid_fp32=False, direct_field=False):
 
 
 def _compare(lib, cfg, lattice, calls, tuning=None, grid_fp32=False, direct_field=False):
-    """Track sum(calls) steps in one caller-order call, and in binned calls of the given step
-    counts with labels 0..n-1; the binned slot i must hold the caller-order particle ids[i]."""
+    """Track the beam in caller-order calls and in binned calls of the given step counts, the
+    latter with labels 0..n-1; the binned slot i must hold the caller-order particle ids[i].
+    Both sides end their calls after the same steps: inside a call a slice's second half map
+    and the next slice's first act as one product, at a call's end they are applied apart."""
     ref = _beam(lib, cfg, tuning, grid_fp32, direct_field)
-    ref.track(lattice, sum(calls))
+    for k in calls:
+        ref.track(lattice, k)
     Xc = ref.X.clone()
     assert ref.check() == lib.PIC_OK
     ref.close()
@@ -50,6 +54,28 @@ def test_binned_calls_equal_caller_order_tracking(lib, shape, grid_fp32):
     cfg = workloads.MEDIUM.with_(n=200_003, nodes=(32, 36, 48), shape=shape)
     # even step counts keep the two-element lattice in phase across calls
     _compare(lib, cfg, cfg.lattice, [2, 4, 2], grid_fp32=grid_fp32)
+
+
+@pytest.mark.parametrize("binned", [False, True])
+def test_a_run_split_into_calls_equals_one_call_to_rounding(lib, binned):
+    # a call's last step applies the slice's second half map alone and the next call starts
+    # with the next slice's first, where one call applies their product: the same linear maps,
+    # rounded in another order
+    cfg = workloads.MEDIUM.with_(n=200_003, nodes=(32, 36, 48), shape=2)
+    one = _beam(lib, cfg)
+    one.track(cfg.lattice, 8)
+    split = _beam(lib, cfg)
+    ids = torch.arange(cfg.n, dtype=torch.int32, device="cuda")
+    for k in [2, 4, 2]:
+        split.track(cfg.lattice, k, binned=binned, ids=ids if binned else None)
+    assert one.check() == lib.PIC_OK and split.check() == lib.PIC_OK
+    X1 = one.X.cpu().numpy()[:, ids.long().cpu().numpy()] if binned else one.X.cpu().numpy()
+    Xs = split.X.cpu().numpy()
+    rms = X1.std(axis=1)
+    err = (np.abs(Xs - X1).max(axis=1) / rms).max()
+    assert err < 1e-13, err
+    one.close()
+    split.close()
 
 
 @pytest.mark.parametrize("calls", [[1], [1, 1], [3, 1, 2]])
