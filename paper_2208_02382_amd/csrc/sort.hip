@@ -485,7 +485,7 @@ __device__ __forceinline__ void add_global(T* p, T v) {
 // integer atomic each, exact in any order); the tile's exponent goes to tscale[t], and
 // k_tile_reduce forms the grid, which then depends neither on the order of the particles nor
 // on that of the atomics.
-template <int S, typename T>
+template <int S, typename T, bool PERM>
 __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
                                                         const uint32_t* __restrict__ perm,
                                                         const Geom* __restrict__ g, Consts c,
@@ -522,37 +522,34 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
     if (threadIdx.x == 0) tscale[t] = k;  // every chunk of the tile writes the same k
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) win[w] = 0ull;
     __syncthreads();
-    // Software-pipelined over the lane's slots i, i + stride, ...: the index of the slot two
-    // ahead and the position of the slot one ahead are loaded before the current particle's
-    // atomics are issued, so that the loads' latency overlaps the LDS work.  Slot i holds
-    // particle perm[i] of B (B itself in slot order without a permutation); an index past n,
-    // impossible for a consistent ranking, is flagged and its particle skipped.
+    // Software-pipelined over the lane's slots i, i + stride, ... in pairs (a, b): before the
+    // atomics of one slot the positions of the lane's next slot and the index of the slot after
+    // that are loaded.  No branch surrounds these loads (slot indices are clamped into the chunk
+    // and particle indices into [0, n), and a result is used only where it is valid), so the
+    // waits for them fall at their first use and they stay in flight during the LDS atomics; a
+    // load inside a branch makes the join wait for every load the wave has issued.  Slot i
+    // holds particle perm[i] of B (B itself in slot order without a permutation); an index past
+    // n, impossible for a consistent ranking, is flagged and its particle skipped.
     const int64_t stride = (int)blockDim.x;
-    auto index_of = [&](int64_t j) -> int64_t { return perm ? (int64_t)perm[j] : j; };
-    int64_t i = ch.y + threadIdx.x;
-    int64_t r_cur = i < ch.z ? index_of(i) : 0;
-    int64_t r_next = i + stride < ch.z ? index_of(i + stride) : 0;
-    double p_cur[3] = {0.0, 0.0, 0.0};
-    if (i < ch.z && r_cur < n) {
-      p_cur[0] = B[r_cur];
-      p_cur[1] = B[2 * n + r_cur];
-      p_cur[2] = B[4 * n + r_cur];
-    }
-    for (; i < ch.z; i += stride) {
-      const bool has_next = i + stride < ch.z;
-      double p_next[3] = {0.0, 0.0, 0.0};
-      if (has_next && r_next < n) {
-        p_next[0] = B[r_next];
-        p_next[1] = B[2 * n + r_next];
-        p_next[2] = B[4 * n + r_next];
-      }
-      const int64_t r_after = i + 2 * stride < ch.z ? index_of(i + 2 * stride) : 0;
-      const bool valid = r_cur < n;
+    const int64_t last = ch.z - 1;  // a work item holds at least one slot
+    auto index_of = [&](int64_t j) -> int64_t {
+      j = j < last ? j : last;
+      if constexpr (PERM) return (int64_t)perm[j];
+      return j;
+    };
+    auto load_pos = [&](int64_t r, double* p) {
+      const int64_t q = r < n ? r : 0;
+      p[0] = B[q];
+      p[1] = B[2 * n + q];
+      p[2] = B[4 * n + q];
+    };
+    auto deposit_one = [&](const double* p, int64_t r) {
+      const bool valid = r < n;
       if (!valid) bin_fault = true;
       double wx[S + 1], wy[S + 1], wz[S + 1];
-      const int bx = stencil<S>((p_cur[0] - o[0]) * ih[0], c.nx, wx);
-      const int by = stencil<S>((p_cur[1] - o[1]) * ih[1], c.ny, wy);
-      const int bz = stencil<S>((p_cur[2] - o[2]) * ih[2], c.nz, wz);
+      const int bx = stencil<S>((p[0] - o[0]) * ih[0], c.nx, wx);
+      const int by = stencil<S>((p[1] - o[1]) * ih[1], c.ny, wy);
+      const int bz = stencil<S>((p[2] - o[2]) * ih[2], c.nz, wz);
       const int lx = bx - ox, ly = by - oy, lz = bz - oz;
       const bool inside = lx >= 0 && lx < sp.T[0] && ly >= 0 && ly < sp.T[1] && lz >= 0 &&
                           lz < sp.T[2];
@@ -579,9 +576,20 @@ __device__ __forceinline__ void deposit_tiles_body(const double* __restrict__ B,
           }
         }
       }
-      r_cur = r_next;
-      r_next = r_after;
-      for (int a = 0; a < 3; ++a) p_cur[a] = p_next[a];
+    };
+    int64_t i = ch.y + threadIdx.x;
+    int64_t ra = index_of(i), rb = index_of(i + stride);
+    double pa[3], pb[3];
+    load_pos(ra, pa);
+    for (; i < ch.z; i += 2 * stride) {
+      const int64_t ra2 = index_of(i + 2 * stride);
+      load_pos(rb, pb);
+      deposit_one(pa, ra);  // slot i
+      const int64_t rb2 = index_of(i + 3 * stride);
+      load_pos(ra2, pa);
+      if (i + stride < ch.z) deposit_one(pb, rb);  // slot i + stride
+      ra = ra2;
+      rb = rb2;
     }
     __syncthreads();
     for (int w = threadIdx.x; w < nw; w += (int)blockDim.x) {
@@ -734,8 +742,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_deposit_tiles(const double* __r
                                                         T* __restrict__ rho,
                                                         unsigned long long* __restrict__ tacc,
                                                         int* __restrict__ tscale) {
-  deposit_tiles_body<S, T>(B, perm, g, c, sp, chunks, nchunks, rho, blockIdx.x, gridDim.x, tacc,
-                           tscale);
+  // the permutation's presence as a template argument: a uniform branch around its loads
+  // inside the loop would make the join wait for all of the wave's loads
+  if (perm)
+    deposit_tiles_body<S, T, true>(B, perm, g, c, sp, chunks, nchunks, rho, blockIdx.x,
+                                   gridDim.x, tacc, tscale);
+  else
+    deposit_tiles_body<S, T, false>(B, nullptr, g, c, sp, chunks, nchunks, rho, blockIdx.x,
+                                    gridDim.x, tacc, tscale);
 }
 
 // Fused second half of step j and first half of step j+1 on the sorted array, one chunk per
@@ -1232,7 +1246,7 @@ template <int S, typename T>
 __global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
-  deposit_tiles_body<S, T>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
+  deposit_tiles_body<S, T, false>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
                            (T*)d.rho, blockIdx.x, gridDim.x, d.tacc, d.tscale);
 }
 
