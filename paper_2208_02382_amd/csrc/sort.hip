@@ -801,8 +801,15 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
   // to back on the kicked state: they are applied as their product (one matrix per plane, the
   // longitudinal coefficients summed), the same linear map in half the arithmetic and with few
   // enough uniform values to stay in scalar registers.
-  HalfMap maps;
-  if constexpr (!DIAG) maps = half_product(second, first_next, has_next != 0);
+  // With the moment sums the two maps stay apart (the sums are taken between them), each in
+  // matrix form.
+  HalfMap maps, next_map;
+  if constexpr (!DIAG) {
+    maps = half_product(second, first_next, has_next != 0);
+  } else {
+    maps = half_product(second, second, false);
+    next_map = half_product(first_next, first_next, false);
+  }
   const double o[3] = {g->origin[0], g->origin[1], g->origin[2]};
   const double ih[3] = {g->inv_h[0], g->inv_h[1], g->inv_h[2]};
   const int Wx = sp.T[0] + S, Wy = sp.T[1] + S, Wz = sp.T[2] + S;
@@ -896,7 +903,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
         v[3] = v[3] + c.C * (double)ey * L;
         v[5] = v[5] + c.gamma * c.C * (double)ez * L;
         if constexpr (DIAG) {
-          apply_half(second, v, c.inv_gamma2);
+          apply_matrix(maps, v, c.inv_gamma2);
           double d[6];
           for (int r = 0; r < 6; ++r) {
             d[r] = v[r] - sh[r];
@@ -905,7 +912,7 @@ __device__ __forceinline__ void gkd_tiles_body(double* __restrict__ B,
           int q = 6;
           for (int a = 0; a < 6; ++a)
             for (int b = a; b < 6; ++b) acc[q++] += d[a] * d[b];
-          if (has_next) apply_half(first_next, v, c.inv_gamma2);
+          if (has_next) apply_matrix(next_map, v, c.inv_gamma2);
         } else {
           apply_matrix(maps, v, c.inv_gamma2);
         }
