@@ -179,6 +179,38 @@ __device__ __forceinline__ const typename TwT<T>::type* stage_twiddles(
   return twl;
 }
 
+// Fills the LB lines of length M in LDS (line l at buf[l (M + 1)]) from global memory, element
+// p of line l from addr(p, l) where ok(p, l) holds and zero elsewhere; consecutive threads take
+// consecutive lines, which are consecutive in memory.  A thread issues its loads four at a time
+// before it stores any of them to LDS, the addresses of elements that are not loaded replaced by
+// `safe` (any valid address) and the values by zero, so that no branch surrounds a load: a load
+// inside a branch is waited for at the branch's join, which would put the latencies of a
+// thread's loads one after another.
+template <typename T, typename Addr, typename Ok>
+__device__ __forceinline__ void load_lines(Cx<T>* buf, int LB, int M, const Cx<T>* safe,
+                                           Addr addr, Ok ok) {
+  const int total = LB * M, nt = (int)blockDim.x;
+  for (int i0 = (int)threadIdx.x; i0 < total; i0 += 4 * nt) {
+    Cx<T> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      const int p = idx / LB, l = idx - p * LB;
+      const bool use = idx < total && ok(p, l);
+      const Cx<T> x = ld(use ? addr(p, l) : safe);
+      v[u] = use ? x : Cx<T>{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      if (idx < total) {
+        const int p = idx / LB, l = idx - p * LB;
+        buf[l * (M + 1) + p] = v[u];
+      }
+    }
+  }
+}
+
 // cyclic index of the ghost-inclusive position p = 0..n+1 (node p - 1): M - 1 for p = 0
 __device__ __forceinline__ int ghost_src(int p, int M) { return p == 0 ? M - 1 : p - 1; }
 
@@ -310,25 +342,40 @@ __device__ __forceinline__ void r2c_x_body(const Geom* __restrict__ g,
   const int y0 = bx * LB, z = by;
   const int nl = min(LB, rows - y0);
   const T* s0 = src + ((int64_t)z * rows + y0) * len;
-  for (int idx = threadIdx.x; idx < LB * H; idx += blockDim.x) {
-    const int l = idx / H, j = idx - l * H;
-    Cx<T> v = {0, 0};
-    if (l < nl) {
-      const T* row = s0 + (int64_t)l * len;
+  // four elements per thread at a time, their loads issued before any is stored and with no
+  // branch around a load (out-of-range addresses replaced by the row's start, values by zero)
+  const int total = LB * H, nt = (int)blockDim.x;
+  for (int i0 = (int)threadIdx.x; i0 < total; i0 += 4 * nt) {
+    T vr[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      const int l = idx / H, j = idx - l * H;
+      const bool row_ok = idx < total && l < nl;
+      const T* row = s0 + (int64_t)(row_ok ? l : 0) * len;
+#pragma unroll
       for (int h2 = 0; h2 < 2; ++h2) {
         const int t = 2 * j + h2;  // cyclic position
-        T val = 0;
+        int at = -1;               // its element in the source row, if any
         if (MODE == 0) {
-          if (t < nx) val = row[t];
+          if (t < nx) at = t;
         } else {
-          if (t <= nx) val = row[t + 1];
-          else if (t == M - 1) val = row[0];
+          if (t <= nx) at = t + 1;
+          else if (t == M - 1) at = 0;
         }
-        if (h2 == 0) v.x = val;
-        else v.y = val;
+        const bool use = row_ok && at >= 0;
+        const T val = row[use ? at : 0];
+        vr[u][h2] = use ? val : T(0);
       }
     }
-    buf[l * (H + 1) + j] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      if (idx < total) {
+        const int l = idx / H, j = idx - l * H;
+        buf[l * (H + 1) + j] = Cx<T>{vr[u][0], vr[u][1]};
+      }
+    }
   }
   const auto* twl = stage_twiddles(buf, LB, H, tw, M);
   __syncthreads();
@@ -374,12 +421,9 @@ __device__ __forceinline__ void c2c_y_body(const Geom* __restrict__ g, Cx<T>* __
   const int nl = min(LB, Kx - a0);
   const int plane = (STAGE == 0 && MODE == 1) ? ghost_src(by, 2 * nz) : (int)by;
   Cx<T>* base = W + (int64_t)plane * M * Kx + a0;
-  for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
-    const int p = idx / LB, l = idx - p * LB;
-    Cx<T> v = {0, 0};
-    if (l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M))) v = ld(base + (int64_t)p * Kx + l);
-    buf[l * (M + 1) + p] = v;
-  }
+  load_lines<T>(
+      buf, LB, M, base, [&](int p, int l) { return base + (int64_t)p * Kx + l; },
+      [&](int p, int l) { return l < nl && (STAGE == 1 || src_nonzero<MODE>(p, ny, M)); });
   const auto* twl = stage_twiddles(buf, LB, M, tw, M);
   __syncthreads();
   fft_lds<T, DIR>(buf, LB, ax, twl, 1);
@@ -421,20 +465,41 @@ __device__ __forceinline__ void zconv_body(const Geom* __restrict__ g, Cx<T>* W,
   const int64_t sz = (int64_t)My * Kx;
   Cx<T>* base = W + (int64_t)ky * Kx + a0;
   Cx<T>* obase = (W2 ? W2 : W) + (int64_t)ky * Kx + a0;
-  for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
-    const int p = idx / LB, l = idx - p * LB;
-    Cx<T> v = {0, 0};
-    if (l < nl && src_nonzero<MODE>(p, nz, M)) v = ld(base + (int64_t)p * sz + l);
-    buf[l * (M + 1) + p] = v;
-  }
+  load_lines<T>(
+      buf, LB, M, base, [&](int p, int l) { return base + (int64_t)p * sz + l; },
+      [&](int p, int l) { return l < nl && src_nonzero<MODE>(p, nz, M); });
   const auto* twl = stage_twiddles(buf, LB, M, tw, M);
-  __syncthreads();
-  fft_lds<T, -1>(buf, LB, ax, twl, 1);
   const int fy = fold(ky, My);
   const T* grow = gh + (int64_t)fy * Kx + a0;
   const int64_t gplane = (int64_t)(ny + 1) * Kx;
   const bool flip_y = IMAG && odd == 1 && ky > ny;
-  for (int idx = threadIdx.x; idx < LB * M; idx += blockDim.x) {
+  const int total = LB * M, nt = (int)blockDim.x;
+  __syncthreads();
+  fft_lds<T, -1>(buf, LB, ax, twl, 1);
+  // the kernel spectrum of the thread's first 4 elements (all of them with the launches'
+  // shapes, LB M <= 4 blockDim.x), loaded together without a branch around a load (loading it
+  // before the transform would hold 8 more registers through it and halve the resident blocks)
+  T gs[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = (int)threadIdx.x + u * nt;
+    const int p = idx / LB, l = idx - p * LB;
+    const bool use = idx < total && l < nl;
+    gs[u] = grow[use ? (int64_t)fold(p, M) * gplane + l : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = (int)threadIdx.x + u * nt;
+    const int p = idx / LB, l = idx - p * LB;
+    if (idx < total && l < nl) {
+      T s = gs[u];
+      if (IMAG && (flip_y || (odd == 2 && p > nz))) s = -s;
+      Cx<T> v = buf[l * (M + 1) + p];
+      buf[l * (M + 1) + p] = IMAG ? Cx<T>{-v.y * s, v.x * s} : Cx<T>{v.x * s, v.y * s};
+    }
+  }
+  // elements past 4 blockDim.x (none with the launches' shapes) load their spectrum here
+  for (int idx = (int)threadIdx.x + 4 * nt; idx < total; idx += nt) {
     const int p = idx / LB, l = idx - p * LB;
     if (l < nl) {
       T s = grow[(int64_t)fold(p, M) * gplane + l];
@@ -491,18 +556,37 @@ __device__ __forceinline__ void c2r_x_body(const Geom* __restrict__ g,
   const int r0 = bx * LB, zz = by;
   const int nl = min(LB, py - r0);
   const Cx<T>* src = W + ((int64_t)zz * My + r0) * Kx;
-  for (int idx = threadIdx.x; idx < LB * H; idx += blockDim.x) {
-    const int l = idx / H, k = idx - l * H;
-    Cx<T> v = {0, 0};
-    if (l < nl) {
-      const Cx<T> xk = ld(src + (int64_t)l * Kx + k);
-      const Cx<T> xc = cconj(ld(src + (int64_t)l * Kx + (H - k)));
-      const auto w = tw[k];
-      const Cx<T> winv = {(T)w.x, (T)-w.y};  // exp(+2 pi i k / M_x)
-      const Cx<T> d = cmul(winv, csub(xk, xc));
-      v = cadd(cadd(xk, xc), Cx<T>{-d.y, d.x});  // + i d
+  // four elements per thread at a time, their loads issued before any is used and with no
+  // branch around a load (rows past the block's last read as row 0, their values not used)
+  const int total = LB * H, nt = (int)blockDim.x;
+  for (int i0 = (int)threadIdx.x; i0 < total; i0 += 4 * nt) {
+    Cx<T> xk[4], xh[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      const int l = idx / H, k = idx - l * H;
+      const bool ok = idx < total && l < nl;
+      const Cx<T>* row = src + (int64_t)(ok ? l : 0) * Kx;
+      const int kk = ok ? k : 0;
+      xk[u] = ld(row + kk);
+      xh[u] = ld(row + (H - kk));
     }
-    buf[l * (H + 1) + k] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * nt;
+      if (idx < total) {
+        const int l = idx / H, k = idx - l * H;
+        const auto w = tw[k];
+        Cx<T> v = {0, 0};
+        if (l < nl) {
+          const Cx<T> xc = cconj(xh[u]);
+          const Cx<T> winv = {(T)w.x, (T)-w.y};  // exp(+2 pi i k / M_x)
+          const Cx<T> d = cmul(winv, csub(xk[u], xc));
+          v = cadd(cadd(xk[u], xc), Cx<T>{-d.y, d.x});  // + i d
+        }
+        buf[l * (H + 1) + k] = v;
+      }
+    }
   }
   const auto* twl = stage_twiddles(buf, LB, H, tw, M);
   __syncthreads();
