@@ -97,7 +97,7 @@ def tuned(cfg, grid_fp32, enabled):
         return None, None
     from paper_2208_02382_amd import autotune
     rec = autotune.tune(cfg, grid_fp32=grid_fp32, log=_log)
-    t = {k: rec[k] for k in ("tile", "chunk", "blocks", "threads") if k in rec}
+    t = {k: rec[k] for k in autotune.FIELDS if k in rec}
     return t, {"tuning": t, "tuned_ms_per_step": rec["s_per_step"] * 1e3,
                "default_ms_per_step": rec["default_s_per_step"] * 1e3,
                "candidates": len(rec["tried"])}

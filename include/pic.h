@@ -77,7 +77,8 @@ typedef struct {
                               the push stay float64) */
   int space_charge;        /* 0/1 (set_space_charge); 0 makes pic_track_n_steps purely linear */
   /* Launch tuning of the binned deposit and gather (0 = the library's default for each).
-   * pic_track_n_steps gives the same bits for every chunk, blocks and threads; the tile shape
+   * pic_track_n_steps gives the same bits for every chunk, blocks, threads and
+   * deposit_threads; the tile shape
    * changes only the rounding of the deposit's fixed-point charges (below 1e-13 of a
    * macroparticle's charge per contribution). */
   int tile[3];             /* tile edge in nodes per axis for the per-step binning; the tile
@@ -97,6 +98,9 @@ typedef struct {
                               of the field itself (the cell averages of u_a/|r|^3; no
                               differencing error), three convolutions instead of one.  1 is not
                               supported in batches (PIC_EUNSUPPORTED) */
+  int deposit_threads;     /* launch tuning: threads per workgroup of the binned charge deposit
+                              alone, a multiple of 64 in 64..1024; default (0) that of
+                              `threads` */
 } pic_beam_desc;
 
 /* Lattice element kinds (Listing 1 of the paper: Drift(ds, nslice), Quad(ds, k, nslice)).

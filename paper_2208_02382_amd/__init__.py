@@ -34,7 +34,8 @@ class BeamDesc(ctypes.Structure):
                 ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("grid_fp32", ctypes.c_int), ("space_charge", ctypes.c_int),
                 ("tile", ctypes.c_int * 3), ("chunk", ctypes.c_int), ("blocks", ctypes.c_int),
-                ("threads", ctypes.c_int), ("direct_field", ctypes.c_int)]
+                ("threads", ctypes.c_int), ("direct_field", ctypes.c_int),
+                ("deposit_threads", ctypes.c_int)]
 
 
 ELEM_THIN, ELEM_DRIFT, ELEM_QUAD = 0, 1, 2
@@ -122,8 +123,9 @@ def moments_noalloc(X, out=None):
 
 def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid_fp32=False,
               space_charge=True, tuning=None, direct_field=False):
-    """tuning: None or a dict with any of tile (3 ints), chunk, blocks, threads (0 = default).
-    direct_field: E' from the field's own integrated Green's functions (no differencing)."""
+    """tuning: None or a dict with any of tile (3 ints), chunk, blocks, threads, deposit_threads
+    (0 = default).  direct_field: E' from the field's own integrated Green's functions (no
+    differencing)."""
     nx, ny, nz = nodes
     t = tuning or {}
     tile = t.get("tile", (0, 0, 0))
@@ -131,7 +133,7 @@ def make_desc(n, qm_qeeV, charge_C, kin_energy_MeV, mass_MeV, shape, nodes, grid
                     float(mass_MeV), int(shape), int(nx), int(ny), int(nz), int(bool(grid_fp32)),
                     int(bool(space_charge)), (ctypes.c_int * 3)(*[int(v) for v in tile]),
                     int(t.get("chunk", 0)), int(t.get("blocks", 0)), int(t.get("threads", 0)),
-                    int(bool(direct_field)))
+                    int(bool(direct_field)), int(t.get("deposit_threads", 0)))
 
 
 def sigma_from_params(sigmaX, sigmaY, sigmaT, sigmaPx, sigmaPy, sigmaPt, muxpx=0.0, muypy=0.0,

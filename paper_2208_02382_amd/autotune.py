@@ -36,6 +36,8 @@ SLABS = ((24, 24, 2), (32, 16, 2), (16, 32, 2), (32, 32, 2), (16, 16, 4), (20, 2
 CHUNKS = (2048, 4096, 8192, 16384, 32768)
 BLOCKS = (0, 1024, 2048, 8192)          # 0: min(work items, 4096)
 THREADS = (256, 512, 1024)
+DEPOSIT_THREADS = (0, 128, 256, 512, 1024)  # 0: that of `threads`
+FIELDS = ("tile", "chunk", "blocks", "threads", "deposit_threads")
 LDS_BYTES = 163840 - 4096               # dynamic LDS one workgroup may allocate
 BATCH_BLOCKS = (32, 64, 128, 256, 512)
 
@@ -61,10 +63,10 @@ def save(table, cache=DEFAULT_CACHE):
 
 
 def lookup(n, nodes, shape, grid_fp32, cache=DEFAULT_CACHE):
-    """The cached tuning dict (tile, chunk, blocks) of this problem class, or None."""
+    """The cached tuning dict (tile, chunk, blocks, threads, deposit_threads) of this problem
+    class, or None."""
     rec = load(cache).get(key(n, nodes, shape, grid_fp32))
-    return None if rec is None else {k: rec[k] for k in ("tile", "chunk", "blocks", "threads")
-                                     if k in rec}
+    return None if rec is None else {k: rec[k] for k in FIELDS if k in rec}
 
 
 def _tile_ok(tile, nodes, shape, grid_fp32):
@@ -157,9 +159,18 @@ def tune(cfg, grid_fp32=False, steps=6, cache=DEFAULT_CACHE, force=False, log=No
         dt = run(cand)
         if dt < best_t:
             best, best_t = cand, dt
+    # the deposit's workgroup size apart from the gather's (the two kernels' best sizes differ)
+    for th in DEPOSIT_THREADS[1:]:
+        if th == best.get("threads", THREADS[0]):
+            continue
+        cand = dict(best, deposit_threads=th)
+        dt = run(cand)
+        if dt < best_t:
+            best, best_t = cand, dt
     del X
     rec = {"tile": list(best.get("tile", (0, 0, 0))), "chunk": int(best.get("chunk", 0)),
            "blocks": int(best.get("blocks", 0)), "threads": int(best.get("threads", 0)),
+           "deposit_threads": int(best.get("deposit_threads", 0)),
            "s_per_step": best_t,
            "default_s_per_step": default, "steps_timed": steps, "tried": tried}
     if cache:

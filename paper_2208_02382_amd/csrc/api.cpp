@@ -99,6 +99,9 @@ pic_status check_desc(const pic_beam_desc* d) {
   if (d->blocks < 0 || d->blocks > 65535) return fail(PIC_EINVAL, "blocks must be 0..65535");
   if (d->threads != 0 && (d->threads < 64 || d->threads > kMaxThreads || d->threads % 64 != 0))
     return fail(PIC_EINVAL, "threads must be 0 or a multiple of 64 in 64..1024");
+  if (d->deposit_threads != 0 && (d->deposit_threads < 64 || d->deposit_threads > kMaxThreads ||
+                                  d->deposit_threads % 64 != 0))
+    return fail(PIC_EINVAL, "deposit_threads must be 0 or a multiple of 64 in 64..1024");
   if (d->direct_field != 0 && d->direct_field != 1) return fail(PIC_EINVAL, "direct_field must be 0 or 1");
   return PIC_OK;
 }
@@ -990,7 +993,8 @@ pic_status pic_beam_create(const pic_beam_desc* d, double* d_X, void* d_work, si
   b->gd3 = (double*)(w + L.gd3);
   b->gh3 = w + L.gh3;
   b->W2 = w + L.W2;
-  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks, d->threads);
+  b->sp = make_sort_plan(d->nx, d->ny, d->nz, d->n, d->tile, d->chunk, d->blocks, d->threads,
+                         d->deposit_threads);
   b->XA = (double*)(w + L.XA);
   b->XB = (double*)(w + L.XB);
   b->idA = (uint32_t*)(w + L.idA);

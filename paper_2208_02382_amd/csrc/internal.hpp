@@ -71,8 +71,9 @@ struct SortPlan {
   int ntiles;
   int chunk;
   int64_t max_chunks;
-  int blocks;   // workgroups of the binned deposit and gather
-  int threads;  // threads per workgroup of the binned deposit and gather (64..1024)
+  int blocks;       // workgroups of the binned deposit and gather
+  int threads;      // threads per workgroup of the binned gather (64..1024)
+  int dep_threads;  // threads per workgroup of the binned charge deposit (64..1024)
 };
 
 // One half of a lattice slice's linear map (applied by apply_half, device_common.hpp).  A slice
@@ -185,7 +186,7 @@ inline int64_t tile_window_nodes(const SortPlan& sp, int S) {
 }
 // tile[a], chunk, blocks: 0 selects the default
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
-                        int blocks, int threads);
+                        int blocks, int threads, int deposit_threads = 0);
 // A = the first half map of X with the box of its positions; idA (if given) = ids_in, or the
 // indices 0..n-1 when ids_in is nullptr
 hipError_t launch_prologue(const double* X, double* A, uint32_t* idA, const uint32_t* ids_in,

@@ -1346,7 +1346,7 @@ int grid_stride(int64_t n) {
 }  // namespace
 
 SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], int chunk,
-                        int blocks, int threads) {
+                        int blocks, int threads, int deposit_threads) {
   SortPlan sp;
   int nn[3] = {nx, ny, nz};
   for (int a = 0; a < 3; ++a) {
@@ -1364,6 +1364,7 @@ SortPlan make_sort_plan(int nx, int ny, int nz, int64_t n, const int tile[3], in
   if (sp.max_chunks < kMaxTiles + 1) sp.max_chunks = kMaxTiles + 1;
   sp.blocks = blocks > 0 ? blocks : (int)(items < 4096 ? items : 4096);
   sp.threads = threads > 0 ? threads : kBlk;
+  sp.dep_threads = deposit_threads > 0 ? deposit_threads : sp.threads;
   return sp;
 }
 
@@ -1445,7 +1446,7 @@ hipError_t launch_deposit_tiles(const double* B, const uint32_t* perm, const Geo
                                 T* rho, hipStream_t s, unsigned long long* tacc, int* tscale) {
   const int S = c.shape;
   size_t lds = sizeof(unsigned long long) * (size_t)(sp.T[0] + S) * (sp.T[1] + S) * (sp.T[2] + S);
-  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.threads);
+  const dim3 grid((unsigned)sp.blocks), block((unsigned)sp.dep_threads);
   if (!tacc || !tscale) return hipErrorInvalidValue;
   const int64_t nodes = (int64_t)c.nx * c.ny * c.nz;
   int rb = (int)((nodes + 255) / 256);

@@ -60,8 +60,10 @@ def test_tuning_fields_are_validated():
     assert pic.workspace_bytes(_desc(tuning={"tile": (32, 32, 32)})) == 0  # window > 160 KB
     assert "LDS" in pic.last_error()
     assert pic.workspace_bytes(_desc(tuning={"threads": 1024})) == base
+    assert pic.workspace_bytes(_desc(tuning={"deposit_threads": 128})) == base
     for bad in (32, 100, 2048, -64):
         assert pic.workspace_bytes(_desc(tuning={"threads": bad})) == 0
+        assert pic.workspace_bytes(_desc(tuning={"deposit_threads": bad})) == 0
     assert pic.workspace_bytes(_desc(tuning={"tile": (-1, 0, 0)})) == 0
     assert pic.workspace_bytes(_desc(tuning={"chunk": 100})) == 0
     assert pic.workspace_bytes(_desc(tuning={"blocks": 70000})) == 0

@@ -49,7 +49,8 @@ def test_chunk_size_and_workgroups_do_not_change_the_bits(lib):
     xi = torch.from_numpy(workloads.draw_xi(cfg, n=n)).cuda()
     out = []
     for tun in ({"tile": (8, 8, 4), "chunk": 2048, "blocks": 64, "threads": 256},
-                {"tile": (8, 8, 4), "chunk": 16384, "blocks": 1024, "threads": 1024}):
+                {"tile": (8, 8, 4), "chunk": 16384, "blocks": 1024, "threads": 1024,
+                 "deposit_threads": 128}):
         b = _beam(lib, cfg, n, nodes, shape, xi, tuning=tun)
         b.track(cfg.lattice, 10)
         out.append(b.X.clone())

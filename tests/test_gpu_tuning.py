@@ -46,11 +46,12 @@ def test_autotune_cache_round_trip(lib, tmp_path):
     cfg = workloads.SMALL.with_(n=20_000)
     cache = str(tmp_path / "tuning.json")
     rec = autotune.tune(cfg, steps=1, cache=cache)
-    assert set(("tile", "chunk", "blocks", "threads", "s_per_step", "tried")) <= set(rec)
+    assert set(("tile", "chunk", "blocks", "threads", "deposit_threads", "s_per_step",
+                "tried")) <= set(rec)
     assert rec["s_per_step"] <= rec["default_s_per_step"]
     assert len(rec["tried"]) >= 5
     t = autotune.lookup(cfg.n, cfg.nodes, cfg.shape, False, cache=cache)
-    assert t == {k: rec[k] for k in ("tile", "chunk", "blocks", "threads")}
+    assert t == {k: rec[k] for k in autotune.FIELDS}
     assert autotune.tune(cfg, steps=1, cache=cache)["tried"] == rec["tried"]   # served cached
     # the chosen shape is a valid description
     b = lib.Beam.from_config(cfg, tuning=t)
