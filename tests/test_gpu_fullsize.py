@@ -28,7 +28,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 # bars of dJ/dX0 at the adjoint workload (1e6 particles, 64^3), relative to each row's largest
 # entry: 1e-12, except the z and delta rows at 5e-12 (measured 9.9e-13 and 6.4e-13 on MI355X
-# with 1e-13 or less in the other rows).  The gradient through the box carries dJ/dmin and
+# with 2e-13 or less in the other rows).  The gradient through the box carries dJ/dmin and
 # dJ/dmax of z to the two particles at the box's z faces; these are differences of grid sums
 # (charge against the h-derivative convolution, e against E', the weights' sums) that cancel
 # by two to three orders of magnitude, so the two sides' rounding differences of 1e-15 in
