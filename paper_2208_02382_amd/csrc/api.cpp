@@ -895,11 +895,11 @@ pic_status enqueue_batch(const BeamDev* tab, int nb, const BatchDims& bd, int sh
     HIP_OK(launch_batch_green<T>(tab, nb, bd, aux), "batch");
     HIP_OK(hipEventRecord(join, aux), "batch");
     HIP_OK(launch_batch_particles_bin(tab, nb, bd, shape, parity, j == 0, s), "batch");
-    HIP_OK(launch_batch_deposit<T>(tab, nb, bd, shape, parity, s), "batch");
+    HIP_OK(launch_batch_deposit<T>(tab, nb, bd, shape, parity, j == 0, s), "batch");
     HIP_OK(hipStreamWaitEvent(s, join, 0), "batch");
     HIP_OK(launch_batch_solve<T>(tab, nb, bd, s), "batch");
     if (j + 1 < n_steps) HIP_OK(launch_batch_box_reset(tab, nb, s), "batch");
-    HIP_OK(launch_batch_gkd<T>(tab, nb, bd, shape, parity, j, n_steps, s), "batch");
+    HIP_OK(launch_batch_gkd<T>(tab, nb, bd, shape, parity, j, n_steps, j == 0, s), "batch");
   }
   HIP_OK(launch_batch_unpermute(tab, nb, bd, n_steps & 1, s), "batch");
   return PIC_OK;
@@ -1393,6 +1393,7 @@ pic_status pic_batch_create(pic_beam* beams, int n_beams, const pic_element* con
     d.idA = h->idA;
     d.idB = h->idB;
     d.keys = h->keys;
+    d.perm = h->perm;
     d.hist = h->hist;
     d.cursor = h->cursor;
     d.chunks = h->chunks;

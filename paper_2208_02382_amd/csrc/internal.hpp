@@ -120,6 +120,7 @@ struct BeamDev {
   uint32_t* idA;
   uint32_t* idB;
   uint32_t* keys;
+  uint32_t* perm;       // the ranking after a call's first step: slot -> index in the step's input
   uint32_t* hist;
   uint32_t* cursor;
   int4* chunks;
@@ -245,12 +246,14 @@ hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchD
                                       int parity, bool first, hipStream_t s);
 // every beam's per-tile integer charge windows set to zero
 hipError_t launch_batch_clear_tacc(const BeamDev* beams, int nb, hipStream_t s);
+// first: the call's first step, whose binning moved the particles into tile order; later steps
+// only rank them, and the deposit and the gather-kick read the step's input through the ranking
 template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
-                                int parity, hipStream_t s);
+                                int parity, bool first, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_gkd(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
-                            int parity, int j, int n_steps, hipStream_t s);
+                            int parity, int j, int n_steps, bool first, hipStream_t s);
 hipError_t launch_batch_unpermute(const BeamDev* beams, int nb, const BatchDims& bd, int parity,
                                   hipStream_t s);
 hipError_t launch_batch_prologue_particles(const BeamDev* beams, int nb, const BatchDims& bd,

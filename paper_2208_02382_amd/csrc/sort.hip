@@ -1240,6 +1240,13 @@ __global__ __launch_bounds__(1024) void k_build_chunks_batch(const BeamDev* __re
   build_chunks_body(d.geom, d.sp, d.hist, d.cursor, d.chunks, d.nchunks);
 }
 
+// after a call's first step: the ranking only (cur_X stays where it is)
+__global__ __launch_bounds__(kBlk) void k_scatter_perm_batch(const BeamDev* __restrict__ beams) {
+  const BeamDev& d = beams[blockIdx.y];
+  if ((int64_t)blockIdx.x * kItems >= d.c.n) return;
+  scatter_perm_body(d.keys, d.geom, d.c.n, d.sp.ntiles, d.cursor, d.perm, blockIdx.x);
+}
+
 template <bool STAGED>
 __global__ __launch_bounds__(kBlk) void k_scatter_batch(const BeamDev* __restrict__ beams,
                                                         int parity) {
@@ -1249,12 +1256,14 @@ __global__ __launch_bounds__(kBlk) void k_scatter_batch(const BeamDev* __restric
                nxt_X(d, parity), nxt_id(d, parity), blockIdx.x, gridDim.x);
 }
 
-template <int S, typename T>
+// PERM: the step's input cur_X through the ranking; else nxt_X, in slot order
+template <int S, typename T, bool PERM>
 __global__ __launch_bounds__(kBlk) void k_deposit_tiles_batch(const BeamDev* __restrict__ beams,
                                                               int parity) {
   const BeamDev& d = beams[blockIdx.y];
-  deposit_tiles_body<S, T, false>(nxt_X(d, parity), nullptr, d.geom, d.c, d.sp, d.chunks, d.nchunks,
-                           (T*)d.rho, blockIdx.x, gridDim.x, d.tacc, d.tscale);
+  deposit_tiles_body<S, T, PERM>(PERM ? cur_X(d, parity) : nxt_X(d, parity),
+                                 PERM ? d.perm : nullptr, d.geom, d.c, d.sp, d.chunks,
+                                 d.nchunks, (T*)d.rho, blockIdx.x, gridDim.x, d.tacc, d.tscale);
 }
 
 template <int S, typename T>
@@ -1272,16 +1281,19 @@ __global__ __launch_bounds__(256) void k_clear_tacc_batch(const BeamDev* __restr
     d.tacc[i] = 0ull;
 }
 
-template <int S, typename T>
+// PERM: reads cur_X (and its ids) through the ranking and writes nxt_X in slot order; else
+// updates nxt_X in place
+template <int S, typename T, bool PERM>
 __global__ __launch_bounds__(kBlk) void k_gkd_tiles_batch(const BeamDev* __restrict__ beams,
                                                           int parity, int j, int n_steps) {
   const BeamDev& d = beams[blockIdx.y];
   const SliceDev& sl = d.slices[j % d.n_slices];
   const SliceDev& sn = d.slices[(j + 1) % d.n_slices];
-  gkd_tiles_body<S, T, false, false>(nxt_X(d, parity), nullptr, nullptr, nullptr, nullptr, d.geom,
-                              (const T*)d.E, d.c, d.sp, d.chunks, d.nchunks,
-                       sl.L, sl.second, j + 1 < n_steps, sn.first, d.box, blockIdx.x,
-                       gridDim.x);
+  gkd_tiles_body<S, T, PERM, false>(nxt_X(d, parity), PERM ? cur_X(d, parity) : nullptr,
+                                    PERM ? d.perm : nullptr, PERM ? cur_id(d, parity) : nullptr,
+                                    PERM ? nxt_id(d, parity) : nullptr, d.geom, (const T*)d.E,
+                                    d.c, d.sp, d.chunks, d.nchunks, sl.L, sl.second,
+                                    j + 1 < n_steps, sn.first, d.box, blockIdx.x, gridDim.x);
 }
 
 // reordering at the end: bucket keys of the ids, bucket offsets, bucket scatter, final scatter
@@ -1620,33 +1632,35 @@ hipError_t launch_batch_particles_bin(const BeamDev* beams, int nb, const BatchD
   hipLaunchKernelGGL(k_build_chunks_batch, dim3(nb), dim3(1024), 0, s, beams);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // the first step reads the caller's order (staged scatter), later steps the previous binning
+  // the first step moves the caller's order into tile order (staged scatter); later steps, whose
+  // input is in the previous step's tile order, only rank
   if (first)
     hipLaunchKernelGGL(k_scatter_batch<true>, grid, dim3(kBlk), 0, s, beams, parity);
   else
-    hipLaunchKernelGGL(k_scatter_batch<false>, grid, dim3(kBlk), 0, s, beams, parity);
+    hipLaunchKernelGGL(k_scatter_perm_batch, grid, dim3(kBlk), 0, s, beams);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_deposit(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
-                                int parity, hipStream_t s) {
+                                int parity, bool first, hipStream_t s) {
   const dim3 grid(bd.max_chunks, nb);
   int rb = (int)(((int64_t)bd.max_nx * bd.max_ny * bd.max_nz + 255) / 256);
   if (rb > 16384) rb = 16384;
+#define PIC_DEP_BATCH(SS, PP)                                                                 \
+  do {                                                                                        \
+    PIC_TRY_LDS((k_deposit_tiles_batch<SS, T, PP>), bd.dep_lds);                              \
+    hipLaunchKernelGGL((k_deposit_tiles_batch<SS, T, PP>), grid, dim3(kBlk), bd.dep_lds, s,   \
+                       beams, parity);                                                        \
+    PIC_TRY(hipGetLastError());                                                               \
+    hipLaunchKernelGGL((k_tile_reduce_batch<SS, T>), dim3(rb, nb), dim3(256), 0, s, beams);   \
+  } while (0)
   if (shape == 1) {
-    PIC_TRY_LDS((k_deposit_tiles_batch<1, T>), bd.dep_lds);
-    hipLaunchKernelGGL((k_deposit_tiles_batch<1, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
-                       parity);
-    PIC_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_tile_reduce_batch<1, T>), dim3(rb, nb), dim3(256), 0, s, beams);
+    if (first) PIC_DEP_BATCH(1, false); else PIC_DEP_BATCH(1, true);
   } else {
-    PIC_TRY_LDS((k_deposit_tiles_batch<2, T>), bd.dep_lds);
-    hipLaunchKernelGGL((k_deposit_tiles_batch<2, T>), grid, dim3(kBlk), bd.dep_lds, s, beams,
-                       parity);
-    PIC_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_tile_reduce_batch<2, T>), dim3(rb, nb), dim3(256), 0, s, beams);
+    if (first) PIC_DEP_BATCH(2, false); else PIC_DEP_BATCH(2, true);
   }
+#undef PIC_DEP_BATCH
   return hipGetLastError();
 }
 
@@ -1657,17 +1671,20 @@ hipError_t launch_batch_clear_tacc(const BeamDev* beams, int nb, hipStream_t s) 
 
 template <typename T>
 hipError_t launch_batch_gkd(const BeamDev* beams, int nb, const BatchDims& bd, int shape,
-                            int parity, int j, int n_steps, hipStream_t s) {
+                            int parity, int j, int n_steps, bool first, hipStream_t s) {
   const dim3 grid(bd.max_chunks, nb);
+#define PIC_GKD_BATCH(SS, PP)                                                                 \
+  do {                                                                                        \
+    PIC_TRY_LDS((k_gkd_tiles_batch<SS, T, PP>), bd.gkd_lds);                                  \
+    hipLaunchKernelGGL((k_gkd_tiles_batch<SS, T, PP>), grid, dim3(kBlk), bd.gkd_lds, s, beams, \
+                       parity, j, n_steps);                                                   \
+  } while (0)
   if (shape == 1) {
-    PIC_TRY_LDS((k_gkd_tiles_batch<1, T>), bd.gkd_lds);
-    hipLaunchKernelGGL((k_gkd_tiles_batch<1, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
-                       j, n_steps);
+    if (first) PIC_GKD_BATCH(1, false); else PIC_GKD_BATCH(1, true);
   } else {
-    PIC_TRY_LDS((k_gkd_tiles_batch<2, T>), bd.gkd_lds);
-    hipLaunchKernelGGL((k_gkd_tiles_batch<2, T>), grid, dim3(kBlk), bd.gkd_lds, s, beams, parity,
-                       j, n_steps);
+    if (first) PIC_GKD_BATCH(2, false); else PIC_GKD_BATCH(2, true);
   }
+#undef PIC_GKD_BATCH
   return hipGetLastError();
 }
 
@@ -1689,13 +1706,13 @@ hipError_t launch_batch_unpermute(const BeamDev* beams, int nb, const BatchDims&
 }
 
 template hipError_t launch_batch_deposit<double>(const BeamDev*, int, const BatchDims&, int, int,
-                                                 hipStream_t);
+                                                 bool, hipStream_t);
 template hipError_t launch_batch_deposit<float>(const BeamDev*, int, const BatchDims&, int, int,
-                                                hipStream_t);
+                                                bool, hipStream_t);
 template hipError_t launch_batch_gkd<double>(const BeamDev*, int, const BatchDims&, int, int, int,
-                                             int, hipStream_t);
+                                             int, bool, hipStream_t);
 template hipError_t launch_batch_gkd<float>(const BeamDev*, int, const BatchDims&, int, int, int,
-                                            int, hipStream_t);
+                                            int, bool, hipStream_t);
 
 template hipError_t launch_deposit_tiles<double>(const double*, const uint32_t*, const Geom*,
                                                  Consts, const SortPlan&, const int4*,
