@@ -238,14 +238,15 @@ def run_batched(n_beams, steps, grid_fp32=False, tune=True, sequential=True):
     cfgs = workloads.batch_beams(n_beams=n_beams, steps=steps)
     blocks = 0
     tune_rec = None
+    from paper_2208_02382_amd import autotune
     if tune:
-        from paper_2208_02382_amd import autotune
         tune_rec = autotune.tune_batch(cfgs, grid_fp32=grid_fp32, log=_log)
         blocks = tune_rec["blocks_per_beam"]
     beams = []
     for c in cfgs:
         b = pic.Beam(c.n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, c.shape, c.nodes,
-                     grid_fp32=grid_fp32)
+                     grid_fp32=grid_fp32,
+                     tuning=autotune.batch_tuning(c, tune_rec, grid_fp32) if tune else None)
         b.init(c.sigma_matrix, seed=c.seed)
         beams.append(b)
     total = sum(c.n for c in cfgs)
@@ -276,7 +277,8 @@ def run_batched(n_beams, steps, grid_fp32=False, tune=True, sequential=True):
             "first_call_s_incl_capture": t_first,
             "grid_dtype": "f32" if grid_fp32 else "f64", "blocks_per_beam": blocks or 256,
             "autotune": None if tune_rec is None else
-            {"tried": tune_rec["tried"], "chosen": tune_rec["blocks_per_beam"]},
+            {"tried": tune_rec["tried"], "chosen": tune_rec["blocks_per_beam"],
+             "tile": tune_rec.get("tile", [0, 0, 0])},
             "per_beam_sequential": None if dt_seq is None else
             {"value": total * steps / dt_seq, "s": dt_seq,
              "note": "same beams, one pic_track_n_steps per beam"}}

@@ -40,6 +40,7 @@ DEPOSIT_THREADS = (0, 128, 256, 512, 1024)  # 0: that of `threads`
 FIELDS = ("tile", "chunk", "blocks", "threads", "deposit_threads")
 LDS_BYTES = 163840 - 4096               # dynamic LDS one workgroup may allocate
 BATCH_BLOCKS = (32, 64, 128, 256, 512)
+BATCH_TILES = (8, 12, 16)                # one tile edge for every beam of a batch
 
 
 def key(n, nodes, shape, grid_fp32):
@@ -180,24 +181,35 @@ def tune(cfg, grid_fp32=False, steps=6, cache=DEFAULT_CACHE, force=False, log=No
     return rec
 
 
+def batch_tuning(c, rec, grid_fp32, cache=DEFAULT_CACHE):
+    """The launch tuning of one beam of a tuned batch: the batch-wide tile edge of the record
+    where the tuner chose one, else the cached tuning of the beam's class (or None)."""
+    if rec and any(rec.get("tile", (0, 0, 0))):
+        return {"tile": list(rec["tile"])}
+    return lookup(c.n, c.nodes, c.shape, grid_fp32, cache) if cache else None
+
+
 def tune_batch(cfgs, grid_fp32=False, steps=10, cache=DEFAULT_CACHE, force=False, log=None):
-    """Workgroups per beam of the batched deposit and gather, timed on the batch itself (every
-    beam re-initialised before each candidate).  Per-beam tile and work-item sizes come from
-    the cache where a beam's class is tuned.  Returns {blocks_per_beam, s_per_step, tried}."""
+    """Workgroups per beam of the batched deposit and gather, then one tile edge for every
+    beam (BATCH_TILES, against the beams' own tuning or default), timed on the batch itself
+    (every beam re-initialised before each candidate).  Returns {blocks_per_beam, tile,
+    s_per_step, tried}; tile [0, 0, 0]: each beam keeps its class's cached tuning or the
+    default."""
     k = "batch-%d-beams-n%d-%s-%s" % (len(cfgs), sum(c.n for c in cfgs),
                                       "tsc" if cfgs[0].shape == 2 else "cic",
                                       "f32" if grid_fp32 else "f64")
     table = load(cache) if cache else {}
     if not force and k in table:
         return table[k]
-    beams = [Beam(c.n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, c.shape, c.nodes,
-                  grid_fp32=grid_fp32,
-                  tuning=lookup(c.n, c.nodes, c.shape, grid_fp32, cache) if cache else None)
-             for c in cfgs]
     tried = []
-    best, best_t = None, float("inf")
-    try:
-        for bl in BATCH_BLOCKS:
+
+    def run(bl, tile):
+        trec = {"tile": tile} if tile else None
+        beams = [Beam(c.n, c.qm_qeeV, c.charge_C, c.kin_energy_MeV, c.mass_MeV, c.shape,
+                      c.nodes, grid_fp32=grid_fp32,
+                      tuning=batch_tuning(c, trec, grid_fp32, cache))
+                 for c in cfgs]
+        try:
             batch = Batch(beams, [c.lattice for c in cfgs], blocks_per_beam=bl)
             for c, b in zip(cfgs, beams):
                 b.init(c.sigma_matrix, seed=c.seed)
@@ -211,15 +223,28 @@ def tune_batch(cfgs, grid_fp32=False, steps=10, cache=DEFAULT_CACHE, force=False
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             batch.close()
-            tried.append({"blocks_per_beam": bl, "s_per_step": dt})
-            if log:
-                log("tune %s blocks_per_beam=%d: %.3f ms/step" % (k, bl, dt * 1e3))
-            if dt < best_t:
-                best, best_t = bl, dt
-    finally:
-        for b in beams:
-            b.close()
-    rec = {"blocks_per_beam": best, "s_per_step": best_t, "steps_timed": steps, "tried": tried}
+        finally:
+            for b in beams:
+                b.close()
+        tried.append({"blocks_per_beam": bl, "tile": tile or [0, 0, 0], "s_per_step": dt})
+        if log:
+            log("tune %s blocks_per_beam=%d tile=%s: %.3f ms/step" % (k, bl, tile, dt * 1e3))
+        return dt
+
+    best_bl, best_tile, best_t = None, None, float("inf")
+    for bl in BATCH_BLOCKS:
+        dt = run(bl, None)
+        if dt < best_t:
+            best_bl, best_t = bl, dt
+    for t in BATCH_TILES:
+        tile = [t, t, t]
+        if not all(_tile_ok(tile, c.nodes, c.shape, grid_fp32) for c in cfgs):
+            continue
+        dt = run(best_bl, tile)
+        if dt < best_t:
+            best_tile, best_t = tile, dt
+    rec = {"blocks_per_beam": best_bl, "tile": best_tile or [0, 0, 0], "s_per_step": best_t,
+           "steps_timed": steps, "tried": tried}
     if cache:
         table = load(cache)
         table[k] = rec

@@ -63,4 +63,8 @@ def test_batch_autotune(lib, tmp_path):
     cfgs = workloads.batch_beams(n_beams=4, n_range=(3e3, 2e4), grids=(16, 24), steps=4)
     rec = autotune.tune_batch(cfgs, steps=2, cache=str(tmp_path / "t.json"))
     assert rec["blocks_per_beam"] in autotune.BATCH_BLOCKS
-    assert len(rec["tried"]) == len(autotune.BATCH_BLOCKS)
+    # the workgroup counts, then every batch-wide tile edge that fits all beams' grids
+    assert len(rec["tried"]) == len(autotune.BATCH_BLOCKS) + len(autotune.BATCH_TILES)
+    assert rec["tile"] == [0, 0, 0] or rec["tile"] in [[t] * 3 for t in autotune.BATCH_TILES]
+    t = autotune.batch_tuning(cfgs[0], rec, False, cache=None)
+    assert (t is None) if rec["tile"] == [0, 0, 0] else (t == {"tile": rec["tile"]})
