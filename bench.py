@@ -209,7 +209,7 @@ def fp32_accuracy(cfg, steps):
     out = {}
     for fp32 in (False, True):
         b = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV,
-                     cfg.shape, cfg.nodes, grid_fp32=fp32)
+                     cfg.shape, cfg.nodes, grid_fp32=fp32, tuning=tuned(cfg, fp32, True)[0])
         b.init_from_normals(cfg.sigma_matrix, xi)
         t0 = time.perf_counter()
         b.track(cfg.lattice, steps)
@@ -292,7 +292,7 @@ def run_adjoint(cfg, ckpt_every=10):
     import paper_2208_02382_amd as pic
 
     b = pic.Beam(cfg.n, cfg.qm_qeeV, cfg.charge_C, cfg.kin_energy_MeV, cfg.mass_MeV, cfg.shape,
-                 cfg.nodes)
+                 cfg.nodes, tuning=tuned(cfg, False, True)[0])
     xi = torch.from_numpy(workloads.draw_xi(cfg)).cuda()
     w = (1.0, 1.0, 1.0, 1.0)
     b.init_from_normals(cfg.sigma_matrix, xi)
